@@ -1,0 +1,237 @@
+/*
+ * hgnn.h - C-ABI of the MI355X (gfx950) PNA-style GCNN hot path.
+ *
+ * The library trains and serves the graph-convolutional surrogate of Choi et
+ * al., "Scalable training of graph convolutional neural networks for fast and
+ * accurate predictions of HOMO-LUMO gap in molecules": a stack of PNA graph
+ * convolution layers (Section 3.1; 6 layers in Section 5.1), global mean
+ * pooling (Section 3.1), fully connected layers (Sections 3.1-3.2), the MSE
+ * loss, the backward phase and the AdamW optimiser step (Section 3.2, Section
+ * 5.1).  Graphs come in the layout of Table 1: x (#nodes, #node features),
+ * edge_index (2, #edges) with row 0 the source and row 1 the destination,
+ * edge_attr (#edges, #edge features) and one graph-level target per graph.
+ *
+ * Layer definition (the paper names PNA without defining it; this is the
+ * reading the library implements), for layer l with input width F:
+ *   m_k   = W^m [h_dst(k) || h_src(k) || e_k] + b^m                   (H wide)
+ *   A_i   = [mean || min || max || std] of m_k over in-edges of node i,
+ *           std = sqrt(population variance + std_eps)
+ *   s+_i  = ln(d_i + 1) / delta,  s-_i = delta / ln(d_i + 1)   (0 if d_i = 0)
+ *   h'_i  = ReLU(W^p [h_i || A_i || s+_i A_i || s-_i A_i] + b^p)
+ * then g_b = mean of h over graph b, y_b = w2 ReLU(W1 g_b + b1) + b2 and
+ * loss = mean over graphs of (y_b - t_b)^2.  A min/max gradient goes to the
+ * first in-edge in (source id, edge id) order that attains the extremum.
+ *
+ * Parameter packing (interchange and checkpoint order, row-major [out, in]):
+ * per layer W^m [H, 2F+Fe], b^m [H], W^p [H, F+12H], b^p [H]; then W1 [H, H],
+ * b1 [H], w2 [1, H], b2 [1].  F = node_feat for the first layer, H after.
+ *
+ * Conventions
+ *  - Every pointer argument named *_dev is device memory; *_host is host
+ *    memory.  Streams are hipStream_t passed as void* (NULL = default stream).
+ *  - All calls are asynchronous on the given stream unless stated otherwise.
+ *    The caller keeps every buffer it passes alive until that stream work is
+ *    done.  The context owns its parameters, gradients, optimiser moments,
+ *    CSR arrays, activation store and workspaces.
+ *  - Status: 0 on success, a negative HGNN_E* code otherwise; nothing aborts.
+ *    hgnn_last_error() returns a thread-local message for the last failure.
+ *    Size and pointer checks are done on the host and return HGNN_EINVAL
+ *    synchronously.  Content checks (edge endpoint out of range, edge across
+ *    graphs, in- or out-degree above max_degree, empty graph) are done on the
+ *    device and set the context's error word: with HGNN_VALIDATE the call
+ *    synchronises and returns HGNN_EINVAL; otherwise hgnn_check() reports it.
+ *    A failed HIP call puts the context in HGNN_ESTATE until hgnn_set_state.
+ *  - Gradients overwrite (never accumulate) and refer to the last forward.
+ *  - Train calls on one context are not thread-safe; serve calls are.
+ *  - Indices are int32: num_nodes and num_edges must be below 2^31.
+ */
+#ifndef HGNN_H
+#define HGNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HGNN_OK = 0,
+  HGNN_EINVAL = -1,  /* bad argument or malformed batch */
+  HGNN_ENOMEM = -2,  /* device or host allocation failed */
+  HGNN_EDEVICE = -3, /* a HIP call failed (no device, launch failure) */
+  HGNN_EAGAIN = -4,  /* serving: queue full or request above the budget */
+  HGNN_ESTATE = -5   /* context unusable after a device failure */
+};
+
+enum { HGNN_VALIDATE = 1 }; /* forward flag: synchronise and check content */
+enum { HGNN_PREC_FP32 = 0, HGNN_PREC_BF16 = 1 };
+
+typedef struct hgnn_ctx hgnn_ctx;
+
+typedef struct {
+  int32_t num_layers; /* L >= 1 */
+  int32_t hidden;     /* H: multiple of 16, 16..512 */
+  int32_t node_feat;  /* F0 >= 1 */
+  int32_t edge_feat;  /* Fe in 0..4 */
+  int32_t max_degree; /* 1..255; in- and out-degree bound of every node */
+  int32_t precision;  /* HGNN_PREC_FP32: FP32 linears; HGNN_PREC_BF16: linear
+                         operands rounded to BF16 (RNE), FP32 accumulation;
+                         aggregation, scalers, pooling and loss stay FP32 */
+  int32_t recompute;  /* 1: keep only layer inputs; the backward pass re-runs
+                         the message linear and the aggregation per layer */
+  int32_t reserved;
+  double delta;       /* PNA degree normaliser (mean ln(d+1) of a calibration
+                         set); a model constant, never recomputed per batch */
+  double std_eps;     /* added to the variance inside the std aggregator */
+} hgnn_config;
+
+typedef struct {
+  int32_t num_graphs, num_nodes, num_edges; /* B >= 1, N >= B, E >= 0 */
+  int32_t reserved;
+  const int32_t *graph_ptr; /* [B+1]; graph b owns nodes [ptr[b], ptr[b+1]) */
+  const float *x;           /* [N, node_feat] */
+  const int32_t *edge_index;/* [2, E]: row 0 sources, row 1 destinations,
+                               global node ids; any order */
+  const float *edge_attr;   /* [E, edge_feat], NULL iff edge_feat == 0 */
+  const float *y;           /* [B] targets, or NULL when no loss is wanted */
+} hgnn_batch;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Validate cfg, select the current HIP device and allocate the context.
+ * Parameters start at zero: set them with hgnn_set_params.  EINVAL for a bad
+ * config (checked before any device call), EDEVICE/ENOMEM otherwise. */
+int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out);
+void hgnn_destroy(hgnn_ctx *ctx); /* synchronises; NULL is ignored */
+int hgnn_num_params(const hgnn_ctx *ctx, int64_t *out);
+/* Copy the packed parameters in (device [P]) and refresh the internal GEMM
+ * copies (padded, transposed, BF16 when precision is BF16). */
+int hgnn_set_params(hgnn_ctx *ctx, const float *params_dev, void *stream);
+int hgnn_get_params(hgnn_ctx *ctx, float *params_dev, void *stream);
+int hgnn_get_grads(hgnn_ctx *ctx, float *grads_dev, void *stream);
+/* Synchronise the stream and report the device error word (EINVAL with a
+ * message naming the first failed check) or a sticky ESTATE. */
+int hgnn_check(hgnn_ctx *ctx, void *stream);
+
+/* ---- training path (Section 3.2: forward, backward, optimiser) ---------- */
+
+/* Build the CSR of the batch and run every layer, the pooling and the head.
+ * pred_dev [B] receives y; loss_dev [1] (optional, needs batch->y) the MSE.
+ * The context keeps what the backward pass needs (and a pointer to batch
+ * buffers: keep them alive until hgnn_backward is done). */
+int hgnn_forward(hgnn_ctx *ctx, const hgnn_batch *batch, float *pred_dev,
+                 float *loss_dev, int32_t flags, void *stream);
+/* Gradients of the loss of the last forward (dpred_dev == NULL, needs
+ * batch->y) or of sum(dpred * y) (dpred_dev [B]) into the context's packed
+ * gradient vector. */
+int hgnn_backward(hgnn_ctx *ctx, const float *dpred_dev, void *stream);
+/* One AdamW step (decoupled decay, bias-corrected, step count kept by the
+ * context starting at 1) on the packed parameters with the current
+ * gradients; refreshes the internal GEMM copies. */
+int hgnn_adam_step(hgnn_ctx *ctx, float lr, float beta1, float beta2,
+                   float eps, float weight_decay, void *stream);
+
+/* ---- checkpoint --------------------------------------------------------- */
+
+/* Serialise config, step count, parameters and AdamW moments into a host
+ * buffer.  With buf_host == NULL only *bytes is set.  Synchronises. */
+int hgnn_get_state(hgnn_ctx *ctx, void *buf_host, size_t *bytes);
+/* Restore a state written by hgnn_get_state for the same config; clears
+ * HGNN_ESTATE.  Synchronises. */
+int hgnn_set_state(hgnn_ctx *ctx, const void *buf_host, size_t bytes);
+
+/* ---- per-operation entries (used by the autograd bindings) -------------- */
+/* These run single steps with explicit buffers.  w_layer_dev points at one
+ * layer's packed slice [W^m, b^m, W^p, b^p]; w_head_dev at [W1, b1, w2, b2];
+ * dw_* receive gradients in the same packing (overwritten). */
+
+/* Step S0: validate sizes, copy x into the padded layer-0 input and build the
+ * destination-sorted CSR, its by-source transpose and the per-node scalers. */
+int hgnn_op_prepare(hgnn_ctx *ctx, const hgnn_batch *batch, int32_t flags,
+                    void *stream);
+/* Layer l forward: h_out_dev [N, H] from h_in_dev [N, F_l].  Stores the
+ * layer's messages, aggregates and arg decisions (unless recompute is on). */
+int hgnn_op_layer_forward(hgnn_ctx *ctx, int32_t layer,
+                          const float *w_layer_dev, const float *h_in_dev,
+                          float *h_out_dev, void *stream);
+/* Layer l backward: from dh_out_dev [N, H] (gradient w.r.t. h_out) write
+ * dw_layer_dev and, when dh_in_dev is not NULL, dh_in_dev [N, F_l]. */
+int hgnn_op_layer_backward(hgnn_ctx *ctx, int32_t layer,
+                           const float *w_layer_dev, const float *h_in_dev,
+                           const float *h_out_dev, const float *dh_out_dev,
+                           float *dh_in_dev, float *dw_layer_dev, void *stream);
+/* Pooling + head (+ loss when target_dev and loss_dev are given). */
+int hgnn_op_head_forward(hgnn_ctx *ctx, const float *w_head_dev,
+                         const float *h_dev, const float *target_dev,
+                         float *pred_dev, float *loss_dev, void *stream);
+/* Head adjoint: dpred_dev [B], or the MSE gradient from target_dev when
+ * dpred_dev is NULL.  Writes dh_dev [N, H] and dw_head_dev. */
+int hgnn_op_head_backward(hgnn_ctx *ctx, const float *w_head_dev,
+                          const float *h_dev, const float *target_dev,
+                          const float *dpred_dev, float *dh_dev,
+                          float *dw_head_dev, void *stream);
+
+/* Inspection of stored results (parity tests).  which:
+ *   0 rowptr [N+1]  1 csr_src [E]  2 csr_eid [E]  3 deg [N]
+ *   4 srcptr [N+1]  5 t2csr [E]    6 node_graph [N]          (int32)
+ *   7 aggregates A of `layer` [N, 4H] (float32)
+ *   8 arg decisions of `layer` [N, 2H] (uint8: argmin offsets then argmax)
+ *   9 head hidden activations ReLU(W1 g + b1) [B, H] (float32)
+ *  10 pooled features g [B, H] (float32)
+ *  11 output of `layer` from the last hgnn_forward [N, H] (float32)
+ * Copies into dst_dev (capacity bytes); EINVAL if too small or not stored. */
+int hgnn_op_fetch(hgnn_ctx *ctx, int32_t which, int32_t layer, void *dst_dev,
+                  size_t capacity, void *stream);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* Opt-in kernel timer: bracket every launch of one launch site with a pair of
+ * HIP events recorded on that launch's stream, for up to max_launches
+ * launches.  Sites: 1 message GEMM, 2 aggregation, 3 update GEMM, 4 update
+ * weight-gradient GEMM, 5 aggregate-gradient GEMM, 6 aggregation adjoint,
+ * 7 input-gradient GEMM.  Synchronises the device. */
+int hgnn_timer_start(hgnn_ctx *ctx, int32_t site, int32_t max_launches);
+/* Sum of the bracketed durations (ms) and the number of launches; stops the
+ * timer.  Waits for the recorded events. */
+int hgnn_timer_read(hgnn_ctx *ctx, double *total_ms, int32_t *launches);
+
+/* ---- serving (continuous batching of inference requests) --------------- */
+
+typedef struct {
+  int64_t hbm_budget_bytes; /* admission budget for in-flight batches */
+  int32_t max_batch_nodes;  /* node capacity of the largest packed batch */
+  int32_t max_batch_edges;  /* edge capacity of the largest packed batch */
+  int32_t max_batch_graphs; /* graph capacity of the largest packed batch */
+  int32_t num_lanes;        /* batches in flight at once (own stream each) */
+  int32_t queue_capacity;   /* pending requests before submit says EAGAIN */
+  int32_t use_graphs;       /* 1: replay captured HIP graphs per bucket */
+} hgnn_serve_config;
+
+typedef struct {
+  int64_t submitted, completed, batches, graph_replays, admission_waits;
+  int64_t peak_inflight_bytes;
+} hgnn_serve_stats;
+
+/* Start the scheduler thread; the weights stay resident and are shared. */
+int hgnn_serve_start(hgnn_ctx *ctx, const hgnn_serve_config *cfg);
+/* Copy a request (host arrays, y ignored) into the queue; returns a ticket.
+ * EAGAIN when the queue is full or the request alone exceeds a lane. */
+int hgnn_serve_submit(hgnn_ctx *ctx, const hgnn_batch *request_host,
+                      uint64_t *ticket);
+/* *done = 1 and pred_host [B_request] filled once finished (the ticket is
+ * then released); *done = 0 while pending.  EINVAL for an unknown ticket or
+ * a request that failed validation. */
+int hgnn_serve_poll(hgnn_ctx *ctx, uint64_t ticket, float *pred_host,
+                    int32_t *done);
+int hgnn_serve_stats_get(hgnn_ctx *ctx, hgnn_serve_stats *out);
+/* Drain in-flight work and stop the thread. */
+int hgnn_serve_stop(hgnn_ctx *ctx);
+
+const char *hgnn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGNN_H */

@@ -1,0 +1,126 @@
+// Step S9: AdamW (Section 5.1: AdamW, learning rate 1e-3) on the packed
+// parameter vector, and the refresh of the GEMM-layout weight copies.
+//
+// The bias corrections are computed on the device from a device-resident
+// step counter so that a captured training step replays correctly.
+#include "common.hpp"
+
+namespace hgnn {
+
+namespace {
+
+inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
+
+// t += 1; corr = [1/(1-b1^t), 1/(1-b2^t)] in double, stored as float.
+__global__ void k_adam_prep(long long *step, float *corr, double b1, double b2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const long long t = *step + 1;
+    *step = t;
+    corr[0] = (float)(1.0 / (1.0 - pow(b1, (double)t)));
+    corr[1] = (float)(1.0 / (1.0 - pow(b2, (double)t)));
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_adamw(float *__restrict__ theta, const float *__restrict__ g, float *__restrict__ m,
+        float *__restrict__ v, long long n, float lr, float b1, float omb1, float b2,
+        float omb2, float eps, float decay, const float *__restrict__ corr) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float c1 = corr[0], c2 = corr[1];
+  const float gi = g[i];
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float th = theta[i] * decay;
+  theta[i] = th - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+template <typename T> __device__ __forceinline__ void put(void *dst, size_t i, float v) {
+  reinterpret_cast<T *>(dst)[i] = (T)v;
+}
+
+// Per layer: the four GEMM-layout copies of W^m and W^p.
+//  Wds   [2H, Fp]     rows n < H: W^m[n, 0:F]; n >= H: W^m[n-H, F:2F]; zero pad
+//  Wpp   [H, Fp+12H]  W^p with its first block padded from F to Fp columns
+//  WpTA  [4H, 3H]     WpTA[c, j H + m] = W^p[m, F + 4 H j + c]
+//  WhdsT [Fp, 3H]     [W^p[:, c]; W^m[:, c]; W^m[:, F + c]]^T, zero rows c >= F
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F, int Fp,
+              int H, int Fe, void *Wds, void *Wpp, void *WpTA, void *WhdsT) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ldm = 2 * F + Fe, ldp = F + 12 * H;
+  const long long n1 = 2LL * H * Fp, n2 = (long long)H * (Fp + 12 * H);
+  const long long n3 = 12LL * H * H, n4 = 3LL * Fp * H;
+  if (t < n1) {
+    const int r = (int)(t / Fp), c = (int)(t % Fp);
+    float v = 0.f;
+    if (c < F) v = r < H ? Wm[(size_t)r * ldm + c] : Wm[(size_t)(r - H) * ldm + F + c];
+    put<T>(Wds, t, v);
+  } else if (t < n1 + n2) {
+    const long long u = t - n1;
+    const int r = (int)(u / (Fp + 12 * H)), c = (int)(u % (Fp + 12 * H));
+    float v = 0.f;
+    if (c < Fp) { if (c < F) v = Wp[(size_t)r * ldp + c]; }
+    else v = Wp[(size_t)r * ldp + F + (c - Fp)];
+    put<T>(Wpp, u, v);
+  } else if (t < n1 + n2 + n3) {
+    const long long u = t - n1 - n2;
+    const int r = (int)(u / (3 * H)), c = (int)(u % (3 * H));
+    const int j = c / H, m = c % H;
+    put<T>(WpTA, u, Wp[(size_t)m * ldp + F + 4 * H * j + r]);
+  } else if (t < n1 + n2 + n3 + n4) {
+    const long long u = t - n1 - n2 - n3;
+    const int r = (int)(u / (3 * H)), c = (int)(u % (3 * H));
+    const int j = c / H, m = c % H;
+    float v = 0.f;
+    if (r < F) {
+      if (j == 0) v = Wp[(size_t)m * ldp + r];
+      else if (j == 1) v = Wm[(size_t)m * ldm + r];
+      else v = Wm[(size_t)m * ldm + F + r];
+    }
+    put<T>(WhdsT, u, v);
+  }
+}
+
+__global__ void k_fill(float *p, long long n, float v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+} // namespace
+
+hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_t n,
+                        float lr, double b1, double b2, float eps, float wd,
+                        long long *step, float *corr, hipStream_t s) {
+  k_adam_prep<<<1, 64, 0, s>>>(step, corr, b1, b2);
+  if (n > 0)
+    k_adamw<<<cdiv(n, 256), 256, 0, s>>>(theta, g, m, v, n, lr, (float)b1,
+                                         (float)(1.0 - b1), (float)b2, (float)(1.0 - b2),
+                                         eps, (float)(1.0 - (double)lr * wd), corr);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp, int H,
+                              int Fe, void *Wds, void *Wpp, void *WpTA, void *WhdsT,
+                              int to_bf16, hipStream_t s) {
+  const long long total = 2LL * H * Fp + (long long)H * (Fp + 12 * H) + 12LL * H * H +
+                          3LL * Fp * H;
+  if (to_bf16)
+    k_stage_layer<__bf16><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, Wds, Wpp,
+                                                           WpTA, WhdsT);
+  else
+    k_stage_layer<float><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, Wds, Wpp,
+                                                          WpTA, WhdsT);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill<<<cdiv(n, 256), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+} // namespace hgnn

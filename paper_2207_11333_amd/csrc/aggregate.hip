@@ -1,0 +1,308 @@
+// Steps S2 and S7: the PNA segmented aggregation over each node's in-edges
+// and its adjoint.
+//
+// Forward: for node i and feature c, over the in-edges k of i (CSR order,
+// i.e. by (source, edge id)), the message m_k = P_i + Q_{src(k)} + e_k w_e + b
+// (the decomposed message linear: P = h W_dst^T, Q = h W_src^T computed by
+// one GEMM) is reduced to mean, min, max and std = sqrt(mean((m - mean)^2)
+// + eps) (two passes).  Strict comparisons keep the first extremum in CSR
+// order; its segment offset is stored as a byte for the backward pass.
+// One thread owns four consecutive features of one node (16-byte loads of
+// the gathered Q rows, coalesced across the H/4 threads of the node).
+//
+// Adjoint: dm_k = dmean/d + [k = argmin] dmin + [k = argmax] dmax
+//               + dstd (m_k - mean) / (d std), with m_k recomputed.  The
+// per-edge dm is stored in CSR order; D_in[i] = sum over in-edges (same
+// pass) and D_out[j] = sum over the out-edges of j through the by-source
+// transpose (second kernel): fixed summation orders, no atomics.
+#include "common.hpp"
+
+namespace hgnn {
+
+namespace {
+
+inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
+
+constexpr int kCache = 4; // messages kept in registers per thread
+
+template <int FE>
+__device__ __forceinline__ f4 message(const float *__restrict__ PQ, int H, int s,
+                                      int c, f4 p, f4 bm, const f4 (&we)[4],
+                                      const float *__restrict__ csr_e, int q) {
+  f4 m = p + *reinterpret_cast<const f4 *>(PQ + (size_t)s * 2 * H + H + c);
+#pragma unroll
+  for (int f = 0; f < FE; ++f) m += csr_e[(size_t)q * FE + f] * we[f];
+  return m + bm;
+}
+
+template <int FE>
+__global__ void __launch_bounds__(256)
+k_aggregate(const Dims *__restrict__ dims, int H, const float *__restrict__ PQ,
+            const int *__restrict__ rowptr, const int *__restrict__ csr_src,
+            const float *__restrict__ csr_e, const float *__restrict__ We, int ldwe,
+            const float *__restrict__ bmv, float *__restrict__ A,
+            uint8_t *__restrict__ args, float eps) {
+  const int tpn = H >> 2;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / tpn), c = (int)(t % tpn) * 4;
+  if (i >= dims->N) return;
+  f4 we[4];
+#pragma unroll
+  for (int f = 0; f < FE; ++f)
+    we[f] = f4{We[(size_t)(c + 0) * ldwe + f], We[(size_t)(c + 1) * ldwe + f],
+               We[(size_t)(c + 2) * ldwe + f], We[(size_t)(c + 3) * ldwe + f]};
+  const f4 bm = *reinterpret_cast<const f4 *>(bmv + c);
+  const f4 p = *reinterpret_cast<const f4 *>(PQ + (size_t)i * 2 * H + c);
+  const int lo = rowptr[i], hi = rowptr[i + 1], d = hi - lo;
+  f4 mu = {0.f, 0.f, 0.f, 0.f}, mn = mu, mx = mu, sd = mu;
+  uint32_t amin = 0, amax = 0;
+  if (d > 0) {
+    f4 cache[kCache];
+    f4 sum = {0.f, 0.f, 0.f, 0.f};
+    int imn[4] = {0, 0, 0, 0}, imx[4] = {0, 0, 0, 0};
+    for (int o = 0; o < d; ++o) {
+      const int q = lo + o;
+      const f4 m = message<FE>(PQ, H, csr_src[q], c, p, bm, we, csr_e, q);
+      if (o < kCache) cache[o] = m;
+      sum += m;
+      if (o == 0) {
+        mn = m;
+        mx = m;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (m[e] < mn[e]) { mn[e] = m[e]; imn[e] = o; }
+          if (m[e] > mx[e]) { mx[e] = m[e]; imx[e] = o; }
+        }
+      }
+    }
+    const float fd = (float)d;
+    mu = sum / fd;
+    f4 ss = {0.f, 0.f, 0.f, 0.f};
+    for (int o = 0; o < d; ++o) {
+      f4 m;
+      if (o < kCache) m = cache[o];
+      else m = message<FE>(PQ, H, csr_src[lo + o], c, p, bm, we, csr_e, lo + o);
+      const f4 dv = m - mu;
+      ss += dv * dv;
+    }
+    const f4 var = ss / fd;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sd[e] = sqrtf(var[e] + eps);
+    amin = (uint32_t)imn[0] | ((uint32_t)imn[1] << 8) | ((uint32_t)imn[2] << 16) |
+           ((uint32_t)imn[3] << 24);
+    amax = (uint32_t)imx[0] | ((uint32_t)imx[1] << 8) | ((uint32_t)imx[2] << 16) |
+           ((uint32_t)imx[3] << 24);
+  }
+  float *Ai = A + (size_t)i * 4 * H;
+  *reinterpret_cast<f4 *>(Ai + c) = mu;
+  *reinterpret_cast<f4 *>(Ai + H + c) = mn;
+  *reinterpret_cast<f4 *>(Ai + 2 * H + c) = mx;
+  *reinterpret_cast<f4 *>(Ai + 3 * H + c) = sd;
+  if (args) {
+    uint8_t *ai = args + (size_t)i * 2 * H;
+    *reinterpret_cast<uint32_t *>(ai + c) = amin;
+    *reinterpret_cast<uint32_t *>(ai + H + c) = amax;
+  }
+}
+
+template <int FE>
+__global__ void __launch_bounds__(256)
+k_aggregate_bwd(const Dims *__restrict__ dims, int H, const float *__restrict__ PQ,
+                const int *__restrict__ rowptr, const int *__restrict__ csr_src,
+                const float *__restrict__ csr_e, const float *__restrict__ We, int ldwe,
+                const float *__restrict__ bmv, const float *__restrict__ A,
+                const uint8_t *__restrict__ args, const float *__restrict__ dA,
+                float *__restrict__ dm, float *__restrict__ Dio,
+                float *__restrict__ De) {
+  const int tpn = H >> 2;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / tpn), c = (int)(t % tpn) * 4;
+  if (i >= dims->N) return;
+  const int lo = rowptr[i], hi = rowptr[i + 1], d = hi - lo;
+  f4 din = {0.f, 0.f, 0.f, 0.f};
+  f4 de[4] = {din, din, din, din};
+  if (d > 0) {
+    f4 we[4];
+#pragma unroll
+    for (int f = 0; f < FE; ++f)
+      we[f] = f4{We[(size_t)(c + 0) * ldwe + f], We[(size_t)(c + 1) * ldwe + f],
+                 We[(size_t)(c + 2) * ldwe + f], We[(size_t)(c + 3) * ldwe + f]};
+    const f4 bm = *reinterpret_cast<const f4 *>(bmv + c);
+    const f4 p = *reinterpret_cast<const f4 *>(PQ + (size_t)i * 2 * H + c);
+    const float *Ai = A + (size_t)i * 4 * H;
+    const float *dAi = dA + (size_t)i * 4 * H;
+    const f4 mu = *reinterpret_cast<const f4 *>(Ai + c);
+    const f4 sd = *reinterpret_cast<const f4 *>(Ai + 3 * H + c);
+    const f4 dmu = *reinterpret_cast<const f4 *>(dAi + c);
+    const f4 dmn = *reinterpret_cast<const f4 *>(dAi + H + c);
+    const f4 dmx = *reinterpret_cast<const f4 *>(dAi + 2 * H + c);
+    const f4 dsd = *reinterpret_cast<const f4 *>(dAi + 3 * H + c);
+    const uint32_t amin = *reinterpret_cast<const uint32_t *>(args + (size_t)i * 2 * H + c);
+    const uint32_t amax = *reinterpret_cast<const uint32_t *>(args + (size_t)i * 2 * H + H + c);
+    const float fd = (float)d;
+    const f4 base = dmu / fd;
+    const f4 coef = dsd / (fd * sd);
+    for (int o = 0; o < d; ++o) {
+      const int q = lo + o;
+      const f4 m = message<FE>(PQ, H, csr_src[q], c, p, bm, we, csr_e, q);
+      f4 g = base + coef * (m - mu);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if ((int)((amin >> (8 * e)) & 0xff) == o) g[e] += dmn[e];
+        if ((int)((amax >> (8 * e)) & 0xff) == o) g[e] += dmx[e];
+      }
+      *reinterpret_cast<f4 *>(dm + (size_t)q * H + c) = g;
+      din += g;
+#pragma unroll
+      for (int f = 0; f < FE; ++f) de[f] += g * csr_e[(size_t)q * FE + f];
+    }
+  }
+  *reinterpret_cast<f4 *>(Dio + (size_t)i * 2 * H + c) = din;
+#pragma unroll
+  for (int f = 0; f < FE; ++f)
+    *reinterpret_cast<f4 *>(De + (size_t)i * FE * H + f * H + c) = de[f];
+}
+
+__global__ void __launch_bounds__(256)
+k_transpose_sum(const Dims *__restrict__ dims, int H, const int *__restrict__ srcptr,
+                const int *__restrict__ t2csr, const float *__restrict__ dm,
+                float *__restrict__ Dio) {
+  const int tpn = H >> 2;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = (int)(t / tpn), c = (int)(t % tpn) * 4;
+  if (j >= dims->N) return;
+  f4 s = {0.f, 0.f, 0.f, 0.f};
+  for (int p = srcptr[j]; p < srcptr[j + 1]; ++p)
+    s += *reinterpret_cast<const f4 *>(dm + (size_t)t2csr[p] * H + c);
+  *reinterpret_cast<f4 *>(Dio + (size_t)j * 2 * H + H + c) = s;
+}
+
+__global__ void __launch_bounds__(256)
+k_relu_mask(const Dims *__restrict__ dims, int H, const float *__restrict__ dh,
+            const float *__restrict__ hout, float *__restrict__ du) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n4 = (long long)dims->N * H / 4;
+  if (t >= n4) return;
+  const f4 g = reinterpret_cast<const f4 *>(dh)[t];
+  const f4 h = reinterpret_cast<const f4 *>(hout)[t];
+  f4 o;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) o[e] = h[e] > 0.f ? g[e] : 0.f;
+  reinterpret_cast<f4 *>(du)[t] = o;
+}
+
+// Column sums, stage 1: partial[z][col] over row chunk z.
+__global__ void __launch_bounds__(256)
+k_colsum_partial(const Dims *__restrict__ dims, const ColSum cs,
+                 float *__restrict__ part, int total_cols, int splits) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (col >= total_cols) return;
+  int a = 0, c = col;
+  while (a + 1 < cs.n && c >= cs.ncols[a]) { c -= cs.ncols[a]; ++a; }
+  const int rows = dims->N;
+  const int chunk = (rows + splits - 1) / splits;
+  const int lo = z * chunk, hi = min(rows, lo + chunk);
+  const float *src = cs.src[a];
+  const int ld = cs.ld[a];
+  float s = 0.f;
+  for (int i = lo; i < hi; ++i) s += src[(size_t)i * ld + c];
+  part[(size_t)z * total_cols + col] = s;
+}
+
+// Stage 2: ordered sum over the chunks; output column c of array a goes to
+// out[a][(c % rs) * ostride + c / rs].
+struct ColSumOut {
+  float *out[3];
+  int rs[3], ostride[3];
+};
+
+__global__ void k_colsum_final(const ColSum cs, const ColSumOut co,
+                               const float *__restrict__ part, int total_cols,
+                               int splits) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= total_cols) return;
+  int a = 0, c = col;
+  while (a + 1 < cs.n && c >= cs.ncols[a]) { c -= cs.ncols[a]; ++a; }
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[(size_t)z * total_cols + col];
+  co.out[a][(size_t)(c % co.rs[a]) * co.ostride[a] + c / co.rs[a]] = s;
+}
+
+} // namespace
+
+hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
+                            const float *PQ, const int *rowptr, const int *csr_src,
+                            const float *csr_e, const float *We, int ldwe,
+                            const float *bm, float *A, uint8_t *args, float eps,
+                            hipStream_t s) {
+  if (capN <= 0) return hipSuccess;
+  const int grid = cdiv((long long)capN * (H / 4), 256);
+  switch (Fe) {
+  case 0: k_aggregate<0><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
+  case 1: k_aggregate<1><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
+  case 2: k_aggregate<2><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
+  case 3: k_aggregate<3><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
+  default: k_aggregate<4><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
+                                const float *PQ, const int *rowptr,
+                                const int *csr_src, const float *csr_e,
+                                const float *We, int ldwe, const float *bm,
+                                const float *A, const uint8_t *args,
+                                const float *dA, float *dm, float *Dio, float *De,
+                                hipStream_t s) {
+  if (capN <= 0) return hipSuccess;
+  const int grid = cdiv((long long)capN * (H / 4), 256);
+#define HGNN_AGG_BWD(FE)                                                               \
+  k_aggregate_bwd<FE><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, \
+                                           bm, A, args, dA, dm, Dio, De)
+  switch (Fe) {
+  case 0: HGNN_AGG_BWD(0); break;
+  case 1: HGNN_AGG_BWD(1); break;
+  case 2: HGNN_AGG_BWD(2); break;
+  case 3: HGNN_AGG_BWD(3); break;
+  default: HGNN_AGG_BWD(4); break;
+  }
+#undef HGNN_AGG_BWD
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_sum(const Dims *dims, int capN, int H, const int *srcptr,
+                                const int *t2csr, const float *dm, float *Dio,
+                                hipStream_t s) {
+  if (capN <= 0) return hipSuccess;
+  k_transpose_sum<<<cdiv((long long)capN * (H / 4), 256), 256, 0, s>>>(dims, H, srcptr,
+                                                                       t2csr, dm, Dio);
+  return hipGetLastError();
+}
+
+hipError_t launch_relu_mask(const Dims *dims, int capN, int H, const float *dh,
+                            const float *hout, float *du, hipStream_t s) {
+  if (capN <= 0) return hipSuccess;
+  k_relu_mask<<<cdiv((long long)capN * H / 4, 256), 256, 0, s>>>(dims, H, dh, hout, du);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const Dims *dims, const ColSum &c, const ColSumMap &map,
+                         float *partials, int splits, hipStream_t s) {
+  int total = 0;
+  for (int a = 0; a < c.n; ++a) total += c.ncols[a];
+  if (total <= 0) return hipSuccess;
+  ColSumOut co;
+  for (int a = 0; a < 3; ++a) {
+    co.out[a] = a < c.n ? c.out[a] : nullptr;
+    co.rs[a] = a < c.n ? map.rs[a] : 1;
+    co.ostride[a] = a < c.n ? map.ostride[a] : 1;
+  }
+  dim3 g1(cdiv(total, 256), splits);
+  k_colsum_partial<<<g1, 256, 0, s>>>(dims, c, partials, total, splits);
+  k_colsum_final<<<cdiv(total, 256), 256, 0, s>>>(c, co, partials, total, splits);
+  return hipGetLastError();
+}
+
+} // namespace hgnn

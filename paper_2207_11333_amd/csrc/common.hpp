@@ -1,0 +1,181 @@
+// Internal declarations shared by the HIP translation units of libhgnn.
+// Every kernel here is written for gfx950 (CDNA4): 64-wide wavefronts,
+// MFMA matrix cores, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace hgnn {
+
+// Device-side sizes of the batch being processed.  Kernels read the live
+// sizes from here so that one launch (or one captured HIP graph) serves any
+// batch up to the capacity its grid was sized for.
+struct Dims {
+  int32_t B, N, E, pad;
+};
+
+// Error-word bits raised by the CSR builder (device side).
+enum : int32_t {
+  ERR_EDGE_RANGE = 1,   // edge endpoint outside [0, N)
+  ERR_EDGE_CROSS = 2,   // edge joins two graphs
+  ERR_DEGREE = 4,       // in- or out-degree above max_degree
+  ERR_GRAPH_PTR = 8,    // graph_ptr not 0..N or a graph without nodes
+};
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------------
+// GEMM descriptors.  Up to four K segments, each a row-major operand with
+// its own leading dimension and an optional per-row scale.  Used for the
+// "virtual" operands [h || A || s+ A || s- A] and [du || s+ du || s- du]
+// that are never materialised.
+// ------------------------------------------------------------------------
+constexpr int kMaxSeg = 4;
+
+struct SegA {
+  const float *ptr;   // [rows, ld] row-major, k-contiguous
+  const float *scale; // per-row scale or nullptr
+  int ld;             // leading dimension (floats)
+  int k;              // segment length (multiple of 4)
+  int boff;           // column offset of this segment inside the B rows
+};
+
+// C[m, n] = act( sum_seg sum_k scale_s[m] A_s[m, k] * B[n, boff_s + k] + bias[n] )
+// for m < dims->N (or M_fixed when >= 0) and n < Ncols.
+struct GemmNT {
+  SegA seg[kMaxSeg];
+  int nseg;
+  const void *B;   // [Ncols, ldb] (float or bf16 per precision), k-contiguous
+  int ldb;
+  int Ncols;
+  const float *bias; // [Ncols] or nullptr
+  int relu;
+  float *C;
+  int ldc;
+  int M_fixed;       // -1: M = dims->N
+};
+
+// Weight-gradient form, reduction over rows i (nodes):
+// P[z][m, n] = sum_{i in chunk z} X[i, m] * Yv[i, n]
+// where Yv = [seg0 || seg1 || ...] with per-row (per-i) scales.
+struct SegY {
+  const float *ptr;
+  const float *scale;
+  int ld;
+  int ncols;  // multiple of 4
+};
+
+struct GemmTN {
+  const float *X;  // [rows, ldx], column m
+  int ldx;
+  int M;           // output rows (columns of X), multiple of 16
+  SegY seg[kMaxSeg];
+  int nseg;
+  int Ncols;       // total columns of Yv
+  float *P;        // partials [splits, M, Ncols]
+  int splits;
+};
+
+// Scatter of reduced partials into the packed gradient vector:
+// out[(r % rsplit) * ldo + (r / rsplit) * rcoloff + cmap(c)]
+// with cmap(c) = c < F ? c : (c < Fp ? skip : c - (Fp - F)).
+struct ReduceMap {
+  const float *P;
+  int splits, M, Ncols;
+  float *out;
+  int ldo, rsplit, rcoloff, F, Fp;
+};
+
+// ------------------------------------------------------------------------
+// launchers (each returns hipGetLastError() of its launch)
+// ------------------------------------------------------------------------
+
+// csr.hip
+struct CsrBufs {
+  int *rowptr, *csr_src, *csr_eid, *deg, *srcptr, *t2csr, *node_graph;
+  int *cnt_in, *cnt_out, *tmp_out, *csr_pos;
+  float *csr_e;       // [E, Fe] edge attributes in CSR order
+  float *sp, *sm;     // per-node degree scalers
+  int *err;           // error word
+};
+hipError_t launch_set_dims(Dims *d, int B, int N, int E, hipStream_t s);
+hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
+                            const int *graph_ptr, const int *edge_index,
+                            const float *edge_attr, int Fe, int max_degree,
+                            const float *scaler_table, const CsrBufs &c,
+                            hipStream_t s);
+hipError_t launch_pad_copy(const Dims *dims, int capN, const float *x, int F,
+                           float *xp, int Fp, hipStream_t s);
+
+// gemm.hip
+hipError_t launch_gemm_nt(const Dims *dims, int capM, const GemmNT &g,
+                          int precision, hipStream_t s);
+hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
+                          hipStream_t s);
+hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s);
+
+// aggregate.hip
+hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
+                            const float *PQ, const int *rowptr,
+                            const int *csr_src, const float *csr_e,
+                            const float *We, int ldwe, const float *bm,
+                            float *A, uint8_t *args, float eps, hipStream_t s);
+hipError_t launch_relu_mask(const Dims *dims, int capN, int H,
+                            const float *dh, const float *hout, float *du,
+                            hipStream_t s);
+hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
+                                const float *PQ, const int *rowptr,
+                                const int *csr_src, const float *csr_e,
+                                const float *We, int ldwe, const float *bm,
+                                const float *A, const uint8_t *args,
+                                const float *dA, float *dm, float *Dio,
+                                float *De, hipStream_t s);
+hipError_t launch_transpose_sum(const Dims *dims, int capN, int H,
+                                const int *srcptr, const int *t2csr,
+                                const float *dm, float *Dio, hipStream_t s);
+// Column sums over the rows of up to 3 [N, ncols] arrays, deterministic.
+// Column c of array a is written to out[a][(c % rs[a]) * ostride[a] + c / rs[a]].
+struct ColSum {
+  const float *src[3];
+  int ld[3], ncols[3];
+  float *out[3];
+  int n;
+};
+struct ColSumMap {
+  int rs[3], ostride[3];
+};
+hipError_t launch_colsum(const Dims *dims, const ColSum &c, const ColSumMap &map,
+                         float *partials, int splits, hipStream_t s);
+
+// head.hip
+hipError_t launch_head_forward(const Dims *dims, int capB, int H,
+                               const int *graph_ptr, const float *h,
+                               const float *W1, const float *b1,
+                               const float *w2, const float *b2, float *g,
+                               float *q, float *pred, float *pred2,
+                               hipStream_t s);
+hipError_t launch_loss(const Dims *dims, const float *pred, const float *t,
+                       float *loss, hipStream_t s);
+// dw_head receives [dW1 (H*H), db1 (H), dw2 (H), db2 (1)].
+hipError_t launch_head_backward(const Dims *dims, int capB, int H,
+                                const int *graph_ptr, const float *W1,
+                                const float *w2, const float *g, const float *q,
+                                const float *pred, const float *target,
+                                const float *dpred, float *dy, float *dq,
+                                float *dh, float *dw_head, hipStream_t s);
+
+// adam.hip
+hipError_t launch_adamw(float *theta, const float *g, float *m, float *v,
+                        int64_t n, float lr, double b1, double b2, float eps,
+                        float wd, long long *step, float *corr, hipStream_t s);
+hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp,
+                              int H, int Fe, void *Wds, void *Wpp, void *WpTA,
+                              void *WhdsT, int to_bf16, hipStream_t s);
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
+
+} // namespace hgnn

@@ -1,0 +1,289 @@
+// Step S0: batch validation and the destination-sorted CSR.
+//
+// Edges of a batch of molecular graphs (Table 1 layout: edge_index (2, E),
+// row 0 source, row 1 destination) are grouped by destination and, within a
+// destination, ordered by (source id, edge id).  The by-source transpose
+// lists, for every node, the CSR positions of its out-edges in ascending
+// order; the aggregation adjoint uses it to sum per-edge gradients by source
+// without atomics.  Atomic counters only place edges into their segment; a
+// per-segment sort then fixes the order, so every integer output is
+// deterministic and independent of the COO edge order.
+#include "common.hpp"
+
+namespace hgnn {
+
+namespace {
+
+__global__ void k_set_dims(Dims *d, int B, int N, int E, int *err) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (d) {
+      d->B = B;
+      d->N = N;
+      d->E = E;
+      d->pad = 0;
+    }
+    if (err) *err = 0;
+  }
+}
+
+// node -> graph id by binary search over graph_ptr; zero the counters;
+// check graph_ptr.
+__global__ void k_csr_init(const Dims *__restrict__ dims,
+                           const int *__restrict__ graph_ptr,
+                           int *__restrict__ node_graph, int *__restrict__ cnt_in,
+                           int *__restrict__ cnt_out, int *__restrict__ err) {
+  const int B = dims->B, N = dims->N;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B) {
+    if (graph_ptr[i + 1] <= graph_ptr[i]) atomicOr(err, ERR_GRAPH_PTR);
+  }
+  if (i == 0) {
+    if (graph_ptr[0] != 0 || graph_ptr[B] != N) atomicOr(err, ERR_GRAPH_PTR);
+  }
+  if (i < N) {
+    int lo = 0, hi = B; // find last b with graph_ptr[b] <= i
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (graph_ptr[mid] <= i) lo = mid; else hi = mid;
+    }
+    node_graph[i] = lo;
+    cnt_in[i] = 0;
+    cnt_out[i] = 0;
+  }
+}
+
+__device__ __forceinline__ bool edge_ok(int s, int d, int N,
+                                        const int *__restrict__ node_graph) {
+  return s >= 0 && s < N && d >= 0 && d < N && node_graph[s] == node_graph[d];
+}
+
+__global__ void k_csr_count(const Dims *__restrict__ dims,
+                            const int *__restrict__ ei,
+                            const int *__restrict__ node_graph,
+                            int *__restrict__ cnt_in, int *__restrict__ cnt_out,
+                            int *__restrict__ err) {
+  const int N = dims->N, E = dims->E;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= E) return;
+  const int s = ei[k], d = ei[E + k];
+  if (s < 0 || s >= N || d < 0 || d >= N) {
+    atomicOr(err, ERR_EDGE_RANGE);
+    return;
+  }
+  if (node_graph[s] != node_graph[d]) {
+    atomicOr(err, ERR_EDGE_CROSS);
+    return;
+  }
+  atomicAdd(&cnt_in[d], 1);
+  atomicAdd(&cnt_out[s], 1);
+}
+
+// One workgroup: exclusive scans of both counters, degrees, scalers, degree
+// check; the counters are reset to zero for use as fill cursors.
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_csr_scan(const Dims *__restrict__ dims, int *__restrict__ cnt_in,
+           int *__restrict__ cnt_out, int *__restrict__ rowptr,
+           int *__restrict__ srcptr, int *__restrict__ deg,
+           const float *__restrict__ table, float *__restrict__ sp,
+           float *__restrict__ sm, int max_degree, int *__restrict__ err) {
+  __shared__ int wsum[2][kScanThreads / 64];
+  __shared__ int carry[2];
+  const int N = dims->N;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) { carry[0] = 0; carry[1] = 0; }
+  __syncthreads();
+  int bad = 0;
+  for (int base = 0; base < N; base += kScanThreads * 4) {
+    int vi[4], vo[4];
+    int si = 0, so = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = base + tid * 4 + j;
+      vi[j] = i < N ? cnt_in[i] : 0;
+      vo[j] = i < N ? cnt_out[i] : 0;
+      si += vi[j];
+      so += vo[j];
+    }
+    const int ii = wave_incl_scan(si), io = wave_incl_scan(so);
+    if (lane == 63) { wsum[0][wid] = ii; wsum[1][wid] = io; }
+    __syncthreads();
+    if (wid == 0) {
+      const int nw = kScanThreads / 64;
+      int a = lane < nw ? wsum[0][lane] : 0;
+      int b = lane < nw ? wsum[1][lane] : 0;
+      a = wave_incl_scan(a);
+      b = wave_incl_scan(b);
+      if (lane < nw) { wsum[0][lane] = a; wsum[1][lane] = b; }
+    }
+    __syncthreads();
+    int ei_ = carry[0] + (wid ? wsum[0][wid - 1] : 0) + ii - si;
+    int eo_ = carry[1] + (wid ? wsum[1][wid - 1] : 0) + io - so;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = base + tid * 4 + j;
+      if (i < N) {
+        rowptr[i] = ei_;
+        srcptr[i] = eo_;
+        deg[i] = vi[j];
+        const int dc = vi[j] < max_degree ? vi[j] : max_degree;
+        sp[i] = table[2 * dc];
+        sm[i] = table[2 * dc + 1];
+        if (vi[j] > max_degree || vo[j] > max_degree) bad = 1;
+        cnt_in[i] = 0;
+        cnt_out[i] = 0;
+      }
+      ei_ += vi[j];
+      eo_ += vo[j];
+    }
+    __syncthreads();
+    if (tid == kScanThreads - 1) { carry[0] = ei_; carry[1] = eo_; }
+    __syncthreads();
+  }
+  if (bad) atomicOr(err, ERR_DEGREE);
+  if (tid == 0) {
+    rowptr[N] = carry[0];
+    srcptr[N] = carry[1];
+  }
+}
+
+__global__ void k_csr_fill(const Dims *__restrict__ dims,
+                           const int *__restrict__ ei,
+                           const int *__restrict__ node_graph,
+                           const int *__restrict__ rowptr,
+                           const int *__restrict__ srcptr,
+                           int *__restrict__ cnt_in, int *__restrict__ cnt_out,
+                           int *__restrict__ csr_eid, int *__restrict__ tmp_out) {
+  const int N = dims->N, E = dims->E;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= E) return;
+  const int s = ei[k], d = ei[E + k];
+  if (!edge_ok(s, d, N, node_graph)) return;
+  csr_eid[rowptr[d] + atomicAdd(&cnt_in[d], 1)] = k;
+  tmp_out[srcptr[s] + atomicAdd(&cnt_out[s], 1)] = k;
+}
+
+// Per destination: order the segment by (source, edge id); write csr_src,
+// the inverse map and the edge attributes in CSR order.
+__global__ void k_csr_sort_in(const Dims *__restrict__ dims,
+                              const int *__restrict__ ei,
+                              const int *__restrict__ rowptr,
+                              int *__restrict__ csr_eid, int *__restrict__ csr_src,
+                              int *__restrict__ csr_pos,
+                              const float *__restrict__ edge_attr, int Fe,
+                              float *__restrict__ csr_e, int max_degree) {
+  const int N = dims->N;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int lo = rowptr[i], hi = rowptr[i + 1];
+  if (hi - lo <= max_degree) {
+    for (int a = lo + 1; a < hi; ++a) { // insertion sort by (src, eid)
+      const int ka = csr_eid[a];
+      const int sa = ei[ka];
+      int b = a - 1;
+      while (b >= lo) {
+        const int kb = csr_eid[b];
+        const int sb = ei[kb];
+        if (sb < sa || (sb == sa && kb < ka)) break;
+        csr_eid[b + 1] = kb;
+        --b;
+      }
+      csr_eid[b + 1] = ka;
+    }
+  }
+  for (int q = lo; q < hi; ++q) {
+    const int k = csr_eid[q];
+    csr_src[q] = ei[k];
+    csr_pos[k] = q;
+    for (int f = 0; f < Fe; ++f) csr_e[(size_t)q * Fe + f] = edge_attr[(size_t)k * Fe + f];
+  }
+}
+
+// Per source: CSR positions of its out-edges, ascending.
+__global__ void k_csr_sort_out(const Dims *__restrict__ dims,
+                               const int *__restrict__ srcptr,
+                               const int *__restrict__ tmp_out,
+                               const int *__restrict__ csr_pos,
+                               int *__restrict__ t2csr, int max_degree) {
+  const int N = dims->N;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int lo = srcptr[j], hi = srcptr[j + 1];
+  for (int p = lo; p < hi; ++p) t2csr[p] = csr_pos[tmp_out[p]];
+  if (hi - lo > max_degree) return;
+  for (int a = lo + 1; a < hi; ++a) {
+    const int va = t2csr[a];
+    int b = a - 1;
+    while (b >= lo && t2csr[b] > va) {
+      t2csr[b + 1] = t2csr[b];
+      --b;
+    }
+    t2csr[b + 1] = va;
+  }
+}
+
+__global__ void k_pad_copy(const Dims *__restrict__ dims, const float *__restrict__ x,
+                           int F, float *__restrict__ xp, int Fp) {
+  const int N = dims->N;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / Fp), c = (int)(t % Fp);
+  if (i >= N) return;
+  xp[t] = c < F ? x[(size_t)i * F + c] : 0.0f;
+}
+
+inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
+
+} // namespace
+
+hipError_t launch_set_dims(Dims *d, int B, int N, int E, hipStream_t s) {
+  k_set_dims<<<1, 64, 0, s>>>(d, B, N, E, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
+                            const int *graph_ptr, const int *edge_index,
+                            const float *edge_attr, int Fe, int max_degree,
+                            const float *table, const CsrBufs &c,
+                            hipStream_t s) {
+  k_set_dims<<<1, 64, 0, s>>>(nullptr, 0, 0, 0, c.err); // clear the error word
+  const int nb = capN > capB ? capN : capB;
+  k_csr_init<<<cdiv(nb > 0 ? nb : 1, 256), 256, 0, s>>>(dims, graph_ptr, c.node_graph,
+                                                        c.cnt_in, c.cnt_out, c.err);
+  if (capE > 0)
+    k_csr_count<<<cdiv(capE, 256), 256, 0, s>>>(dims, edge_index, c.node_graph,
+                                                c.cnt_in, c.cnt_out, c.err);
+  k_csr_scan<<<1, kScanThreads, 0, s>>>(dims, c.cnt_in, c.cnt_out, c.rowptr, c.srcptr,
+                                        c.deg, table, c.sp, c.sm, max_degree, c.err);
+  if (capE > 0)
+    k_csr_fill<<<cdiv(capE, 256), 256, 0, s>>>(dims, edge_index, c.node_graph, c.rowptr,
+                                               c.srcptr, c.cnt_in, c.cnt_out, c.csr_eid,
+                                               c.tmp_out);
+  if (capN > 0) {
+    k_csr_sort_in<<<cdiv(capN, 128), 128, 0, s>>>(dims, edge_index, c.rowptr, c.csr_eid,
+                                                  c.csr_src, c.csr_pos, edge_attr, Fe,
+                                                  c.csr_e, max_degree);
+    k_csr_sort_out<<<cdiv(capN, 128), 128, 0, s>>>(dims, c.srcptr, c.tmp_out, c.csr_pos,
+                                                   c.t2csr, max_degree);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_copy(const Dims *dims, int capN, const float *x, int F,
+                           float *xp, int Fp, hipStream_t s) {
+  if (capN <= 0) return hipSuccess;
+  k_pad_copy<<<cdiv((long long)capN * Fp, 256), 256, 0, s>>>(dims, x, F, xp, Fp);
+  return hipGetLastError();
+}
+
+} // namespace hgnn

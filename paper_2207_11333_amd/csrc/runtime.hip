@@ -1,0 +1,919 @@
+// Context, buffer management and the training-path C-ABI (hgnn.h).
+//
+// One pass of the hot path per batch: S0 CSR build, then per layer S1
+// message linear (one GEMM producing P = h W_dst^T and Q = h W_src^T), S2
+// segmented aggregation and S3 update linear + ReLU, then S4 pooling + head
+// + loss; the backward pass runs S5 head adjoint and per layer (last first)
+// S6 update adjoint, S7 aggregation adjoint and S8 message adjoint; S9 is
+// the AdamW step.  Everything runs asynchronously on the caller's stream.
+#include "runtime.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+using namespace hgnn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+inline int ru(int a, int b) { return (a + b - 1) / b * b; }
+
+} // namespace
+
+namespace hgnn {
+
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+int hip_fail(hgnn_ctx *c, hipError_t e, const char *what) {
+  if (c) c->sticky = 1;
+  return fail(HGNN_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static void dfree(void *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+template <typename T> static hipError_t dalloc(T *&p, size_t count) {
+  void *q = nullptr;
+  const size_t bytes = count * sizeof(T) < 256 ? 256 : count * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  p = reinterpret_cast<T *>(q);
+  return e;
+}
+
+int tn_splits(int M, int Ncols) {
+  const int tiles = ((M + 63) / 64) * ((Ncols + 63) / 64);
+  int s = (512 + tiles - 1) / tiles;
+  if (s < 1) s = 1;
+  if (s > 64) s = 64;
+  return s;
+}
+
+void free_work(hgnn_ctx *c) {
+  Work &w = c->w;
+  void **ptrs[] = {(void **)&w.csr.rowptr, (void **)&w.csr.csr_src, (void **)&w.csr.csr_eid,
+                   (void **)&w.csr.deg, (void **)&w.csr.srcptr, (void **)&w.csr.t2csr,
+                   (void **)&w.csr.node_graph, (void **)&w.csr.cnt_in,
+                   (void **)&w.csr.cnt_out, (void **)&w.csr.tmp_out,
+                   (void **)&w.csr.csr_pos, (void **)&w.csr.csr_e, (void **)&w.csr.sp,
+                   (void **)&w.csr.sm, (void **)&w.xpad, (void **)&w.g, (void **)&w.q,
+                   (void **)&w.ypred, (void **)&w.dy, (void **)&w.dq, (void **)&w.du,
+                   (void **)&w.dA, (void **)&w.dm, (void **)&w.Dio, (void **)&w.De,
+                   (void **)&w.dh0, (void **)&w.dh1, (void **)&w.colpart};
+  for (void **p : ptrs) dfree(*p);
+  for (auto &p : w.hbuf) dfree(reinterpret_cast<void *&>(p));
+  for (auto &p : w.PQ) dfree(reinterpret_cast<void *&>(p));
+  for (auto &p : w.A) dfree(reinterpret_cast<void *&>(p));
+  for (auto &p : w.args) dfree(reinterpret_cast<void *&>(p));
+  w.hbuf.clear();
+  w.PQ.clear();
+  w.A.clear();
+  w.args.clear();
+  w.capB = w.capN = w.capE = 0;
+}
+
+int ensure_work(hgnn_ctx *c, int B, int N, int E) {
+  Work &w = c->w;
+  if (B <= w.capB && N <= w.capN && E <= w.capE) return HGNN_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+  free_work(c);
+  const int capB = B > w.capB ? B : w.capB;
+  const int capN = N, capE = E;
+  const int H = c->H, L = c->L, Fe = c->Fe;
+  const int nstore = c->recompute ? 1 : L;
+#define HGNN_ALLOC(p, n)                                                                \
+  do {                                                                                 \
+    hipError_t e_ = dalloc(p, (size_t)(n));                                            \
+    if (e_ != hipSuccess) {                                                            \
+      free_work(c);                                                                    \
+      return fail(HGNN_ENOMEM, std::string("hipMalloc failed for ") + #p);             \
+    }                                                                                  \
+  } while (0)
+  HGNN_ALLOC(w.csr.rowptr, capN + 1);
+  HGNN_ALLOC(w.csr.srcptr, capN + 1);
+  HGNN_ALLOC(w.csr.csr_src, capE);
+  HGNN_ALLOC(w.csr.csr_eid, capE);
+  HGNN_ALLOC(w.csr.t2csr, capE);
+  HGNN_ALLOC(w.csr.tmp_out, capE);
+  HGNN_ALLOC(w.csr.csr_pos, capE);
+  HGNN_ALLOC(w.csr.deg, capN);
+  HGNN_ALLOC(w.csr.node_graph, capN);
+  HGNN_ALLOC(w.csr.cnt_in, capN);
+  HGNN_ALLOC(w.csr.cnt_out, capN);
+  HGNN_ALLOC(w.csr.csr_e, (size_t)capE * (Fe > 0 ? Fe : 1));
+  HGNN_ALLOC(w.csr.sp, capN);
+  HGNN_ALLOC(w.csr.sm, capN);
+  HGNN_ALLOC(w.xpad, (size_t)capN * c->F0p);
+  w.hbuf.assign(L, nullptr);
+  for (int l = 0; l < L; ++l) HGNN_ALLOC(w.hbuf[l], (size_t)capN * H);
+  w.PQ.assign(nstore, nullptr);
+  w.A.assign(nstore, nullptr);
+  w.args.assign(nstore, nullptr);
+  for (int l = 0; l < nstore; ++l) {
+    HGNN_ALLOC(w.PQ[l], (size_t)capN * 2 * H);
+    HGNN_ALLOC(w.A[l], (size_t)capN * 4 * H);
+    HGNN_ALLOC(w.args[l], (size_t)capN * 2 * H);
+  }
+  HGNN_ALLOC(w.g, (size_t)capB * H);
+  HGNN_ALLOC(w.q, (size_t)capB * H);
+  HGNN_ALLOC(w.dq, (size_t)capB * H);
+  HGNN_ALLOC(w.ypred, capB);
+  HGNN_ALLOC(w.dy, capB);
+  HGNN_ALLOC(w.du, (size_t)capN * H);
+  HGNN_ALLOC(w.dA, (size_t)capN * 4 * H);
+  HGNN_ALLOC(w.dm, (size_t)capE * H);
+  HGNN_ALLOC(w.Dio, (size_t)capN * 2 * H);
+  HGNN_ALLOC(w.De, (size_t)capN * H * (Fe > 0 ? Fe : 1));
+  HGNN_ALLOC(w.dh0, (size_t)capN * H);
+  HGNN_ALLOC(w.dh1, (size_t)capN * H);
+  HGNN_ALLOC(w.colpart, (size_t)kColSplits * (2 + (Fe > 0 ? Fe : 1)) * H);
+#undef HGNN_ALLOC
+  w.capB = capB;
+  w.capN = capN;
+  w.capE = capE;
+  w.stored_layer = -1;
+  return HGNN_OK;
+}
+
+int stage_all(hgnn_ctx *c, hipStream_t s) {
+  for (int l = 0; l < c->L; ++l) {
+    const LayerDesc &d = c->ld[l];
+    hipError_t e = launch_stage_layer(c->params + d.oWm, c->params + d.oWp, d.F, d.Fp, c->H,
+                                      c->Fe, c->Wds[l], c->Wpp[l], c->WpTA[l], c->WhdsT[l],
+                                      c->prec, s);
+    if (e != hipSuccess) return hip_fail(c, e, "stage weights");
+  }
+  c->staged_from_params = true;
+  return HGNN_OK;
+}
+
+static int stage_layer_from(hgnn_ctx *c, int l, const float *wl, hipStream_t s) {
+  const LayerDesc &d = c->ld[l];
+  hipError_t e = launch_stage_layer(wl + (d.oWm - d.off), wl + (d.oWp - d.off), d.F, d.Fp,
+                                    c->H, c->Fe, c->Wds[l], c->Wpp[l], c->WpTA[l],
+                                    c->WhdsT[l], c->prec, s);
+  if (e != hipSuccess) return hip_fail(c, e, "stage layer weights");
+  c->staged_from_params = false;
+  return HGNN_OK;
+}
+
+int check_batch_host(hgnn_ctx *c, const hgnn_batch *b) {
+  if (!b) return fail(HGNN_EINVAL, "batch is NULL");
+  if (b->num_graphs < 1) return fail(HGNN_EINVAL, "num_graphs must be >= 1");
+  if (b->num_nodes < b->num_graphs)
+    return fail(HGNN_EINVAL, "num_nodes must be >= num_graphs (no empty graph)");
+  if (b->num_edges < 0) return fail(HGNN_EINVAL, "num_edges must be >= 0");
+  if (!b->graph_ptr || !b->x) return fail(HGNN_EINVAL, "graph_ptr and x are required");
+  if (b->num_edges > 0 && !b->edge_index) return fail(HGNN_EINVAL, "edge_index is NULL");
+  if ((c->Fe > 0) != (b->edge_attr != nullptr) && b->num_edges > 0)
+    return fail(HGNN_EINVAL, "edge_attr must be given iff edge_feat > 0");
+  if ((long long)b->num_nodes * c->F0p >= (1LL << 31) ||
+      (long long)b->num_edges * c->H >= (1LL << 40))
+    return fail(HGNN_EINVAL, "batch too large");
+  return HGNN_OK;
+}
+
+std::string decode_err(int bits) {
+  std::string m = "malformed batch:";
+  if (bits & ERR_GRAPH_PTR) m += " graph_ptr does not run from 0 to num_nodes or a graph is empty;";
+  if (bits & ERR_EDGE_RANGE) m += " edge endpoint out of range;";
+  if (bits & ERR_EDGE_CROSS) m += " edge crosses graphs;";
+  if (bits & ERR_DEGREE) m += " node degree above max_degree;";
+  return m;
+}
+
+int prepare(hgnn_ctx *c, const hgnn_batch *b, int flags, hipStream_t s) {
+  int rc = check_batch_host(c, b);
+  if (rc) return rc;
+  rc = ensure_work(c, b->num_graphs, b->num_nodes, b->num_edges);
+  if (rc) return rc;
+  Work &w = c->w;
+  hipError_t e = launch_set_dims(c->dims, b->num_graphs, b->num_nodes, b->num_edges, s);
+  if (e == hipSuccess)
+    e = launch_csr_build(c->dims, b->num_graphs, b->num_nodes, b->num_edges, b->graph_ptr,
+                         b->edge_index, b->edge_attr, c->Fe, c->maxd, c->table, w.csr, s);
+  if (e != hipSuccess) return hip_fail(c, e, "csr build");
+  c->B = b->num_graphs;
+  c->N = b->num_nodes;
+  c->E = b->num_edges;
+  c->graph_ptr = b->graph_ptr;
+  c->x = b->x;
+  c->target = b->y;
+  c->prepared = true;
+  w.stored_layer = -1;
+  if (flags & HGNN_VALIDATE) {
+    int bits = 0;
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(&bits, w.csr.err, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "validate");
+    if (bits) return fail(HGNN_EINVAL, decode_err(bits));
+  }
+  return HGNN_OK;
+}
+
+// Layer l: S1 (P|Q GEMM), S2 (aggregation) into the given buffers.
+static int message_and_aggregate(hgnn_ctx *c, int l, const float *wl, const float *hin,
+                                 int ldh, float *PQ, float *A, uint8_t *args,
+                                 hipStream_t s) {
+  const LayerDesc &d = c->ld[l];
+  const int H = c->H;
+  Work &w = c->w;
+  GemmNT g{};
+  g.nseg = 1;
+  g.seg[0] = SegA{hin, nullptr, ldh, d.Fp, 0};
+  g.B = c->Wds[l];
+  g.ldb = d.Fp;
+  g.Ncols = 2 * H;
+  g.C = PQ;
+  g.ldc = 2 * H;
+  g.M_fixed = -1;
+  hipError_t e;
+  {
+    TimedLaunch tl(c, SITE_MESSAGE_GEMM, s);
+    e = launch_gemm_nt(c->dims, c->N, g, c->prec, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "message GEMM");
+  const float *Wm = wl + (d.oWm - d.off);
+  const float *bm = wl + (d.obm - d.off);
+  {
+    TimedLaunch tl(c, SITE_AGGREGATE, s);
+    e = launch_aggregate(c->dims, c->N, H, c->Fe, PQ, w.csr.rowptr, w.csr.csr_src,
+                         w.csr.csr_e, Wm + 2 * d.F, 2 * d.F + c->Fe, bm, A, args,
+                         (float)c->cfg.std_eps, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "aggregate");
+  return HGNN_OK;
+}
+
+static const float *layer_input(hgnn_ctx *c, int l, const float *h_in, int *ldh,
+                                hipStream_t s, int *rc) {
+  *rc = HGNN_OK;
+  if (l == 0) {
+    hipError_t e = launch_pad_copy(c->dims, c->N, h_in, c->F0, c->w.xpad, c->F0p, s);
+    if (e != hipSuccess) *rc = hip_fail(c, e, "pad input");
+    *ldh = c->F0p;
+    return c->w.xpad;
+  }
+  *ldh = c->H;
+  return h_in;
+}
+
+int layer_forward(hgnn_ctx *c, int l, const float *wl, const float *h_in, float *h_out,
+                  hipStream_t s) {
+  const LayerDesc &d = c->ld[l];
+  const int H = c->H;
+  Work &w = c->w;
+  int rc, ldh;
+  const float *hin = layer_input(c, l, h_in, &ldh, s, &rc);
+  if (rc) return rc;
+  const int slot = c->recompute ? 0 : l;
+  rc = message_and_aggregate(c, l, wl, hin, ldh, w.PQ[slot], w.A[slot], w.args[slot], s);
+  if (rc) return rc;
+  w.stored_layer = l;
+  float *A = w.A[slot];
+  GemmNT g{};
+  g.nseg = 4;
+  g.seg[0] = SegA{hin, nullptr, ldh, d.Fp, 0};
+  g.seg[1] = SegA{A, nullptr, 4 * H, 4 * H, d.Fp};
+  g.seg[2] = SegA{A, w.csr.sp, 4 * H, 4 * H, d.Fp + 4 * H};
+  g.seg[3] = SegA{A, w.csr.sm, 4 * H, 4 * H, d.Fp + 8 * H};
+  g.B = c->Wpp[l];
+  g.ldb = d.Fp + 12 * H;
+  g.Ncols = H;
+  g.bias = wl + (d.obp - d.off);
+  g.relu = 1;
+  g.C = h_out;
+  g.ldc = H;
+  g.M_fixed = -1;
+  hipError_t e;
+  {
+    TimedLaunch tl(c, SITE_UPDATE_GEMM, s);
+    e = launch_gemm_nt(c->dims, c->N, g, c->prec, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "update GEMM");
+  return HGNN_OK;
+}
+
+int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
+                   const float *h_out, const float *dh_out, float *dh_in, float *dwl,
+                   hipStream_t s) {
+  const LayerDesc &d = c->ld[l];
+  const int H = c->H, Fe = c->Fe;
+  Work &w = c->w;
+  int rc, ldh;
+  const float *hin = layer_input(c, l, h_in, &ldh, s, &rc);
+  if (rc) return rc;
+  const int slot = c->recompute ? 0 : l;
+  if (c->recompute && w.stored_layer != l) { // S10: re-run S1/S2 for this layer
+    rc = message_and_aggregate(c, l, wl, hin, ldh, w.PQ[0], w.A[0], w.args[0], s);
+    if (rc) return rc;
+    w.stored_layer = l;
+  }
+  float *PQ = w.PQ[slot], *A = w.A[slot];
+  const uint8_t *args = w.args[slot];
+  const float *Wm = wl + (d.oWm - d.off);
+  const float *bm = wl + (d.obm - d.off);
+  float *dWm = dwl + (d.oWm - d.off), *dbm = dwl + (d.obm - d.off);
+  float *dWp = dwl + (d.oWp - d.off), *dbp = dwl + (d.obp - d.off);
+  hipError_t e = launch_relu_mask(c->dims, c->N, H, dh_out, h_out, w.du, s);
+  if (e != hipSuccess) return hip_fail(c, e, "relu mask");
+  // S6: dW^p = du^T [h || A || s+ A || s- A]
+  {
+    GemmTN t{};
+    t.X = w.du;
+    t.ldx = H;
+    t.M = H;
+    t.nseg = 4;
+    t.seg[0] = SegY{hin, nullptr, ldh, d.Fp};
+    t.seg[1] = SegY{A, nullptr, 4 * H, 4 * H};
+    t.seg[2] = SegY{A, w.csr.sp, 4 * H, 4 * H};
+    t.seg[3] = SegY{A, w.csr.sm, 4 * H, 4 * H};
+    t.Ncols = d.Fp + 12 * H;
+    t.P = c->part;
+    t.splits = d.split_p;
+    {
+      TimedLaunch tl(c, SITE_UPDATE_WGRAD, s);
+      e = launch_gemm_tn(c->dims, t, c->prec, s);
+    }
+    if (e == hipSuccess) {
+      ReduceMap r{c->part, d.split_p, H, d.Fp + 12 * H, dWp, d.F + 12 * H, H, 0, d.F, d.Fp};
+      e = launch_reduce_map(r, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "update weight gradient");
+  }
+  // S6: dA = [du || s+ du || s- du] [W0; W+; W-]
+  {
+    GemmNT g{};
+    g.nseg = 3;
+    g.seg[0] = SegA{w.du, nullptr, H, H, 0};
+    g.seg[1] = SegA{w.du, w.csr.sp, H, H, H};
+    g.seg[2] = SegA{w.du, w.csr.sm, H, H, 2 * H};
+    g.B = c->WpTA[l];
+    g.ldb = 3 * H;
+    g.Ncols = 4 * H;
+    g.C = w.dA;
+    g.ldc = 4 * H;
+    g.M_fixed = -1;
+    {
+      TimedLaunch tl(c, SITE_AGG_INPUT_GEMM, s);
+      e = launch_gemm_nt(c->dims, c->N, g, c->prec, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "aggregate-input gradient GEMM");
+  }
+  // S7: per-edge dm, D_in, De; then D_out through the transpose
+  {
+    TimedLaunch tl(c, SITE_AGGREGATE_BWD, s);
+    e = launch_aggregate_bwd(c->dims, c->N, H, Fe, PQ, w.csr.rowptr, w.csr.csr_src,
+                             w.csr.csr_e, Wm + 2 * d.F, 2 * d.F + Fe, bm, A, args, w.dA,
+                             w.dm, w.Dio, w.De, s);
+  }
+  if (e == hipSuccess)
+    e = launch_transpose_sum(c->dims, c->N, H, w.csr.srcptr, w.csr.t2csr, w.dm, w.Dio, s);
+  if (e != hipSuccess) return hip_fail(c, e, "aggregation adjoint");
+  // S8: [dW_dst | dW_src] = [D_in | D_out]^T h
+  {
+    GemmTN t{};
+    t.X = w.Dio;
+    t.ldx = 2 * H;
+    t.M = 2 * H;
+    t.nseg = 1;
+    t.seg[0] = SegY{hin, nullptr, ldh, d.Fp};
+    t.Ncols = d.Fp;
+    t.P = c->part;
+    t.splits = d.split_m;
+    e = launch_gemm_tn(c->dims, t, c->prec, s);
+    if (e == hipSuccess) {
+      ReduceMap r{c->part, d.split_m, 2 * H, d.Fp, dWm, 2 * d.F + Fe, H, d.F, d.F, d.Fp};
+      e = launch_reduce_map(r, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "message weight gradient");
+  }
+  // biases and edge-feature weights: ordered column sums
+  {
+    ColSum cs{};
+    ColSumMap mp{};
+    cs.src[0] = w.du; cs.ld[0] = H; cs.ncols[0] = H; cs.out[0] = dbp;
+    mp.rs[0] = H; mp.ostride[0] = 1;
+    cs.src[1] = w.Dio; cs.ld[1] = 2 * H; cs.ncols[1] = H; cs.out[1] = dbm;
+    mp.rs[1] = H; mp.ostride[1] = 1;
+    cs.n = 2;
+    if (Fe > 0) {
+      cs.src[2] = w.De; cs.ld[2] = Fe * H; cs.ncols[2] = Fe * H; cs.out[2] = dWm + 2 * d.F;
+      mp.rs[2] = H; mp.ostride[2] = 2 * d.F + Fe;
+      cs.n = 3;
+    }
+    e = launch_colsum(c->dims, cs, mp, w.colpart, kColSplits, s);
+    if (e != hipSuccess) return hip_fail(c, e, "bias gradients");
+  }
+  // S6 + S8 input gradient: dh = [du || D_in || D_out] [W_h; W_dst; W_src]
+  if (dh_in) {
+    GemmNT g{};
+    g.nseg = 3;
+    g.seg[0] = SegA{w.du, nullptr, H, H, 0};
+    g.seg[1] = SegA{w.Dio, nullptr, 2 * H, H, H};
+    g.seg[2] = SegA{w.Dio + H, nullptr, 2 * H, H, 2 * H};
+    g.B = c->WhdsT[l];
+    g.ldb = 3 * H;
+    g.Ncols = d.F;
+    g.C = dh_in;
+    g.ldc = d.F;
+    g.M_fixed = -1;
+    {
+      TimedLaunch tl(c, SITE_INPUT_GEMM, s);
+      e = launch_gemm_nt(c->dims, c->N, g, c->prec, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "input gradient GEMM");
+  }
+  return HGNN_OK;
+}
+
+int head_forward(hgnn_ctx *c, const float *wh, const float *h, const float *target,
+                 float *pred, float *loss, hipStream_t s) {
+  const int H = c->H;
+  Work &w = c->w;
+  hipError_t e = launch_head_forward(c->dims, c->B, H, c->graph_ptr, h, wh, wh + H * H,
+                                     wh + H * H + H, wh + H * H + 2 * H, w.g, w.q, w.ypred,
+                                     pred, s);
+  if (e == hipSuccess && loss && target) e = launch_loss(c->dims, w.ypred, target, loss, s);
+  if (e != hipSuccess) return hip_fail(c, e, "head forward");
+  return HGNN_OK;
+}
+
+int head_backward(hgnn_ctx *c, const float *wh, const float *target, const float *dpred,
+                  float *dh, float *dwh, hipStream_t s) {
+  const int H = c->H;
+  Work &w = c->w;
+  hipError_t e = launch_head_backward(c->dims, c->B, H, c->graph_ptr, wh, wh + H * H + H,
+                                      w.g, w.q, w.ypred, target, dpred, w.dy, w.dq, dh, dwh,
+                                      s);
+  if (e != hipSuccess) return hip_fail(c, e, "head backward");
+  return HGNN_OK;
+}
+
+} // namespace hgnn
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+
+#define HGNN_GUARD(c)                                                                  \
+  do {                                                                                 \
+    if (!(c)) return fail(HGNN_EINVAL, "context is NULL");                             \
+    if ((c)->sticky) return fail(HGNN_ESTATE, "context failed earlier; restore state"); \
+    hipError_t e_ = hipSetDevice((c)->dev);                                            \
+    if (e_ != hipSuccess) return hip_fail((c), e_, "hipSetDevice");                    \
+  } while (0)
+
+extern "C" {
+
+const char *hgnn_last_error(void) { return g_err.c_str(); }
+
+int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
+  if (!cfg || !out) return fail(HGNN_EINVAL, "cfg and out are required");
+  *out = nullptr;
+  if (cfg->num_layers < 1 || cfg->num_layers > 64)
+    return fail(HGNN_EINVAL, "num_layers must be in 1..64");
+  if (cfg->hidden < 16 || cfg->hidden > 512 || cfg->hidden % 16)
+    return fail(HGNN_EINVAL, "hidden must be a multiple of 16 in 16..512");
+  if (cfg->node_feat < 1 || cfg->node_feat > 4096)
+    return fail(HGNN_EINVAL, "node_feat must be in 1..4096");
+  if (cfg->edge_feat < 0 || cfg->edge_feat > 4)
+    return fail(HGNN_EINVAL, "edge_feat must be in 0..4");
+  if (cfg->max_degree < 1 || cfg->max_degree > 255)
+    return fail(HGNN_EINVAL, "max_degree must be in 1..255");
+  if (cfg->precision != HGNN_PREC_FP32 && cfg->precision != HGNN_PREC_BF16)
+    return fail(HGNN_EINVAL, "precision must be HGNN_PREC_FP32 or HGNN_PREC_BF16");
+  if (cfg->recompute != 0 && cfg->recompute != 1)
+    return fail(HGNN_EINVAL, "recompute must be 0 or 1");
+  if (!(cfg->delta > 0.0) || !std::isfinite(cfg->delta))
+    return fail(HGNN_EINVAL, "delta must be positive and finite");
+  if (!(cfg->std_eps >= 0.0) || !std::isfinite(cfg->std_eps))
+    return fail(HGNN_EINVAL, "std_eps must be >= 0");
+
+  hgnn_ctx *c = new (std::nothrow) hgnn_ctx();
+  if (!c) return fail(HGNN_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->L = cfg->num_layers;
+  c->H = cfg->hidden;
+  c->F0 = cfg->node_feat;
+  c->F0p = ru(cfg->node_feat, 16);
+  c->Fe = cfg->edge_feat;
+  c->maxd = cfg->max_degree;
+  c->prec = cfg->precision;
+  c->recompute = cfg->recompute;
+  const int H = c->H;
+  int64_t off = 0;
+  size_t part_max = 0;
+  for (int l = 0; l < c->L; ++l) {
+    LayerDesc d;
+    d.F = l == 0 ? c->F0 : H;
+    d.Fp = l == 0 ? c->F0p : H;
+    d.off = off;
+    d.oWm = off;
+    off += (int64_t)H * (2 * d.F + c->Fe);
+    d.obm = off;
+    off += H;
+    d.oWp = off;
+    off += (int64_t)H * (d.F + 12 * H);
+    d.obp = off;
+    off += H;
+    d.size = off - d.off;
+    d.split_p = tn_splits(H, d.Fp + 12 * H);
+    d.split_m = tn_splits(2 * H, d.Fp);
+    const size_t a = (size_t)d.split_p * H * (d.Fp + 12 * H);
+    const size_t b = (size_t)d.split_m * 2 * H * d.Fp;
+    part_max = std::max(part_max, std::max(a, b));
+    c->ld.push_back(d);
+  }
+  c->off_head = off;
+  off += (int64_t)H * H + H + H + 1;
+  c->P = off;
+
+  hipError_t e = hipGetDevice(&c->dev);
+  int ndev = 0;
+  if (e == hipSuccess) e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) {
+    delete c;
+    return fail(HGNN_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+  }
+#define HGNN_CALLOC(p, n)                                                               \
+  do {                                                                                 \
+    if (dalloc(p, (size_t)(n)) != hipSuccess) {                                         \
+      hgnn_destroy(c);                                                                 \
+      return fail(HGNN_ENOMEM, std::string("hipMalloc failed for ") + #p);             \
+    }                                                                                  \
+  } while (0)
+  HGNN_CALLOC(c->params, c->P);
+  HGNN_CALLOC(c->grads, c->P);
+  HGNN_CALLOC(c->adam_m, c->P);
+  HGNN_CALLOC(c->adam_v, c->P);
+  HGNN_CALLOC(c->step_dev, 1);
+  HGNN_CALLOC(c->corr, 2);
+  HGNN_CALLOC(c->table, 2 * (c->maxd + 1));
+  HGNN_CALLOC(c->dims, 1);
+  HGNN_CALLOC(c->w.csr.err, 1);
+  HGNN_CALLOC(c->part, part_max);
+  const size_t esz = c->prec ? 2 : 4;
+  for (int l = 0; l < c->L; ++l) {
+    const LayerDesc &d = c->ld[l];
+    uint8_t *p1, *p2, *p3, *p4;
+    HGNN_CALLOC(p1, esz * 2 * H * d.Fp);
+    c->Wds.push_back(p1);
+    HGNN_CALLOC(p2, esz * H * (d.Fp + 12 * H));
+    c->Wpp.push_back(p2);
+    HGNN_CALLOC(p3, esz * 12 * H * H);
+    c->WpTA.push_back(p3);
+    HGNN_CALLOC(p4, esz * 3 * H * d.Fp);
+    c->WhdsT.push_back(p4);
+  }
+#undef HGNN_CALLOC
+  // Degree-scaler table: s+(d) = ln(d+1)/delta, s-(d) = delta/ln(d+1) in FP64,
+  // rounded once to FP32; d = 0 maps to 0 (the aggregates are 0 there).
+  std::vector<float> tab(2 * (c->maxd + 1));
+  for (int d = 0; d <= c->maxd; ++d) {
+    const double lg = std::log((double)d + 1.0);
+    tab[2 * d] = d ? (float)(lg / cfg->delta) : 0.f;
+    tab[2 * d + 1] = d ? (float)(cfg->delta / lg) : 0.f;
+  }
+  e = hipMemcpy(c->table, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->params, 0, c->P * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(c->grads, 0, c->P * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(c->adam_m, 0, c->P * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(c->adam_v, 0, c->P * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(c->step_dev, 0, sizeof(long long));
+  if (e == hipSuccess) e = hipMemset(c->w.csr.err, 0, sizeof(int));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    hgnn_destroy(c);
+    return fail(HGNN_EDEVICE, std::string("context init: ") + hipGetErrorString(e));
+  }
+  if (stage_all(c, nullptr) || hipDeviceSynchronize() != hipSuccess) {
+    hgnn_destroy(c);
+    return fail(HGNN_EDEVICE, "initial weight staging failed");
+  }
+  *out = c;
+  return HGNN_OK;
+}
+
+void hgnn_destroy(hgnn_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->dev);
+  serve_shutdown(c);
+  (void)hipDeviceSynchronize();
+  free_work(c);
+  for (hipEvent_t ev : c->timer.ev) (void)hipEventDestroy(ev);
+  c->timer.ev.clear();
+  void **ptrs[] = {(void **)&c->params, (void **)&c->grads, (void **)&c->adam_m,
+                   (void **)&c->adam_v, (void **)&c->step_dev, (void **)&c->corr,
+                   (void **)&c->table, (void **)&c->dims, (void **)&c->w.csr.err,
+                   (void **)&c->part};
+  for (void **p : ptrs) dfree(*p);
+  for (auto *v : {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT})
+    for (auto &p : *v) dfree(reinterpret_cast<void *&>(p));
+  delete c;
+}
+
+int hgnn_num_params(const hgnn_ctx *c, int64_t *out) {
+  if (!c || !out) return fail(HGNN_EINVAL, "ctx and out are required");
+  *out = c->P;
+  return HGNN_OK;
+}
+
+int hgnn_set_params(hgnn_ctx *c, const float *src, void *stream) {
+  HGNN_GUARD(c);
+  if (!src) return fail(HGNN_EINVAL, "params_dev is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(c->params, src, c->P * sizeof(float), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(c, e, "copy params");
+  return stage_all(c, s);
+}
+
+int hgnn_get_params(hgnn_ctx *c, float *dst, void *stream) {
+  HGNN_GUARD(c);
+  if (!dst) return fail(HGNN_EINVAL, "params_dev is NULL");
+  hipError_t e = hipMemcpyAsync(dst, c->params, c->P * sizeof(float), hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream);
+  return e == hipSuccess ? HGNN_OK : hip_fail(c, e, "copy params");
+}
+
+int hgnn_get_grads(hgnn_ctx *c, float *dst, void *stream) {
+  HGNN_GUARD(c);
+  if (!dst) return fail(HGNN_EINVAL, "grads_dev is NULL");
+  hipError_t e = hipMemcpyAsync(dst, c->grads, c->P * sizeof(float), hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream);
+  return e == hipSuccess ? HGNN_OK : hip_fail(c, e, "copy grads");
+}
+
+int hgnn_check(hgnn_ctx *c, void *stream) {
+  HGNN_GUARD(c);
+  int bits = 0;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e == hipSuccess) e = hipMemcpy(&bits, c->w.csr.err, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "check");
+  if (bits) return fail(HGNN_EINVAL, decode_err(bits));
+  return HGNN_OK;
+}
+
+int hgnn_forward(hgnn_ctx *c, const hgnn_batch *b, float *pred, float *loss, int32_t flags,
+                 void *stream) {
+  HGNN_GUARD(c);
+  if (!pred) return fail(HGNN_EINVAL, "pred_dev is NULL");
+  if (loss && !b->y) return fail(HGNN_EINVAL, "loss requested without targets");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = prepare(c, b, flags, s);
+  if (rc) return rc;
+  if (!c->staged_from_params && (rc = stage_all(c, s))) return rc;
+  const float *h = b->x;
+  for (int l = 0; l < c->L; ++l) {
+    rc = layer_forward(c, l, c->params + c->ld[l].off, h, c->w.hbuf[l], s);
+    if (rc) return rc;
+    h = c->w.hbuf[l];
+  }
+  return head_forward(c, c->params + c->off_head, h, b->y, pred, loss, s);
+}
+
+int hgnn_backward(hgnn_ctx *c, const float *dpred, void *stream) {
+  HGNN_GUARD(c);
+  if (!c->prepared) return fail(HGNN_EINVAL, "no forward to differentiate");
+  if (!dpred && !c->target) return fail(HGNN_EINVAL, "no targets and no dpred");
+  if (!c->staged_from_params) return fail(HGNN_EINVAL, "weights changed since the forward");
+  hipStream_t s = (hipStream_t)stream;
+  Work &w = c->w;
+  float *cur = w.dh0, *nxt = w.dh1;
+  int rc = head_backward(c, c->params + c->off_head, c->target, dpred, cur,
+                         c->grads + c->off_head, s);
+  if (rc) return rc;
+  for (int l = c->L - 1; l >= 0; --l) {
+    const float *h_in = l ? w.hbuf[l - 1] : c->x;
+    rc = layer_backward(c, l, c->params + c->ld[l].off, h_in, w.hbuf[l], cur,
+                        l ? nxt : nullptr, c->grads + c->ld[l].off, s);
+    if (rc) return rc;
+    std::swap(cur, nxt);
+  }
+  return HGNN_OK;
+}
+
+int hgnn_adam_step(hgnn_ctx *c, float lr, float beta1, float beta2, float eps, float wd,
+                   void *stream) {
+  HGNN_GUARD(c);
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f) || !(wd >= 0.f))
+    return fail(HGNN_EINVAL, "bad AdamW hyperparameters");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_adamw(c->params, c->grads, c->adam_m, c->adam_v, c->P, lr,
+                              (double)beta1, (double)beta2, eps, wd, c->step_dev, c->corr, s);
+  if (e != hipSuccess) return hip_fail(c, e, "adamw");
+  return stage_all(c, s);
+}
+
+// ---- checkpoint -----------------------------------------------------------
+namespace {
+struct StateHeader {
+  char magic[8];
+  hgnn_config cfg;
+  int64_t P;
+  int64_t step;
+};
+} // namespace
+
+int hgnn_get_state(hgnn_ctx *c, void *buf, size_t *bytes) {
+  if (!c || !bytes) return fail(HGNN_EINVAL, "ctx and bytes are required");
+  const size_t need = sizeof(StateHeader) + 3 * (size_t)c->P * sizeof(float);
+  if (!buf) {
+    *bytes = need;
+    return HGNN_OK;
+  }
+  if (*bytes < need) return fail(HGNN_EINVAL, "state buffer too small");
+  HGNN_GUARD(c);
+  StateHeader h{};
+  std::memcpy(h.magic, "HGNNST01", 8);
+  h.cfg = c->cfg;
+  h.P = c->P;
+  long long step = 0;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(&step, c->step_dev, sizeof(step), hipMemcpyDeviceToHost);
+  h.step = step;
+  char *p = reinterpret_cast<char *>(buf);
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  const size_t n = (size_t)c->P * sizeof(float);
+  if (e == hipSuccess) e = hipMemcpy(p, c->params, n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(p + n, c->adam_m, n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(p + 2 * n, c->adam_v, n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "get_state");
+  *bytes = need;
+  return HGNN_OK;
+}
+
+int hgnn_set_state(hgnn_ctx *c, const void *buf, size_t bytes) {
+  if (!c || !buf) return fail(HGNN_EINVAL, "ctx and buf are required");
+  StateHeader h;
+  if (bytes < sizeof(h)) return fail(HGNN_EINVAL, "state buffer too small");
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, "HGNNST01", 8) != 0) return fail(HGNN_EINVAL, "not an hgnn state");
+  if (h.P != c->P || h.cfg.num_layers != c->cfg.num_layers || h.cfg.hidden != c->cfg.hidden ||
+      h.cfg.node_feat != c->cfg.node_feat || h.cfg.edge_feat != c->cfg.edge_feat)
+    return fail(HGNN_EINVAL, "state belongs to a different model shape");
+  const size_t n = (size_t)c->P * sizeof(float);
+  if (bytes < sizeof(h) + 3 * n) return fail(HGNN_EINVAL, "state buffer truncated");
+  (void)hipSetDevice(c->dev);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) (void)hipGetLastError(); // clear a sticky launch error if possible
+  const char *p = reinterpret_cast<const char *>(buf) + sizeof(h);
+  long long step = h.step;
+  e = hipMemcpy(c->params, p, n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->adam_m, p + n, n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->adam_v, p + 2 * n, n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->step_dev, &step, sizeof(step), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(c, e, "set_state");
+  c->sticky = 0;
+  int rc = stage_all(c, nullptr);
+  if (rc) return rc;
+  e = hipDeviceSynchronize();
+  return e == hipSuccess ? HGNN_OK : hip_fail(c, e, "set_state sync");
+}
+
+// ---- per-operation entries -------------------------------------------------
+
+int hgnn_op_prepare(hgnn_ctx *c, const hgnn_batch *b, int32_t flags, void *stream) {
+  HGNN_GUARD(c);
+  return prepare(c, b, flags, (hipStream_t)stream);
+}
+
+int hgnn_op_layer_forward(hgnn_ctx *c, int32_t l, const float *wl, const float *h_in,
+                          float *h_out, void *stream) {
+  HGNN_GUARD(c);
+  if (!c->prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (l < 0 || l >= c->L) return fail(HGNN_EINVAL, "layer out of range");
+  if (!wl || !h_in || !h_out) return fail(HGNN_EINVAL, "NULL buffer");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = stage_layer_from(c, l, wl, s);
+  if (rc) return rc;
+  return layer_forward(c, l, wl, h_in, h_out, s);
+}
+
+int hgnn_op_layer_backward(hgnn_ctx *c, int32_t l, const float *wl, const float *h_in,
+                           const float *h_out, const float *dh_out, float *dh_in,
+                           float *dwl, void *stream) {
+  HGNN_GUARD(c);
+  if (!c->prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (l < 0 || l >= c->L) return fail(HGNN_EINVAL, "layer out of range");
+  if (!wl || !h_in || !h_out || !dh_out || !dwl) return fail(HGNN_EINVAL, "NULL buffer");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = stage_layer_from(c, l, wl, s);
+  if (rc) return rc;
+  return layer_backward(c, l, wl, h_in, h_out, dh_out, dh_in, dwl, s);
+}
+
+int hgnn_op_head_forward(hgnn_ctx *c, const float *wh, const float *h, const float *target,
+                         float *pred, float *loss, void *stream) {
+  HGNN_GUARD(c);
+  if (!c->prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (!wh || !h || !pred) return fail(HGNN_EINVAL, "NULL buffer");
+  if (loss && !target) return fail(HGNN_EINVAL, "loss requested without targets");
+  return head_forward(c, wh, h, target, pred, loss, (hipStream_t)stream);
+}
+
+int hgnn_op_head_backward(hgnn_ctx *c, const float *wh, const float *h, const float *target,
+                          const float *dpred, float *dh, float *dwh, void *stream) {
+  HGNN_GUARD(c);
+  (void)h;
+  if (!c->prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (!wh || !dh || !dwh) return fail(HGNN_EINVAL, "NULL buffer");
+  if (!dpred && !target) return fail(HGNN_EINVAL, "need dpred or targets");
+  return head_backward(c, wh, target, dpred, dh, dwh, (hipStream_t)stream);
+}
+
+int hgnn_timer_start(hgnn_ctx *c, int32_t site, int32_t max_launches) {
+  HGNN_GUARD(c);
+  if (site < 0 || site >= SITE_COUNT || max_launches < 0 || max_launches > 1 << 16)
+    return fail(HGNN_EINVAL, "bad timer site or launch count");
+  SiteTimer &t = c->timer;
+  hipError_t e = hipDeviceSynchronize();
+  for (hipEvent_t ev : t.ev) (void)hipEventDestroy(ev);
+  t.ev.clear();
+  t.used = 0;
+  t.site = SITE_NONE;
+  if (e != hipSuccess) return hip_fail(c, e, "timer sync");
+  for (int i = 0; i < 2 * max_launches; ++i) {
+    hipEvent_t ev;
+    e = hipEventCreate(&ev);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+    t.ev.push_back(ev);
+  }
+  t.site = site;
+  return HGNN_OK;
+}
+
+int hgnn_timer_read(hgnn_ctx *c, double *total_ms, int32_t *launches) {
+  HGNN_GUARD(c);
+  if (!total_ms || !launches) return fail(HGNN_EINVAL, "NULL output");
+  SiteTimer &t = c->timer;
+  double tot = 0.0;
+  for (int i = 0; i + 1 < t.used; i += 2) {
+    hipError_t e = hipEventSynchronize(t.ev[i + 1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(c, e, "timer read");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = t.used / 2;
+  t.site = SITE_NONE;
+  return HGNN_OK;
+}
+
+int hgnn_op_fetch(hgnn_ctx *c, int32_t which, int32_t layer, void *dst, size_t cap,
+                  void *stream) {
+  HGNN_GUARD(c);
+  if (!c->prepared) return fail(HGNN_EINVAL, "nothing prepared");
+  if (!dst) return fail(HGNN_EINVAL, "dst is NULL");
+  Work &w = c->w;
+  const int N = c->N, E = c->E, H = c->H, B = c->B;
+  const void *src = nullptr;
+  size_t bytes = 0;
+  switch (which) {
+  case 0: src = w.csr.rowptr; bytes = (N + 1) * 4; break;
+  case 1: src = w.csr.csr_src; bytes = (size_t)E * 4; break;
+  case 2: src = w.csr.csr_eid; bytes = (size_t)E * 4; break;
+  case 3: src = w.csr.deg; bytes = (size_t)N * 4; break;
+  case 4: src = w.csr.srcptr; bytes = (N + 1) * 4; break;
+  case 5: src = w.csr.t2csr; bytes = (size_t)E * 4; break;
+  case 6: src = w.csr.node_graph; bytes = (size_t)N * 4; break;
+  case 7:
+  case 8: {
+    if (layer < 0 || layer >= c->L) return fail(HGNN_EINVAL, "layer out of range");
+    int slot = layer;
+    if (c->recompute) {
+      if (w.stored_layer != layer) return fail(HGNN_EINVAL, "layer not stored (recompute on)");
+      slot = 0;
+    }
+    if (which == 7) { src = w.A[slot]; bytes = (size_t)N * 4 * H * 4; }
+    else { src = w.args[slot]; bytes = (size_t)N * 2 * H; }
+    break;
+  }
+  case 9: src = w.q; bytes = (size_t)B * H * 4; break;
+  case 10: src = w.g; bytes = (size_t)B * H * 4; break;
+  case 11:
+    if (layer < 0 || layer >= c->L) return fail(HGNN_EINVAL, "layer out of range");
+    src = w.hbuf[layer];
+    bytes = (size_t)N * H * 4;
+    break;
+  default: return fail(HGNN_EINVAL, "unknown fetch id");
+  }
+  if (cap < bytes) return fail(HGNN_EINVAL, "destination too small");
+  if (bytes == 0) return HGNN_OK;
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  return e == hipSuccess ? HGNN_OK : hip_fail(c, e, "fetch");
+}
+
+} // extern "C"

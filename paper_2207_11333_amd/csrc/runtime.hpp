@@ -1,0 +1,111 @@
+// Context layout shared by the training runtime and the serving scheduler.
+#pragma once
+
+#include "common.hpp"
+#include "hgnn.h"
+
+#include <string>
+#include <vector>
+
+namespace hgnn {
+
+constexpr int kColSplits = 32;
+
+struct LayerDesc {
+  int F, Fp;                       // input width and its padding to 16
+  int64_t off, oWm, obm, oWp, obp; // offsets into the packed vector
+  int64_t size;
+  int split_p, split_m;            // split-K counts of the two weight gradients
+};
+
+// Capacity-sized device buffers of one batch.
+struct Work {
+  int capB = 0, capN = 0, capE = 0;
+  CsrBufs csr{};
+  float *xpad = nullptr;                 // [N, F0p] padded layer-0 input
+  std::vector<float *> hbuf;             // [L] layer outputs [N, H]
+  std::vector<float *> PQ, A;            // [L] (or 1 with recompute)
+  std::vector<uint8_t *> args;
+  int stored_layer = -1;                 // layer held by the shared slot
+  float *g = nullptr, *q = nullptr, *ypred = nullptr, *dy = nullptr, *dq = nullptr;
+  float *du = nullptr, *dA = nullptr, *dm = nullptr, *Dio = nullptr, *De = nullptr;
+  float *dh0 = nullptr, *dh1 = nullptr, *colpart = nullptr;
+};
+
+struct Server;
+
+// Launch sites that the opt-in event timer can bracket.
+enum Site : int {
+  SITE_NONE = 0,
+  SITE_MESSAGE_GEMM = 1,   // S1
+  SITE_AGGREGATE = 2,      // S2
+  SITE_UPDATE_GEMM = 3,    // S3
+  SITE_UPDATE_WGRAD = 4,   // S6 weight gradient (split-K GEMM)
+  SITE_AGG_INPUT_GEMM = 5, // S6 gradient of the aggregates
+  SITE_AGGREGATE_BWD = 6,  // S7 per-edge adjoint
+  SITE_INPUT_GEMM = 7,     // S6+S8 input gradient
+  SITE_COUNT = 8
+};
+
+struct SiteTimer {
+  int site = SITE_NONE;
+  std::vector<hipEvent_t> ev; // pairs
+  int used = 0;
+};
+
+} // namespace hgnn
+
+struct hgnn_ctx {
+  hgnn_config cfg{};
+  int dev = 0;
+  int L = 0, H = 0, F0 = 0, F0p = 0, Fe = 0, maxd = 0, prec = 0, recompute = 0;
+  int64_t P = 0, off_head = 0;
+  std::vector<hgnn::LayerDesc> ld;
+  float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+  long long *step_dev = nullptr;
+  float *corr = nullptr;
+  float *table = nullptr;
+  std::vector<void *> Wds, Wpp, WpTA, WhdsT; // GEMM-layout weight copies per layer
+  bool staged_from_params = false;
+  hgnn::Dims *dims = nullptr;
+  float *part = nullptr;
+  hgnn::Work w;
+  // the batch of the last prepare
+  int B = 0, N = 0, E = 0;
+  const int *graph_ptr = nullptr;
+  const float *x = nullptr, *target = nullptr;
+  bool prepared = false;
+  int sticky = 0;
+  hgnn::Server *server = nullptr;
+  hgnn::SiteTimer timer;
+};
+
+namespace hgnn {
+
+int set_error(int code, const std::string &msg);
+int hip_fail(hgnn_ctx *c, hipError_t e, const char *what);
+std::string decode_err(int bits);
+void serve_shutdown(hgnn_ctx *c);
+
+// Records an event pair around one launch when the timer watches `site`.
+struct TimedLaunch {
+  hgnn_ctx *c;
+  hipStream_t s;
+  bool on;
+  TimedLaunch(hgnn_ctx *c_, int site, hipStream_t s_) : c(c_), s(s_), on(false) {
+    SiteTimer &t = c->timer;
+    if (t.site == site && t.used + 2 <= (int)t.ev.size()) {
+      on = true;
+      (void)hipEventRecord(t.ev[t.used], s);
+    }
+  }
+  ~TimedLaunch() {
+    if (on) {
+      SiteTimer &t = c->timer;
+      (void)hipEventRecord(t.ev[t.used + 1], s);
+      t.used += 2;
+    }
+  }
+};
+
+} // namespace hgnn

@@ -1,0 +1,411 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances: FP32 path 1e-5 relative (L2 norm ratio per tensor) on outputs,
+loss and every parameter-gradient tensor; BF16 path 2e-2 relative on the
+outputs and the loss, gradient error reported.  Integer CSR work is bit-exact.
+Gradient comparisons use decision replay: the oracle adopts the GPU's min/max
+and ReLU decisions only where its own FP64 values are within a tie window.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2207_11333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TAU_FP32 = 1e-4
+TAU_BF16 = 3e-2
+
+
+def _hgnn():
+    from paper_2207_11333_amd import hgnn
+    return hgnn
+
+
+def rel(a, r):
+    a = np.asarray(a, np.float64)
+    r = np.asarray(r, np.float64)
+    nr = np.linalg.norm(r)
+    return float(np.linalg.norm(a - r) / (nr if nr > 0 else 1.0))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_model(L, H, Fe, prec=0, recompute=0, delta=1.0, maxd=4, F0=9):
+    return _hgnn().Model(L, H, F0, Fe, maxd, prec, recompute, delta)
+
+
+def run_train_step(model, batch, params, backward=True):
+    hg = _hgnn()
+    model.set_params(params)
+    db = hg.DeviceBatch.from_host(batch)
+    B = batch.num_graphs
+    pred = torch.empty(B, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    model.forward(db, pred, loss, validate=True)
+    out = {"db": db, "pred": pred, "loss": loss}
+    if backward:
+        model.backward()
+        out["grads"] = model.grads()
+    torch.cuda.synchronize()
+    return out
+
+
+def gpu_decisions(model, L, H, N, B):
+    am, ax, rl = [], [], []
+    for l in range(L):
+        a = model.fetch(8, l, (N, 2 * H), torch.uint8).cpu().numpy().astype(np.int64)
+        am.append(a[:, :H])
+        ax.append(a[:, H:])
+        rl.append(model.fetch(11, l, (N, H), torch.float32).cpu().numpy() > 0)
+    q = model.fetch(9, 0, (B, H), torch.float32).cpu().numpy()
+    return oracle.Decisions(am, ax, rl, q > 0)
+
+
+def grad_report(model, g_gpu, g_ref, shape):
+    offs = shape.offsets()
+    out = {}
+    for name, (off, shp) in offs.items():
+        n = int(np.prod(shp))
+        out[name] = rel(g_gpu[off:off + n], g_ref[off:off + n])
+    return out
+
+
+# ---------------------------------------------------------------------------
+# S0: CSR, bit-exact
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,permute", [("c0_small_fp32", False), ("c1_train_fp32", False),
+                                          ("c1_train_fp32", True)])
+def test_csr_bit_exact(name, permute):
+    w = synth.WORKLOADS[name]
+    b = w.batch()
+    if permute:
+        p = np.random.default_rng(5).permutation(b.num_edges)
+        b = synth.Batch(b.graph_ptr, b.x, b.edge_index[:, p].copy(),
+                        None if b.edge_attr is None else b.edge_attr[p].copy(), b.y)
+    say(f"csr {name} permute={permute} N={b.num_nodes} E={b.num_edges}")
+    m = make_model(1, 16, w.edge_feat)
+    m.prepare(_hgnn().DeviceBatch.from_host(b), validate=True)
+    ref = oracle.csr_build(b.graph_ptr, b.edge_index, b.num_nodes)
+    N, E = b.num_nodes, b.num_edges
+    got = {k: m.fetch(i, 0, (n,)).cpu().numpy() for k, i, n in
+           [("rowptr", 0, N + 1), ("csr_src", 1, E), ("csr_eid", 2, E), ("deg", 3, N),
+            ("srcptr", 4, N + 1), ("t2csr", 5, E), ("node_graph", 6, N)]}
+    for k, v in got.items():
+        assert np.array_equal(v, getattr(ref, k)), k
+    m.close()
+
+
+# ---------------------------------------------------------------------------
+# the hand-worked path graph, embedded in a 16-wide model
+# ---------------------------------------------------------------------------
+
+def _path3_embedded(x):
+    H, F = 16, 1
+    shape = synth.ModelShape(1, H, F, 0)
+    offs = shape.offsets()
+    p = np.zeros(shape.num_params(), np.float32)
+    o, _ = offs["l0.Wm"]
+    p[o + 0 * (2 * F) + 1] = 1.0                      # row 0: [h_dst, h_src] = [0, 1]
+    o, _ = offs["l0.Wp"]
+    ld = F + 12 * H
+    p[o + 0] = 1.0                                    # self
+    for j in range(3):
+        for a in range(4):
+            p[o + F + j * 4 * H + a * H + 0] = 1.0    # feature 0 of every block
+    o, _ = offs["W1"]
+    p[o] = 1.0
+    o, _ = offs["w2"]
+    p[o] = 1.0
+    b = synth.Batch(np.array([0, 3], np.int32), np.array(x, np.float32)[:, None],
+                    np.array([[0, 1, 1, 2], [1, 0, 2, 1]], np.int32), None,
+                    np.zeros(1, np.float32))
+    return b, p, shape
+
+
+@pytest.mark.parametrize("x,y,loss,dx", [
+    ([1, 2, 4], 23.987338224741155, 575.3923951081281,
+     [67.41874608958747, 303.83961751338796, 118.84576193948516]),
+    ([1, 2, 1], 16.558939991024037, 274.1984936263351,
+     [99.79223808806668, 209.74657321963778, 28.789882279492826])])
+def test_hand_worked_example_on_gpu(x, y, loss, dx):
+    hg = _hgnn()
+    b, p, shape = _path3_embedded(x)
+    m = hg.Model(1, 16, 1, 0, 4, 0, 0, math.log(2.0))
+    out = run_train_step(m, b, p)
+    assert out["pred"].item() == pytest.approx(y, rel=1e-5)
+    assert out["loss"].item() == pytest.approx(loss, rel=1e-5)
+    net = hg.PNANet(m, p)
+    db = hg.DeviceBatch.from_host(b)
+    xt = db.x.clone().requires_grad_(True)
+    pred = net(db, xt)
+    ((pred - db.y) ** 2).mean().backward()
+    np.testing.assert_allclose(xt.grad.cpu().numpy()[:, 0], dx, rtol=1e-5)
+    m.close()
+
+
+# ---------------------------------------------------------------------------
+# FP32 forward and backward parity
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["c0_small_fp32", "c1_train_fp32"])
+def test_fp32_forward_backward_parity(name):
+    w = synth.WORKLOADS[name]
+    b, params = w.batch(), w.params()
+    L, H = w.num_layers, w.hidden
+    say(f"fp32 parity {name}: N={b.num_nodes} E={b.num_edges}")
+    m = make_model(L, H, w.edge_feat, 0, 0, w.delta)
+    out = run_train_step(m, b, params)
+    rec = oracle.forward(params, b, L, H, w.delta)
+    r_pred = rel(out["pred"].cpu().numpy(), rec.y)
+    r_loss = rel([out["loss"].item()], [rec.loss])
+    say(f"  pred rel {r_pred:.2e}  loss rel {r_loss:.2e}")
+    for l in range(L):
+        A = m.fetch(7, l, (b.num_nodes, 4 * H), torch.float32).cpu().numpy()
+        hl = m.fetch(11, l, (b.num_nodes, H), torch.float32).cpu().numpy()
+        say(f"  layer {l}: A rel {rel(A, rec.layers[l].A):.2e}  h rel "
+            f"{rel(hl, rec.layers[l].h_out):.2e}")
+        assert rel(A, rec.layers[l].A) <= 1e-5
+        assert rel(hl, rec.layers[l].h_out) <= 1e-5
+    assert r_pred <= 1e-5 and r_loss <= 1e-5
+    dec = gpu_decisions(m, L, H, b.num_nodes, b.num_graphs)
+    g_ref, _, stats = oracle.backward(rec, hint=dec, tau=TAU_FP32)
+    g = out["grads"].cpu().numpy()
+    rep = grad_report(m, g, g_ref, w.shape)
+    worst = max(rep, key=rep.get)
+    say(f"  adopted decisions {stats}; worst grad {worst} rel {rep[worst]:.2e}")
+    for k, v in rep.items():
+        assert v <= 1e-5, (k, v)
+    m.close()
+
+
+def test_recompute_matches_stored_activations():
+    w = synth.WORKLOADS["c0_small_fp32"]
+    b, params = w.batch(), w.params()
+    m0 = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+    m1 = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 1, w.delta)
+    o0 = run_train_step(m0, b, params)
+    o1 = run_train_step(m1, b, params)
+    assert torch.equal(o0["pred"], o1["pred"])
+    assert torch.equal(o0["grads"], o1["grads"])
+    m0.close()
+    m1.close()
+
+
+def test_determinism_bitwise():
+    w = synth.WORKLOADS["c1_train_fp32"]
+    b, params = w.batch(), w.params()
+    m = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+    o1 = run_train_step(m, b, params)
+    g1, p1 = o1["grads"].clone(), o1["pred"].clone()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        o2 = run_train_step(m, b, params)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, o2["pred"])
+    assert torch.equal(g1, o2["grads"])
+    m.close()
+
+
+def test_autograd_functions_match_fused_entry_points():
+    hg = _hgnn()
+    w = synth.WORKLOADS["c0_small_fp32"]
+    b, params = w.batch(), w.params()
+    m = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+    out = run_train_step(m, b, params)
+    net = hg.PNANet(m, params)
+    db = hg.DeviceBatch.from_host(b)
+    pred = net(db)
+    loss = ((pred - db.y) ** 2).mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert torch.equal(pred.detach(), out["pred"])
+    g = net.packed_grad()
+    assert rel(g.cpu().numpy(), out["grads"].cpu().numpy()) <= 1e-6
+    m.close()
+
+
+def test_gpu_path_central_differences():
+    """FP32 finite differences through the GPU forward (loose: FP32 noise)."""
+    hg = _hgnn()
+    b = synth.make_batch(77, 4, 5, 12, 1)
+    shape = synth.ModelShape(2, 16, 9, 1)
+    params = synth.init_params(shape, 78).astype(np.float64)
+    m = hg.Model(2, 16, 9, 1, 4, 0, 0, 1.0)
+    out = run_train_step(m, b, params.astype(np.float32))
+    g = out["grads"].cpu().numpy()
+    db = hg.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    idx = np.argsort(-np.abs(g))[:12]
+    for j in idx:
+        hstep = 1e-2 * max(1.0, abs(params[j]))
+        vals = []
+        for sgn in (1, -1):
+            p = params.copy()
+            p[j] += sgn * hstep
+            m.set_params(p.astype(np.float32))
+            m.forward(db, pred, loss)
+            torch.cuda.synchronize()
+            vals.append(loss.item())
+        fd = (vals[0] - vals[1]) / (2 * hstep)
+        assert fd == pytest.approx(g[j], rel=2e-2, abs=1e-3 * abs(g).max()), j
+    m.close()
+
+
+def test_adamw_step_isolated():
+    """The GPU AdamW given the GPU gradient equals the oracle's AdamW."""
+    w = synth.WORKLOADS["c0_small_fp32"]
+    b, params = w.batch(), w.params()
+    m = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+    theta = params.astype(np.float64)
+    mm = np.zeros_like(theta)
+    vv = np.zeros_like(theta)
+    m.set_params(params)
+    hg = _hgnn()
+    db = hg.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+    for t in range(1, 4):
+        m.forward(db, pred)
+        m.backward()
+        g = m.grads().cpu().numpy().astype(np.float64)
+        p0 = m.params().cpu().numpy().astype(np.float64)
+        m.adam_step(lr=1e-3, weight_decay=0.01)
+        p1 = m.params().cpu().numpy().astype(np.float64)
+        ref, mm, vv = oracle.adamw(p0, g, mm, vv, t, lr=1e-3, weight_decay=0.01)
+        r = rel(p1 - p0, ref - p0)
+        say(f"  adam step {t}: update rel {r:.2e}")
+        assert r <= 1e-5
+        assert rel(p1, ref) <= 1e-6
+    m.close()
+
+
+def test_checkpoint_resume_bitwise():
+    hg = _hgnn()
+    w = synth.WORKLOADS["c0_small_fp32"]
+    b, params = w.batch(), w.params()
+    db = hg.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+
+    def steps(model, k):
+        for _ in range(k):
+            model.forward(db, pred)
+            model.backward()
+            model.adam_step()
+
+    m = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+    m.set_params(params)
+    steps(m, 2)
+    state = m.get_state()
+    steps(m, 2)
+    ref = m.params().clone()
+    m2 = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+    m2.set_state(state)
+    steps(m2, 2)
+    assert torch.equal(m2.params(), ref)
+    m.close()
+    m2.close()
+
+
+# ---------------------------------------------------------------------------
+# BF16 path
+# ---------------------------------------------------------------------------
+
+def test_bf16_outputs_within_2e2():
+    w = synth.WORKLOADS["c2_train_bf16"]
+    b, params = w.batch(), w.params()
+    L, H = w.num_layers, w.hidden
+    m = make_model(L, H, w.edge_feat, 1, 0, w.delta)
+    out = run_train_step(m, b, params)
+    rec = oracle.forward(params, b, L, H, w.delta)
+    r_pred = rel(out["pred"].cpu().numpy(), rec.y)
+    r_loss = rel([out["loss"].item()], [rec.loss])
+    g_ref, _, stats = oracle.backward(rec, hint=gpu_decisions(m, L, H, b.num_nodes,
+                                                              b.num_graphs), tau=TAU_BF16)
+    rep = grad_report(m, out["grads"].cpu().numpy(), g_ref, w.shape)
+    worst = max(rep, key=rep.get)
+    say(f"bf16 c2: pred rel {r_pred:.2e} loss rel {r_loss:.2e}; grad worst {worst} "
+        f"{rep[worst]:.2e} median {np.median(list(rep.values())):.2e}; adopted {stats}")
+    assert r_pred <= 2e-2 and r_loss <= 2e-2
+    m.close()
+
+
+def test_large_config_sampled_graphs():
+    """8 layers, H=256, 1024 graphs, BF16 + recompute: graphs are independent,
+    so the oracle checks a sample of them one at a time."""
+    w = synth.WORKLOADS["c3_large_bf16"]
+    b, params = w.batch(), w.params()
+    L, H = w.num_layers, w.hidden
+    m = make_model(L, H, w.edge_feat, 1, 1, w.delta)
+    out = run_train_step(m, b, params)
+    assert torch.isfinite(out["grads"]).all()
+    pred = out["pred"].cpu().numpy()
+    sample = [0, 1, 511, 1000, 1023]
+    sub = synth.select_graphs(b, sample)
+    rec = oracle.forward(params, sub, L, H, w.delta)
+    r = rel(pred[sample], rec.y)
+    say(f"c3 sampled pred rel {r:.2e}")
+    assert r <= 2e-2
+    m.close()
+
+
+# ---------------------------------------------------------------------------
+# edge cases and malformed input
+# ---------------------------------------------------------------------------
+
+def test_edge_cases_empty_and_ragged():
+    hg = _hgnn()
+    shape = synth.ModelShape(2, 32, 9, 1)
+    params = synth.init_params(shape, 9)
+    rng = np.random.default_rng(0)
+    # no edges at all: every node isolated (d = 0)
+    b0 = synth.Batch(np.array([0, 1, 4], np.int32), rng.standard_normal((4, 9)).astype(np.float32),
+                     np.zeros((2, 0), np.int32), np.zeros((0, 1), np.float32),
+                     np.array([1.0, 2.0], np.float32))
+    # single-node graphs mixed with ragged ones
+    parts = [synth.make_batch(s, 1, n, n, 1) for s, n in [(1, 1), (2, 7), (3, 1), (4, 33)]]
+    b1 = synth.concat_batches(parts)
+    for b in (b0, b1):
+        m = hg.Model(2, 32, 9, 1, 4, 0, 0, 1.0)
+        out = run_train_step(m, b, params)
+        rec = oracle.forward(params, b, 2, 32, 1.0)
+        assert rel(out["pred"].cpu().numpy(), rec.y) <= 1e-5
+        g_ref, _, _ = oracle.backward(rec, hint=gpu_decisions(m, 2, 32, b.num_nodes,
+                                                              b.num_graphs), tau=TAU_FP32)
+        assert rel(out["grads"].cpu().numpy(), g_ref) <= 1e-5
+        m.close()
+
+
+@pytest.mark.parametrize("kind", ["range", "cross", "degree", "empty"])
+def test_malformed_batches_are_rejected(kind):
+    hg = _hgnn()
+    b = synth.make_batch(3, 3, 5, 8, 1)
+    gp, ei = b.graph_ptr.copy(), b.edge_index.copy()
+    if kind == "range":
+        ei[0, 0] = b.num_nodes + 5
+    elif kind == "cross":
+        ei[0, 0] = b.num_nodes - 1
+        ei[1, 0] = 0
+    elif kind == "degree":
+        pass
+    elif kind == "empty":
+        gp[1] = gp[0]
+    bad = synth.Batch(gp, b.x, ei, b.edge_attr, b.y)
+    m = hg.Model(1, 16, 9, 1, 1 if kind == "degree" else 4, 0, 0, 1.0)
+    with pytest.raises(hg.HgnnError) as ei_:
+        m.prepare(hg.DeviceBatch.from_host(bad), validate=True)
+    assert ei_.value.code == hg.EINVAL
+    # the context stays usable
+    m.prepare(hg.DeviceBatch.from_host(b if kind != "degree" else
+                                       synth.make_batch(3, 1, 2, 2, 1)), validate=True)
+    m.close()
