@@ -37,11 +37,20 @@ k_adamw(float *__restrict__ theta, const float *__restrict__ g, float *__restric
   theta[i] = th - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
-template <typename T> __device__ __forceinline__ void put(void *dst, size_t i, float v) {
-  reinterpret_cast<T *>(dst)[i] = (T)v;
+// FP32 copies store the value; BF16 copies store hi = bf16(v) and, in a
+// second array, lo = bf16(v - hi), so that hi + lo carries ~16 mantissa bits.
+template <typename T>
+__device__ __forceinline__ void put(void *dst, void *dst_lo, size_t i, float v) {
+  if constexpr (sizeof(T) == 4) {
+    reinterpret_cast<float *>(dst)[i] = v;
+  } else {
+    const __bf16 hi = (__bf16)v;
+    reinterpret_cast<__bf16 *>(dst)[i] = hi;
+    reinterpret_cast<__bf16 *>(dst_lo)[i] = (__bf16)(v - (float)hi);
+  }
 }
 
-// Per layer: the four GEMM-layout copies of W^m and W^p.
+// Per layer: the four GEMM-layout copies of W^m and W^p (index 0..3 of o).
 //  Wds   [2H, Fp]     rows n < H: W^m[n, 0:F]; n >= H: W^m[n-H, F:2F]; zero pad
 //  Wpp   [H, Fp+12H]  W^p with its first block padded from F to Fp columns
 //  WpTA  [4H, 3H]     WpTA[c, j H + m] = W^p[m, F + 4 H j + c]
@@ -49,7 +58,7 @@ template <typename T> __device__ __forceinline__ void put(void *dst, size_t i, f
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F, int Fp,
-              int H, int Fe, void *Wds, void *Wpp, void *WpTA, void *WhdsT) {
+              int H, int Fe, StageOut o) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int ldm = 2 * F + Fe, ldp = F + 12 * H;
   const long long n1 = 2LL * H * Fp, n2 = (long long)H * (Fp + 12 * H);
@@ -58,19 +67,19 @@ k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F,
     const int r = (int)(t / Fp), c = (int)(t % Fp);
     float v = 0.f;
     if (c < F) v = r < H ? Wm[(size_t)r * ldm + c] : Wm[(size_t)(r - H) * ldm + F + c];
-    put<T>(Wds, t, v);
+    put<T>(o.hi[0], o.lo[0], t, v);
   } else if (t < n1 + n2) {
     const long long u = t - n1;
     const int r = (int)(u / (Fp + 12 * H)), c = (int)(u % (Fp + 12 * H));
     float v = 0.f;
     if (c < Fp) { if (c < F) v = Wp[(size_t)r * ldp + c]; }
     else v = Wp[(size_t)r * ldp + F + (c - Fp)];
-    put<T>(Wpp, u, v);
+    put<T>(o.hi[1], o.lo[1], u, v);
   } else if (t < n1 + n2 + n3) {
     const long long u = t - n1 - n2;
     const int r = (int)(u / (3 * H)), c = (int)(u % (3 * H));
     const int j = c / H, m = c % H;
-    put<T>(WpTA, u, Wp[(size_t)m * ldp + F + 4 * H * j + r]);
+    put<T>(o.hi[2], o.lo[2], u, Wp[(size_t)m * ldp + F + 4 * H * j + r]);
   } else if (t < n1 + n2 + n3 + n4) {
     const long long u = t - n1 - n2 - n3;
     const int r = (int)(u / (3 * H)), c = (int)(u % (3 * H));
@@ -81,7 +90,7 @@ k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F,
       else if (j == 1) v = Wm[(size_t)m * ldm + r];
       else v = Wm[(size_t)m * ldm + F + r];
     }
-    put<T>(WhdsT, u, v);
+    put<T>(o.hi[3], o.lo[3], u, v);
   }
 }
 
@@ -104,16 +113,13 @@ hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_
 }
 
 hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp, int H,
-                              int Fe, void *Wds, void *Wpp, void *WpTA, void *WhdsT,
-                              int to_bf16, hipStream_t s) {
+                              int Fe, const StageOut &o, int to_bf16, hipStream_t s) {
   const long long total = 2LL * H * Fp + (long long)H * (Fp + 12 * H) + 12LL * H * H +
                           3LL * Fp * H;
   if (to_bf16)
-    k_stage_layer<__bf16><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, Wds, Wpp,
-                                                           WpTA, WhdsT);
+    k_stage_layer<__bf16><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, o);
   else
-    k_stage_layer<float><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, Wds, Wpp,
-                                                          WpTA, WhdsT);
+    k_stage_layer<float><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, o);
   return hipGetLastError();
 }
 

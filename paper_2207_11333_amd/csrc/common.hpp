@@ -51,6 +51,7 @@ struct GemmNT {
   SegA seg[kMaxSeg];
   int nseg;
   const void *B;   // [Ncols, ldb] (float or bf16 per precision), k-contiguous
+  const void *B_lo; // BF16 only: low halves of B (hi + lo split) or nullptr
   int ldb;
   int Ncols;
   const float *bias; // [Ncols] or nullptr
@@ -173,9 +174,15 @@ hipError_t launch_head_backward(const Dims *dims, int capB, int H,
 hipError_t launch_adamw(float *theta, const float *g, float *m, float *v,
                         int64_t n, float lr, double b1, double b2, float eps,
                         float wd, long long *step, float *corr, hipStream_t s);
+// Destinations of the four GEMM-layout weight copies of a layer; lo[] is
+// used only for BF16 copies (the low half of a hi + lo split).
+struct StageOut {
+  void *hi[4];
+  void *lo[4];
+};
 hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp,
-                              int H, int Fe, void *Wds, void *Wpp, void *WpTA,
-                              void *WhdsT, int to_bf16, hipStream_t s);
+                              int H, int Fe, const StageOut &o, int to_bf16,
+                              hipStream_t s);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
 
 } // namespace hgnn

@@ -12,7 +12,10 @@
 //    and need no atomics.
 // Precision 0 runs v_mfma_f32_16x16x4_f32 on FP32 operands; precision 1
 // rounds operands to BF16 (RNE, v_cvt_pk_bf16_f32) while staging and runs
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Weights in BF16 mode come
+// as a hi + lo pair of BF16 arrays (two MFMAs per tile): a weight's rounding
+// error is the same for every node, so unlike the activations' it does not
+// average out and it dominates the output error of deep stacks.
 //
 // MFMA lane layout (16x16 output block, wave64): lane l supplies row
 // (l % 16) of A and column (l % 16) of B for the k-slots of lane group
@@ -100,7 +103,7 @@ __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
 // --------------------------------------------------------------------------
 // NT form
 // --------------------------------------------------------------------------
-template <int PREC, int BM, int BN>
+template <int PREC, int BM, int BN, bool SPLIT>
 __global__ void __launch_bounds__(256)
 k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
   using P = Prec<PREC>;
@@ -115,6 +118,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
   static_assert(NA >= 1 && NB >= 1, "tile too small for 256 threads");
   __shared__ __attribute__((aligned(16))) T As[BM * LDA];
   __shared__ __attribute__((aligned(16))) T Bs[BN * LDA];
+  __shared__ __attribute__((aligned(16))) T Bl[SPLIT ? BN * LDA : 1];
 
   const int M = g.M_fixed >= 0 ? g.M_fixed : dims->N;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -129,8 +133,10 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
     for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   const T *Bg = reinterpret_cast<const T *>(g.B);
+  const T *Blg = reinterpret_cast<const T *>(g.B_lo);
   f4 ra[NA];
   f4 rb[NB]; // raw 16-byte B vectors (FP32 or BF16) kept as f4 bit patterns
+  f4 rl[SPLIT ? NB : 1];
 
   auto load = [&](int sidx, int k0) {
     const SegA &sg = g.seg[sidx];
@@ -154,10 +160,14 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
       const int v = tid + j * 256;
       const int r = v / (BK / BVEC), c = (v % (BK / BVEC)) * BVEC;
       const int n = n0 + r, k = k0 + c;
-      f4 val = f4{0.f, 0.f, 0.f, 0.f};
-      if (n < g.Ncols && k < sg.k)
+      f4 val = f4{0.f, 0.f, 0.f, 0.f}, vlo = val;
+      if (n < g.Ncols && k < sg.k) {
         val = *reinterpret_cast<const f4 *>(Bg + (size_t)n * g.ldb + sg.boff + k);
+        if constexpr (SPLIT)
+          vlo = *reinterpret_cast<const f4 *>(Blg + (size_t)n * g.ldb + sg.boff + k);
+      }
       rb[j] = val;
+      if constexpr (SPLIT) rl[j] = vlo;
     }
   };
   auto stash = [&]() {
@@ -172,6 +182,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
       const int v = tid + j * 256;
       const int r = v / (BK / BVEC), c = (v % (BK / BVEC)) * BVEC;
       *reinterpret_cast<f4 *>(Bs + r * LDA + c) = rb[j]; // 16 raw bytes
+      if constexpr (SPLIT) *reinterpret_cast<f4 *>(Bl + r * LDA + c) = rl[j];
     }
   };
 
@@ -194,6 +205,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
       const bool more = ns < g.nseg;
       if (more) load(ns, nk);
       mma_tile<PREC, TM, TN, LDA>(As, Bs, wm0, wn0, acc);
+      if constexpr (SPLIT) mma_tile<PREC, TM, TN, LDA>(As, Bl, wm0, wn0, acc);
       if (!more) break;
       sidx = ns;
       k0 = nk;
@@ -351,7 +363,10 @@ inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 template <int PREC, int BM, int BN>
 hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s) {
   dim3 grid(cdiv(capM, BM), cdiv(g.Ncols, BN));
-  k_gemm_nt<PREC, BM, BN><<<grid, 256, 0, s>>>(dims, g);
+  if (PREC == 1 && g.B_lo)
+    k_gemm_nt<PREC, BM, BN, true><<<grid, 256, 0, s>>>(dims, g);
+  else
+    k_gemm_nt<PREC, BM, BN, false><<<grid, 256, 0, s>>>(dims, g);
   return hipGetLastError();
 }
 

@@ -144,12 +144,26 @@ int ensure_work(hgnn_ctx *c, int B, int N, int E) {
   return HGNN_OK;
 }
 
+static StageOut stage_out(hgnn_ctx *c, int l) {
+  StageOut o{};
+  o.hi[0] = c->Wds[l];
+  o.hi[1] = c->Wpp[l];
+  o.hi[2] = c->WpTA[l];
+  o.hi[3] = c->WhdsT[l];
+  if (c->prec) {
+    o.lo[0] = c->Wds_lo[l];
+    o.lo[1] = c->Wpp_lo[l];
+    o.lo[2] = c->WpTA_lo[l];
+    o.lo[3] = c->WhdsT_lo[l];
+  }
+  return o;
+}
+
 int stage_all(hgnn_ctx *c, hipStream_t s) {
   for (int l = 0; l < c->L; ++l) {
     const LayerDesc &d = c->ld[l];
     hipError_t e = launch_stage_layer(c->params + d.oWm, c->params + d.oWp, d.F, d.Fp, c->H,
-                                      c->Fe, c->Wds[l], c->Wpp[l], c->WpTA[l], c->WhdsT[l],
-                                      c->prec, s);
+                                      c->Fe, stage_out(c, l), c->prec, s);
     if (e != hipSuccess) return hip_fail(c, e, "stage weights");
   }
   c->staged_from_params = true;
@@ -159,8 +173,7 @@ int stage_all(hgnn_ctx *c, hipStream_t s) {
 static int stage_layer_from(hgnn_ctx *c, int l, const float *wl, hipStream_t s) {
   const LayerDesc &d = c->ld[l];
   hipError_t e = launch_stage_layer(wl + (d.oWm - d.off), wl + (d.oWp - d.off), d.F, d.Fp,
-                                    c->H, c->Fe, c->Wds[l], c->Wpp[l], c->WpTA[l],
-                                    c->WhdsT[l], c->prec, s);
+                                    c->H, c->Fe, stage_out(c, l), c->prec, s);
   if (e != hipSuccess) return hip_fail(c, e, "stage layer weights");
   c->staged_from_params = false;
   return HGNN_OK;
@@ -231,6 +244,7 @@ static int message_and_aggregate(hgnn_ctx *c, int l, const float *wl, const floa
   g.nseg = 1;
   g.seg[0] = SegA{hin, nullptr, ldh, d.Fp, 0};
   g.B = c->Wds[l];
+  g.B_lo = c->prec ? c->Wds_lo[l] : nullptr;
   g.ldb = d.Fp;
   g.Ncols = 2 * H;
   g.C = PQ;
@@ -287,6 +301,7 @@ int layer_forward(hgnn_ctx *c, int l, const float *wl, const float *h_in, float 
   g.seg[2] = SegA{A, w.csr.sp, 4 * H, 4 * H, d.Fp + 4 * H};
   g.seg[3] = SegA{A, w.csr.sm, 4 * H, 4 * H, d.Fp + 8 * H};
   g.B = c->Wpp[l];
+  g.B_lo = c->prec ? c->Wpp_lo[l] : nullptr;
   g.ldb = d.Fp + 12 * H;
   g.Ncols = H;
   g.bias = wl + (d.obp - d.off);
@@ -358,6 +373,7 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
     g.seg[1] = SegA{w.du, w.csr.sp, H, H, H};
     g.seg[2] = SegA{w.du, w.csr.sm, H, H, 2 * H};
     g.B = c->WpTA[l];
+    g.B_lo = c->prec ? c->WpTA_lo[l] : nullptr;
     g.ldb = 3 * H;
     g.Ncols = 4 * H;
     g.C = w.dA;
@@ -422,6 +438,7 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
     g.seg[1] = SegA{w.Dio, nullptr, 2 * H, H, H};
     g.seg[2] = SegA{w.Dio + H, nullptr, 2 * H, H, 2 * H};
     g.B = c->WhdsT[l];
+    g.B_lo = c->prec ? c->WhdsT_lo[l] : nullptr;
     g.ldb = 3 * H;
     g.Ncols = d.F;
     g.C = dh_in;
@@ -565,15 +582,19 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
   const size_t esz = c->prec ? 2 : 4;
   for (int l = 0; l < c->L; ++l) {
     const LayerDesc &d = c->ld[l];
-    uint8_t *p1, *p2, *p3, *p4;
-    HGNN_CALLOC(p1, esz * 2 * H * d.Fp);
-    c->Wds.push_back(p1);
-    HGNN_CALLOC(p2, esz * H * (d.Fp + 12 * H));
-    c->Wpp.push_back(p2);
-    HGNN_CALLOC(p3, esz * 12 * H * H);
-    c->WpTA.push_back(p3);
-    HGNN_CALLOC(p4, esz * 3 * H * d.Fp);
-    c->WhdsT.push_back(p4);
+    const size_t n[4] = {(size_t)2 * H * d.Fp, (size_t)H * (d.Fp + 12 * H), (size_t)12 * H * H,
+                         (size_t)3 * H * d.Fp};
+    std::vector<void *> *hi[4] = {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT};
+    std::vector<void *> *lo[4] = {&c->Wds_lo, &c->Wpp_lo, &c->WpTA_lo, &c->WhdsT_lo};
+    for (int k = 0; k < 4; ++k) {
+      uint8_t *p;
+      HGNN_CALLOC(p, esz * n[k]);
+      hi[k]->push_back(p);
+      if (c->prec) {
+        HGNN_CALLOC(p, esz * n[k]);
+        lo[k]->push_back(p);
+      }
+    }
   }
 #undef HGNN_CALLOC
   // Degree-scaler table: s+(d) = ln(d+1)/delta, s-(d) = delta/ln(d+1) in FP64,
@@ -617,7 +638,8 @@ void hgnn_destroy(hgnn_ctx *c) {
                    (void **)&c->table, (void **)&c->dims, (void **)&c->w.csr.err,
                    (void **)&c->part};
   for (void **p : ptrs) dfree(*p);
-  for (auto *v : {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT})
+  for (auto *v : {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT, &c->Wds_lo, &c->Wpp_lo, &c->WpTA_lo,
+                  &c->WhdsT_lo})
     for (auto &p : *v) dfree(reinterpret_cast<void *&>(p));
   delete c;
 }

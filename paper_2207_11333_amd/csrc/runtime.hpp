@@ -66,6 +66,7 @@ struct hgnn_ctx {
   float *corr = nullptr;
   float *table = nullptr;
   std::vector<void *> Wds, Wpp, WpTA, WhdsT; // GEMM-layout weight copies per layer
+  std::vector<void *> Wds_lo, Wpp_lo, WpTA_lo, WhdsT_lo; // BF16 low halves
   bool staged_from_params = false;
   hgnn::Dims *dims = nullptr;
   float *part = nullptr;
