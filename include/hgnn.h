@@ -211,6 +211,8 @@ typedef struct {
 typedef struct {
   int64_t submitted, completed, batches, graph_replays, admission_waits;
   int64_t peak_inflight_bytes;
+  int64_t lanes;      /* lanes that fit the budget */
+  int64_t lane_bytes; /* device footprint of one lane */
 } hgnn_serve_stats;
 
 /* Start the scheduler thread; the weights stay resident and are shared. */

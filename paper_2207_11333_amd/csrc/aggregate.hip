@@ -192,23 +192,40 @@ k_relu_mask(const Dims *__restrict__ dims, int H, const float *__restrict__ dh,
   reinterpret_cast<f4 *>(du)[t] = o;
 }
 
-// Column sums, stage 1: partial[z][col] over row chunk z.
+// Column sums, stage 1: partial[z][col] over row chunk z.  A workgroup owns
+// 64 columns and one chunk; its 4 wavefronts take interleaved rows, and the
+// four wave sums are added in a fixed order.
+constexpr int kColRowGroups = 4;
+
 __global__ void __launch_bounds__(256)
 k_colsum_partial(const Dims *__restrict__ dims, const ColSum cs,
                  float *__restrict__ part, int total_cols, int splits) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float red[kColRowGroups][64];
+  const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
   const int z = blockIdx.y;
-  if (col >= total_cols) return;
-  int a = 0, c = col;
-  while (a + 1 < cs.n && c >= cs.ncols[a]) { c -= cs.ncols[a]; ++a; }
-  const int rows = dims->N;
-  const int chunk = (rows + splits - 1) / splits;
-  const int lo = z * chunk, hi = min(rows, lo + chunk);
-  const float *src = cs.src[a];
-  const int ld = cs.ld[a];
   float s = 0.f;
-  for (int i = lo; i < hi; ++i) s += src[(size_t)i * ld + c];
-  part[(size_t)z * total_cols + col] = s;
+  if (col < total_cols) {
+    int a = 0, c = col;
+    while (a + 1 < cs.n && c >= cs.ncols[a]) { c -= cs.ncols[a]; ++a; }
+    const int rows = dims->N;
+    const int chunk = (rows + splits - 1) / splits;
+    const int lo = z * chunk, hi = min(rows, lo + chunk);
+    const float *src = cs.src[a] + c;
+    const size_t ld = cs.ld[a];
+    int i = lo + rg;
+    float s0 = 0.f, s1 = 0.f;
+    for (; i + kColRowGroups < hi; i += 2 * kColRowGroups) {
+      s0 += src[(size_t)i * ld];
+      s1 += src[(size_t)(i + kColRowGroups) * ld];
+    }
+    if (i < hi) s0 += src[(size_t)i * ld];
+    s = s0 + s1;
+  }
+  red[rg][lane] = s;
+  __syncthreads();
+  if (rg == 0 && col < total_cols)
+    part[(size_t)z * total_cols + col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // Stage 2: ordered sum over the chunks; output column c of array a goes to
@@ -218,16 +235,25 @@ struct ColSumOut {
   int rs[3], ostride[3];
 };
 
-__global__ void k_colsum_final(const ColSum cs, const ColSumOut co,
-                               const float *__restrict__ part, int total_cols,
-                               int splits) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= total_cols) return;
+__global__ void __launch_bounds__(256)
+k_colsum_final(const ColSum cs, const ColSumOut co, const float *__restrict__ part,
+               int total_cols, int splits) {
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int col = gt >> 2, q = gt & 3;
+  const int cc = col < total_cols ? col : total_cols - 1;
+  // 4 lanes per column: each adds a contiguous quarter of the chunks in
+  // order, then the quarters are added in order
+  const int per = (splits + 3) / 4;
+  const int z0 = q * per, z1 = min(splits, z0 + per);
+  float s = 0.f;
+  for (int z = z0; z < z1; ++z) s += part[(size_t)z * total_cols + cc];
+  const int lane = threadIdx.x & 63;
+  const float s0 = __shfl(s, lane & ~3, 64), s1 = __shfl(s, (lane & ~3) + 1, 64);
+  const float s2 = __shfl(s, (lane & ~3) + 2, 64), s3 = __shfl(s, (lane & ~3) + 3, 64);
+  if (col >= total_cols || q != 0) return;
   int a = 0, c = col;
   while (a + 1 < cs.n && c >= cs.ncols[a]) { c -= cs.ncols[a]; ++a; }
-  float s = 0.f;
-  for (int z = 0; z < splits; ++z) s += part[(size_t)z * total_cols + col];
-  co.out[a][(size_t)(c % co.rs[a]) * co.ostride[a] + c / co.rs[a]] = s;
+  co.out[a][(size_t)(c % co.rs[a]) * co.ostride[a] + c / co.rs[a]] = ((s0 + s1) + s2) + s3;
 }
 
 } // namespace
@@ -299,9 +325,9 @@ hipError_t launch_colsum(const Dims *dims, const ColSum &c, const ColSumMap &map
     co.rs[a] = a < c.n ? map.rs[a] : 1;
     co.ostride[a] = a < c.n ? map.ostride[a] : 1;
   }
-  dim3 g1(cdiv(total, 256), splits);
+  dim3 g1(cdiv(total, 64), splits);
   k_colsum_partial<<<g1, 256, 0, s>>>(dims, c, partials, total, splits);
-  k_colsum_final<<<cdiv(total, 256), 256, 0, s>>>(c, co, partials, total, splits);
+  k_colsum_final<<<cdiv(4 * total, 256), 256, 0, s>>>(c, co, partials, total, splits);
   return hipGetLastError();
 }
 

@@ -59,6 +59,14 @@ struct GemmNT {
   float *C;
   int ldc;
   int M_fixed;       // -1: M = dims->N
+  // split-K: with splits > 1 each split writes raw partial sums to
+  // P[z][m][n] (splits x capM x Ncols) and a second kernel adds them in
+  // order z = 0..splits-1 and applies bias and ReLU.
+  int splits;
+  float *P;
+  // optional: zero C[m, n] where mask[m * ldc + n] <= 0 (ReLU adjoint of the
+  // layer that produced `mask`)
+  const float *mask;
 };
 
 // Weight-gradient form, reduction over rows i (nodes):
@@ -114,8 +122,13 @@ hipError_t launch_pad_copy(const Dims *dims, int capN, const float *x, int F,
                            float *xp, int Fp, hipStream_t s);
 
 // gemm.hip
-hipError_t launch_gemm_nt(const Dims *dims, int capM, const GemmNT &g,
-                          int precision, hipStream_t s);
+// Picks the tile shape and the split count from the capacity capM and the
+// shape; g.splits/g.P are set here (P must hold nt_partial_floats()).
+hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
+                          float *partials, hipStream_t s);
+// Split count launch_gemm_nt will use, and the partial buffer it needs.
+int nt_splits(int capM, int Ncols, int Ktot, int precision);
+size_t nt_partial_floats(int capM, int Ncols, int Ktot, int precision);
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
                           hipStream_t s);
 hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s);

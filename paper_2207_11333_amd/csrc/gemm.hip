@@ -26,6 +26,8 @@
 // assignment, so the sum over all k is unchanged.
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace hgnn {
 
 namespace {
@@ -33,7 +35,7 @@ namespace {
 template <int PREC> struct Prec;
 template <> struct Prec<0> {
   using T = float;
-  static constexpr int BK = 32;   // k per LDS tile
+  static constexpr int BK = 64;   // k per LDS tile
   static constexpr int PAD = 4;   // elements of row padding (16 bytes)
 };
 template <> struct Prec<1> {
@@ -41,6 +43,18 @@ template <> struct Prec<1> {
   static constexpr int BK = 64;
   static constexpr int PAD = 8;
 };
+
+template <int V> using IC = std::integral_constant<int, V>;
+
+// Map the dispatch order (round-robin over the 8 XCDs) to tiles so that each
+// XCD receives a contiguous range of tiles: neighbouring tiles, which share
+// A rows, then share that XCD's L2.  A bijection on [0, T).
+__device__ __forceinline__ int xcd_tile(int bid, int T) {
+  constexpr int X = 8;
+  const int xcd = bid % X, local = bid / X;
+  const int per = T / X, rem = T % X;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
 
 __device__ __forceinline__ void store4(float *dst, f4 v) {
   *reinterpret_cast<f4 *>(dst) = v;
@@ -57,7 +71,7 @@ __device__ __forceinline__ void store1(float *dst, float v) { *dst = v; }
 __device__ __forceinline__ void store1(__bf16 *dst, float v) { *dst = (__bf16)v; }
 
 // Multiply-accumulate one BK-deep LDS tile into the wave's accumulators.
-template <int PREC, int TM, int TN, int LDA>
+template <int PREC, int TM, int TN, int LDA, int BK>
 __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
                                          const typename Prec<PREC>::T *Bs,
                                          int wm0, int wn0, f4 (&acc)[TM][TN]) {
@@ -65,7 +79,7 @@ __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
   const int r = lane & 15, g = lane >> 4;
   if constexpr (PREC == 0) {
 #pragma unroll
-    for (int kc = 0; kc < Prec<0>::BK; kc += 16) {
+    for (int kc = 0; kc < BK; kc += 16) {
       f4 a[TM], b[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -83,7 +97,7 @@ __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
     }
   } else {
 #pragma unroll
-    for (int kc = 0; kc < Prec<1>::BK; kc += 32) {
+    for (int kc = 0; kc < BK; kc += 32) {
       bf16x8 a[TM], b[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -105,7 +119,7 @@ __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
 // --------------------------------------------------------------------------
 template <int PREC, int BM, int BN, bool SPLIT>
 __global__ void __launch_bounds__(256)
-k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
+k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   using P = Prec<PREC>;
   using T = typename P::T;
   constexpr int BK = P::BK, LDA = BK + P::PAD;
@@ -121,10 +135,24 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
   __shared__ __attribute__((aligned(16))) T Bl[SPLIT ? BN * LDA : 1];
 
   const int M = g.M_fixed >= 0 ? g.M_fixed : dims->N;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  if (m0 >= M) return;
+  const int mtiles = (M + BM - 1) / BM;
+  const int z = blockIdx.y;
+  if ((int)blockIdx.x >= mtiles * ntiles_n) return;
+  const int tile = xcd_tile(blockIdx.x, mtiles * ntiles_n);
+  const int m0 = (tile / ntiles_n) * BM, n0 = (tile % ntiles_n) * BN;
   const int tid = threadIdx.x, wid = tid >> 6;
   const int wm0 = (wid >> 1) * WM, wn0 = (wid & 1) * WN;
+
+  // K tiles over all segments: cum[s] = first tile of segment s
+  int cum[kMaxSeg + 1];
+  cum[0] = 0;
+#pragma unroll
+  for (int q = 0; q < kMaxSeg; ++q)
+    cum[q + 1] = cum[q] + (q < g.nseg && g.seg[q].k > 0 ? (g.seg[q].k + BK - 1) / BK : 0);
+  // this split's contiguous range of K tiles [t_lo, t_lo + KT)
+  const int KT_all = cum[kMaxSeg];
+  const int t_lo = (int)((long long)KT_all * z / g.splits);
+  const int KT = (int)((long long)KT_all * (z + 1) / g.splits) - t_lo;
 
   f4 acc[TM][TN];
 #pragma unroll
@@ -134,86 +162,118 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
 
   const T *Bg = reinterpret_cast<const T *>(g.B);
   const T *Blg = reinterpret_cast<const T *>(g.B_lo);
-  f4 ra[NA];
-  f4 rb[NB]; // raw 16-byte B vectors (FP32 or BF16) kept as f4 bit patterns
-  f4 rl[SPLIT ? NB : 1];
+  // two register stages: tiles t and t+1 are in flight while t-1 computes.
+  // Loads are unconditional from clamped (in-bounds) addresses and masked
+  // by a select, so no branch forces the compiler to drain the load queue.
+  f4 ra[2][NA], rb[2][NB], rl[2][SPLIT ? NB : 1];
+  float rs[2][NA];
+  int a_row[NA], a_col[NA];
+  bool a_ok[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    const int v = tid + j * 256;
+    const int m = m0 + v / (BK / 4);
+    a_ok[j] = m < M;
+    a_row[j] = min(m, M - 1);
+    a_col[j] = (v % (BK / 4)) * 4;
+  }
+  int b_row[NB], b_col[NB];
+  bool b_ok[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int v = tid + j * 256;
+    const int n = n0 + v / (BK / BVEC);
+    b_ok[j] = n < g.Ncols;
+    b_row[j] = min(n, g.Ncols - 1);
+    b_col[j] = (v % (BK / BVEC)) * BVEC;
+  }
 
-  auto load = [&](int sidx, int k0) {
-    const SegA &sg = g.seg[sidx];
+  auto load = [&](auto st, int t) {
+    constexpr int S = decltype(st)::value;
+    t = t_lo + min(t, KT - 1);
+    int q = 0;
+#pragma unroll
+    for (int u = 1; u < kMaxSeg; ++u) q += (t >= cum[u]) ? 1 : 0;
+    const float *aptr = g.seg[q].ptr;
+    const float *scale = g.seg[q].scale;
+    const int lda = g.seg[q].ld, ks = g.seg[q].k, boff = g.seg[q].boff;
+    const int k0 = (t - cum[q]) * BK;
+    const float *sbase = scale ? scale : aptr;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int k = k0 + a_col[j];
+      const f4 val = *reinterpret_cast<const f4 *>(aptr + (size_t)a_row[j] * lda + min(k, ks - 4));
+      ra[S][j] = (a_ok[j] && k < ks) ? val : f4{0.f, 0.f, 0.f, 0.f};
+      rs[S][j] = sbase[a_row[j]];
+    }
+    if (!scale) {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) rs[S][j] = 1.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int k = k0 + b_col[j];
+      const size_t off = (size_t)b_row[j] * g.ldb + boff + min(k, ks - BVEC);
+      const bool ok = b_ok[j] && k < ks;
+      const f4 val = *reinterpret_cast<const f4 *>(Bg + off);
+      rb[S][j] = ok ? val : f4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (SPLIT) {
+        const f4 vlo = *reinterpret_cast<const f4 *>(Blg + off);
+        rl[S][j] = ok ? vlo : f4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  };
+  auto stash = [&](auto st) {
+    constexpr int S = decltype(st)::value;
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       const int v = tid + j * 256;
       const int r = v / (BK / 4), c = (v % (BK / 4)) * 4;
-      const int m = m0 + r, k = k0 + c;
-      f4 val = f4{0.f, 0.f, 0.f, 0.f};
-      if (m < M && k < sg.k) {
-        val = *reinterpret_cast<const f4 *>(sg.ptr + (size_t)m * sg.ld + k);
-        if (sg.scale) {
-          const float s = sg.scale[m];
-          val *= s;
-        }
-      }
-      ra[j] = val;
+      store4(As + r * LDA + c, ra[S][j] * rs[S][j]);
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int v = tid + j * 256;
       const int r = v / (BK / BVEC), c = (v % (BK / BVEC)) * BVEC;
-      const int n = n0 + r, k = k0 + c;
-      f4 val = f4{0.f, 0.f, 0.f, 0.f}, vlo = val;
-      if (n < g.Ncols && k < sg.k) {
-        val = *reinterpret_cast<const f4 *>(Bg + (size_t)n * g.ldb + sg.boff + k);
-        if constexpr (SPLIT)
-          vlo = *reinterpret_cast<const f4 *>(Blg + (size_t)n * g.ldb + sg.boff + k);
-      }
-      rb[j] = val;
-      if constexpr (SPLIT) rl[j] = vlo;
+      *reinterpret_cast<f4 *>(Bs + r * LDA + c) = rb[S][j]; // 16 raw bytes
+      if constexpr (SPLIT) *reinterpret_cast<f4 *>(Bl + r * LDA + c) = rl[S][j];
     }
   };
-  auto stash = [&]() {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int v = tid + j * 256;
-      const int r = v / (BK / 4), c = (v % (BK / 4)) * 4;
-      store4(As + r * LDA + c, ra[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int v = tid + j * 256;
-      const int r = v / (BK / BVEC), c = (v % (BK / BVEC)) * BVEC;
-      *reinterpret_cast<f4 *>(Bs + r * LDA + c) = rb[j]; // 16 raw bytes
-      if constexpr (SPLIT) *reinterpret_cast<f4 *>(Bl + r * LDA + c) = rl[j];
-    }
+  auto step = [&](auto st, int t) {
+    __syncthreads();
+    stash(st);
+    __syncthreads();
+    load(st, t + 2);
+    mma_tile<PREC, TM, TN, LDA, BK>(As, Bs, wm0, wn0, acc);
+    if constexpr (SPLIT) mma_tile<PREC, TM, TN, LDA, BK>(As, Bl, wm0, wn0, acc);
   };
 
-  int sidx = 0, k0 = 0;
-  // skip empty segments
-  while (sidx < g.nseg && g.seg[sidx].k <= 0) ++sidx;
-  if (sidx < g.nseg) {
-    load(sidx, k0);
-    while (true) {
-      __syncthreads();
-      stash();
-      __syncthreads();
-      // advance to the next tile and prefetch it while this one computes
-      int ns = sidx, nk = k0 + BK;
-      if (nk >= g.seg[ns].k) {
-        ++ns;
-        nk = 0;
-        while (ns < g.nseg && g.seg[ns].k <= 0) ++ns;
-      }
-      const bool more = ns < g.nseg;
-      if (more) load(ns, nk);
-      mma_tile<PREC, TM, TN, LDA>(As, Bs, wm0, wn0, acc);
-      if constexpr (SPLIT) mma_tile<PREC, TM, TN, LDA>(As, Bl, wm0, wn0, acc);
-      if (!more) break;
-      sidx = ns;
-      k0 = nk;
-    }
+  if (KT > 0) load(IC<0>{}, 0);
+  if (KT > 1) load(IC<1>{}, 1);
+  for (int t = 0; t < KT; t += 2) {
+    step(IC<0>{}, t);
+    if (t + 1 >= KT) break;
+    step(IC<1>{}, t + 1);
   }
 
   const int lane = tid & 63;
   const int cr = 4 * (lane >> 4), cc = lane & 15;
+  if (g.splits > 1) {
+    float *Pz = g.P + (size_t)z * M * g.Ncols;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = n0 + wn0 + j * 16 + cc;
+      if (n >= g.Ncols) continue;
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = m0 + wm0 + i * 16 + cr + v;
+          if (m < M) Pz[(size_t)m * g.Ncols + n] = acc[i][j][v];
+        }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int n = n0 + wn0 + j * 16 + cc;
@@ -227,6 +287,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
         if (m < M) {
           float o = acc[i][j][v] + bias;
           if (g.relu) o = o > 0.f ? o : 0.f;
+          if (g.mask && !(g.mask[(size_t)m * g.ldc + n] > 0.f)) o = 0.f;
           g.C[(size_t)m * g.ldc + n] = o;
         }
       }
@@ -239,10 +300,10 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g) {
 // --------------------------------------------------------------------------
 template <int PREC, int BM, int BN>
 __global__ void __launch_bounds__(256)
-k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g) {
+k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   using P = Prec<PREC>;
   using T = typename P::T;
-  constexpr int BK = P::BK, LDA = BK + P::PAD;
+  constexpr int BK = P::BK / 2, LDA = BK + P::PAD;
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
   constexpr int NA = BM * BK / 4 / 256;
   constexpr int NB = BN * BK / 4 / 256;
@@ -250,11 +311,16 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g) {
   __shared__ __attribute__((aligned(16))) T Bs[BN * LDA];
 
   const int rows = dims->N;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN, z = blockIdx.z;
+  const int mtiles = (g.M + BM - 1) / BM;
+  const int T2 = mtiles * ntiles_n;
+  const int tile = xcd_tile(blockIdx.x % T2, T2);
+  const int z = blockIdx.x / T2;
+  const int m0 = (tile / ntiles_n) * BM, n0 = (tile % ntiles_n) * BN;
   int chunk = (rows + g.splits - 1) / g.splits;
   chunk = (chunk + BK - 1) / BK * BK;
   const int i_lo = z * chunk;
   const int i_hi = min(rows, i_lo + chunk);
+  const int KT = i_hi > i_lo ? (i_hi - i_lo + BK - 1) / BK : 0;
   const int tid = threadIdx.x, wid = tid >> 6;
   const int wm0 = (wid >> 1) * WM, wn0 = (wid & 1) * WN;
 
@@ -264,65 +330,92 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  f4 ra[NA], rb[NB];
-  auto load = [&](int i0) {
+  // Per-thread column pointers are fixed over the K loop (only the row i
+  // moves); loads are unconditional from clamped rows and masked by select.
+  f4 ra[2][NA], rb[2][NB];
+  float rsc[2][NB];
+  int a_il[NA], a_m[NA];
+  bool a_ok[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    const int v = tid + j * 256;
+    a_il[j] = v / (BM / 4);
+    const int m = m0 + (v % (BM / 4)) * 4;
+    a_ok[j] = m < g.M;
+    a_m[j] = min(m, g.M - 4);
+  }
+  const float *b_ptr[NB];
+  const float *b_sptr[NB]; // row scales, or the operand itself when unscaled
+  int b_ld[NB], b_il[NB], b_sstride[NB];
+  bool b_ok[NB], b_has_scale[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int v = tid + j * 256;
+    b_il[j] = v / (BN / 4);
+    int n = n0 + (v % (BN / 4)) * 4;
+    b_ok[j] = n < g.Ncols;
+    n = min(n, g.Ncols - 4);
+    int q = 0;
+    while (q + 1 < g.nseg && n >= g.seg[q].ncols) { n -= g.seg[q].ncols; ++q; }
+    b_ptr[j] = g.seg[q].ptr + n;
+    b_ld[j] = g.seg[q].ld;
+    b_has_scale[j] = g.seg[q].scale != nullptr;
+    b_sptr[j] = b_has_scale[j] ? g.seg[q].scale : b_ptr[j];
+    b_sstride[j] = b_has_scale[j] ? 1 : b_ld[j];
+  }
+  const int i_last = max(i_hi - 1, 0);
+  auto load = [&](auto st, int t) {
+    constexpr int S = decltype(st)::value;
+    const int i0 = i_lo + t * BK;
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-      const int v = tid + j * 256;
-      const int il = v / (BM / 4), mc = (v % (BM / 4)) * 4;
-      const int i = i0 + il, m = m0 + mc;
-      f4 val = f4{0.f, 0.f, 0.f, 0.f};
-      if (i < i_hi && m < g.M) val = *reinterpret_cast<const f4 *>(g.X + (size_t)i * g.ldx + m);
-      ra[j] = val;
+      const int i = i0 + a_il[j];
+      const f4 val = *reinterpret_cast<const f4 *>(g.X + (size_t)min(i, i_last) * g.ldx + a_m[j]);
+      ra[S][j] = (a_ok[j] && i < i_hi) ? val : f4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int v = tid + j * 256;
-      const int il = v / (BN / 4), nc = (v % (BN / 4)) * 4;
-      const int i = i0 + il;
-      int n = n0 + nc;
-      f4 val = f4{0.f, 0.f, 0.f, 0.f};
-      if (i < i_hi && n < g.Ncols) {
-        int s = 0;
-        while (s + 1 < g.nseg && n >= g.seg[s].ncols) { n -= g.seg[s].ncols; ++s; }
-        const SegY &sg = g.seg[s];
-        val = *reinterpret_cast<const f4 *>(sg.ptr + (size_t)i * sg.ld + n);
-        if (sg.scale) val *= sg.scale[i];
-      }
-      rb[j] = val;
+      const int i = i0 + b_il[j];
+      const int ic = min(i, i_last);
+      const f4 val = *reinterpret_cast<const f4 *>(b_ptr[j] + (size_t)ic * b_ld[j]);
+      const float sv = b_sptr[j][(size_t)ic * b_sstride[j]];
+      const float sc = b_has_scale[j] ? sv : 1.0f;
+      rb[S][j] = (b_ok[j] && i < i_hi) ? val : f4{0.f, 0.f, 0.f, 0.f};
+      rsc[S][j] = sc;
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](auto st) {
+    constexpr int S = decltype(st)::value;
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       const int v = tid + j * 256;
       const int il = v / (BM / 4), mc = (v % (BM / 4)) * 4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) store1(As + (mc + e) * LDA + il, ra[j][e]);
+      for (int e = 0; e < 4; ++e) store1(As + (mc + e) * LDA + il, ra[S][j][e]);
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int v = tid + j * 256;
       const int il = v / (BN / 4), nc = (v % (BN / 4)) * 4;
+      const f4 val = rb[S][j] * rsc[S][j];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) store1(Bs + (nc + e) * LDA + il, rb[j][e]);
+      for (int e = 0; e < 4; ++e) store1(Bs + (nc + e) * LDA + il, val[e]);
     }
+  };
+  auto step = [&](auto st, int t) {
+    __syncthreads();
+    stash(st);
+    __syncthreads();
+    load(st, min(t + 2, KT - 1));
+    mma_tile<PREC, TM, TN, LDA, BK>(As, Bs, wm0, wn0, acc);
   };
 
-  if (i_lo < i_hi) {
-    int i0 = i_lo;
-    load(i0);
-    while (true) {
-      __syncthreads();
-      stash();
-      __syncthreads();
-      const int ni = i0 + BK;
-      const bool more = ni < i_hi;
-      if (more) load(ni);
-      mma_tile<PREC, TM, TN, LDA>(As, Bs, wm0, wn0, acc);
-      if (!more) break;
-      i0 = ni;
-    }
+  if (KT > 0) load(IC<0>{}, 0);
+  if (KT > 1) load(IC<1>{}, 1);
+  for (int t = 0; t < KT; t += 2) {
+    step(IC<0>{}, t);
+    if (t + 1 >= KT) break;
+    step(IC<1>{}, t + 1);
   }
 
   const int lane = tid & 63;
@@ -342,19 +435,56 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g) {
   }
 }
 
-// Sum the split-K partials in order z = 0..splits-1 and scatter them into the
-// packed gradient layout.
-__global__ void k_reduce_map(const ReduceMap r) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// Ordered sum over split partials: 4 lanes per output each add a contiguous
+// quarter of the splits in order, then the quarters are added in order
+// (a fixed association, so the result is deterministic).
+__device__ __forceinline__ float ordered_split_sum(const float *__restrict__ P, int splits,
+                                                  long long stride, long long t, int q) {
+  const int per = (splits + 3) / 4;
+  const int z0 = q * per, z1 = min(splits, z0 + per);
+  float s = 0.f;
+  for (int z = z0; z < z1; ++z) s += P[(size_t)z * stride + t];
+  const int lane = threadIdx.x & 63;
+  const float s1 = __shfl(s, (lane & ~3) + 1, 64);
+  const float s2 = __shfl(s, (lane & ~3) + 2, 64);
+  const float s3 = __shfl(s, (lane & ~3) + 3, 64);
+  const float s0 = __shfl(s, lane & ~3, 64);
+  return ((s0 + s1) + s2) + s3;
+}
+
+// NT split-K: C = act(sum_z P[z] + bias) (* mask), z in order.
+__global__ void __launch_bounds__(256)
+k_reduce_nt(const Dims *__restrict__ dims, const GemmNT g) {
+  const int M = g.M_fixed >= 0 ? g.M_fixed : dims->N;
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = gt >> 2;
+  const int q = (int)(gt & 3);
+  const long long total = (long long)M * g.Ncols;
+  const long long tc = t < total ? t : total - 1;
+  float s = ordered_split_sum(g.P, g.splits, total, tc, q);
+  if (t >= total || q != 0) return;
+  const int m = (int)(t / g.Ncols), n = (int)(t % g.Ncols);
+  if (g.bias) s += g.bias[n];
+  if (g.relu) s = s > 0.f ? s : 0.f;
+  if (g.mask && !(g.mask[(size_t)m * g.ldc + n] > 0.f)) s = 0.f;
+  g.C[(size_t)m * g.ldc + n] = s;
+}
+
+// Sum the split-K partials in order and scatter them into the packed
+// gradient layout.
+__global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = gt >> 2;
+  const int q = (int)(gt & 3);
   const long long total = (long long)r.M * r.Ncols;
-  if (t >= total) return;
+  const long long tc = t < total ? t : total - 1;
+  const float s = ordered_split_sum(r.P, r.splits, total, tc, q);
+  if (t >= total || q != 0) return;
   const int m = (int)(t / r.Ncols), c = (int)(t % r.Ncols);
   int oc;
   if (c < r.F) oc = c;
   else if (c < r.Fp) return;
   else oc = c - (r.Fp - r.F);
-  float s = 0.f;
-  for (int z = 0; z < r.splits; ++z) s += r.P[(size_t)z * total + t];
   r.out[(size_t)(m % r.rsplit) * r.ldo + (size_t)(m / r.rsplit) * r.rcoloff + oc] = s;
 }
 
@@ -362,42 +492,79 @@ inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 
 template <int PREC, int BM, int BN>
 hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s) {
-  dim3 grid(cdiv(capM, BM), cdiv(g.Ncols, BN));
+  const int nt = cdiv(g.Ncols, BN);
+  dim3 grid(cdiv(capM, BM) * nt, g.splits);
   if (PREC == 1 && g.B_lo)
-    k_gemm_nt<PREC, BM, BN, true><<<grid, 256, 0, s>>>(dims, g);
+    k_gemm_nt<PREC, BM, BN, true><<<grid, 256, 0, s>>>(dims, g, nt);
   else
-    k_gemm_nt<PREC, BM, BN, false><<<grid, 256, 0, s>>>(dims, g);
+    k_gemm_nt<PREC, BM, BN, false><<<grid, 256, 0, s>>>(dims, g, nt);
+  if (g.splits > 1)
+    k_reduce_nt<<<cdiv(4LL * capM * g.Ncols, 256), 256, 0, s>>>(dims, g);
   return hipGetLastError();
+}
+
+// Output tiles are 64 rows x 128 columns: one tile spans the whole hidden
+// width, so each weight tile is staged once per 64 rows.  When the tiles
+// cannot give every SIMD two waves (512 workgroups of 4 waves on 256 CUs),
+// K is split (at least three K tiles per split, at most 8 splits).
+constexpr int kNtBM = 64, kNtBN = 128;
+
+int nt_ktiles(int Ktot, int precision) {
+  const int BK = precision ? Prec<1>::BK : Prec<0>::BK;
+  return (Ktot + BK - 1) / BK;
 }
 
 } // namespace
 
-hipError_t launch_gemm_nt(const Dims *dims, int capM, const GemmNT &g,
-                          int precision, hipStream_t s) {
+int nt_splits(int capM, int Ncols, int Ktot, int precision) {
+  const int tiles = cdiv(capM, kNtBM) * cdiv(Ncols, kNtBN);
+  const int kt = nt_ktiles(Ktot, precision);
+  int sp = (512 + tiles - 1) / (tiles > 0 ? tiles : 1);
+  if (sp > kt / 3) sp = kt / 3;
+  if (sp > 8) sp = 8;
+  return sp < 1 ? 1 : sp;
+}
+
+// Upper bound of splits x capM x Ncols over every shape: a split is taken
+// only while the tiles number fewer than 512, and then splits x tiles < 1024,
+// so splits x capM x Ncols <= 1024 x 64 x 128 floats.
+size_t nt_partial_floats(int, int, int, int) { return (size_t)1024 * kNtBM * kNtBN; }
+
+hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
+                          float *partials, hipStream_t s) {
   if (capM <= 0 || g.Ncols <= 0) return hipSuccess;
-  // Small node counts leave most of the 256 CUs idle with 64-row tiles.
-  const long long tiles64 = (long long)cdiv(capM, 64) * cdiv(g.Ncols, 64);
-  const bool small = tiles64 < 512;
-  if (precision == 0)
-    return small ? run_nt<0, 32, 64>(dims, capM, g, s) : run_nt<0, 64, 64>(dims, capM, g, s);
-  return small ? run_nt<1, 32, 64>(dims, capM, g, s) : run_nt<1, 64, 64>(dims, capM, g, s);
+  int Ktot = 0;
+  for (int q = 0; q < g.nseg; ++q) Ktot += g.seg[q].k > 0 ? ((g.seg[q].k + 15) / 16) * 16 : 0;
+  // segment tiles are counted per segment; bound the split by the sum
+  int kt = 0;
+  for (int q = 0; q < g.nseg; ++q)
+    if (g.seg[q].k > 0) kt += nt_ktiles(g.seg[q].k, precision);
+  g.splits = nt_splits(capM, g.Ncols, Ktot, precision);
+  if (g.splits > kt / 2) g.splits = kt / 2 > 0 ? kt / 2 : 1;
+  g.P = partials;
+  if (g.splits > 1 && !partials) g.splits = 1;
+  while (g.splits > 1 && (size_t)g.splits * capM * g.Ncols > nt_partial_floats(0, 0, 0, 0))
+    --g.splits;
+  if (precision == 0) return run_nt<0, kNtBM, kNtBN>(dims, capM, g, s);
+  return run_nt<1, kNtBM, kNtBN>(dims, capM, g, s);
 }
 
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
                           hipStream_t s) {
   if (g.M <= 0 || g.Ncols <= 0) return hipSuccess;
-  dim3 grid(cdiv(g.M, 64), cdiv(g.Ncols, 64), g.splits);
+  const int nt = cdiv(g.Ncols, 64);
+  const int grid = cdiv(g.M, 64) * nt * g.splits;
   if (precision == 0)
-    k_gemm_tn<0, 64, 64><<<grid, 256, 0, s>>>(dims, g);
+    k_gemm_tn<0, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
   else
-    k_gemm_tn<1, 64, 64><<<grid, 256, 0, s>>>(dims, g);
+    k_gemm_tn<1, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s) {
   const long long total = (long long)r.M * r.Ncols;
   if (total <= 0) return hipSuccess;
-  k_reduce_map<<<cdiv(total, 256), 256, 0, s>>>(r);
+  k_reduce_map<<<cdiv(4 * total, 256), 256, 0, s>>>(r);
   return hipGetLastError();
 }
 

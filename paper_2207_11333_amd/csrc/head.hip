@@ -116,33 +116,39 @@ k_head_bwd_graph(const Dims *__restrict__ dims, int H, const int *__restrict__ g
 }
 
 // Head weight gradients, each a fixed-order sum over the graphs.
-// Output layout (packed): dW1 [H, H], db1 [H], dw2 [H], db2 [1].
+// Output layout (packed): dW1 [H, H], db1 [H], dw2 [H], db2 [1].  A
+// workgroup owns 32 outputs; its 8 thread groups sum interleaved graphs and
+// the 8 partial sums are added in a fixed order.
+constexpr int kHeadOut = 32, kHeadParts = 8;
+
 __global__ void __launch_bounds__(256)
 k_head_bwd_weights(const Dims *__restrict__ dims, int H, const float *__restrict__ g,
                    const float *__restrict__ q, const float *__restrict__ dy,
                    const float *__restrict__ dq, float *__restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float red[kHeadParts][kHeadOut];
+  const int o = threadIdx.x % kHeadOut, p = threadIdx.x / kHeadOut;
+  const int t = blockIdx.x * kHeadOut + o;
   const int B = dims->B;
-  const int n1 = H * H;
+  const int n1 = H * H, total = n1 + 2 * H + 1;
+  float s = 0.f;
   if (t < n1) {
     const int c = t / H, k = t % H;
-    float s = 0.f;
-    for (int b = 0; b < B; ++b) s += dq[(size_t)b * H + c] * g[(size_t)b * H + k];
-    out[t] = s;
+    for (int b = p; b < B; b += kHeadParts) s += dq[(size_t)b * H + c] * g[(size_t)b * H + k];
   } else if (t < n1 + H) {
     const int c = t - n1;
-    float s = 0.f;
-    for (int b = 0; b < B; ++b) s += dq[(size_t)b * H + c];
-    out[t] = s;
+    for (int b = p; b < B; b += kHeadParts) s += dq[(size_t)b * H + c];
   } else if (t < n1 + 2 * H) {
     const int c = t - n1 - H;
-    float s = 0.f;
-    for (int b = 0; b < B; ++b) s += dy[b] * q[(size_t)b * H + c];
-    out[t] = s;
-  } else if (t == n1 + 2 * H) {
-    float s = 0.f;
-    for (int b = 0; b < B; ++b) s += dy[b];
-    out[t] = s;
+    for (int b = p; b < B; b += kHeadParts) s += dy[b] * q[(size_t)b * H + c];
+  } else if (t < total) {
+    for (int b = p; b < B; b += kHeadParts) s += dy[b];
+  }
+  red[p][o] = s;
+  __syncthreads();
+  if (p == 0 && t < total) {
+    float acc = red[0][o];
+    for (int j = 1; j < kHeadParts; ++j) acc += red[j][o];
+    out[t] = acc;
   }
 }
 
@@ -173,7 +179,7 @@ hipError_t launch_head_backward(const Dims *dims, int capB, int H, const int *gr
   k_head_bwd_graph<<<capB, kHeadThreads, 0, s>>>(dims, H, graph_ptr, W1, w2, q, pred,
                                                  target, dpred, dy, dq, dh);
   const int n = H * H + 2 * H + 1;
-  k_head_bwd_weights<<<cdiv(n, 256), 256, 0, s>>>(dims, H, g, q, dy, dq, dw_head);
+  k_head_bwd_weights<<<cdiv(n, kHeadOut), 256, 0, s>>>(dims, H, g, q, dy, dq, dw_head);
   return hipGetLastError();
 }
 

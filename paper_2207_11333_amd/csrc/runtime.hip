@@ -57,8 +57,8 @@ int tn_splits(int M, int Ncols) {
   return s;
 }
 
-void free_work(hgnn_ctx *c) {
-  Work &w = c->w;
+void free_work(Exec &ex) {
+  Work &w = ex.w;
   void **ptrs[] = {(void **)&w.csr.rowptr, (void **)&w.csr.csr_src, (void **)&w.csr.csr_eid,
                    (void **)&w.csr.deg, (void **)&w.csr.srcptr, (void **)&w.csr.t2csr,
                    (void **)&w.csr.node_graph, (void **)&w.csr.cnt_in,
@@ -67,7 +67,7 @@ void free_work(hgnn_ctx *c) {
                    (void **)&w.csr.sm, (void **)&w.xpad, (void **)&w.g, (void **)&w.q,
                    (void **)&w.ypred, (void **)&w.dy, (void **)&w.dq, (void **)&w.du,
                    (void **)&w.dA, (void **)&w.dm, (void **)&w.Dio, (void **)&w.De,
-                   (void **)&w.dh0, (void **)&w.dh1, (void **)&w.colpart};
+                   (void **)&w.dh0, (void **)&w.dh1, (void **)&w.colpart, (void **)&w.ntpart};
   for (void **p : ptrs) dfree(*p);
   for (auto &p : w.hbuf) dfree(reinterpret_cast<void *&>(p));
   for (auto &p : w.PQ) dfree(reinterpret_cast<void *&>(p));
@@ -80,63 +80,74 @@ void free_work(hgnn_ctx *c) {
   w.capB = w.capN = w.capE = 0;
 }
 
-int ensure_work(hgnn_ctx *c, int B, int N, int E) {
-  Work &w = c->w;
+// Every capacity-sized buffer of an Exec, with its element count: the one
+// table used both to allocate and to price a batch for HBM admission.
+template <typename F>
+static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int capE,
+                            bool inference, F &&f) {
+  const int H = c->H, L = c->L, Fe = c->Fe > 0 ? c->Fe : 1;
+  const int nstore = (c->recompute || inference) ? 1 : L;
+  const int nh = inference ? 2 : L;
+  bool ok = true;
+  ok = ok && f(w.csr.rowptr, (size_t)capN + 1) && f(w.csr.srcptr, (size_t)capN + 1);
+  ok = ok && f(w.csr.csr_src, (size_t)capE) && f(w.csr.csr_eid, (size_t)capE) &&
+       f(w.csr.t2csr, (size_t)capE) && f(w.csr.tmp_out, (size_t)capE) &&
+       f(w.csr.csr_pos, (size_t)capE);
+  ok = ok && f(w.csr.deg, (size_t)capN) && f(w.csr.node_graph, (size_t)capN) &&
+       f(w.csr.cnt_in, (size_t)capN) && f(w.csr.cnt_out, (size_t)capN);
+  ok = ok && f(w.csr.csr_e, (size_t)capE * Fe) && f(w.csr.sp, (size_t)capN) &&
+       f(w.csr.sm, (size_t)capN) && f(w.xpad, (size_t)capN * c->F0p);
+  if (w.hbuf.size() != (size_t)nh) w.hbuf.assign(nh, nullptr);
+  for (int l = 0; l < nh && ok; ++l) ok = f(w.hbuf[l], (size_t)capN * H);
+  if (w.PQ.size() != (size_t)nstore) {
+    w.PQ.assign(nstore, nullptr);
+    w.A.assign(nstore, nullptr);
+    w.args.assign(nstore, nullptr);
+  }
+  for (int l = 0; l < nstore && ok; ++l)
+    ok = f(w.PQ[l], (size_t)capN * 2 * H) && f(w.A[l], (size_t)capN * 4 * H) &&
+         f(w.args[l], (size_t)capN * 2 * H);
+  ok = ok && f(w.g, (size_t)capB * H) && f(w.q, (size_t)capB * H) && f(w.ypred, (size_t)capB);
+  {
+    const size_t np = nt_partial_floats(capN, H, 12 * H, c->prec);
+    ok = ok && f(w.ntpart, np);
+  }
+  if (!inference) {
+    ok = ok && f(w.dq, (size_t)capB * H) && f(w.dy, (size_t)capB);
+    ok = ok && f(w.du, (size_t)capN * H) && f(w.dA, (size_t)capN * 4 * H) &&
+         f(w.dm, (size_t)capE * H) && f(w.Dio, (size_t)capN * 2 * H) &&
+         f(w.De, (size_t)capN * H * Fe) && f(w.dh0, (size_t)capN * H) &&
+         f(w.dh1, (size_t)capN * H) && f(w.colpart, (size_t)kColSplits * (2 + Fe) * H);
+  }
+  return ok;
+}
+
+size_t work_bytes(const hgnn_ctx *c, int B, int N, int E, bool inference_only) {
+  Work tmp;
+  size_t bytes = 0;
+  for_each_buffer(c, tmp, B, N, E, inference_only, [&](auto &p, size_t n) {
+    const size_t b = n * sizeof(*p);
+    bytes += (b < 256 ? 256 : (b + 255) / 256 * 256);
+    return true;
+  });
+  return bytes;
+}
+
+int ensure_work(hgnn_ctx *c, Exec &ex, int B, int N, int E) {
+  Work &w = ex.w;
   if (B <= w.capB && N <= w.capN && E <= w.capE) return HGNN_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
-  free_work(c);
   const int capB = B > w.capB ? B : w.capB;
-  const int capN = N, capE = E;
-  const int H = c->H, L = c->L, Fe = c->Fe;
-  const int nstore = c->recompute ? 1 : L;
-#define HGNN_ALLOC(p, n)                                                                \
-  do {                                                                                 \
-    hipError_t e_ = dalloc(p, (size_t)(n));                                            \
-    if (e_ != hipSuccess) {                                                            \
-      free_work(c);                                                                    \
-      return fail(HGNN_ENOMEM, std::string("hipMalloc failed for ") + #p);             \
-    }                                                                                  \
-  } while (0)
-  HGNN_ALLOC(w.csr.rowptr, capN + 1);
-  HGNN_ALLOC(w.csr.srcptr, capN + 1);
-  HGNN_ALLOC(w.csr.csr_src, capE);
-  HGNN_ALLOC(w.csr.csr_eid, capE);
-  HGNN_ALLOC(w.csr.t2csr, capE);
-  HGNN_ALLOC(w.csr.tmp_out, capE);
-  HGNN_ALLOC(w.csr.csr_pos, capE);
-  HGNN_ALLOC(w.csr.deg, capN);
-  HGNN_ALLOC(w.csr.node_graph, capN);
-  HGNN_ALLOC(w.csr.cnt_in, capN);
-  HGNN_ALLOC(w.csr.cnt_out, capN);
-  HGNN_ALLOC(w.csr.csr_e, (size_t)capE * (Fe > 0 ? Fe : 1));
-  HGNN_ALLOC(w.csr.sp, capN);
-  HGNN_ALLOC(w.csr.sm, capN);
-  HGNN_ALLOC(w.xpad, (size_t)capN * c->F0p);
-  w.hbuf.assign(L, nullptr);
-  for (int l = 0; l < L; ++l) HGNN_ALLOC(w.hbuf[l], (size_t)capN * H);
-  w.PQ.assign(nstore, nullptr);
-  w.A.assign(nstore, nullptr);
-  w.args.assign(nstore, nullptr);
-  for (int l = 0; l < nstore; ++l) {
-    HGNN_ALLOC(w.PQ[l], (size_t)capN * 2 * H);
-    HGNN_ALLOC(w.A[l], (size_t)capN * 4 * H);
-    HGNN_ALLOC(w.args[l], (size_t)capN * 2 * H);
+  const int capN = N > w.capN ? N : w.capN;
+  const int capE = E > w.capE ? E : w.capE;
+  free_work(ex);
+  const bool ok = for_each_buffer(c, w, capB, capN, capE, ex.inference_only,
+                                  [&](auto &p, size_t n) { return dalloc(p, n) == hipSuccess; });
+  if (!ok) {
+    free_work(ex);
+    return fail(HGNN_ENOMEM, "hipMalloc failed for the batch workspace");
   }
-  HGNN_ALLOC(w.g, (size_t)capB * H);
-  HGNN_ALLOC(w.q, (size_t)capB * H);
-  HGNN_ALLOC(w.dq, (size_t)capB * H);
-  HGNN_ALLOC(w.ypred, capB);
-  HGNN_ALLOC(w.dy, capB);
-  HGNN_ALLOC(w.du, (size_t)capN * H);
-  HGNN_ALLOC(w.dA, (size_t)capN * 4 * H);
-  HGNN_ALLOC(w.dm, (size_t)capE * H);
-  HGNN_ALLOC(w.Dio, (size_t)capN * 2 * H);
-  HGNN_ALLOC(w.De, (size_t)capN * H * (Fe > 0 ? Fe : 1));
-  HGNN_ALLOC(w.dh0, (size_t)capN * H);
-  HGNN_ALLOC(w.dh1, (size_t)capN * H);
-  HGNN_ALLOC(w.colpart, (size_t)kColSplits * (2 + (Fe > 0 ? Fe : 1)) * H);
-#undef HGNN_ALLOC
   w.capB = capB;
   w.capN = capN;
   w.capE = capE;
@@ -204,24 +215,24 @@ std::string decode_err(int bits) {
   return m;
 }
 
-int prepare(hgnn_ctx *c, const hgnn_batch *b, int flags, hipStream_t s) {
+int prepare(hgnn_ctx *c, Exec &ex, const hgnn_batch *b, int flags, hipStream_t s) {
   int rc = check_batch_host(c, b);
   if (rc) return rc;
-  rc = ensure_work(c, b->num_graphs, b->num_nodes, b->num_edges);
+  rc = ensure_work(c, ex, b->num_graphs, b->num_nodes, b->num_edges);
   if (rc) return rc;
-  Work &w = c->w;
-  hipError_t e = launch_set_dims(c->dims, b->num_graphs, b->num_nodes, b->num_edges, s);
+  Work &w = ex.w;
+  hipError_t e = launch_set_dims(ex.dims, b->num_graphs, b->num_nodes, b->num_edges, s);
   if (e == hipSuccess)
-    e = launch_csr_build(c->dims, b->num_graphs, b->num_nodes, b->num_edges, b->graph_ptr,
+    e = launch_csr_build(ex.dims, b->num_graphs, b->num_nodes, b->num_edges, b->graph_ptr,
                          b->edge_index, b->edge_attr, c->Fe, c->maxd, c->table, w.csr, s);
   if (e != hipSuccess) return hip_fail(c, e, "csr build");
-  c->B = b->num_graphs;
-  c->N = b->num_nodes;
-  c->E = b->num_edges;
-  c->graph_ptr = b->graph_ptr;
-  c->x = b->x;
-  c->target = b->y;
-  c->prepared = true;
+  ex.B = b->num_graphs;
+  ex.N = b->num_nodes;
+  ex.E = b->num_edges;
+  ex.graph_ptr = b->graph_ptr;
+  ex.xin = b->x;
+  ex.target = b->y;
+  ex.prepared = true;
   w.stored_layer = -1;
   if (flags & HGNN_VALIDATE) {
     int bits = 0;
@@ -234,12 +245,12 @@ int prepare(hgnn_ctx *c, const hgnn_batch *b, int flags, hipStream_t s) {
 }
 
 // Layer l: S1 (P|Q GEMM), S2 (aggregation) into the given buffers.
-static int message_and_aggregate(hgnn_ctx *c, int l, const float *wl, const float *hin,
+static int message_and_aggregate(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *hin,
                                  int ldh, float *PQ, float *A, uint8_t *args,
                                  hipStream_t s) {
   const LayerDesc &d = c->ld[l];
   const int H = c->H;
-  Work &w = c->w;
+  Work &w = ex.w;
   GemmNT g{};
   g.nseg = 1;
   g.seg[0] = SegA{hin, nullptr, ldh, d.Fp, 0};
@@ -252,15 +263,15 @@ static int message_and_aggregate(hgnn_ctx *c, int l, const float *wl, const floa
   g.M_fixed = -1;
   hipError_t e;
   {
-    TimedLaunch tl(c, SITE_MESSAGE_GEMM, s);
-    e = launch_gemm_nt(c->dims, c->N, g, c->prec, s);
+    TimedLaunch tl(c, ex, SITE_MESSAGE_GEMM, s);
+    e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "message GEMM");
   const float *Wm = wl + (d.oWm - d.off);
   const float *bm = wl + (d.obm - d.off);
   {
-    TimedLaunch tl(c, SITE_AGGREGATE, s);
-    e = launch_aggregate(c->dims, c->N, H, c->Fe, PQ, w.csr.rowptr, w.csr.csr_src,
+    TimedLaunch tl(c, ex, SITE_AGGREGATE, s);
+    e = launch_aggregate(ex.dims, ex.N, H, c->Fe, PQ, w.csr.rowptr, w.csr.csr_src,
                          w.csr.csr_e, Wm + 2 * d.F, 2 * d.F + c->Fe, bm, A, args,
                          (float)c->cfg.std_eps, s);
   }
@@ -268,29 +279,30 @@ static int message_and_aggregate(hgnn_ctx *c, int l, const float *wl, const floa
   return HGNN_OK;
 }
 
-static const float *layer_input(hgnn_ctx *c, int l, const float *h_in, int *ldh,
+static const float *layer_input(hgnn_ctx *c, Exec &ex, int l, const float *h_in, int *ldh,
                                 hipStream_t s, int *rc) {
   *rc = HGNN_OK;
   if (l == 0) {
-    hipError_t e = launch_pad_copy(c->dims, c->N, h_in, c->F0, c->w.xpad, c->F0p, s);
+    hipError_t e = launch_pad_copy(ex.dims, ex.N, h_in, c->F0, ex.w.xpad, c->F0p, s);
     if (e != hipSuccess) *rc = hip_fail(c, e, "pad input");
     *ldh = c->F0p;
-    return c->w.xpad;
+    return ex.w.xpad;
   }
   *ldh = c->H;
   return h_in;
 }
 
-int layer_forward(hgnn_ctx *c, int l, const float *wl, const float *h_in, float *h_out,
+int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_in, float *h_out,
                   hipStream_t s) {
   const LayerDesc &d = c->ld[l];
   const int H = c->H;
-  Work &w = c->w;
+  Work &w = ex.w;
   int rc, ldh;
-  const float *hin = layer_input(c, l, h_in, &ldh, s, &rc);
+  const float *hin = layer_input(c, ex, l, h_in, &ldh, s, &rc);
   if (rc) return rc;
-  const int slot = c->recompute ? 0 : l;
-  rc = message_and_aggregate(c, l, wl, hin, ldh, w.PQ[slot], w.A[slot], w.args[slot], s);
+  const int slot = (c->recompute || ex.inference_only) ? 0 : l;
+  rc = message_and_aggregate(c, ex, l, wl, hin, ldh, w.PQ[slot], w.A[slot],
+                             ex.inference_only ? nullptr : w.args[slot], s);
   if (rc) return rc;
   w.stored_layer = l;
   float *A = w.A[slot];
@@ -311,25 +323,27 @@ int layer_forward(hgnn_ctx *c, int l, const float *wl, const float *h_in, float 
   g.M_fixed = -1;
   hipError_t e;
   {
-    TimedLaunch tl(c, SITE_UPDATE_GEMM, s);
-    e = launch_gemm_nt(c->dims, c->N, g, c->prec, s);
+    TimedLaunch tl(c, ex, SITE_UPDATE_GEMM, s);
+    e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "update GEMM");
   return HGNN_OK;
 }
 
-int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
+// dh_out_masked: dh_out already carries this layer's ReLU adjoint (it is du).
+// mask_dh_in: fold the previous layer's ReLU adjoint (h_in > 0) into dh_in.
+int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_in,
                    const float *h_out, const float *dh_out, float *dh_in, float *dwl,
-                   hipStream_t s) {
+                   hipStream_t s, bool dh_out_masked = false, bool mask_dh_in = false) {
   const LayerDesc &d = c->ld[l];
   const int H = c->H, Fe = c->Fe;
-  Work &w = c->w;
+  Work &w = ex.w;
   int rc, ldh;
-  const float *hin = layer_input(c, l, h_in, &ldh, s, &rc);
+  const float *hin = layer_input(c, ex, l, h_in, &ldh, s, &rc);
   if (rc) return rc;
   const int slot = c->recompute ? 0 : l;
   if (c->recompute && w.stored_layer != l) { // S10: re-run S1/S2 for this layer
-    rc = message_and_aggregate(c, l, wl, hin, ldh, w.PQ[0], w.A[0], w.args[0], s);
+    rc = message_and_aggregate(c, ex, l, wl, hin, ldh, w.PQ[0], w.A[0], w.args[0], s);
     if (rc) return rc;
     w.stored_layer = l;
   }
@@ -339,12 +353,17 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
   const float *bm = wl + (d.obm - d.off);
   float *dWm = dwl + (d.oWm - d.off), *dbm = dwl + (d.obm - d.off);
   float *dWp = dwl + (d.oWp - d.off), *dbp = dwl + (d.obp - d.off);
-  hipError_t e = launch_relu_mask(c->dims, c->N, H, dh_out, h_out, w.du, s);
-  if (e != hipSuccess) return hip_fail(c, e, "relu mask");
+  hipError_t e = hipSuccess;
+  const float *du = dh_out;
+  if (!dh_out_masked) {
+    e = launch_relu_mask(ex.dims, ex.N, H, dh_out, h_out, w.du, s);
+    if (e != hipSuccess) return hip_fail(c, e, "relu mask");
+    du = w.du;
+  }
   // S6: dW^p = du^T [h || A || s+ A || s- A]
   {
     GemmTN t{};
-    t.X = w.du;
+    t.X = du;
     t.ldx = H;
     t.M = H;
     t.nseg = 4;
@@ -356,8 +375,8 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
     t.P = c->part;
     t.splits = d.split_p;
     {
-      TimedLaunch tl(c, SITE_UPDATE_WGRAD, s);
-      e = launch_gemm_tn(c->dims, t, c->prec, s);
+      TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, s);
+      e = launch_gemm_tn(ex.dims, t, c->prec, s);
     }
     if (e == hipSuccess) {
       ReduceMap r{c->part, d.split_p, H, d.Fp + 12 * H, dWp, d.F + 12 * H, H, 0, d.F, d.Fp};
@@ -369,9 +388,9 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
   {
     GemmNT g{};
     g.nseg = 3;
-    g.seg[0] = SegA{w.du, nullptr, H, H, 0};
-    g.seg[1] = SegA{w.du, w.csr.sp, H, H, H};
-    g.seg[2] = SegA{w.du, w.csr.sm, H, H, 2 * H};
+    g.seg[0] = SegA{du, nullptr, H, H, 0};
+    g.seg[1] = SegA{du, w.csr.sp, H, H, H};
+    g.seg[2] = SegA{du, w.csr.sm, H, H, 2 * H};
     g.B = c->WpTA[l];
     g.B_lo = c->prec ? c->WpTA_lo[l] : nullptr;
     g.ldb = 3 * H;
@@ -380,20 +399,20 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
     g.ldc = 4 * H;
     g.M_fixed = -1;
     {
-      TimedLaunch tl(c, SITE_AGG_INPUT_GEMM, s);
-      e = launch_gemm_nt(c->dims, c->N, g, c->prec, s);
+      TimedLaunch tl(c, ex, SITE_AGG_INPUT_GEMM, s);
+      e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
     }
     if (e != hipSuccess) return hip_fail(c, e, "aggregate-input gradient GEMM");
   }
   // S7: per-edge dm, D_in, De; then D_out through the transpose
   {
-    TimedLaunch tl(c, SITE_AGGREGATE_BWD, s);
-    e = launch_aggregate_bwd(c->dims, c->N, H, Fe, PQ, w.csr.rowptr, w.csr.csr_src,
+    TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s);
+    e = launch_aggregate_bwd(ex.dims, ex.N, H, Fe, PQ, w.csr.rowptr, w.csr.csr_src,
                              w.csr.csr_e, Wm + 2 * d.F, 2 * d.F + Fe, bm, A, args, w.dA,
                              w.dm, w.Dio, w.De, s);
   }
   if (e == hipSuccess)
-    e = launch_transpose_sum(c->dims, c->N, H, w.csr.srcptr, w.csr.t2csr, w.dm, w.Dio, s);
+    e = launch_transpose_sum(ex.dims, ex.N, H, w.csr.srcptr, w.csr.t2csr, w.dm, w.Dio, s);
   if (e != hipSuccess) return hip_fail(c, e, "aggregation adjoint");
   // S8: [dW_dst | dW_src] = [D_in | D_out]^T h
   {
@@ -406,7 +425,7 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
     t.Ncols = d.Fp;
     t.P = c->part;
     t.splits = d.split_m;
-    e = launch_gemm_tn(c->dims, t, c->prec, s);
+    e = launch_gemm_tn(ex.dims, t, c->prec, s);
     if (e == hipSuccess) {
       ReduceMap r{c->part, d.split_m, 2 * H, d.Fp, dWm, 2 * d.F + Fe, H, d.F, d.F, d.Fp};
       e = launch_reduce_map(r, s);
@@ -417,7 +436,7 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
   {
     ColSum cs{};
     ColSumMap mp{};
-    cs.src[0] = w.du; cs.ld[0] = H; cs.ncols[0] = H; cs.out[0] = dbp;
+    cs.src[0] = du; cs.ld[0] = H; cs.ncols[0] = H; cs.out[0] = dbp;
     mp.rs[0] = H; mp.ostride[0] = 1;
     cs.src[1] = w.Dio; cs.ld[1] = 2 * H; cs.ncols[1] = H; cs.out[1] = dbm;
     mp.rs[1] = H; mp.ostride[1] = 1;
@@ -427,14 +446,14 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
       mp.rs[2] = H; mp.ostride[2] = 2 * d.F + Fe;
       cs.n = 3;
     }
-    e = launch_colsum(c->dims, cs, mp, w.colpart, kColSplits, s);
+    e = launch_colsum(ex.dims, cs, mp, w.colpart, kColSplits, s);
     if (e != hipSuccess) return hip_fail(c, e, "bias gradients");
   }
   // S6 + S8 input gradient: dh = [du || D_in || D_out] [W_h; W_dst; W_src]
   if (dh_in) {
     GemmNT g{};
     g.nseg = 3;
-    g.seg[0] = SegA{w.du, nullptr, H, H, 0};
+    g.seg[0] = SegA{du, nullptr, H, H, 0};
     g.seg[1] = SegA{w.Dio, nullptr, 2 * H, H, H};
     g.seg[2] = SegA{w.Dio + H, nullptr, 2 * H, H, 2 * H};
     g.B = c->WhdsT[l];
@@ -444,32 +463,33 @@ int layer_backward(hgnn_ctx *c, int l, const float *wl, const float *h_in,
     g.C = dh_in;
     g.ldc = d.F;
     g.M_fixed = -1;
+    g.mask = (mask_dh_in && l > 0) ? h_in : nullptr;
     {
-      TimedLaunch tl(c, SITE_INPUT_GEMM, s);
-      e = launch_gemm_nt(c->dims, c->N, g, c->prec, s);
+      TimedLaunch tl(c, ex, SITE_INPUT_GEMM, s);
+      e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
     }
     if (e != hipSuccess) return hip_fail(c, e, "input gradient GEMM");
   }
   return HGNN_OK;
 }
 
-int head_forward(hgnn_ctx *c, const float *wh, const float *h, const float *target,
+int head_forward(hgnn_ctx *c, Exec &ex, const float *wh, const float *h, const float *target,
                  float *pred, float *loss, hipStream_t s) {
   const int H = c->H;
-  Work &w = c->w;
-  hipError_t e = launch_head_forward(c->dims, c->B, H, c->graph_ptr, h, wh, wh + H * H,
+  Work &w = ex.w;
+  hipError_t e = launch_head_forward(ex.dims, ex.B, H, ex.graph_ptr, h, wh, wh + H * H,
                                      wh + H * H + H, wh + H * H + 2 * H, w.g, w.q, w.ypred,
                                      pred, s);
-  if (e == hipSuccess && loss && target) e = launch_loss(c->dims, w.ypred, target, loss, s);
+  if (e == hipSuccess && loss && target) e = launch_loss(ex.dims, w.ypred, target, loss, s);
   if (e != hipSuccess) return hip_fail(c, e, "head forward");
   return HGNN_OK;
 }
 
-int head_backward(hgnn_ctx *c, const float *wh, const float *target, const float *dpred,
+int head_backward(hgnn_ctx *c, Exec &ex, const float *wh, const float *target, const float *dpred,
                   float *dh, float *dwh, hipStream_t s) {
   const int H = c->H;
-  Work &w = c->w;
-  hipError_t e = launch_head_backward(c->dims, c->B, H, c->graph_ptr, wh, wh + H * H + H,
+  Work &w = ex.w;
+  hipError_t e = launch_head_backward(ex.dims, ex.B, H, ex.graph_ptr, wh, wh + H * H + H,
                                       w.g, w.q, w.ypred, target, dpred, w.dy, w.dq, dh, dwh,
                                       s);
   if (e != hipSuccess) return hip_fail(c, e, "head backward");
@@ -576,8 +596,8 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
   HGNN_CALLOC(c->step_dev, 1);
   HGNN_CALLOC(c->corr, 2);
   HGNN_CALLOC(c->table, 2 * (c->maxd + 1));
-  HGNN_CALLOC(c->dims, 1);
-  HGNN_CALLOC(c->w.csr.err, 1);
+  HGNN_CALLOC(c->ex.dims, 1);
+  HGNN_CALLOC(c->ex.w.csr.err, 1);
   HGNN_CALLOC(c->part, part_max);
   const size_t esz = c->prec ? 2 : 4;
   for (int l = 0; l < c->L; ++l) {
@@ -611,7 +631,7 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
   if (e == hipSuccess) e = hipMemset(c->adam_m, 0, c->P * sizeof(float));
   if (e == hipSuccess) e = hipMemset(c->adam_v, 0, c->P * sizeof(float));
   if (e == hipSuccess) e = hipMemset(c->step_dev, 0, sizeof(long long));
-  if (e == hipSuccess) e = hipMemset(c->w.csr.err, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(c->ex.w.csr.err, 0, sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     hgnn_destroy(c);
@@ -630,12 +650,12 @@ void hgnn_destroy(hgnn_ctx *c) {
   (void)hipSetDevice(c->dev);
   serve_shutdown(c);
   (void)hipDeviceSynchronize();
-  free_work(c);
+  free_work(c->ex);
   for (hipEvent_t ev : c->timer.ev) (void)hipEventDestroy(ev);
   c->timer.ev.clear();
   void **ptrs[] = {(void **)&c->params, (void **)&c->grads, (void **)&c->adam_m,
                    (void **)&c->adam_v, (void **)&c->step_dev, (void **)&c->corr,
-                   (void **)&c->table, (void **)&c->dims, (void **)&c->w.csr.err,
+                   (void **)&c->table, (void **)&c->ex.dims, (void **)&c->ex.w.csr.err,
                    (void **)&c->part};
   for (void **p : ptrs) dfree(*p);
   for (auto *v : {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT, &c->Wds_lo, &c->Wpp_lo, &c->WpTA_lo,
@@ -679,7 +699,7 @@ int hgnn_check(hgnn_ctx *c, void *stream) {
   HGNN_GUARD(c);
   int bits = 0;
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-  if (e == hipSuccess) e = hipMemcpy(&bits, c->w.csr.err, sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&bits, c->ex.w.csr.err, sizeof(int), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(c, e, "check");
   if (bits) return fail(HGNN_EINVAL, decode_err(bits));
   return HGNN_OK;
@@ -691,33 +711,35 @@ int hgnn_forward(hgnn_ctx *c, const hgnn_batch *b, float *pred, float *loss, int
   if (!pred) return fail(HGNN_EINVAL, "pred_dev is NULL");
   if (loss && !b->y) return fail(HGNN_EINVAL, "loss requested without targets");
   hipStream_t s = (hipStream_t)stream;
-  int rc = prepare(c, b, flags, s);
+  Exec &ex = c->ex;
+  int rc = prepare(c, ex, b, flags, s);
   if (rc) return rc;
   if (!c->staged_from_params && (rc = stage_all(c, s))) return rc;
   const float *h = b->x;
   for (int l = 0; l < c->L; ++l) {
-    rc = layer_forward(c, l, c->params + c->ld[l].off, h, c->w.hbuf[l], s);
+    rc = layer_forward(c, ex, l, c->params + c->ld[l].off, h, c->ex.w.hbuf[l], s);
     if (rc) return rc;
-    h = c->w.hbuf[l];
+    h = c->ex.w.hbuf[l];
   }
-  return head_forward(c, c->params + c->off_head, h, b->y, pred, loss, s);
+  return head_forward(c, ex, c->params + c->off_head, h, b->y, pred, loss, s);
 }
 
 int hgnn_backward(hgnn_ctx *c, const float *dpred, void *stream) {
   HGNN_GUARD(c);
-  if (!c->prepared) return fail(HGNN_EINVAL, "no forward to differentiate");
-  if (!dpred && !c->target) return fail(HGNN_EINVAL, "no targets and no dpred");
+  if (!c->ex.prepared) return fail(HGNN_EINVAL, "no forward to differentiate");
+  if (!dpred && !c->ex.target) return fail(HGNN_EINVAL, "no targets and no dpred");
   if (!c->staged_from_params) return fail(HGNN_EINVAL, "weights changed since the forward");
   hipStream_t s = (hipStream_t)stream;
-  Work &w = c->w;
+  Work &w = c->ex.w;
   float *cur = w.dh0, *nxt = w.dh1;
-  int rc = head_backward(c, c->params + c->off_head, c->target, dpred, cur,
+  int rc = head_backward(c, c->ex, c->params + c->off_head, c->ex.target, dpred, cur,
                          c->grads + c->off_head, s);
   if (rc) return rc;
   for (int l = c->L - 1; l >= 0; --l) {
-    const float *h_in = l ? w.hbuf[l - 1] : c->x;
-    rc = layer_backward(c, l, c->params + c->ld[l].off, h_in, w.hbuf[l], cur,
-                        l ? nxt : nullptr, c->grads + c->ld[l].off, s);
+    const float *h_in = l ? w.hbuf[l - 1] : c->ex.xin;
+    rc = layer_backward(c, c->ex, l, c->params + c->ld[l].off, h_in, w.hbuf[l], cur,
+                        l ? nxt : nullptr, c->grads + c->ld[l].off, s,
+                        /*dh_out_masked=*/l < c->L - 1, /*mask_dh_in=*/true);
     if (rc) return rc;
     std::swap(cur, nxt);
   }
@@ -808,51 +830,51 @@ int hgnn_set_state(hgnn_ctx *c, const void *buf, size_t bytes) {
 
 int hgnn_op_prepare(hgnn_ctx *c, const hgnn_batch *b, int32_t flags, void *stream) {
   HGNN_GUARD(c);
-  return prepare(c, b, flags, (hipStream_t)stream);
+  return prepare(c, c->ex, b, flags, (hipStream_t)stream);
 }
 
 int hgnn_op_layer_forward(hgnn_ctx *c, int32_t l, const float *wl, const float *h_in,
                           float *h_out, void *stream) {
   HGNN_GUARD(c);
-  if (!c->prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
   if (l < 0 || l >= c->L) return fail(HGNN_EINVAL, "layer out of range");
   if (!wl || !h_in || !h_out) return fail(HGNN_EINVAL, "NULL buffer");
   hipStream_t s = (hipStream_t)stream;
   int rc = stage_layer_from(c, l, wl, s);
   if (rc) return rc;
-  return layer_forward(c, l, wl, h_in, h_out, s);
+  return layer_forward(c, c->ex, l, wl, h_in, h_out, s);
 }
 
 int hgnn_op_layer_backward(hgnn_ctx *c, int32_t l, const float *wl, const float *h_in,
                            const float *h_out, const float *dh_out, float *dh_in,
                            float *dwl, void *stream) {
   HGNN_GUARD(c);
-  if (!c->prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
   if (l < 0 || l >= c->L) return fail(HGNN_EINVAL, "layer out of range");
   if (!wl || !h_in || !h_out || !dh_out || !dwl) return fail(HGNN_EINVAL, "NULL buffer");
   hipStream_t s = (hipStream_t)stream;
   int rc = stage_layer_from(c, l, wl, s);
   if (rc) return rc;
-  return layer_backward(c, l, wl, h_in, h_out, dh_out, dh_in, dwl, s);
+  return layer_backward(c, c->ex, l, wl, h_in, h_out, dh_out, dh_in, dwl, s);
 }
 
 int hgnn_op_head_forward(hgnn_ctx *c, const float *wh, const float *h, const float *target,
                          float *pred, float *loss, void *stream) {
   HGNN_GUARD(c);
-  if (!c->prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
   if (!wh || !h || !pred) return fail(HGNN_EINVAL, "NULL buffer");
   if (loss && !target) return fail(HGNN_EINVAL, "loss requested without targets");
-  return head_forward(c, wh, h, target, pred, loss, (hipStream_t)stream);
+  return head_forward(c, c->ex, wh, h, target, pred, loss, (hipStream_t)stream);
 }
 
 int hgnn_op_head_backward(hgnn_ctx *c, const float *wh, const float *h, const float *target,
                           const float *dpred, float *dh, float *dwh, void *stream) {
   HGNN_GUARD(c);
   (void)h;
-  if (!c->prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
   if (!wh || !dh || !dwh) return fail(HGNN_EINVAL, "NULL buffer");
   if (!dpred && !target) return fail(HGNN_EINVAL, "need dpred or targets");
-  return head_backward(c, wh, target, dpred, dh, dwh, (hipStream_t)stream);
+  return head_backward(c, c->ex, wh, target, dpred, dh, dwh, (hipStream_t)stream);
 }
 
 int hgnn_timer_start(hgnn_ctx *c, int32_t site, int32_t max_launches) {
@@ -897,10 +919,10 @@ int hgnn_timer_read(hgnn_ctx *c, double *total_ms, int32_t *launches) {
 int hgnn_op_fetch(hgnn_ctx *c, int32_t which, int32_t layer, void *dst, size_t cap,
                   void *stream) {
   HGNN_GUARD(c);
-  if (!c->prepared) return fail(HGNN_EINVAL, "nothing prepared");
+  if (!c->ex.prepared) return fail(HGNN_EINVAL, "nothing prepared");
   if (!dst) return fail(HGNN_EINVAL, "dst is NULL");
-  Work &w = c->w;
-  const int N = c->N, E = c->E, H = c->H, B = c->B;
+  Work &w = c->ex.w;
+  const int N = c->ex.N, E = c->ex.E, H = c->H, B = c->ex.B;
   const void *src = nullptr;
   size_t bytes = 0;
   switch (which) {

@@ -9,7 +9,7 @@
 
 namespace hgnn {
 
-constexpr int kColSplits = 32;
+constexpr int kColSplits = 64;
 
 struct LayerDesc {
   int F, Fp;                       // input width and its padding to 16
@@ -30,6 +30,20 @@ struct Work {
   float *g = nullptr, *q = nullptr, *ypred = nullptr, *dy = nullptr, *dq = nullptr;
   float *du = nullptr, *dA = nullptr, *dm = nullptr, *Dio = nullptr, *De = nullptr;
   float *dh0 = nullptr, *dh1 = nullptr, *colpart = nullptr;
+  float *ntpart = nullptr;               // split-K partials of the NT GEMMs
+};
+
+// Batch-local execution state: device size header, CSR, activations and
+// workspaces of one batch.  The training path owns one; every serving lane
+// owns another, so lanes run concurrently against the shared weights.
+struct Exec {
+  Work w;
+  Dims *dims = nullptr;
+  int B = 0, N = 0, E = 0;
+  const int *graph_ptr = nullptr;
+  const float *xin = nullptr, *target = nullptr;
+  bool prepared = false;
+  bool inference_only = false;  // no backward buffers, two rotating h slots
 };
 
 struct Server;
@@ -68,14 +82,8 @@ struct hgnn_ctx {
   std::vector<void *> Wds, Wpp, WpTA, WhdsT; // GEMM-layout weight copies per layer
   std::vector<void *> Wds_lo, Wpp_lo, WpTA_lo, WhdsT_lo; // BF16 low halves
   bool staged_from_params = false;
-  hgnn::Dims *dims = nullptr;
   float *part = nullptr;
-  hgnn::Work w;
-  // the batch of the last prepare
-  int B = 0, N = 0, E = 0;
-  const int *graph_ptr = nullptr;
-  const float *x = nullptr, *target = nullptr;
-  bool prepared = false;
+  hgnn::Exec ex; // the training path's batch state
   int sticky = 0;
   hgnn::Server *server = nullptr;
   hgnn::SiteTimer timer;
@@ -88,14 +96,26 @@ int hip_fail(hgnn_ctx *c, hipError_t e, const char *what);
 std::string decode_err(int bits);
 void serve_shutdown(hgnn_ctx *c);
 
+// forward-path building blocks shared by training and serving
+int ensure_work(hgnn_ctx *c, Exec &ex, int B, int N, int E);
+void free_work(Exec &ex);
+size_t work_bytes(const hgnn_ctx *c, int B, int N, int E, bool inference_only);
+int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_in,
+                  float *h_out, hipStream_t s);
+int head_forward(hgnn_ctx *c, Exec &ex, const float *wh, const float *h,
+                 const float *target, float *pred, float *loss, hipStream_t s);
+int stage_all(hgnn_ctx *c, hipStream_t s);
+
 // Records an event pair around one launch when the timer watches `site`.
+// Only the training path's launches are timed (serving lanes never are).
 struct TimedLaunch {
   hgnn_ctx *c;
   hipStream_t s;
   bool on;
-  TimedLaunch(hgnn_ctx *c_, int site, hipStream_t s_) : c(c_), s(s_), on(false) {
+  TimedLaunch(hgnn_ctx *c_, const Exec &ex, int site, hipStream_t s_)
+      : c(c_), s(s_), on(false) {
     SiteTimer &t = c->timer;
-    if (t.site == site && t.used + 2 <= (int)t.ev.size()) {
+    if (&ex == &c->ex && t.site == site && t.used + 2 <= (int)t.ev.size()) {
       on = true;
       (void)hipEventRecord(t.ev[t.used], s);
     }

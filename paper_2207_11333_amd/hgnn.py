@@ -56,7 +56,8 @@ class ServeConfig(ctypes.Structure):
 class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
-                ("admission_waits", ctypes.c_int64), ("peak_inflight_bytes", ctypes.c_int64)]
+                ("admission_waits", ctypes.c_int64), ("peak_inflight_bytes", ctypes.c_int64),
+                ("lanes", ctypes.c_int64), ("lane_bytes", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p

@@ -1,0 +1,195 @@
+"""Serving loop (continuous batching) and captured training steps.
+
+A request's predictions must not depend on what it was batched with: each is
+compared alone and in a mix (FP32 model: 1e-5 relative; BF16 model: 2e-2),
+with the oracle checking a sample.  Forced admission pressure (a budget that
+fits a single lane) must leave results unchanged.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2207_11333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _hg():
+    from paper_2207_11333_amd import hgnn
+    return hgnn
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, r):
+    a, r = np.asarray(a, np.float64), np.asarray(r, np.float64)
+    return float(np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-300))
+
+
+def _requests(n, seed, mol_hi=12):
+    rng = np.random.default_rng(seed)
+    return [synth.make_request(rng, 1, mol_hi, 5, 40, 1) for _ in range(n)]
+
+
+def _wait(m, tickets, sizes, timeout=60.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t, b in zip(tickets, sizes):
+            if t in out:
+                continue
+            r = m.serve_poll(t, b)
+            if r is not None:
+                out[t] = r
+        assert time.time() - t0 < timeout, "serving did not complete"
+    return [out[t] for t in tickets]
+
+
+def _model(prec):
+    sw = synth.SERVE_WORKLOAD
+    shape = synth.ModelShape(sw["num_layers"], sw["hidden"], 9, sw["edge_feat"])
+    params = synth.init_params(shape, sw["weight_seed"])
+    m = _hg().Model(sw["num_layers"], sw["hidden"], 9, sw["edge_feat"], 4, prec, 0, sw["delta"])
+    m.set_params(params)
+    return m, params, sw
+
+
+@pytest.mark.parametrize("prec,use_graphs", [(0, 1), (1, 1), (0, 0)])
+def test_alone_equals_mixed(prec, use_graphs):
+    m, params, sw = _model(prec)
+    reqs = _requests(10, 123)
+    say(f"serve prec={prec} graphs={use_graphs}: {len(reqs)} requests, "
+        f"{sum(r.num_graphs for r in reqs)} molecules")
+    m.serve_start(hbm_budget_bytes=4 << 30, max_batch_nodes=4096, max_batch_edges=9216,
+                  max_batch_graphs=256, num_lanes=3, use_graphs=use_graphs)
+    alone = []
+    for r in reqs:
+        t = m.serve_submit(r)
+        alone += _wait(m, [t], [r.num_graphs])
+    tickets = [m.serve_submit(r) for r in reqs]
+    mixed = _wait(m, tickets, [r.num_graphs for r in reqs])
+    st = m.serve_stats()
+    say(f"  stats {st}")
+    tol = 1e-5 if prec == 0 else 2e-2
+    worst = max(rel(a, b) for a, b in zip(mixed, alone))
+    say(f"  alone vs mixed worst rel {worst:.2e}")
+    assert worst <= tol
+    assert st["completed"] == 2 * len(reqs)
+    if use_graphs:
+        assert st["graph_replays"] > 0
+    for i in (0, 5):
+        rec = oracle.forward(params, reqs[i], sw["num_layers"], sw["hidden"], sw["delta"],
+                             with_loss=False)
+        r = rel(mixed[i], rec.y)
+        say(f"  request {i} vs oracle rel {r:.2e}")
+        assert r <= tol
+    m.serve_stop()
+    m.close()
+
+
+def test_admission_pressure_keeps_results():
+    m, params, sw = _model(0)
+    reqs = _requests(16, 7, mol_hi=20)
+    caps = dict(max_batch_nodes=2048, max_batch_edges=4608, max_batch_graphs=128)
+    m.serve_start(hbm_budget_bytes=1 << 30, num_lanes=1, **caps)
+    lane = m.serve_stats()["lane_bytes"]
+    m.serve_stop()
+    # a budget of 1.5 lanes: one lane in flight, the rest of the requests wait
+    budget = int(1.5 * lane)
+    m.serve_start(hbm_budget_bytes=budget, num_lanes=8, use_graphs=1, **caps)
+    assert m.serve_stats()["lanes"] == 1
+    tickets = [m.serve_submit(r) for r in reqs]
+    got = _wait(m, tickets, [r.num_graphs for r in reqs])
+    st = m.serve_stats()
+    say(f"pressure stats {st}")
+    assert st["batches"] > 1 and st["admission_waits"] > 0
+    assert st["peak_inflight_bytes"] <= budget
+    m.serve_stop()
+    m2, _, _ = _model(0)
+    m2.serve_start(hbm_budget_bytes=4 << 30, max_batch_nodes=2048, max_batch_edges=4608,
+                   max_batch_graphs=128, num_lanes=2, use_graphs=0)
+    for r, g in zip(reqs, got):
+        t = m2.serve_submit(r)
+        a = _wait(m2, [t], [r.num_graphs])[0]
+        assert rel(g, a) <= 1e-5
+    m2.serve_stop()
+    m.close()
+    m2.close()
+
+
+def test_serve_errors():
+    hg = _hg()
+    m, _, _ = _model(0)
+    with pytest.raises(hg.HgnnError):
+        m.serve_poll(1, 1)                       # not started
+    with pytest.raises(hg.HgnnError):
+        m.serve_start(hbm_budget_bytes=1 << 10)  # budget below one lane
+    m.serve_start(hbm_budget_bytes=1 << 30, max_batch_nodes=1024, max_batch_edges=2304,
+                  max_batch_graphs=64, num_lanes=1, queue_capacity=2)
+    with pytest.raises(hg.HgnnError) as e:
+        m.serve_poll(987654, 1)
+    assert e.value.code == hg.EINVAL
+    big = synth.make_batch(1, 64, 30, 40, 1)     # > 1024 nodes
+    assert m.serve_submit(big) == -1             # EAGAIN
+    bad = synth.make_batch(2, 2, 5, 6, 1)
+    bad.edge_index[0, 0] = bad.num_nodes + 3
+    with pytest.raises(hg.HgnnError) as e:
+        m.serve_submit(bad)
+    assert e.value.code == hg.EINVAL
+    ok = synth.make_batch(3, 2, 5, 6, 1)
+    t = m.serve_submit(ok)
+    _wait(m, [t], [ok.num_graphs])
+    m.serve_stop()
+    m.close()
+
+
+def test_training_step_graph_replay_matches_eager():
+    hg = _hg()
+    w = synth.WORKLOADS["c0_small_fp32"]
+    b, params = w.batch(), w.params()
+    db = hg.DeviceBatch.from_host(b)
+
+    def mk():
+        m = hg.Model(w.num_layers, w.hidden, 9, w.edge_feat, 4, 0, 0, w.delta)
+        m.set_params(params)
+        return m
+
+    pred_a = torch.empty(b.num_graphs, device="cuda")
+    pred_b = torch.empty(b.num_graphs, device="cuda")
+    loss_b = torch.empty(1, device="cuda")
+    ma, mb = mk(), mk()
+
+    def step(m, pred, loss=None):
+        m.forward(db, pred, loss)
+        m.backward()
+        m.adam_step()
+
+    step(ma, pred_a)
+    step(mb, pred_b, loss_b)                  # warm: sizes the workspaces
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            step(mb, pred_b, loss_b)
+    torch.cuda.synchronize()
+    for k in range(3):
+        step(ma, pred_a)
+        g.replay()
+        torch.cuda.synchronize()
+        # eager work between replays
+        pa, pb = ma.params(), mb.params()
+        torch.cuda.synchronize()
+        assert torch.equal(pa, pb), f"replay {k} diverged"
+        assert torch.equal(pred_a, pred_b)
+    ma.close()
+    mb.close()
