@@ -162,6 +162,48 @@ def serve_bench(qps=500.0, warm_s=2.0, measure_s=10.0, pool=48):
             "graph_replays": stats["graph_replays"]}
 
 
+def aggregate_bytes(N, E, H, Fe):
+    """Algorithmic bytes of one forward aggregation launch (S2): gathered Q
+    rows (E x H), own P rows (N x H), CSR arrays and edge attributes read; the
+    aggregates A (N x 4H, FP32) and the arg bytes (N x 2H) written."""
+    return 4 * H * E + 4 * H * N + 4 * (N + 1) + 4 * E + 4 * E * Fe + 16 * H * N + 2 * H * N
+
+
+def aggregate_bwd_bytes(N, E, H, Fe):
+    """Algorithmic bytes of one aggregation-adjoint launch (S7): dA (4H), mean
+    and std (2H), arg bytes (2H) and P (H) per node, gathered Q (H) per edge and
+    the CSR read; per-edge dm (E x H), D_in (N x H) and De (N x H Fe) written."""
+    reads = 16 * H * N + 8 * H * N + 2 * H * N + 4 * H * N + 4 * H * E
+    reads += 4 * (N + 1) + 4 * E + 4 * E * Fe
+    writes = 4 * H * E + 4 * H * N + 4 * H * N * Fe
+    return reads + writes
+
+
+def c3_measure(steps=8, warmup=2):
+    """One GPU's share of the large data-parallel step: 8 layers, hidden 256,
+    1024 molecules, BF16 linears, recomputation on.  Times the step and the two
+    aggregation kernels against the HBM roofline."""
+    from paper_2207_11333_amd import synth
+    w = synth.WORKLOADS["c3_large_bf16"]
+    out = {}
+    for site in ("aggregate", "aggregate_bwd"):
+        r = train_rate(w, steps, warmup, roofline_site=site)
+        out.setdefault("graphs_per_s", r["graphs_per_s"])
+        out.setdefault("ms_per_step", r["ms_per_step"])
+        out.setdefault("nodes", r["N"])
+        out.setdefault("edges", r["E"])
+        fn = aggregate_bytes if site == "aggregate" else aggregate_bwd_bytes
+        nbytes = fn(r["N"], r["E"], w.hidden, w.edge_feat)
+        avg = r["site_ms_total"] / 1e3 / max(1, r["site_launches"])
+        gbs = nbytes / avg / 1e9
+        out[site] = {"avg_us": avg * 1e6, "bytes_per_launch": nbytes, "achieved": gbs,
+                     "unit": "GB/s", "peak": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
+                     "launches": r["site_launches"]}
+    out["workload"] = ("c3_large_bf16: 8-layer PNA, hidden 256, 1024 molecules of 10-70 atoms, "
+                       "BF16 linears, FP32 aggregation, recomputation on")
+    return out
+
+
 def update_gemm_flops(w, N):
     """Algorithmic FLOPs of one launch of the update linear, averaged over layers:
     [N, F + 12H] x [F + 12H, H] with F = 9 for the first layer, H after."""
@@ -208,6 +250,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--qps", type=float, default=500.0, help="serving request rate")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a 256 MiB copy kernel (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the BF16 and serving measurements")
     args = ap.parse_args()
@@ -222,6 +266,13 @@ def main():
     from paper_2207_11333_amd import synth
     torch.cuda.set_device(0)
     w = synth.WORKLOADS["c1_train_fp32"]
+    if args.calib_copy:
+        from paper_2207_11333_amd import hgnn
+        src = torch.ones(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
+        hgnn.calib_copy(src, dst)
+        torch.cuda.synchronize()
+        del src, dst
     _log(f"bench: {w.name} steps={args.steps} warmup={args.warmup}")
     r = train_rate(w, args.steps, args.warmup, roofline_site="update_gemm")
     _log(f"bench: fp32 {r['graphs_per_s']:.1f} graphs/s, {r['ms_per_step']:.3f} ms/step")
@@ -238,7 +289,7 @@ def main():
                                "CSR build + forward + backward + Adam per step",
                    "graphs_per_step": r["B"], "nodes": r["N"], "edges": r["E"],
                    "layers": w.num_layers, "hidden": w.hidden, "precision": "fp32"},
-        "roofline": {"kernel": "update GEMM (S3) k_gemm_nt", "bound": "mfma",
+        "roofline": {"kernel": "update GEMM (S3) k_gemm_nt<0, 64, 128, false, 1>", "bound": "mfma",
                      "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
                      "launches": r["site_launches"], "avg_us": avg_s * 1e6,
@@ -259,6 +310,11 @@ def main():
                         "ratio_vs_fp32": rb["graphs_per_s"] / r["graphs_per_s"],
                         "graph_replay_value": rbg["graphs_per_s"],
                         "graph_replay_ratio_vs_fp32": rbg["graphs_per_s"] / rg["graphs_per_s"]}
+        _log("bench: large configuration")
+        line["c3"] = c3_measure()
+        _log(f"bench: c3 {line['c3']['graphs_per_s']:.1f} graphs/s; aggregation "
+             f"{line['c3']['aggregate']['achieved']:.0f} GB/s, adjoint "
+             f"{line['c3']['aggregate_bwd']['achieved']:.0f} GB/s")
         _log("bench: serving")
         line["serve"] = serve_bench(qps=args.qps)
         _log(f"bench: serve p50 {line['serve']['p50_ms']} ms p99 {line['serve']['p99_ms']} ms")

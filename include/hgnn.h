@@ -195,6 +195,9 @@ int hgnn_timer_start(hgnn_ctx *ctx, int32_t site, int32_t max_launches);
 /* Sum of the bracketed durations (ms) and the number of launches; stops the
  * timer.  Waits for the recorded events. */
 int hgnn_timer_read(hgnn_ctx *ctx, double *total_ms, int32_t *launches);
+/* Plain copy of n floats (n a multiple of 4, both device, 16-byte aligned):
+ * a kernel of known traffic for calibrating hardware byte counters. */
+int hgnn_calib_copy(const float *src_dev, float *dst_dev, int64_t n, void *stream);
 
 /* ---- serving (continuous batching of inference requests) --------------- */
 

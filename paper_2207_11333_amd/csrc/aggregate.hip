@@ -113,8 +113,7 @@ k_aggregate_bwd(const Dims *__restrict__ dims, int H, const float *__restrict__ 
                 const float *__restrict__ csr_e, const float *__restrict__ We, int ldwe,
                 const float *__restrict__ bmv, const float *__restrict__ A,
                 const uint8_t *__restrict__ args, const float *__restrict__ dA,
-                float *__restrict__ dm, float *__restrict__ Dio,
-                float *__restrict__ De) {
+                float *__restrict__ dm, float *__restrict__ D, int ldD) {
   const int tpn = H >> 2;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)(t / tpn), c = (int)(t % tpn) * 4;
@@ -158,16 +157,16 @@ k_aggregate_bwd(const Dims *__restrict__ dims, int H, const float *__restrict__ 
       for (int f = 0; f < FE; ++f) de[f] += g * csr_e[(size_t)q * FE + f];
     }
   }
-  *reinterpret_cast<f4 *>(Dio + (size_t)i * 2 * H + c) = din;
+  float *Di = D + (size_t)i * ldD;
+  *reinterpret_cast<f4 *>(Di + c) = din;
 #pragma unroll
-  for (int f = 0; f < FE; ++f)
-    *reinterpret_cast<f4 *>(De + (size_t)i * FE * H + f * H + c) = de[f];
+  for (int f = 0; f < FE; ++f) *reinterpret_cast<f4 *>(Di + (2 + f) * H + c) = de[f];
 }
 
 __global__ void __launch_bounds__(256)
 k_transpose_sum(const Dims *__restrict__ dims, int H, const int *__restrict__ srcptr,
                 const int *__restrict__ t2csr, const float *__restrict__ dm,
-                float *__restrict__ Dio) {
+                float *__restrict__ D, int ldD) {
   const int tpn = H >> 2;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = (int)(t / tpn), c = (int)(t % tpn) * 4;
@@ -175,7 +174,7 @@ k_transpose_sum(const Dims *__restrict__ dims, int H, const int *__restrict__ sr
   f4 s = {0.f, 0.f, 0.f, 0.f};
   for (int p = srcptr[j]; p < srcptr[j + 1]; ++p)
     s += *reinterpret_cast<const f4 *>(dm + (size_t)t2csr[p] * H + c);
-  *reinterpret_cast<f4 *>(Dio + (size_t)j * 2 * H + H + c) = s;
+  *reinterpret_cast<f4 *>(D + (size_t)j * ldD + H + c) = s;
 }
 
 __global__ void __launch_bounds__(256)
@@ -190,70 +189,6 @@ k_relu_mask(const Dims *__restrict__ dims, int H, const float *__restrict__ dh,
 #pragma unroll
   for (int e = 0; e < 4; ++e) o[e] = h[e] > 0.f ? g[e] : 0.f;
   reinterpret_cast<f4 *>(du)[t] = o;
-}
-
-// Column sums, stage 1: partial[z][col] over row chunk z.  A workgroup owns
-// 64 columns and one chunk; its 4 wavefronts take interleaved rows, and the
-// four wave sums are added in a fixed order.
-constexpr int kColRowGroups = 4;
-
-__global__ void __launch_bounds__(256)
-k_colsum_partial(const Dims *__restrict__ dims, const ColSum cs,
-                 float *__restrict__ part, int total_cols, int splits) {
-  __shared__ float red[kColRowGroups][64];
-  const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int col = blockIdx.x * 64 + lane;
-  const int z = blockIdx.y;
-  float s = 0.f;
-  if (col < total_cols) {
-    int a = 0, c = col;
-    while (a + 1 < cs.n && c >= cs.ncols[a]) { c -= cs.ncols[a]; ++a; }
-    const int rows = dims->N;
-    const int chunk = (rows + splits - 1) / splits;
-    const int lo = z * chunk, hi = min(rows, lo + chunk);
-    const float *src = cs.src[a] + c;
-    const size_t ld = cs.ld[a];
-    int i = lo + rg;
-    float s0 = 0.f, s1 = 0.f;
-    for (; i + kColRowGroups < hi; i += 2 * kColRowGroups) {
-      s0 += src[(size_t)i * ld];
-      s1 += src[(size_t)(i + kColRowGroups) * ld];
-    }
-    if (i < hi) s0 += src[(size_t)i * ld];
-    s = s0 + s1;
-  }
-  red[rg][lane] = s;
-  __syncthreads();
-  if (rg == 0 && col < total_cols)
-    part[(size_t)z * total_cols + col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-}
-
-// Stage 2: ordered sum over the chunks; output column c of array a goes to
-// out[a][(c % rs) * ostride + c / rs].
-struct ColSumOut {
-  float *out[3];
-  int rs[3], ostride[3];
-};
-
-__global__ void __launch_bounds__(256)
-k_colsum_final(const ColSum cs, const ColSumOut co, const float *__restrict__ part,
-               int total_cols, int splits) {
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int col = gt >> 2, q = gt & 3;
-  const int cc = col < total_cols ? col : total_cols - 1;
-  // 4 lanes per column: each adds a contiguous quarter of the chunks in
-  // order, then the quarters are added in order
-  const int per = (splits + 3) / 4;
-  const int z0 = q * per, z1 = min(splits, z0 + per);
-  float s = 0.f;
-  for (int z = z0; z < z1; ++z) s += part[(size_t)z * total_cols + cc];
-  const int lane = threadIdx.x & 63;
-  const float s0 = __shfl(s, lane & ~3, 64), s1 = __shfl(s, (lane & ~3) + 1, 64);
-  const float s2 = __shfl(s, (lane & ~3) + 2, 64), s3 = __shfl(s, (lane & ~3) + 3, 64);
-  if (col >= total_cols || q != 0) return;
-  int a = 0, c = col;
-  while (a + 1 < cs.n && c >= cs.ncols[a]) { c -= cs.ncols[a]; ++a; }
-  co.out[a][(size_t)(c % co.rs[a]) * co.ostride[a] + c / co.rs[a]] = ((s0 + s1) + s2) + s3;
 }
 
 } // namespace
@@ -280,13 +215,13 @@ hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
                                 const int *csr_src, const float *csr_e,
                                 const float *We, int ldwe, const float *bm,
                                 const float *A, const uint8_t *args,
-                                const float *dA, float *dm, float *Dio, float *De,
+                                const float *dA, float *dm, float *D, int ldD,
                                 hipStream_t s) {
   if (capN <= 0) return hipSuccess;
   const int grid = cdiv((long long)capN * (H / 4), 256);
 #define HGNN_AGG_BWD(FE)                                                               \
   k_aggregate_bwd<FE><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, \
-                                           bm, A, args, dA, dm, Dio, De)
+                                           bm, A, args, dA, dm, D, ldD)
   switch (Fe) {
   case 0: HGNN_AGG_BWD(0); break;
   case 1: HGNN_AGG_BWD(1); break;
@@ -299,11 +234,11 @@ hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
 }
 
 hipError_t launch_transpose_sum(const Dims *dims, int capN, int H, const int *srcptr,
-                                const int *t2csr, const float *dm, float *Dio,
+                                const int *t2csr, const float *dm, float *D, int ldD,
                                 hipStream_t s) {
   if (capN <= 0) return hipSuccess;
   k_transpose_sum<<<cdiv((long long)capN * (H / 4), 256), 256, 0, s>>>(dims, H, srcptr,
-                                                                       t2csr, dm, Dio);
+                                                                       t2csr, dm, D, ldD);
   return hipGetLastError();
 }
 
@@ -311,23 +246,6 @@ hipError_t launch_relu_mask(const Dims *dims, int capN, int H, const float *dh,
                             const float *hout, float *du, hipStream_t s) {
   if (capN <= 0) return hipSuccess;
   k_relu_mask<<<cdiv((long long)capN * H / 4, 256), 256, 0, s>>>(dims, H, dh, hout, du);
-  return hipGetLastError();
-}
-
-hipError_t launch_colsum(const Dims *dims, const ColSum &c, const ColSumMap &map,
-                         float *partials, int splits, hipStream_t s) {
-  int total = 0;
-  for (int a = 0; a < c.n; ++a) total += c.ncols[a];
-  if (total <= 0) return hipSuccess;
-  ColSumOut co;
-  for (int a = 0; a < 3; ++a) {
-    co.out[a] = a < c.n ? c.out[a] : nullptr;
-    co.rs[a] = a < c.n ? map.rs[a] : 1;
-    co.ostride[a] = a < c.n ? map.ostride[a] : 1;
-  }
-  dim3 g1(cdiv(total, 64), splits);
-  k_colsum_partial<<<g1, 256, 0, s>>>(dims, c, partials, total, splits);
-  k_colsum_final<<<cdiv(4 * total, 256), 256, 0, s>>>(c, co, partials, total, splits);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 // "virtual" operands [h || A || s+ A || s- A] and [du || s+ du || s- du]
 // that are never materialised.
 // ------------------------------------------------------------------------
-constexpr int kMaxSeg = 4;
+constexpr int kMaxSeg = 5;
 
 struct SegA {
   const float *ptr;   // [rows, ld] row-major, k-contiguous
@@ -73,7 +73,8 @@ struct GemmNT {
 // P[z][m, n] = sum_{i in chunk z} X[i, m] * Yv[i, n]
 // where Yv = [seg0 || seg1 || ...] with per-row (per-i) scales.
 struct SegY {
-  const float *ptr;
+  const float *ptr;   // nullptr: a constant segment [1, 0, 0, 0] (4 columns), which
+                      // turns the GEMM's last output column into sum_i X[i, m]
   const float *scale;
   int ld;
   int ncols;  // multiple of 4
@@ -90,14 +91,26 @@ struct GemmTN {
   int splits;
 };
 
-// Scatter of reduced partials into the packed gradient vector:
-// out[(r % rsplit) * ldo + (r / rsplit) * rcoloff + cmap(c)]
-// with cmap(c) = c < F ? c : (c < Fp ? skip : c - (Fp - F)).
+// Scatter of reduced partials into the packed gradient vector.  Columns
+// [0, main_cols) are the weight columns, with cmap(c) = c < F ? c :
+// (c < Fp ? skip : c - (Fp - F)); column main_cols is the sum column (from a
+// constant-one segment); later columns are padding.  Up to three row ranges
+// route rows m in [r0, r1) (local row u = m - r0):
+//   weight columns -> main[u * main_ld + main_coloff + cmap(c)] (main may be null)
+//   sum column     -> ones[(u % ones_split) * ones_stride + u / ones_split] (or null)
+struct ReduceRoute {
+  int r0, r1;
+  float *main;
+  int main_ld, main_coloff;
+  float *ones;
+  int ones_stride, ones_split;
+};
 struct ReduceMap {
   const float *P;
   int splits, M, Ncols;
-  float *out;
-  int ldo, rsplit, rcoloff, F, Fp;
+  int main_cols, F, Fp;
+  ReduceRoute route[3];
+  int nroute;
 };
 
 // ------------------------------------------------------------------------
@@ -124,8 +137,12 @@ hipError_t launch_pad_copy(const Dims *dims, int capN, const float *x, int F,
 // gemm.hip
 // Picks the tile shape and the split count from the capacity capM and the
 // shape; g.splits/g.P are set here (P must hold nt_partial_floats()).
+// tag 1 names the update-linear instantiation; ev0/ev1 (optional) bracket
+// the GEMM kernel alone (not the split-K reduction).
 hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
-                          float *partials, hipStream_t s);
+                          float *partials, hipStream_t s, int tag = 0,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_calib_copy(const float *src, float *dst, long long n, hipStream_t s);
 // Split count launch_gemm_nt will use, and the partial buffer it needs.
 int nt_splits(int capM, int Ncols, int Ktot, int precision);
 size_t nt_partial_floats(int capM, int Ncols, int Ktot, int precision);
@@ -142,30 +159,17 @@ hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
 hipError_t launch_relu_mask(const Dims *dims, int capN, int H,
                             const float *dh, const float *hout, float *du,
                             hipStream_t s);
+// D = [D_in | D_out | De] per node, leading dimension ldD = (2 + Fe) H.
 hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
                                 const float *PQ, const int *rowptr,
                                 const int *csr_src, const float *csr_e,
                                 const float *We, int ldwe, const float *bm,
                                 const float *A, const uint8_t *args,
-                                const float *dA, float *dm, float *Dio,
-                                float *De, hipStream_t s);
+                                const float *dA, float *dm, float *D, int ldD,
+                                hipStream_t s);
 hipError_t launch_transpose_sum(const Dims *dims, int capN, int H,
                                 const int *srcptr, const int *t2csr,
-                                const float *dm, float *Dio, hipStream_t s);
-// Column sums over the rows of up to 3 [N, ncols] arrays, deterministic.
-// Column c of array a is written to out[a][(c % rs[a]) * ostride[a] + c / rs[a]].
-struct ColSum {
-  const float *src[3];
-  int ld[3], ncols[3];
-  float *out[3];
-  int n;
-};
-struct ColSumMap {
-  int rs[3], ostride[3];
-};
-hipError_t launch_colsum(const Dims *dims, const ColSum &c, const ColSumMap &map,
-                         float *partials, int splits, hipStream_t s);
-
+                                const float *dm, float *D, int ldD, hipStream_t s);
 // head.hip
 hipError_t launch_head_forward(const Dims *dims, int capB, int H,
                                const int *graph_ptr, const float *h,

@@ -117,7 +117,8 @@ __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
 // --------------------------------------------------------------------------
 // NT form
 // --------------------------------------------------------------------------
-template <int PREC, int BM, int BN, bool SPLIT>
+// TAG only distinguishes launch sites in profiles (1: the update linear).
+template <int PREC, int BM, int BN, bool SPLIT, int TAG>
 __global__ void __launch_bounds__(256)
 k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   using P = Prec<PREC>;
@@ -347,7 +348,7 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   const float *b_ptr[NB];
   const float *b_sptr[NB]; // row scales, or the operand itself when unscaled
   int b_ld[NB], b_il[NB], b_sstride[NB];
-  bool b_ok[NB], b_has_scale[NB];
+  bool b_ok[NB], b_has_scale[NB], b_ones[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int v = tid + j * 256;
@@ -357,11 +358,14 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     n = min(n, g.Ncols - 4);
     int q = 0;
     while (q + 1 < g.nseg && n >= g.seg[q].ncols) { n -= g.seg[q].ncols; ++q; }
-    b_ptr[j] = g.seg[q].ptr + n;
-    b_ld[j] = g.seg[q].ld;
+    // a constant segment reads nothing: point it at X (valid rows) and select
+    b_ones[j] = g.seg[q].ptr == nullptr;
+    b_ptr[j] = b_ones[j] ? g.X : g.seg[q].ptr + n;
+    b_ld[j] = b_ones[j] ? g.ldx : g.seg[q].ld;
     b_has_scale[j] = g.seg[q].scale != nullptr;
     b_sptr[j] = b_has_scale[j] ? g.seg[q].scale : b_ptr[j];
     b_sstride[j] = b_has_scale[j] ? 1 : b_ld[j];
+    if (b_ones[j]) b_ok[j] = b_ok[j] && n == 0;
   }
   const int i_last = max(i_hi - 1, 0);
   auto load = [&](auto st, int t) {
@@ -377,9 +381,10 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     for (int j = 0; j < NB; ++j) {
       const int i = i0 + b_il[j];
       const int ic = min(i, i_last);
-      const f4 val = *reinterpret_cast<const f4 *>(b_ptr[j] + (size_t)ic * b_ld[j]);
+      f4 val = *reinterpret_cast<const f4 *>(b_ptr[j] + (size_t)ic * b_ld[j]);
       const float sv = b_sptr[j][(size_t)ic * b_sstride[j]];
       const float sc = b_has_scale[j] ? sv : 1.0f;
+      if (b_ones[j]) val = f4{1.f, 0.f, 0.f, 0.f};
       rb[S][j] = (b_ok[j] && i < i_hi) ? val : f4{0.f, 0.f, 0.f, 0.f};
       rsc[S][j] = sc;
     }
@@ -471,7 +476,7 @@ k_reduce_nt(const Dims *__restrict__ dims, const GemmNT g) {
 }
 
 // Sum the split-K partials in order and scatter them into the packed
-// gradient layout.
+// gradient layout (routes: see ReduceMap).
 __global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
   const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long t = gt >> 2;
@@ -481,23 +486,37 @@ __global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
   const float s = ordered_split_sum(r.P, r.splits, total, tc, q);
   if (t >= total || q != 0) return;
   const int m = (int)(t / r.Ncols), c = (int)(t % r.Ncols);
-  int oc;
-  if (c < r.F) oc = c;
-  else if (c < r.Fp) return;
-  else oc = c - (r.Fp - r.F);
-  r.out[(size_t)(m % r.rsplit) * r.ldo + (size_t)(m / r.rsplit) * r.rcoloff + oc] = s;
+  for (int k = 0; k < r.nroute; ++k) {
+    const ReduceRoute &ro = r.route[k];
+    if (m < ro.r0 || m >= ro.r1) continue;
+    const int u = m - ro.r0;
+    if (c < r.main_cols) {
+      if (!ro.main) return;
+      int oc;
+      if (c < r.F) oc = c;
+      else if (c < r.Fp) return;
+      else oc = c - (r.Fp - r.F);
+      ro.main[(size_t)u * ro.main_ld + ro.main_coloff + oc] = s;
+    } else if (c == r.main_cols && ro.ones) {
+      ro.ones[(size_t)(u % ro.ones_split) * ro.ones_stride + u / ro.ones_split] = s;
+    }
+    return;
+  }
 }
 
 inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 
-template <int PREC, int BM, int BN>
-hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s) {
+template <int PREC, int BM, int BN, int TAG>
+hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
+                  hipEvent_t ev0, hipEvent_t ev1) {
   const int nt = cdiv(g.Ncols, BN);
   dim3 grid(cdiv(capM, BM) * nt, g.splits);
+  if (ev0) (void)hipEventRecord(ev0, s);
   if (PREC == 1 && g.B_lo)
-    k_gemm_nt<PREC, BM, BN, true><<<grid, 256, 0, s>>>(dims, g, nt);
+    k_gemm_nt<PREC, BM, BN, true, TAG><<<grid, 256, 0, s>>>(dims, g, nt);
   else
-    k_gemm_nt<PREC, BM, BN, false><<<grid, 256, 0, s>>>(dims, g, nt);
+    k_gemm_nt<PREC, BM, BN, false, TAG><<<grid, 256, 0, s>>>(dims, g, nt);
+  if (ev1) (void)hipEventRecord(ev1, s);
   if (g.splits > 1)
     k_reduce_nt<<<cdiv(4LL * capM * g.Ncols, 256), 256, 0, s>>>(dims, g);
   return hipGetLastError();
@@ -505,8 +524,9 @@ hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s) {
 
 // Output tiles are 64 rows x 128 columns: one tile spans the whole hidden
 // width, so each weight tile is staged once per 64 rows.  When the tiles
-// cannot give every SIMD two waves (512 workgroups of 4 waves on 256 CUs),
-// K is split (at least three K tiles per split, at most 8 splits).
+// alone cannot cover the 256 CUs, K is split (at least three K tiles per
+// split, at most 8 splits).  Measured: more splits lose to their partial
+// traffic at these sizes.
 constexpr int kNtBM = 64, kNtBN = 128;
 
 int nt_ktiles(int Ktot, int precision) {
@@ -519,19 +539,20 @@ int nt_ktiles(int Ktot, int precision) {
 int nt_splits(int capM, int Ncols, int Ktot, int precision) {
   const int tiles = cdiv(capM, kNtBM) * cdiv(Ncols, kNtBN);
   const int kt = nt_ktiles(Ktot, precision);
-  int sp = (512 + tiles - 1) / (tiles > 0 ? tiles : 1);
+  int sp = 256 / (tiles > 0 ? tiles : 1);
   if (sp > kt / 3) sp = kt / 3;
   if (sp > 8) sp = 8;
   return sp < 1 ? 1 : sp;
 }
 
 // Upper bound of splits x capM x Ncols over every shape: a split is taken
-// only while the tiles number fewer than 512, and then splits x tiles < 1024,
-// so splits x capM x Ncols <= 1024 x 64 x 128 floats.
-size_t nt_partial_floats(int, int, int, int) { return (size_t)1024 * kNtBM * kNtBN; }
+// only while the tiles number fewer than 256, and then splits x tiles <= 256,
+// so splits x capM x Ncols <= 256 x 64 x 128 floats.
+size_t nt_partial_floats(int, int, int, int) { return (size_t)256 * kNtBM * kNtBN; }
 
 hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
-                          float *partials, hipStream_t s) {
+                          float *partials, hipStream_t s, int tag, hipEvent_t ev0,
+                          hipEvent_t ev1) {
   if (capM <= 0 || g.Ncols <= 0) return hipSuccess;
   int Ktot = 0;
   for (int q = 0; q < g.nseg; ++q) Ktot += g.seg[q].k > 0 ? ((g.seg[q].k + 15) / 16) * 16 : 0;
@@ -545,8 +566,12 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
   if (g.splits > 1 && !partials) g.splits = 1;
   while (g.splits > 1 && (size_t)g.splits * capM * g.Ncols > nt_partial_floats(0, 0, 0, 0))
     --g.splits;
-  if (precision == 0) return run_nt<0, kNtBM, kNtBN>(dims, capM, g, s);
-  return run_nt<1, kNtBM, kNtBN>(dims, capM, g, s);
+  if (tag == 1) {
+    if (precision == 0) return run_nt<0, kNtBM, kNtBN, 1>(dims, capM, g, s, ev0, ev1);
+    return run_nt<1, kNtBM, kNtBN, 1>(dims, capM, g, s, ev0, ev1);
+  }
+  if (precision == 0) return run_nt<0, kNtBM, kNtBN, 0>(dims, capM, g, s, ev0, ev1);
+  return run_nt<1, kNtBM, kNtBN, 0>(dims, capM, g, s, ev0, ev1);
 }
 
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
@@ -558,6 +583,23 @@ hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
     k_gemm_tn<0, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
   else
     k_gemm_tn<1, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
+  return hipGetLastError();
+}
+
+namespace {
+// Plain float4 copy used to calibrate the HBM byte counters.
+__global__ void __launch_bounds__(256) k_calib_copy(const f4 *__restrict__ src,
+                                                    f4 *__restrict__ dst, long long n4) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n4) dst[i] = src[i];
+}
+} // namespace
+
+hipError_t launch_calib_copy(const float *src, float *dst, long long n, hipStream_t s) {
+  const long long n4 = n / 4;
+  if (n4 <= 0) return hipSuccess;
+  k_calib_copy<<<cdiv(n4, 256), 256, 0, s>>>(reinterpret_cast<const f4 *>(src),
+                                             reinterpret_cast<f4 *>(dst), n4);
   return hipGetLastError();
 }
 

@@ -66,8 +66,8 @@ void free_work(Exec &ex) {
                    (void **)&w.csr.csr_pos, (void **)&w.csr.csr_e, (void **)&w.csr.sp,
                    (void **)&w.csr.sm, (void **)&w.xpad, (void **)&w.g, (void **)&w.q,
                    (void **)&w.ypred, (void **)&w.dy, (void **)&w.dq, (void **)&w.du,
-                   (void **)&w.dA, (void **)&w.dm, (void **)&w.Dio, (void **)&w.De,
-                   (void **)&w.dh0, (void **)&w.dh1, (void **)&w.colpart, (void **)&w.ntpart};
+                   (void **)&w.dA, (void **)&w.dm, (void **)&w.D, (void **)&w.dh0,
+                   (void **)&w.dh1, (void **)&w.ntpart};
   for (void **p : ptrs) dfree(*p);
   for (auto &p : w.hbuf) dfree(reinterpret_cast<void *&>(p));
   for (auto &p : w.PQ) dfree(reinterpret_cast<void *&>(p));
@@ -115,9 +115,8 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
   if (!inference) {
     ok = ok && f(w.dq, (size_t)capB * H) && f(w.dy, (size_t)capB);
     ok = ok && f(w.du, (size_t)capN * H) && f(w.dA, (size_t)capN * 4 * H) &&
-         f(w.dm, (size_t)capE * H) && f(w.Dio, (size_t)capN * 2 * H) &&
-         f(w.De, (size_t)capN * H * Fe) && f(w.dh0, (size_t)capN * H) &&
-         f(w.dh1, (size_t)capN * H) && f(w.colpart, (size_t)kColSplits * (2 + Fe) * H);
+         f(w.dm, (size_t)capE * H) && f(w.D, (size_t)capN * (2 + c->Fe) * H) &&
+         f(w.dh0, (size_t)capN * H) && f(w.dh1, (size_t)capN * H);
   }
   return ok;
 }
@@ -323,8 +322,9 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
   g.M_fixed = -1;
   hipError_t e;
   {
-    TimedLaunch tl(c, ex, SITE_UPDATE_GEMM, s);
-    e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
+    TimedLaunch tl(c, ex, SITE_UPDATE_GEMM, s, /*manual=*/true);
+    hipEvent_t e0 = tl.start(), e1 = tl.stop();
+    e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s, /*tag=*/1, e0, e1);
   }
   if (e != hipSuccess) return hip_fail(c, e, "update GEMM");
   return HGNN_OK;
@@ -336,7 +336,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
                    const float *h_out, const float *dh_out, float *dh_in, float *dwl,
                    hipStream_t s, bool dh_out_masked = false, bool mask_dh_in = false) {
   const LayerDesc &d = c->ld[l];
-  const int H = c->H, Fe = c->Fe;
+  const int H = c->H, Fe = c->Fe, ldD = (2 + Fe) * H;
   Work &w = ex.w;
   int rc, ldh;
   const float *hin = layer_input(c, ex, l, h_in, &ldh, s, &rc);
@@ -371,7 +371,9 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     t.seg[1] = SegY{A, nullptr, 4 * H, 4 * H};
     t.seg[2] = SegY{A, w.csr.sp, 4 * H, 4 * H};
     t.seg[3] = SegY{A, w.csr.sm, 4 * H, 4 * H};
-    t.Ncols = d.Fp + 12 * H;
+    t.seg[4] = SegY{nullptr, nullptr, 0, 4}; // sum column: db^p
+    t.nseg = 5;
+    t.Ncols = d.Fp + 12 * H + 4;
     t.P = c->part;
     t.splits = d.split_p;
     {
@@ -379,7 +381,16 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       e = launch_gemm_tn(ex.dims, t, c->prec, s);
     }
     if (e == hipSuccess) {
-      ReduceMap r{c->part, d.split_p, H, d.Fp + 12 * H, dWp, d.F + 12 * H, H, 0, d.F, d.Fp};
+      ReduceMap r{};
+      r.P = c->part;
+      r.splits = d.split_p;
+      r.M = H;
+      r.Ncols = d.Fp + 12 * H + 4;
+      r.main_cols = d.Fp + 12 * H;
+      r.F = d.F;
+      r.Fp = d.Fp;
+      r.route[0] = ReduceRoute{0, H, dWp, d.F + 12 * H, 0, dbp, 1, H};
+      r.nroute = 1;
       e = launch_reduce_map(r, s);
     }
     if (e != hipSuccess) return hip_fail(c, e, "update weight gradient");
@@ -409,53 +420,49 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s);
     e = launch_aggregate_bwd(ex.dims, ex.N, H, Fe, PQ, w.csr.rowptr, w.csr.csr_src,
                              w.csr.csr_e, Wm + 2 * d.F, 2 * d.F + Fe, bm, A, args, w.dA,
-                             w.dm, w.Dio, w.De, s);
+                             w.dm, w.D, ldD, s);
   }
   if (e == hipSuccess)
-    e = launch_transpose_sum(ex.dims, ex.N, H, w.csr.srcptr, w.csr.t2csr, w.dm, w.Dio, s);
+    e = launch_transpose_sum(ex.dims, ex.N, H, w.csr.srcptr, w.csr.t2csr, w.dm, w.D, ldD, s);
   if (e != hipSuccess) return hip_fail(c, e, "aggregation adjoint");
   // S8: [dW_dst | dW_src] = [D_in | D_out]^T h
   {
     GemmTN t{};
-    t.X = w.Dio;
-    t.ldx = 2 * H;
-    t.M = 2 * H;
-    t.nseg = 1;
+    t.X = w.D;
+    t.ldx = ldD;
+    t.M = ldD;
+    t.nseg = 2;
     t.seg[0] = SegY{hin, nullptr, ldh, d.Fp};
-    t.Ncols = d.Fp;
+    t.seg[1] = SegY{nullptr, nullptr, 0, 4}; // sum column: db^m and the e_k weights
+    t.Ncols = d.Fp + 4;
     t.P = c->part;
     t.splits = d.split_m;
     e = launch_gemm_tn(ex.dims, t, c->prec, s);
     if (e == hipSuccess) {
-      ReduceMap r{c->part, d.split_m, 2 * H, d.Fp, dWm, 2 * d.F + Fe, H, d.F, d.F, d.Fp};
+      const int ldm = 2 * d.F + Fe;
+      ReduceMap r{};
+      r.P = c->part;
+      r.splits = d.split_m;
+      r.M = ldD;
+      r.Ncols = d.Fp + 4;
+      r.main_cols = d.Fp;
+      r.F = d.F;
+      r.Fp = d.Fp;
+      r.route[0] = ReduceRoute{0, H, dWm, ldm, 0, dbm, 1, H};               // D_in
+      r.route[1] = ReduceRoute{H, 2 * H, dWm, ldm, d.F, nullptr, 0, 1};      // D_out
+      r.route[2] = ReduceRoute{2 * H, ldD, nullptr, 0, 0, dWm + 2 * d.F, ldm, H}; // De
+      r.nroute = Fe > 0 ? 3 : 2;
       e = launch_reduce_map(r, s);
     }
     if (e != hipSuccess) return hip_fail(c, e, "message weight gradient");
-  }
-  // biases and edge-feature weights: ordered column sums
-  {
-    ColSum cs{};
-    ColSumMap mp{};
-    cs.src[0] = du; cs.ld[0] = H; cs.ncols[0] = H; cs.out[0] = dbp;
-    mp.rs[0] = H; mp.ostride[0] = 1;
-    cs.src[1] = w.Dio; cs.ld[1] = 2 * H; cs.ncols[1] = H; cs.out[1] = dbm;
-    mp.rs[1] = H; mp.ostride[1] = 1;
-    cs.n = 2;
-    if (Fe > 0) {
-      cs.src[2] = w.De; cs.ld[2] = Fe * H; cs.ncols[2] = Fe * H; cs.out[2] = dWm + 2 * d.F;
-      mp.rs[2] = H; mp.ostride[2] = 2 * d.F + Fe;
-      cs.n = 3;
-    }
-    e = launch_colsum(ex.dims, cs, mp, w.colpart, kColSplits, s);
-    if (e != hipSuccess) return hip_fail(c, e, "bias gradients");
   }
   // S6 + S8 input gradient: dh = [du || D_in || D_out] [W_h; W_dst; W_src]
   if (dh_in) {
     GemmNT g{};
     g.nseg = 3;
     g.seg[0] = SegA{du, nullptr, H, H, 0};
-    g.seg[1] = SegA{w.Dio, nullptr, 2 * H, H, H};
-    g.seg[2] = SegA{w.Dio + H, nullptr, 2 * H, H, 2 * H};
+    g.seg[1] = SegA{w.D, nullptr, ldD, H, H};
+    g.seg[2] = SegA{w.D + H, nullptr, ldD, H, 2 * H};
     g.B = c->WhdsT[l];
     g.B_lo = c->prec ? c->WhdsT_lo[l] : nullptr;
     g.ldb = 3 * H;
@@ -564,10 +571,10 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
     d.obp = off;
     off += H;
     d.size = off - d.off;
-    d.split_p = tn_splits(H, d.Fp + 12 * H);
-    d.split_m = tn_splits(2 * H, d.Fp);
-    const size_t a = (size_t)d.split_p * H * (d.Fp + 12 * H);
-    const size_t b = (size_t)d.split_m * 2 * H * d.Fp;
+    d.split_p = tn_splits(H, d.Fp + 12 * H + 4);
+    d.split_m = tn_splits((2 + c->Fe) * H, d.Fp + 4);
+    const size_t a = (size_t)d.split_p * H * (d.Fp + 12 * H + 4);
+    const size_t b = (size_t)d.split_m * (2 + c->Fe) * H * (d.Fp + 4);
     part_max = std::max(part_max, std::max(a, b));
     c->ld.push_back(d);
   }
@@ -914,6 +921,12 @@ int hgnn_timer_read(hgnn_ctx *c, double *total_ms, int32_t *launches) {
   *launches = t.used / 2;
   t.site = SITE_NONE;
   return HGNN_OK;
+}
+
+int hgnn_calib_copy(const float *src, float *dst, int64_t n, void *stream) {
+  if (!src || !dst || n < 0 || n % 4) return fail(HGNN_EINVAL, "bad copy arguments");
+  hipError_t e = launch_calib_copy(src, dst, n, (hipStream_t)stream);
+  return e == hipSuccess ? HGNN_OK : fail(HGNN_EDEVICE, hipGetErrorString(e));
 }
 
 int hgnn_op_fetch(hgnn_ctx *c, int32_t which, int32_t layer, void *dst, size_t cap,

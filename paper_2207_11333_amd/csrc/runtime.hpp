@@ -9,7 +9,6 @@
 
 namespace hgnn {
 
-constexpr int kColSplits = 64;
 
 struct LayerDesc {
   int F, Fp;                       // input width and its padding to 16
@@ -28,8 +27,9 @@ struct Work {
   std::vector<uint8_t *> args;
   int stored_layer = -1;                 // layer held by the shared slot
   float *g = nullptr, *q = nullptr, *ypred = nullptr, *dy = nullptr, *dq = nullptr;
-  float *du = nullptr, *dA = nullptr, *dm = nullptr, *Dio = nullptr, *De = nullptr;
-  float *dh0 = nullptr, *dh1 = nullptr, *colpart = nullptr;
+  float *du = nullptr, *dA = nullptr, *dm = nullptr;
+  float *D = nullptr;                    // [N, (2 + Fe) H] = [D_in | D_out | De]
+  float *dh0 = nullptr, *dh1 = nullptr;
   float *ntpart = nullptr;               // split-K partials of the NT GEMMs
 };
 
@@ -108,25 +108,30 @@ int stage_all(hgnn_ctx *c, hipStream_t s);
 
 // Records an event pair around one launch when the timer watches `site`.
 // Only the training path's launches are timed (serving lanes never are).
+// RAII form: the pair brackets everything launched in the scope.  Manual
+// form: start()/stop() hand the pair to a launcher that records it around
+// one kernel of a multi-kernel launch.
 struct TimedLaunch {
   hgnn_ctx *c;
   hipStream_t s;
-  bool on;
-  TimedLaunch(hgnn_ctx *c_, const Exec &ex, int site, hipStream_t s_)
-      : c(c_), s(s_), on(false) {
+  bool on, manual;
+  TimedLaunch(hgnn_ctx *c_, const Exec &ex, int site, hipStream_t s_, bool manual_ = false)
+      : c(c_), s(s_), on(false), manual(manual_) {
     SiteTimer &t = c->timer;
     if (&ex == &c->ex && t.site == site && t.used + 2 <= (int)t.ev.size()) {
       on = true;
-      (void)hipEventRecord(t.ev[t.used], s);
+      if (!manual) (void)hipEventRecord(t.ev[t.used], s);
     }
   }
   ~TimedLaunch() {
     if (on) {
       SiteTimer &t = c->timer;
-      (void)hipEventRecord(t.ev[t.used + 1], s);
+      if (!manual) (void)hipEventRecord(t.ev[t.used + 1], s);
       t.used += 2;
     }
   }
+  hipEvent_t start() const { return on ? c->timer.ev[c->timer.used] : nullptr; }
+  hipEvent_t stop() const { return on ? c->timer.ev[c->timer.used + 1] : nullptr; }
 };
 
 } // namespace hgnn

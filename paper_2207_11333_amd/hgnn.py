@@ -89,6 +89,7 @@ _SIGS = {
     "hgnn_serve_stop": ([_P], _I),
     "hgnn_timer_start": ([_P, _I, _I], _I),
     "hgnn_timer_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)], _I),
+    "hgnn_calib_copy": ([_P, _P, ctypes.c_int64, _P], _I),
     "hgnn_last_error": ([], ctypes.c_char_p),
 }
 
@@ -320,6 +321,11 @@ class Model:
 # ---------------------------------------------------------------------------
 # autograd: one Function per GC layer, one for pooling + head
 # ---------------------------------------------------------------------------
+
+def calib_copy(src: torch.Tensor, dst: torch.Tensor):
+    """Plain float4 copy kernel (known traffic) for counter calibration."""
+    _check(lib().hgnn_calib_copy(_ptr(src), _ptr(dst), src.numel(), _stream()))
+
 
 class PNALayerFunction(torch.autograd.Function):
     """h_out = PNA layer l (message, aggregation, scalers, update, ReLU)."""
