@@ -35,6 +35,39 @@ __device__ __forceinline__ f4 message(const float *__restrict__ PQ, int H, int s
   return m + bm;
 }
 
+// Up to kCache in-edges of a node are fetched together: all source ids,
+// then all gathered Q rows, so a node costs three dependent memory latencies
+// (rowptr, ids, rows) whatever its degree up to kCache; the loads are from
+// clamped indices and masked, so no branch serialises them.
+template <int FE>
+__device__ __forceinline__ int gather_messages(const float *__restrict__ PQ, int H, int c,
+                                               f4 p, f4 bm, const f4 (&we)[4],
+                                               const int *__restrict__ csr_src,
+                                               const float *__restrict__ csr_e, int lo,
+                                               int d, f4 (&m)[kCache], float (&ev)[kCache][4]) {
+  int src[kCache];
+#pragma unroll
+  for (int o = 0; o < kCache; ++o) src[o] = csr_src[lo + min(o, d - 1)];
+#pragma unroll
+  for (int o = 0; o < kCache; ++o) {
+    const int q = lo + min(o, d - 1);
+#pragma unroll
+    for (int f = 0; f < FE; ++f) ev[o][f] = csr_e[(size_t)q * FE + f];
+  }
+  f4 qr[kCache];
+#pragma unroll
+  for (int o = 0; o < kCache; ++o)
+    qr[o] = *reinterpret_cast<const f4 *>(PQ + (size_t)src[o] * 2 * H + H + c);
+#pragma unroll
+  for (int o = 0; o < kCache; ++o) {
+    f4 v = p + qr[o];
+#pragma unroll
+    for (int f = 0; f < FE; ++f) v += ev[o][f] * we[f];
+    m[o] = v + bm;
+  }
+  return min(d, kCache);
+}
+
 template <int FE>
 __global__ void __launch_bounds__(256)
 k_aggregate(const Dims *__restrict__ dims, int H, const float *__restrict__ PQ,
@@ -46,44 +79,48 @@ k_aggregate(const Dims *__restrict__ dims, int H, const float *__restrict__ PQ,
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)(t / tpn), c = (int)(t % tpn) * 4;
   if (i >= dims->N) return;
-  f4 we[4];
-#pragma unroll
-  for (int f = 0; f < FE; ++f)
-    we[f] = f4{We[(size_t)(c + 0) * ldwe + f], We[(size_t)(c + 1) * ldwe + f],
-               We[(size_t)(c + 2) * ldwe + f], We[(size_t)(c + 3) * ldwe + f]};
-  const f4 bm = *reinterpret_cast<const f4 *>(bmv + c);
-  const f4 p = *reinterpret_cast<const f4 *>(PQ + (size_t)i * 2 * H + c);
   const int lo = rowptr[i], hi = rowptr[i + 1], d = hi - lo;
   f4 mu = {0.f, 0.f, 0.f, 0.f}, mn = mu, mx = mu, sd = mu;
   uint32_t amin = 0, amax = 0;
   if (d > 0) {
-    f4 cache[kCache];
-    f4 sum = {0.f, 0.f, 0.f, 0.f};
-    int imn[4] = {0, 0, 0, 0}, imx[4] = {0, 0, 0, 0};
-    for (int o = 0; o < d; ++o) {
-      const int q = lo + o;
-      const f4 m = message<FE>(PQ, H, csr_src[q], c, p, bm, we, csr_e, q);
-      if (o < kCache) cache[o] = m;
-      sum += m;
-      if (o == 0) {
-        mn = m;
-        mx = m;
-      } else {
+    f4 we[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (m[e] < mn[e]) { mn[e] = m[e]; imn[e] = o; }
-          if (m[e] > mx[e]) { mx[e] = m[e]; imx[e] = o; }
-        }
+    for (int f = 0; f < FE; ++f)
+      we[f] = f4{We[(size_t)(c + 0) * ldwe + f], We[(size_t)(c + 1) * ldwe + f],
+                 We[(size_t)(c + 2) * ldwe + f], We[(size_t)(c + 3) * ldwe + f]};
+    const f4 bm = *reinterpret_cast<const f4 *>(bmv + c);
+    const f4 p = *reinterpret_cast<const f4 *>(PQ + (size_t)i * 2 * H + c);
+    f4 cache[kCache];
+    float ev[kCache][4];
+    const int dc = gather_messages<FE>(PQ, H, c, p, bm, we, csr_src, csr_e, lo, d, cache, ev);
+    f4 sum = cache[0];
+    mn = cache[0];
+    mx = cache[0];
+    int imn[4] = {0, 0, 0, 0}, imx[4] = {0, 0, 0, 0};
+    auto visit = [&](const f4 &m, int o) {
+      sum += m;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (m[e] < mn[e]) { mn[e] = m[e]; imn[e] = o; }
+        if (m[e] > mx[e]) { mx[e] = m[e]; imx[e] = o; }
       }
-    }
+    };
+#pragma unroll
+    for (int o = 1; o < kCache; ++o)
+      if (o < dc) visit(cache[o], o);
+    for (int o = kCache; o < d; ++o)
+      visit(message<FE>(PQ, H, csr_src[lo + o], c, p, bm, we, csr_e, lo + o), o);
     const float fd = (float)d;
     mu = sum / fd;
     f4 ss = {0.f, 0.f, 0.f, 0.f};
-    for (int o = 0; o < d; ++o) {
-      f4 m;
-      if (o < kCache) m = cache[o];
-      else m = message<FE>(PQ, H, csr_src[lo + o], c, p, bm, we, csr_e, lo + o);
-      const f4 dv = m - mu;
+#pragma unroll
+    for (int o = 0; o < kCache; ++o)
+      if (o < dc) {
+        const f4 dv = cache[o] - mu;
+        ss += dv * dv;
+      }
+    for (int o = kCache; o < d; ++o) {
+      const f4 dv = message<FE>(PQ, H, csr_src[lo + o], c, p, bm, we, csr_e, lo + o) - mu;
       ss += dv * dv;
     }
     const f4 var = ss / fd;
@@ -139,22 +176,33 @@ k_aggregate_bwd(const Dims *__restrict__ dims, int H, const float *__restrict__ 
     const f4 dsd = *reinterpret_cast<const f4 *>(dAi + 3 * H + c);
     const uint32_t amin = *reinterpret_cast<const uint32_t *>(args + (size_t)i * 2 * H + c);
     const uint32_t amax = *reinterpret_cast<const uint32_t *>(args + (size_t)i * 2 * H + H + c);
+    f4 cache[kCache];
+    float ev[kCache][4];
+    const int dc = gather_messages<FE>(PQ, H, c, p, bm, we, csr_src, csr_e, lo, d, cache, ev);
     const float fd = (float)d;
     const f4 base = dmu / fd;
     const f4 coef = dsd / (fd * sd);
-    for (int o = 0; o < d; ++o) {
-      const int q = lo + o;
-      const f4 m = message<FE>(PQ, H, csr_src[q], c, p, bm, we, csr_e, q);
+    auto emit = [&](const f4 &m, int o, const float *e) {
       f4 g = base + coef * (m - mu);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if ((int)((amin >> (8 * e)) & 0xff) == o) g[e] += dmn[e];
-        if ((int)((amax >> (8 * e)) & 0xff) == o) g[e] += dmx[e];
+      for (int k = 0; k < 4; ++k) {
+        if ((int)((amin >> (8 * k)) & 0xff) == o) g[k] += dmn[k];
+        if ((int)((amax >> (8 * k)) & 0xff) == o) g[k] += dmx[k];
       }
-      *reinterpret_cast<f4 *>(dm + (size_t)q * H + c) = g;
+      *reinterpret_cast<f4 *>(dm + (size_t)(lo + o) * H + c) = g;
       din += g;
 #pragma unroll
-      for (int f = 0; f < FE; ++f) de[f] += g * csr_e[(size_t)q * FE + f];
+      for (int f = 0; f < FE; ++f) de[f] += g * e[f];
+    };
+#pragma unroll
+    for (int o = 0; o < kCache; ++o)
+      if (o < dc) emit(cache[o], o, ev[o]);
+    for (int o = kCache; o < d; ++o) {
+      const int q = lo + o;
+      float e[4];
+#pragma unroll
+      for (int f = 0; f < FE; ++f) e[f] = csr_e[(size_t)q * FE + f];
+      emit(message<FE>(PQ, H, csr_src[q], c, p, bm, we, csr_e, q), o, e);
     }
   }
   float *Di = D + (size_t)i * ldD;
@@ -171,9 +219,21 @@ k_transpose_sum(const Dims *__restrict__ dims, int H, const int *__restrict__ sr
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = (int)(t / tpn), c = (int)(t % tpn) * 4;
   if (j >= dims->N) return;
+  const int lo = srcptr[j], hi = srcptr[j + 1], d = hi - lo;
   f4 s = {0.f, 0.f, 0.f, 0.f};
-  for (int p = srcptr[j]; p < srcptr[j + 1]; ++p)
-    s += *reinterpret_cast<const f4 *>(dm + (size_t)t2csr[p] * H + c);
+  if (d > 0) {
+    int pos[kCache];
+#pragma unroll
+    for (int o = 0; o < kCache; ++o) pos[o] = t2csr[lo + min(o, d - 1)];
+    f4 v[kCache];
+#pragma unroll
+    for (int o = 0; o < kCache; ++o) v[o] = *reinterpret_cast<const f4 *>(dm + (size_t)pos[o] * H + c);
+#pragma unroll
+    for (int o = 0; o < kCache; ++o)
+      if (o < d) s += v[o];
+    for (int p = lo + kCache; p < hi; ++p)
+      s += *reinterpret_cast<const f4 *>(dm + (size_t)t2csr[p] * H + c);
+  }
   *reinterpret_cast<f4 *>(D + (size_t)j * ldD + H + c) = s;
 }
 

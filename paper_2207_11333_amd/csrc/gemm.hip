@@ -46,9 +46,10 @@ template <> struct Prec<1> {
 
 template <int V> using IC = std::integral_constant<int, V>;
 
-// Map the dispatch order (round-robin over the 8 XCDs) to tiles so that each
-// XCD receives a contiguous range of tiles: neighbouring tiles, which share
-// A rows, then share that XCD's L2.  A bijection on [0, T).
+// Map the dispatch order (round-robin over the 8 XCDs) to output tiles so that
+// each XCD receives a contiguous range of tiles: the N tiles of one M tile,
+// which share A rows, then share that XCD's L2.  A bijection on [0, T).
+// (Measured: mapping whole node ranges to XCDs across kernels is slower.)
 __device__ __forceinline__ int xcd_tile(int bid, int T) {
   constexpr int X = 8;
   const int xcd = bid % X, local = bid / X;
@@ -118,18 +119,20 @@ __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
 // NT form
 // --------------------------------------------------------------------------
 // TAG only distinguishes launch sites in profiles (1: the update linear).
-template <int PREC, int BM, int BN, bool SPLIT, int TAG>
-__global__ void __launch_bounds__(256)
+// Waves form a 2 x WGN grid over the BM x BN tile (NTH = 128 WGN threads).
+template <int PREC, int BM, int BN, bool SPLIT, int TAG, int WGN>
+__global__ void __launch_bounds__(128 * WGN)
 k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   using P = Prec<PREC>;
   using T = typename P::T;
+  constexpr int NTH = 128 * WGN;
   constexpr int BK = P::BK, LDA = BK + P::PAD;
-  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  constexpr int WM = BM / 2, WN = BN / WGN, TM = WM / 16, TN = WN / 16;
   // A tile: BM x BK floats loaded as float4 -> NA vectors per thread
-  constexpr int NA = BM * BK / 4 / 256;
+  constexpr int NA = BM * BK / 4 / NTH;
   // B tile: BN x BK elements loaded 16 bytes at a time
   constexpr int BVEC = (PREC == 0) ? 4 : 8;
-  constexpr int NB = BN * BK / BVEC / 256;
+  constexpr int NB = BN * BK / BVEC / NTH;
   static_assert(NA >= 1 && NB >= 1, "tile too small for 256 threads");
   __shared__ __attribute__((aligned(16))) T As[BM * LDA];
   __shared__ __attribute__((aligned(16))) T Bs[BN * LDA];
@@ -142,7 +145,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   const int tile = xcd_tile(blockIdx.x, mtiles * ntiles_n);
   const int m0 = (tile / ntiles_n) * BM, n0 = (tile % ntiles_n) * BN;
   const int tid = threadIdx.x, wid = tid >> 6;
-  const int wm0 = (wid >> 1) * WM, wn0 = (wid & 1) * WN;
+  const int wm0 = (wid / WGN) * WM, wn0 = (wid % WGN) * WN;
 
   // K tiles over all segments: cum[s] = first tile of segment s
   int cum[kMaxSeg + 1];
@@ -172,7 +175,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   bool a_ok[NA];
 #pragma unroll
   for (int j = 0; j < NA; ++j) {
-    const int v = tid + j * 256;
+    const int v = tid + j * NTH;
     const int m = m0 + v / (BK / 4);
     a_ok[j] = m < M;
     a_row[j] = min(m, M - 1);
@@ -182,7 +185,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   bool b_ok[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const int v = tid + j * 256;
+    const int v = tid + j * NTH;
     const int n = n0 + v / (BK / BVEC);
     b_ok[j] = n < g.Ncols;
     b_row[j] = min(n, g.Ncols - 1);
@@ -228,13 +231,13 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     constexpr int S = decltype(st)::value;
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-      const int v = tid + j * 256;
+      const int v = tid + j * NTH;
       const int r = v / (BK / 4), c = (v % (BK / 4)) * 4;
       store4(As + r * LDA + c, ra[S][j] * rs[S][j]);
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int v = tid + j * 256;
+      const int v = tid + j * NTH;
       const int r = v / (BK / BVEC), c = (v % (BK / BVEC)) * BVEC;
       *reinterpret_cast<f4 *>(Bs + r * LDA + c) = rb[S][j]; // 16 raw bytes
       if constexpr (SPLIT) *reinterpret_cast<f4 *>(Bl + r * LDA + c) = rl[S][j];
@@ -506,6 +509,8 @@ __global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
 
 inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 
+constexpr int kNtWGN = 4; // 8 waves per workgroup
+
 template <int PREC, int BM, int BN, int TAG>
 hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
                   hipEvent_t ev0, hipEvent_t ev1) {
@@ -513,9 +518,9 @@ hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
   dim3 grid(cdiv(capM, BM) * nt, g.splits);
   if (ev0) (void)hipEventRecord(ev0, s);
   if (PREC == 1 && g.B_lo)
-    k_gemm_nt<PREC, BM, BN, true, TAG><<<grid, 256, 0, s>>>(dims, g, nt);
+    k_gemm_nt<PREC, BM, BN, true, TAG, kNtWGN><<<grid, 128 * kNtWGN, 0, s>>>(dims, g, nt);
   else
-    k_gemm_nt<PREC, BM, BN, false, TAG><<<grid, 256, 0, s>>>(dims, g, nt);
+    k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN><<<grid, 128 * kNtWGN, 0, s>>>(dims, g, nt);
   if (ev1) (void)hipEventRecord(ev1, s);
   if (g.splits > 1)
     k_reduce_nt<<<cdiv(4LL * capM * g.Ncols, 256), 256, 0, s>>>(dims, g);
