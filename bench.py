@@ -201,7 +201,30 @@ def c3_measure(steps=8, warmup=2):
                      "launches": r["site_launches"]}
     out["workload"] = ("c3_large_bf16: 8-layer PNA, hidden 256, 1024 molecules of 10-70 atoms, "
                        "BF16 linears, FP32 aggregation, recomputation on")
+    copy = copy_bandwidth()
+    out["copy_gbs"] = copy
+    for site in ("aggregate", "aggregate_bwd"):
+        out[site]["frac_of_copy"] = out[site]["achieved"] / copy
     return out
+
+
+def copy_bandwidth(mib=1024, reps=20):
+    """Practical HBM bandwidth: a plain float4 copy of `mib` MiB (read + write)."""
+    import torch
+    from paper_2207_11333_amd import hgnn
+    n = mib << 18
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    hgnn.calib_copy(src, dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        hgnn.calib_copy(src, dst)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2 * n * 4 / sec / 1e9
 
 
 def update_gemm_flops(w, N):

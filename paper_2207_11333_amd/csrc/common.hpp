@@ -143,6 +143,7 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
                           float *partials, hipStream_t s, int tag = 0,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_calib_copy(const float *src, float *dst, long long n, hipStream_t s);
+
 // Split count launch_gemm_nt will use, and the partial buffer it needs.
 int nt_splits(int capM, int Ncols, int Ktot, int precision);
 size_t nt_partial_floats(int capM, int Ncols, int Ktot, int precision);

@@ -360,6 +360,11 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     if (e != hipSuccess) return hip_fail(c, e, "relu mask");
     du = w.du;
   }
+  // fork: the weight gradients run on the aux stream
+  hipStream_t a = c->aux;
+  e = hipEventRecord(c->fork_ev[0], s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(a, c->fork_ev[0], 0);
+  if (e != hipSuccess) return hip_fail(c, e, "fork");
   // S6: dW^p = du^T [h || A || s+ A || s- A]
   {
     GemmTN t{};
@@ -377,8 +382,8 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     t.P = c->part;
     t.splits = d.split_p;
     {
-      TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, s);
-      e = launch_gemm_tn(ex.dims, t, c->prec, s);
+      TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, a);
+      e = launch_gemm_tn(ex.dims, t, c->prec, a);
     }
     if (e == hipSuccess) {
       ReduceMap r{};
@@ -391,7 +396,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       r.Fp = d.Fp;
       r.route[0] = ReduceRoute{0, H, dWp, d.F + 12 * H, 0, dbp, 1, H};
       r.nroute = 1;
-      e = launch_reduce_map(r, s);
+      e = launch_reduce_map(r, a);
     }
     if (e != hipSuccess) return hip_fail(c, e, "update weight gradient");
   }
@@ -425,6 +430,10 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   if (e == hipSuccess)
     e = launch_transpose_sum(ex.dims, ex.N, H, w.csr.srcptr, w.csr.t2csr, w.dm, w.D, ldD, s);
   if (e != hipSuccess) return hip_fail(c, e, "aggregation adjoint");
+  // second fork: D = [D_in | D_out | De] is ready
+  e = hipEventRecord(c->fork_ev[1], s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(a, c->fork_ev[1], 0);
+  if (e != hipSuccess) return hip_fail(c, e, "fork");
   // S8: [dW_dst | dW_src] = [D_in | D_out]^T h
   {
     GemmTN t{};
@@ -437,7 +446,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     t.Ncols = d.Fp + 4;
     t.P = c->part;
     t.splits = d.split_m;
-    e = launch_gemm_tn(ex.dims, t, c->prec, s);
+    e = launch_gemm_tn(ex.dims, t, c->prec, a);
     if (e == hipSuccess) {
       const int ldm = 2 * d.F + Fe;
       ReduceMap r{};
@@ -452,7 +461,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       r.route[1] = ReduceRoute{H, 2 * H, dWm, ldm, d.F, nullptr, 0, 1};      // D_out
       r.route[2] = ReduceRoute{2 * H, ldD, nullptr, 0, 0, dWm + 2 * d.F, ldm, H}; // De
       r.nroute = Fe > 0 ? 3 : 2;
-      e = launch_reduce_map(r, s);
+      e = launch_reduce_map(r, a);
     }
     if (e != hipSuccess) return hip_fail(c, e, "message weight gradient");
   }
@@ -477,6 +486,10 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     }
     if (e != hipSuccess) return hip_fail(c, e, "input gradient GEMM");
   }
+  // join
+  e = hipEventRecord(c->join_ev, a);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join_ev, 0);
+  if (e != hipSuccess) return hip_fail(c, e, "join");
   return HGNN_OK;
 }
 
@@ -644,6 +657,13 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
     hgnn_destroy(c);
     return fail(HGNN_EDEVICE, std::string("context init: ") + hipGetErrorString(e));
   }
+  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork_ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+    hgnn_destroy(c);
+    return fail(HGNN_EDEVICE, "stream/event creation failed");
+  }
   if (stage_all(c, nullptr) || hipDeviceSynchronize() != hipSuccess) {
     hgnn_destroy(c);
     return fail(HGNN_EDEVICE, "initial weight staging failed");
@@ -660,6 +680,9 @@ void hgnn_destroy(hgnn_ctx *c) {
   free_work(c->ex);
   for (hipEvent_t ev : c->timer.ev) (void)hipEventDestroy(ev);
   c->timer.ev.clear();
+  for (hipEvent_t ev : {c->fork_ev[0], c->fork_ev[1], c->join_ev})
+    if (ev) (void)hipEventDestroy(ev);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   void **ptrs[] = {(void **)&c->params, (void **)&c->grads, (void **)&c->adam_m,
                    (void **)&c->adam_v, (void **)&c->step_dev, (void **)&c->corr,
                    (void **)&c->table, (void **)&c->ex.dims, (void **)&c->ex.w.csr.err,

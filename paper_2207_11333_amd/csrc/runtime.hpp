@@ -87,6 +87,10 @@ struct hgnn_ctx {
   int sticky = 0;
   hgnn::Server *server = nullptr;
   hgnn::SiteTimer timer;
+  // The backward pass runs the weight-gradient GEMMs on this stream,
+  // concurrently with the input-gradient chain (event fork/join).
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev = nullptr;
 };
 
 namespace hgnn {
