@@ -414,3 +414,27 @@ def test_malformed_batches_are_rejected(kind):
     m.prepare(hg.DeviceBatch.from_host(b if kind != "degree" else
                                        synth.make_batch(3, 1, 2, 2, 1)), validate=True)
     m.close()
+
+
+def test_deferred_validation_reports_through_check():
+    """Without the validate flag a malformed batch runs to completion (the
+    CSR builder skips bad edges, nothing reads out of bounds) and the error
+    surfaces at the next check."""
+    hg = _hgnn()
+    b = synth.make_batch(4, 3, 5, 8, 1)
+    ei = b.edge_index.copy()
+    ei[0, 1] = b.num_nodes + 100
+    bad = synth.Batch(b.graph_ptr, b.x, ei, b.edge_attr, b.y)
+    m = hg.Model(2, 16, 9, 1, 4, 0, 0, 1.0)
+    m.set_params(synth.init_params(synth.ModelShape(2, 16, 9, 1), 5))
+    db = hg.DeviceBatch.from_host(bad)
+    pred = torch.empty(bad.num_graphs, device="cuda")
+    m.forward(db, pred)                     # no synchronisation, no error yet
+    m.backward()
+    with pytest.raises(hg.HgnnError) as e:
+        m.check()
+    assert e.value.code == hg.EINVAL and "out of range" in str(e.value)
+    good = hg.DeviceBatch.from_host(b)
+    m.forward(good, pred)
+    m.check()                               # cleared by the next batch
+    m.close()
