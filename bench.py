@@ -28,6 +28,35 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Counter-derived HBM traffic per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+# scaled by a plain copy kernel), kept as short text summaries in profiles/.
+# Each names a digest of the kernel's sources; a summary taken before the
+# sources changed no longer describes the kernel and is not used.
+UPDATE_GEMM_TRAFFIC = ("update_gemm_c1_fp32_traffic.txt",
+                       ["csrc/gemm_nt.hip", "csrc/mfma_tile.hpp", "csrc/common.hpp"])
+AGGREGATE_TRAFFIC = {
+    "aggregate": ("aggregate_c3_traffic.txt", ["csrc/aggregate.hip", "csrc/common.hpp"]),
+    "aggregate_bwd": ("aggregate_bwd_c3_traffic.txt", ["csrc/aggregate.hip",
+                                                       "csrc/common.hpp"]),
+}
+
+
+def measured_traffic(name, sources):
+    """Bytes per launch from a committed counter summary, or None when there is
+    none or the kernel's sources changed since the counters were taken."""
+    from paper_2207_11333_amd import profile_summary as ps
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    info = ps.read_summary(path)
+    if info.get("sources_sha256") != ps.sources_digest(sources):
+        return None
+    try:
+        return float(info["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def train_rate(workload, steps, warmup, roofline_site=None):
     import torch
     from paper_2207_11333_amd import hgnn
@@ -198,7 +227,8 @@ def c3_measure(steps=8, warmup=2):
         gbs = nbytes / avg / 1e9
         out[site] = {"avg_us": avg * 1e6, "bytes_per_launch": nbytes, "achieved": gbs,
                      "unit": "GB/s", "peak": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
-                     "launches": r["site_launches"]}
+                     "launches": r["site_launches"],
+                     "traffic": measured_traffic(*AGGREGATE_TRAFFIC[site])}
     out["workload"] = ("c3_large_bf16: 8-layer PNA, hidden 256, 1024 molecules of 10-70 atoms, "
                        "BF16 linears, FP32 aggregation, recomputation on")
     copy = copy_bandwidth()
@@ -225,6 +255,18 @@ def copy_bandwidth(mib=1024, reps=20):
     sec = e0.elapsed_time(e1) / 1e3 / reps
     del src, dst
     return 2 * n * 4 / sec / 1e9
+
+
+def update_gemm_bytes(w, N):
+    """Algorithmic HBM bytes of one launch of the update linear, averaged over
+    layers: read h [N, F], A [N, 4H], the two scalers [N, 2] and the weight
+    [F + 12H, H]; write h' [N, H] once (FP32 throughout)."""
+    H, L = w.hidden, w.num_layers
+    tot = 0.0
+    for l in range(L):
+        F = 12 if l == 0 else H      # the first layer's 9 features are padded to 12
+        tot += 4.0 * (N * (F + 4 * H + 2) + (F + 12 * H) * H + N * H)
+    return tot / L
 
 
 def update_gemm_flops(w, N):
@@ -277,6 +319,13 @@ def main():
                     help="first run a 256 MiB copy kernel (counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the BF16 and serving measurements")
+    ap.add_argument("--workload", default="c1_train_fp32",
+                    choices=["c1_train_fp32", "c2_train_bf16"],
+                    help="training workload of the headline line (the BF16 choice is "
+                         "for profiling; the default line is the FP32 one)")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the large-configuration measurement (for profiling) "
+                         "and print its JSON")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -288,7 +337,8 @@ def main():
     import torch
     from paper_2207_11333_amd import synth
     torch.cuda.set_device(0)
-    w = synth.WORKLOADS["c1_train_fp32"]
+    w = synth.WORKLOADS[args.workload]
+    bf16 = w.precision == 1
     if args.calib_copy:
         from paper_2207_11333_amd import hgnn
         src = torch.ones(64 << 20, device="cuda")
@@ -296,29 +346,42 @@ def main():
         hgnn.calib_copy(src, dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_large:
+        _log("bench: large configuration only")
+        print(json.dumps({"c3": c3_measure()}), flush=True)
+        return
     _log(f"bench: {w.name} steps={args.steps} warmup={args.warmup}")
     r = train_rate(w, args.steps, args.warmup, roofline_site="update_gemm")
-    _log(f"bench: fp32 {r['graphs_per_s']:.1f} graphs/s, {r['ms_per_step']:.3f} ms/step")
+    _log(f"bench: {'bf16' if bf16 else 'fp32'} {r['graphs_per_s']:.1f} graphs/s, "
+         f"{r['ms_per_step']:.3f} ms/step")
     flops = update_gemm_flops(w, r["N"])
     avg_s = r["site_ms_total"] / 1e3 / max(1, r["site_launches"])
     achieved = flops / avg_s / 1e12
+    peak = BF16_PEAK_TFLOPS if bf16 else FP32_PEAK_TFLOPS
+    kname = f"update GEMM (S3) k_gemm_nt<{w.precision}, 64, 128, {'true' if bf16 else 'false'}, 1, 4>"
+    wdesc = (f"{w.name}: {w.num_layers}-layer PNA GCNN, hidden {w.hidden}, {w.num_graphs} "
+             f"synthetic molecules of {w.n_lo}-{w.n_hi} atoms, {w.edge_feat} edge feature, "
+             f"{'BF16 linears, FP32 aggregation' if bf16 else 'FP32'}, "
+             "CSR build + forward + backward + Adam per step")
     line = {
         "metric": "train graphs/s fwd+bwd (BF16 vs FP32) at stated error; serve p50/p99 ms",
         "value": r["graphs_per_s"], "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "c1_train_fp32: 6-layer PNA GCNN, hidden 128, 128 synthetic "
-                               "molecules of 10-60 atoms, 1 edge feature, FP32, "
-                               "CSR build + forward + backward + Adam per step",
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if bf16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": wdesc,
                    "graphs_per_step": r["B"], "nodes": r["N"], "edges": r["E"],
-                   "layers": w.num_layers, "hidden": w.hidden, "precision": "fp32"},
-        "roofline": {"kernel": "update GEMM (S3) k_gemm_nt<0, 64, 128, false, 1>", "bound": "mfma",
-                     "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                   "layers": w.num_layers, "hidden": w.hidden,
+                   "precision": "bf16" if bf16 else "fp32"},
+        "roofline": {"kernel": kname, "bound": "mfma",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak,
+                     "traffic": None if bf16 else measured_traffic(*UPDATE_GEMM_TRAFFIC),
                      "launches": r["site_launches"], "avg_us": avg_s * 1e6,
-                     "flops_per_launch": flops},
+                     "flops_per_launch": flops,
+                     "algorithmic_bytes_per_launch": update_gemm_bytes(w, r["N"])},
     }
-    if not args.no_extras:
+    if not args.no_extras and not bf16:
         rg = train_rate_graph(w, args.steps, args.warmup)
         _log(f"bench: fp32 graph-replayed {rg['graphs_per_s']:.1f} graphs/s")
         line["fp32_graph_replay"] = {"value": rg["graphs_per_s"], "unit": "graphs/s",

@@ -253,20 +253,26 @@ k_relu_mask(const Dims *__restrict__ dims, int H, const float *__restrict__ dh,
 
 } // namespace
 
+// A non-null event pair is stamped with the kernel's own start and end
+// (hipExtLaunchKernelGGL), so its elapsed time is the kernel's duration.
 hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
                             const float *PQ, const int *rowptr, const int *csr_src,
                             const float *csr_e, const float *We, int ldwe,
                             const float *bm, float *A, uint8_t *args, float eps,
-                            hipStream_t s) {
+                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (capN <= 0) return hipSuccess;
-  const int grid = cdiv((long long)capN * (H / 4), 256);
+  const dim3 grid(cdiv((long long)capN * (H / 4), 256));
+#define HGNN_AGG(FE)                                                                      \
+  hipExtLaunchKernelGGL(k_aggregate<FE>, grid, dim3(256), 0, s, ev0, ev1, 0, dims, H, PQ,  \
+                        rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps)
   switch (Fe) {
-  case 0: k_aggregate<0><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
-  case 1: k_aggregate<1><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
-  case 2: k_aggregate<2><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
-  case 3: k_aggregate<3><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
-  default: k_aggregate<4><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps); break;
+  case 0: HGNN_AGG(0); break;
+  case 1: HGNN_AGG(1); break;
+  case 2: HGNN_AGG(2); break;
+  case 3: HGNN_AGG(3); break;
+  default: HGNN_AGG(4); break;
   }
+#undef HGNN_AGG
   return hipGetLastError();
 }
 
@@ -276,12 +282,12 @@ hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
                                 const float *We, int ldwe, const float *bm,
                                 const float *A, const uint8_t *args,
                                 const float *dA, float *dm, float *D, int ldD,
-                                hipStream_t s) {
+                                hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (capN <= 0) return hipSuccess;
-  const int grid = cdiv((long long)capN * (H / 4), 256);
-#define HGNN_AGG_BWD(FE)                                                               \
-  k_aggregate_bwd<FE><<<grid, 256, 0, s>>>(dims, H, PQ, rowptr, csr_src, csr_e, We, ldwe, \
-                                           bm, A, args, dA, dm, D, ldD)
+  const dim3 grid(cdiv((long long)capN * (H / 4), 256));
+#define HGNN_AGG_BWD(FE)                                                                  \
+  hipExtLaunchKernelGGL(k_aggregate_bwd<FE>, grid, dim3(256), 0, s, ev0, ev1, 0, dims, H,  \
+                        PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, dA, dm, D, ldD)
   switch (Fe) {
   case 0: HGNN_AGG_BWD(0); break;
   case 1: HGNN_AGG_BWD(1); break;

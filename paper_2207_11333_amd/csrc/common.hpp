@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <string>
@@ -156,7 +157,8 @@ hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
                             const float *PQ, const int *rowptr,
                             const int *csr_src, const float *csr_e,
                             const float *We, int ldwe, const float *bm,
-                            float *A, uint8_t *args, float eps, hipStream_t s);
+                            float *A, uint8_t *args, float eps, hipStream_t s,
+                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_relu_mask(const Dims *dims, int capN, int H,
                             const float *dh, const float *hout, float *du,
                             hipStream_t s);
@@ -167,7 +169,8 @@ hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
                                 const float *We, int ldwe, const float *bm,
                                 const float *A, const uint8_t *args,
                                 const float *dA, float *dm, float *D, int ldD,
-                                hipStream_t s);
+                                hipStream_t s, hipEvent_t ev0 = nullptr,
+                                hipEvent_t ev1 = nullptr);
 hipError_t launch_transpose_sum(const Dims *dims, int capN, int H,
                                 const int *srcptr, const int *t2csr,
                                 const float *dm, float *D, int ldD, hipStream_t s);

@@ -1,0 +1,205 @@
+// TN-form MFMA GEMM (the weight gradients of S6 and S8, split-K over node
+// chunks) and the ordered reduction that scatters it into the packed
+// gradient.  Shared tile code: mfma_tile.hpp.
+#include "mfma_tile.hpp"
+
+namespace hgnn {
+
+namespace {
+
+// --------------------------------------------------------------------------
+// TN form (split-K weight gradients)
+// --------------------------------------------------------------------------
+template <int PREC, int BM, int BN>
+__global__ void __launch_bounds__(256)
+k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
+  using P = Prec<PREC>;
+  using T = typename P::T;
+  constexpr int BK = P::BK / 2, LDA = BK + P::PAD;
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  constexpr int NA = BM * BK / 4 / 256;
+  constexpr int NB = BN * BK / 4 / 256;
+  __shared__ __attribute__((aligned(16))) T As[BM * LDA];
+  __shared__ __attribute__((aligned(16))) T Bs[BN * LDA];
+
+  const int rows = dims->N;
+  const int mtiles = (g.M + BM - 1) / BM;
+  const int T2 = mtiles * ntiles_n;
+  const int tile = xcd_tile(blockIdx.x % T2, T2);
+  const int z = blockIdx.x / T2;
+  const int m0 = (tile / ntiles_n) * BM, n0 = (tile % ntiles_n) * BN;
+  int chunk = (rows + g.splits - 1) / g.splits;
+  chunk = (chunk + BK - 1) / BK * BK;
+  const int i_lo = z * chunk;
+  const int i_hi = min(rows, i_lo + chunk);
+  const int KT = i_hi > i_lo ? (i_hi - i_lo + BK - 1) / BK : 0;
+  const int tid = threadIdx.x, wid = tid >> 6;
+  const int wm0 = (wid >> 1) * WM, wn0 = (wid & 1) * WN;
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // Per-thread column pointers are fixed over the K loop (only the row i
+  // moves); loads are unconditional from clamped rows and masked by select.
+  f4 ra[2][NA], rb[2][NB];
+  float rsc[2][NB];
+  int a_il[NA], a_m[NA];
+  bool a_ok[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    const int v = tid + j * 256;
+    a_il[j] = v / (BM / 4);
+    const int m = m0 + (v % (BM / 4)) * 4;
+    a_ok[j] = m < g.M;
+    a_m[j] = min(m, g.M - 4);
+  }
+  const float *b_ptr[NB];
+  const float *b_sptr[NB]; // row scales, or the operand itself when unscaled
+  int b_ld[NB], b_il[NB], b_sstride[NB];
+  bool b_ok[NB], b_has_scale[NB], b_ones[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int v = tid + j * 256;
+    b_il[j] = v / (BN / 4);
+    int n = n0 + (v % (BN / 4)) * 4;
+    b_ok[j] = n < g.Ncols;
+    n = min(n, g.Ncols - 4);
+    int q = 0;
+    while (q + 1 < g.nseg && n >= g.seg[q].ncols) { n -= g.seg[q].ncols; ++q; }
+    // a constant segment reads nothing: point it at X (valid rows) and select
+    b_ones[j] = g.seg[q].ptr == nullptr;
+    b_ptr[j] = b_ones[j] ? g.X : g.seg[q].ptr + n;
+    b_ld[j] = b_ones[j] ? g.ldx : g.seg[q].ld;
+    b_has_scale[j] = g.seg[q].scale != nullptr;
+    b_sptr[j] = b_has_scale[j] ? g.seg[q].scale : b_ptr[j];
+    b_sstride[j] = b_has_scale[j] ? 1 : b_ld[j];
+    if (b_ones[j]) b_ok[j] = b_ok[j] && n == 0;
+  }
+  const int i_last = max(i_hi - 1, 0);
+  auto load = [&](auto st, int t) {
+    constexpr int S = decltype(st)::value;
+    const int i0 = i_lo + t * BK;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int i = i0 + a_il[j];
+      const f4 val = *reinterpret_cast<const f4 *>(g.X + (size_t)min(i, i_last) * g.ldx + a_m[j]);
+      ra[S][j] = (a_ok[j] && i < i_hi) ? val : f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int i = i0 + b_il[j];
+      const int ic = min(i, i_last);
+      f4 val = *reinterpret_cast<const f4 *>(b_ptr[j] + (size_t)ic * b_ld[j]);
+      const float sv = b_sptr[j][(size_t)ic * b_sstride[j]];
+      const float sc = b_has_scale[j] ? sv : 1.0f;
+      if (b_ones[j]) val = f4{1.f, 0.f, 0.f, 0.f};
+      rb[S][j] = (b_ok[j] && i < i_hi) ? val : f4{0.f, 0.f, 0.f, 0.f};
+      rsc[S][j] = sc;
+    }
+  };
+  auto stash = [&](auto st) {
+    constexpr int S = decltype(st)::value;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int v = tid + j * 256;
+      const int il = v / (BM / 4), mc = (v % (BM / 4)) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) store1(As + (mc + e) * LDA + il, ra[S][j][e]);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int v = tid + j * 256;
+      const int il = v / (BN / 4), nc = (v % (BN / 4)) * 4;
+      const f4 val = rb[S][j] * rsc[S][j];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) store1(Bs + (nc + e) * LDA + il, val[e]);
+    }
+  };
+  auto step = [&](auto st, int t) {
+    __syncthreads();
+    stash(st);
+    __syncthreads();
+    load(st, min(t + 2, KT - 1));
+    mma_tile<PREC, TM, TN, LDA, BK>(As, Bs, wm0, wn0, acc);
+  };
+
+  if (KT > 0) load(IC<0>{}, 0);
+  if (KT > 1) load(IC<1>{}, 1);
+  for (int t = 0; t < KT; t += 2) {
+    step(IC<0>{}, t);
+    if (t + 1 >= KT) break;
+    step(IC<1>{}, t + 1);
+  }
+
+  const int lane = tid & 63;
+  const int cr = 4 * (lane >> 4), cc = lane & 15;
+  float *Pz = g.P + (size_t)z * g.M * g.Ncols;
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + wn0 + j * 16 + cc;
+    if (n >= g.Ncols) continue;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm0 + i * 16 + cr + v;
+        if (m < g.M) Pz[(size_t)m * g.Ncols + n] = acc[i][j][v];
+      }
+  }
+}
+
+
+// Sum the split-K partials in order and scatter them into the packed
+// gradient layout (routes: see ReduceMap).
+__global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = gt >> 2;
+  const int q = (int)(gt & 3);
+  const long long total = (long long)r.M * r.Ncols;
+  const long long tc = t < total ? t : total - 1;
+  const float s = ordered_split_sum(r.P, r.splits, total, tc, q);
+  if (t >= total || q != 0) return;
+  const int m = (int)(t / r.Ncols), c = (int)(t % r.Ncols);
+  for (int k = 0; k < r.nroute; ++k) {
+    const ReduceRoute &ro = r.route[k];
+    if (m < ro.r0 || m >= ro.r1) continue;
+    const int u = m - ro.r0;
+    if (c < r.main_cols) {
+      if (!ro.main) return;
+      int oc;
+      if (c < r.F) oc = c;
+      else if (c < r.Fp) return;
+      else oc = c - (r.Fp - r.F);
+      ro.main[(size_t)u * ro.main_ld + ro.main_coloff + oc] = s;
+    } else if (c == r.main_cols && ro.ones) {
+      ro.ones[(size_t)(u % ro.ones_split) * ro.ones_stride + u / ro.ones_split] = s;
+    }
+    return;
+  }
+}
+
+} // namespace
+
+hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
+                          hipStream_t s) {
+  if (g.M <= 0 || g.Ncols <= 0) return hipSuccess;
+  const int nt = cdiv(g.Ncols, 64);
+  const int grid = cdiv(g.M, 64) * nt * g.splits;
+  if (precision == 0)
+    k_gemm_tn<0, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
+  else
+    k_gemm_tn<1, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s) {
+  const long long total = (long long)r.M * r.Ncols;
+  if (total <= 0) return hipSuccess;
+  k_reduce_map<<<cdiv(4 * total, 256), 256, 0, s>>>(r);
+  return hipGetLastError();
+}
+
+} // namespace hgnn

@@ -1,0 +1,145 @@
+// Shared pieces of the MFMA GEMMs (gemm_nt.hip, gemm_tn.hip): operand types
+// per precision, the XCD-aware tile order, LDS tile multiply-accumulate and
+// the ordered split-K sum.
+//
+// MFMA GEMMs of the message, update and head-free linears (steps S1, S3 and
+// their adjoints S6, S8).
+//
+// Two forms, both tiled for 256-thread workgroups (4 wave64s in a 2x2 grid)
+// with operands staged through LDS in [row][k] order (k contiguous):
+//  * gemm_nt:  C = act(sum_seg diag(scale_seg) A_seg B_seg^T + bias).  The
+//    K dimension is a list of segments so that the update input
+//    [h || A || s+ A || s- A] and the adjoint input [du || s+ du || s- du]
+//    are read in place and scaled while being staged, never materialised.
+//  * gemm_tn:  P[z] = X^T Yv over a fixed chunk z of the node rows (split-K),
+//    reduced afterwards in a fixed order: weight gradients are deterministic
+//    and need no atomics.
+// Precision 0 runs v_mfma_f32_16x16x4_f32 on FP32 operands; precision 1
+// rounds operands to BF16 (RNE, v_cvt_pk_bf16_f32) while staging and runs
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Weights in BF16 mode come
+// as a hi + lo pair of BF16 arrays (two MFMAs per tile): a weight's rounding
+// error is the same for every node, so unlike the activations' it does not
+// average out and it dominates the output error of deep stacks.
+//
+// MFMA lane layout (16x16 output block, wave64): lane l supplies row
+// (l % 16) of A and column (l % 16) of B for the k-slots of lane group
+// l / 16, and receives D[4 (l / 16) + v][l % 16] in accumulator v.  The
+// FP32 form consumes one k per lane group per instruction; a lane reads four
+// consecutive k with one 16-byte LDS load and issues four instructions, so
+// the k-slot of group g in instruction s is k = 4 g + s.  A and B use the same
+// assignment, so the sum over all k is unchanged.
+#pragma once
+#include "common.hpp"
+
+#include <type_traits>
+
+namespace hgnn {
+
+namespace {
+
+template <int PREC> struct Prec;
+template <> struct Prec<0> {
+  using T = float;
+  static constexpr int BK = 64;   // k per LDS tile
+  static constexpr int PAD = 4;   // elements of row padding (16 bytes)
+};
+template <> struct Prec<1> {
+  using T = __bf16;
+  static constexpr int BK = 64;
+  static constexpr int PAD = 8;
+};
+
+template <int V> using IC = std::integral_constant<int, V>;
+
+// Map the dispatch order (round-robin over the 8 XCDs) to output tiles so that
+// each XCD receives a contiguous range of tiles: the N tiles of one M tile,
+// which share A rows, then share that XCD's L2.  A bijection on [0, T).
+// (Measured: mapping whole node ranges to XCDs across kernels is slower.)
+__device__ __forceinline__ int xcd_tile(int bid, int T) {
+  constexpr int X = 8;
+  const int xcd = bid % X, local = bid / X;
+  const int per = T / X, rem = T % X;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+__device__ __forceinline__ void store4(float *dst, f4 v) {
+  *reinterpret_cast<f4 *>(dst) = v;
+}
+__device__ __forceinline__ void store4(__bf16 *dst, f4 v) {
+  bf16x4 b;
+  b[0] = (__bf16)v[0];
+  b[1] = (__bf16)v[1];
+  b[2] = (__bf16)v[2];
+  b[3] = (__bf16)v[3];
+  *reinterpret_cast<bf16x4 *>(dst) = b;
+}
+__device__ __forceinline__ void store1(float *dst, float v) { *dst = v; }
+__device__ __forceinline__ void store1(__bf16 *dst, float v) { *dst = (__bf16)v; }
+
+// Multiply-accumulate one BK-deep LDS tile into the wave's accumulators.
+template <int PREC, int TM, int TN, int LDA, int BK>
+__device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
+                                         const typename Prec<PREC>::T *Bs,
+                                         int wm0, int wn0, f4 (&acc)[TM][TN]) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  if constexpr (PREC == 0) {
+#pragma unroll
+    for (int kc = 0; kc < BK; kc += 16) {
+      f4 a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        a[i] = *reinterpret_cast<const f4 *>(As + (wm0 + i * 16 + r) * LDA + kc + 4 * g);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = *reinterpret_cast<const f4 *>(Bs + (wn0 + j * 16 + r) * LDA + kc + 4 * g);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int kc = 0; kc < BK; kc += 32) {
+      bf16x8 a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        a[i] = *reinterpret_cast<const bf16x8 *>(As + (wm0 + i * 16 + r) * LDA + kc + 8 * g);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn0 + j * 16 + r) * LDA + kc + 8 * g);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+}
+
+
+// Ordered sum over split partials: 4 lanes per output each add a contiguous
+// quarter of the splits in order, then the quarters are added in order
+// (a fixed association, so the result is deterministic).
+__device__ __forceinline__ float ordered_split_sum(const float *__restrict__ P, int splits,
+                                                  long long stride, long long t, int q) {
+  const int per = (splits + 3) / 4;
+  const int z0 = q * per, z1 = min(splits, z0 + per);
+  float s = 0.f;
+  for (int z = z0; z < z1; ++z) s += P[(size_t)z * stride + t];
+  const int lane = threadIdx.x & 63;
+  const float s1 = __shfl(s, (lane & ~3) + 1, 64);
+  const float s2 = __shfl(s, (lane & ~3) + 2, 64);
+  const float s3 = __shfl(s, (lane & ~3) + 3, 64);
+  const float s0 = __shfl(s, lane & ~3, 64);
+  return ((s0 + s1) + s2) + s3;
+}
+
+inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
+
+} // namespace
+
+} // namespace hgnn

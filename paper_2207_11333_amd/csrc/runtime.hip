@@ -271,10 +271,10 @@ static int message_and_aggregate(hgnn_ctx *c, Exec &ex, int l, const float *wl, 
   const float *Wm = wl + (d.oWm - d.off);
   const float *bm = wl + (d.obm - d.off);
   {
-    TimedLaunch tl(c, ex, SITE_AGGREGATE, s);
+    TimedLaunch tl(c, ex, SITE_AGGREGATE, s, /*manual=*/true);
     e = launch_aggregate(ex.dims, ex.N, H, c->Fe, PQ, w.csr.rowptr, w.csr.csr_src,
                          w.csr.csr_e, Wm + 2 * d.F, 2 * d.F + c->Fe, bm, A, args,
-                         (float)c->cfg.std_eps, s);
+                         (float)c->cfg.std_eps, s, tl.start(), tl.stop());
   }
   if (e != hipSuccess) return hip_fail(c, e, "aggregate");
   return HGNN_OK;
@@ -424,10 +424,10 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   }
   // S7: per-edge dm, D_in, De; then D_out through the transpose
   {
-    TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s);
+    TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s, /*manual=*/true);
     e = launch_aggregate_bwd(ex.dims, ex.N, H, Fe, PQ, w.csr.rowptr, w.csr.csr_src,
                              w.csr.csr_e, Wm + 2 * d.F, 2 * d.F + Fe, bm, A, args, w.dA,
-                             w.dm, w.D, ldD, s);
+                             w.dm, w.D, ldD, s, tl.start(), tl.stop());
   }
   if (e == hipSuccess)
     e = launch_transpose_sum(ex.dims, ex.N, H, w.csr.srcptr, w.csr.t2csr, w.dm, w.D, ldD, s);

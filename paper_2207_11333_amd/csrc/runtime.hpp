@@ -113,8 +113,8 @@ int stage_all(hgnn_ctx *c, hipStream_t s);
 // Records an event pair around one launch when the timer watches `site`.
 // Only the training path's launches are timed (serving lanes never are).
 // RAII form: the pair brackets everything launched in the scope.  Manual
-// form: start()/stop() hand the pair to a launcher that records it around
-// one kernel of a multi-kernel launch.
+// form: start()/stop() hand the pair to a launcher that binds it to one
+// kernel's dispatch, so the pair measures that kernel's duration alone.
 struct TimedLaunch {
   hgnn_ctx *c;
   hipStream_t s;
