@@ -56,6 +56,7 @@ __device__ __forceinline__ void put(void *dst, void *dst_lo, size_t i, float v) 
 //  Wpp   [H, Fp+12H]  W^p with its first block padded from F to Fp columns
 //  WpTA  [4H, 3H]     WpTA[c, j H + m] = W^p[m, F + 4 H j + c]
 //  WhdsT [Fp, 3H]     [W^p[:, c]; W^m[:, c]; W^m[:, F + c]]^T, zero rows c >= F
+//  weT   [Fe, H]      weT[f, c] = W^m[c, 2F + f] (FP32 in both precisions)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F, int Fp,
@@ -63,7 +64,7 @@ k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F,
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int ldm = 2 * F + Fe, ldp = F + 12 * H;
   const long long n1 = 2LL * H * Fp, n2 = (long long)H * (Fp + 12 * H);
-  const long long n3 = 12LL * H * H, n4 = 3LL * Fp * H;
+  const long long n3 = 12LL * H * H, n4 = 3LL * Fp * H, n5 = (long long)Fe * H;
   if (t < n1) {
     const int r = (int)(t / Fp), c = (int)(t % Fp);
     float v = 0.f;
@@ -92,6 +93,10 @@ k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F,
       else v = Wm[(size_t)m * ldm + F + r];
     }
     put<T>(o.hi[3], o.lo[3], u, v);
+  } else if (t < n1 + n2 + n3 + n4 + n5) {
+    const long long u = t - n1 - n2 - n3 - n4;
+    const int f = (int)(u / H), c = (int)(u % H);
+    o.weT[u] = Wm[(size_t)c * ldm + 2 * F + f];
   }
 }
 
@@ -123,7 +128,7 @@ hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_
 hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp, int H,
                               int Fe, const StageOut &o, int to_bf16, hipStream_t s) {
   const long long total = 2LL * H * Fp + (long long)H * (Fp + 12 * H) + 12LL * H * H +
-                          3LL * Fp * H;
+                          3LL * Fp * H + (long long)Fe * H;
   if (to_bf16)
     k_stage_layer<__bf16><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, o);
   else

@@ -72,7 +72,7 @@ template <int FE>
 __global__ void __launch_bounds__(256)
 k_aggregate(const Dims *__restrict__ dims, int H, const float *__restrict__ PQ,
             const int *__restrict__ rowptr, const int *__restrict__ csr_src,
-            const float *__restrict__ csr_e, const float *__restrict__ We, int ldwe,
+            const float *__restrict__ csr_e, const float *__restrict__ WeT,
             const float *__restrict__ bmv, float *__restrict__ A,
             uint8_t *__restrict__ args, float eps) {
   const int tpn = H >> 2;
@@ -86,8 +86,7 @@ k_aggregate(const Dims *__restrict__ dims, int H, const float *__restrict__ PQ,
     f4 we[4];
 #pragma unroll
     for (int f = 0; f < FE; ++f)
-      we[f] = f4{We[(size_t)(c + 0) * ldwe + f], We[(size_t)(c + 1) * ldwe + f],
-                 We[(size_t)(c + 2) * ldwe + f], We[(size_t)(c + 3) * ldwe + f]};
+      we[f] = *reinterpret_cast<const f4 *>(WeT + (size_t)f * H + c);
     const f4 bm = *reinterpret_cast<const f4 *>(bmv + c);
     const f4 p = *reinterpret_cast<const f4 *>(PQ + (size_t)i * 2 * H + c);
     f4 cache[kCache];
@@ -147,7 +146,7 @@ template <int FE>
 __global__ void __launch_bounds__(256)
 k_aggregate_bwd(const Dims *__restrict__ dims, int H, const float *__restrict__ PQ,
                 const int *__restrict__ rowptr, const int *__restrict__ csr_src,
-                const float *__restrict__ csr_e, const float *__restrict__ We, int ldwe,
+                const float *__restrict__ csr_e, const float *__restrict__ WeT,
                 const float *__restrict__ bmv, const float *__restrict__ A,
                 const uint8_t *__restrict__ args, const float *__restrict__ dA,
                 float *__restrict__ dm, float *__restrict__ D, int ldD) {
@@ -162,8 +161,7 @@ k_aggregate_bwd(const Dims *__restrict__ dims, int H, const float *__restrict__ 
     f4 we[4];
 #pragma unroll
     for (int f = 0; f < FE; ++f)
-      we[f] = f4{We[(size_t)(c + 0) * ldwe + f], We[(size_t)(c + 1) * ldwe + f],
-                 We[(size_t)(c + 2) * ldwe + f], We[(size_t)(c + 3) * ldwe + f]};
+      we[f] = *reinterpret_cast<const f4 *>(WeT + (size_t)f * H + c);
     const f4 bm = *reinterpret_cast<const f4 *>(bmv + c);
     const f4 p = *reinterpret_cast<const f4 *>(PQ + (size_t)i * 2 * H + c);
     const float *Ai = A + (size_t)i * 4 * H;
@@ -257,14 +255,14 @@ k_relu_mask(const Dims *__restrict__ dims, int H, const float *__restrict__ dh,
 // (hipExtLaunchKernelGGL), so its elapsed time is the kernel's duration.
 hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
                             const float *PQ, const int *rowptr, const int *csr_src,
-                            const float *csr_e, const float *We, int ldwe,
+                            const float *csr_e, const float *WeT,
                             const float *bm, float *A, uint8_t *args, float eps,
                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (capN <= 0) return hipSuccess;
   const dim3 grid(cdiv((long long)capN * (H / 4), 256));
 #define HGNN_AGG(FE)                                                                      \
   hipExtLaunchKernelGGL(k_aggregate<FE>, grid, dim3(256), 0, s, ev0, ev1, 0, dims, H, PQ,  \
-                        rowptr, csr_src, csr_e, We, ldwe, bm, A, args, eps)
+                        rowptr, csr_src, csr_e, WeT, bm, A, args, eps)
   switch (Fe) {
   case 0: HGNN_AGG(0); break;
   case 1: HGNN_AGG(1); break;
@@ -279,7 +277,7 @@ hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
 hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
                                 const float *PQ, const int *rowptr,
                                 const int *csr_src, const float *csr_e,
-                                const float *We, int ldwe, const float *bm,
+                                const float *WeT, const float *bm,
                                 const float *A, const uint8_t *args,
                                 const float *dA, float *dm, float *D, int ldD,
                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
@@ -287,7 +285,7 @@ hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
   const dim3 grid(cdiv((long long)capN * (H / 4), 256));
 #define HGNN_AGG_BWD(FE)                                                                  \
   hipExtLaunchKernelGGL(k_aggregate_bwd<FE>, grid, dim3(256), 0, s, ev0, ev1, 0, dims, H,  \
-                        PQ, rowptr, csr_src, csr_e, We, ldwe, bm, A, args, dA, dm, D, ldD)
+                        PQ, rowptr, csr_src, csr_e, WeT, bm, A, args, dA, dm, D, ldD)
   switch (Fe) {
   case 0: HGNN_AGG_BWD(0); break;
   case 1: HGNN_AGG_BWD(1); break;

@@ -156,7 +156,7 @@ hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s);
 hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
                             const float *PQ, const int *rowptr,
                             const int *csr_src, const float *csr_e,
-                            const float *We, int ldwe, const float *bm,
+                            const float *WeT, const float *bm,
                             float *A, uint8_t *args, float eps, hipStream_t s,
                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_relu_mask(const Dims *dims, int capN, int H,
@@ -166,7 +166,7 @@ hipError_t launch_relu_mask(const Dims *dims, int capN, int H,
 hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
                                 const float *PQ, const int *rowptr,
                                 const int *csr_src, const float *csr_e,
-                                const float *We, int ldwe, const float *bm,
+                                const float *WeT, const float *bm,
                                 const float *A, const uint8_t *args,
                                 const float *dA, float *dm, float *D, int ldD,
                                 hipStream_t s, hipEvent_t ev0 = nullptr,
@@ -200,6 +200,7 @@ hipError_t launch_adamw(float *theta, const float *g, float *m, float *v,
 struct StageOut {
   void *hi[4];
   void *lo[4];
+  float *weT; // [Fe, H] edge-feature columns of W^m, contiguous per feature (FP32)
 };
 hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp,
                               int H, int Fe, const StageOut &o, int to_bf16,

@@ -168,6 +168,7 @@ static StageOut stage_out(hgnn_ctx *c, int l) {
     o.lo[2] = c->WpTA_lo[l];
     o.lo[3] = c->WhdsT_lo[l];
   }
+  o.weT = static_cast<float *>(c->WeT[l]);
   return o;
 }
 
@@ -268,12 +269,11 @@ static int message_and_aggregate(hgnn_ctx *c, Exec &ex, int l, const float *wl, 
     e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "message GEMM");
-  const float *Wm = wl + (d.oWm - d.off);
   const float *bm = wl + (d.obm - d.off);
   {
     TimedLaunch tl(c, ex, SITE_AGGREGATE, s, /*manual=*/true);
     e = launch_aggregate(ex.dims, ex.N, H, c->Fe, PQ, w.csr.rowptr, w.csr.csr_src,
-                         w.csr.csr_e, Wm + 2 * d.F, 2 * d.F + c->Fe, bm, A, args,
+                         w.csr.csr_e, static_cast<const float *>(c->WeT[l]), bm, A, args,
                          (float)c->cfg.std_eps, s, tl.start(), tl.stop());
   }
   if (e != hipSuccess) return hip_fail(c, e, "aggregate");
@@ -351,7 +351,6 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   }
   float *PQ = w.PQ[slot], *A = w.A[slot];
   const uint8_t *args = w.args[slot];
-  const float *Wm = wl + (d.oWm - d.off);
   const float *bm = wl + (d.obm - d.off);
   float *dWm = dwl + (d.oWm - d.off), *dbm = dwl + (d.obm - d.off);
   float *dWp = dwl + (d.oWp - d.off), *dbp = dwl + (d.obp - d.off);
@@ -426,7 +425,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   {
     TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s, /*manual=*/true);
     e = launch_aggregate_bwd(ex.dims, ex.N, H, Fe, PQ, w.csr.rowptr, w.csr.csr_src,
-                             w.csr.csr_e, Wm + 2 * d.F, 2 * d.F + Fe, bm, A, args, w.dA,
+                             w.csr.csr_e, static_cast<const float *>(c->WeT[l]), bm, A, args, w.dA,
                              w.dm, w.D, ldD, s, tl.start(), tl.stop());
   }
   if (e == hipSuccess)
@@ -637,6 +636,9 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
         lo[k]->push_back(p);
       }
     }
+    float *we = nullptr;
+    if (c->Fe > 0) HGNN_CALLOC(we, (size_t)c->Fe * H);
+    c->WeT.push_back(we);
   }
 #undef HGNN_CALLOC
   // Degree-scaler table: s+(d) = ln(d+1)/delta, s-(d) = delta/ln(d+1) in FP64,
@@ -691,7 +693,7 @@ void hgnn_destroy(hgnn_ctx *c) {
                    (void **)&c->part};
   for (void **p : ptrs) dfree(*p);
   for (auto *v : {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT, &c->Wds_lo, &c->Wpp_lo, &c->WpTA_lo,
-                  &c->WhdsT_lo})
+                  &c->WhdsT_lo, &c->WeT})
     for (auto &p : *v) dfree(reinterpret_cast<void *&>(p));
   delete c;
 }

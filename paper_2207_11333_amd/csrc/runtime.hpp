@@ -81,6 +81,7 @@ struct hgnn_ctx {
   float *table = nullptr;
   std::vector<void *> Wds, Wpp, WpTA, WhdsT; // GEMM-layout weight copies per layer
   std::vector<void *> Wds_lo, Wpp_lo, WpTA_lo, WhdsT_lo; // BF16 low halves
+  std::vector<void *> WeT; // per layer [Fe, H] edge-feature weights (FP32), or null
   bool staged_from_params = false;
   float *part = nullptr;
   hgnn::Exec ex; // the training path's batch state
