@@ -1,9 +1,6 @@
 // Step S9: AdamW (Section 5.1: AdamW, learning rate 1e-3) on the packed
 // parameter vector, the refresh of the GEMM-layout weight copies, and two
 // memory utilities (a fill, and the plain copy that calibrates HBM counters).
-//
-// The bias corrections are computed on the device from a device-resident
-// step counter so that a captured training step replays correctly.
 #include "common.hpp"
 
 namespace hgnn {
@@ -12,20 +9,23 @@ namespace {
 
 inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 
-// t += 1; corr = [1/(1-b1^t), 1/(1-b2^t)] in double, stored as float.
-__global__ void k_adam_prep(long long *step, float *corr, double b1, double b2) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const long long t = *step + 1;
-    *step = t;
-    corr[0] = (float)(1.0 / (1.0 - pow(b1, (double)t)));
-    corr[1] = (float)(1.0 / (1.0 - pow(b2, (double)t)));
-  }
-}
-
+// AdamW over the packed vector.  *step counts the completed steps; this one
+// is t = *step + 1 (the staging launch that follows advances the counter).
+// Each workgroup derives the bias corrections 1/(1-b1^t), 1/(1-b2^t) in
+// double from the device-resident counter, so a captured step replays
+// correctly.
 __global__ void __launch_bounds__(256)
 k_adamw(float *__restrict__ theta, const float *__restrict__ g, float *__restrict__ m,
-        float *__restrict__ v, long long n, float lr, float b1, float omb1, float b2,
-        float omb2, float eps, float decay, const float *__restrict__ corr) {
+        float *__restrict__ v, long long n, float lr, double b1d, double b2d, float b1,
+        float omb1, float b2, float omb2, float eps, float decay,
+        const long long *__restrict__ step) {
+  __shared__ float corr[2];
+  if (threadIdx.x == 0) {
+    const double t = (double)(*step + 1);
+    corr[0] = (float)(1.0 / (1.0 - pow(b1d, t)));
+    corr[1] = (float)(1.0 / (1.0 - pow(b2d, t)));
+  }
+  __syncthreads();
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float c1 = corr[0], c2 = corr[1];
@@ -58,10 +58,9 @@ __device__ __forceinline__ void put(void *dst, void *dst_lo, size_t i, float v) 
 //  WhdsT [Fp, 3H]     [W^p[:, c]; W^m[:, c]; W^m[:, F + c]]^T, zero rows c >= F
 //  weT   [Fe, H]      weT[f, c] = W^m[c, 2F + f] (FP32 in both precisions)
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F, int Fp,
-              int H, int Fe, StageOut o) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void stage_elem(const float *__restrict__ Wm,
+                                           const float *__restrict__ Wp, int F, int Fp,
+                                           int H, int Fe, const StageOut &o, long long t) {
   const int ldm = 2 * F + Fe, ldp = F + 12 * H;
   const long long n1 = 2LL * H * Fp, n2 = (long long)H * (Fp + 12 * H);
   const long long n3 = 12LL * H * H, n4 = 3LL * Fp * H, n5 = (long long)Fe * H;
@@ -100,6 +99,24 @@ k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F,
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F, int Fp,
+              int H, int Fe, StageOut o) {
+  stage_elem<T>(Wm, Wp, F, Fp, H, Fe, o, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Every layer in one launch (blockIdx.y = layer); optionally advances the
+// AdamW step counter once the preceding update has been applied.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_stage_all(const StageDesc *__restrict__ tab, int H, int Fe, long long *bump) {
+  const StageDesc &d = tab[blockIdx.y];
+  stage_elem<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, d.o,
+                (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  if (bump && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *bump += 1;
+}
+
 __global__ void k_fill(float *p, long long n, float v) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -116,19 +133,33 @@ __global__ void __launch_bounds__(256) k_calib_copy(const f4 *__restrict__ src,
 
 hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_t n,
                         float lr, double b1, double b2, float eps, float wd,
-                        long long *step, float *corr, hipStream_t s) {
-  k_adam_prep<<<1, 64, 0, s>>>(step, corr, b1, b2);
+                        const long long *step, hipStream_t s) {
   if (n > 0)
-    k_adamw<<<cdiv(n, 256), 256, 0, s>>>(theta, g, m, v, n, lr, (float)b1,
+    k_adamw<<<cdiv(n, 256), 256, 0, s>>>(theta, g, m, v, n, lr, b1, b2, (float)b1,
                                          (float)(1.0 - b1), (float)b2, (float)(1.0 - b2),
-                                         eps, (float)(1.0 - (double)lr * wd), corr);
+                                         eps, (float)(1.0 - (double)lr * wd), step);
+  return hipGetLastError();
+}
+
+static long long stage_total(int F, int Fp, int H, int Fe) {
+  (void)F;
+  return 2LL * H * Fp + (long long)H * (Fp + 12 * H) + 12LL * H * H + 3LL * Fp * H +
+         (long long)Fe * H;
+}
+
+hipError_t launch_stage_all(const StageDesc *tab, int L, int maxFp, int H, int Fe,
+                            int to_bf16, long long *bump, hipStream_t s) {
+  const dim3 grid(cdiv(stage_total(0, maxFp, H, Fe), 256), L);
+  if (to_bf16)
+    k_stage_all<__bf16><<<grid, 256, 0, s>>>(tab, H, Fe, bump);
+  else
+    k_stage_all<float><<<grid, 256, 0, s>>>(tab, H, Fe, bump);
   return hipGetLastError();
 }
 
 hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp, int H,
                               int Fe, const StageOut &o, int to_bf16, hipStream_t s) {
-  const long long total = 2LL * H * Fp + (long long)H * (Fp + 12 * H) + 12LL * H * H +
-                          3LL * Fp * H + (long long)Fe * H;
+  const long long total = stage_total(F, Fp, H, Fe);
   if (to_bf16)
     k_stage_layer<__bf16><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, o);
   else

@@ -126,12 +126,15 @@ struct CsrBufs {
   float *sp, *sm;     // per-node degree scalers
   int *err;           // error word
 };
-hipError_t launch_set_dims(Dims *d, int B, int N, int E, hipStream_t s);
+// sets the batch sizes; also zeroes *err when err is non-null
+hipError_t launch_set_dims(Dims *d, int B, int N, int E, int *err, hipStream_t s);
+// clear_err: zero the error word first (else the caller has).  x non-null:
+// also write the first layer's input zero-padded to Fp columns into xpad.
 hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
                             const int *graph_ptr, const int *edge_index,
                             const float *edge_attr, int Fe, int max_degree,
-                            const float *scaler_table, const CsrBufs &c,
-                            hipStream_t s);
+                            const float *scaler_table, const CsrBufs &c, bool clear_err,
+                            const float *x, int F, float *xpad, int Fp, hipStream_t s);
 hipError_t launch_pad_copy(const Dims *dims, int capN, const float *x, int F,
                            float *xp, int Fp, hipStream_t s);
 
@@ -184,17 +187,20 @@ hipError_t launch_head_forward(const Dims *dims, int capB, int H,
 hipError_t launch_loss(const Dims *dims, const float *pred, const float *t,
                        float *loss, hipStream_t s);
 // dw_head receives [dW1 (H*H), db1 (H), dw2 (H), db2 (1)].
+// relu_of (nullable): write dh masked by relu_of > 0 (the ReLU adjoint of the
+// layer whose output was pooled).
 hipError_t launch_head_backward(const Dims *dims, int capB, int H,
                                 const int *graph_ptr, const float *W1,
                                 const float *w2, const float *g, const float *q,
                                 const float *pred, const float *target,
                                 const float *dpred, float *dy, float *dq,
-                                float *dh, float *dw_head, hipStream_t s);
+                                float *dh, float *dw_head, const float *relu_of,
+                                hipStream_t s);
 
 // adam.hip
-hipError_t launch_adamw(float *theta, const float *g, float *m, float *v,
-                        int64_t n, float lr, double b1, double b2, float eps,
-                        float wd, long long *step, float *corr, hipStream_t s);
+hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_t n,
+                        float lr, double b1, double b2, float eps, float wd,
+                        const long long *step, hipStream_t s);
 // Destinations of the four GEMM-layout weight copies of a layer; lo[] is
 // used only for BF16 copies (the low half of a hi + lo split).
 struct StageOut {
@@ -202,6 +208,14 @@ struct StageOut {
   void *lo[4];
   float *weT; // [Fe, H] edge-feature columns of W^m, contiguous per feature (FP32)
 };
+// per-layer staging sources and destinations, kept in device memory
+struct StageDesc {
+  const float *Wm, *Wp;
+  int F, Fp;
+  StageOut o;
+};
+hipError_t launch_stage_all(const StageDesc *tab, int L, int maxFp, int H, int Fe,
+                            int to_bf16, long long *bump, hipStream_t s);
 hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp,
                               int H, int Fe, const StageOut &o, int to_bf16,
                               hipStream_t s);

@@ -31,7 +31,9 @@ __global__ void k_set_dims(Dims *d, int B, int N, int E, int *err) {
 __global__ void k_csr_init(const Dims *__restrict__ dims,
                            const int *__restrict__ graph_ptr,
                            int *__restrict__ node_graph, int *__restrict__ cnt_in,
-                           int *__restrict__ cnt_out, int *__restrict__ err) {
+                           int *__restrict__ cnt_out, int *__restrict__ err,
+                           const float *__restrict__ x, int F, float *__restrict__ xpad,
+                           int Fp) {
   const int B = dims->B, N = dims->N;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < B) {
@@ -49,6 +51,8 @@ __global__ void k_csr_init(const Dims *__restrict__ dims,
     node_graph[i] = lo;
     cnt_in[i] = 0;
     cnt_out[i] = 0;
+    if (x) // the first layer's input, zero-padded from F to Fp columns
+      for (int c = 0; c < Fp; ++c) xpad[(size_t)i * Fp + c] = c < F ? x[(size_t)i * F + c] : 0.f;
   }
 }
 
@@ -246,20 +250,21 @@ inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 
 } // namespace
 
-hipError_t launch_set_dims(Dims *d, int B, int N, int E, hipStream_t s) {
-  k_set_dims<<<1, 64, 0, s>>>(d, B, N, E, nullptr);
+hipError_t launch_set_dims(Dims *d, int B, int N, int E, int *err, hipStream_t s) {
+  k_set_dims<<<1, 64, 0, s>>>(d, B, N, E, err);
   return hipGetLastError();
 }
 
 hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
                             const int *graph_ptr, const int *edge_index,
                             const float *edge_attr, int Fe, int max_degree,
-                            const float *table, const CsrBufs &c,
-                            hipStream_t s) {
-  k_set_dims<<<1, 64, 0, s>>>(nullptr, 0, 0, 0, c.err); // clear the error word
+                            const float *table, const CsrBufs &c, bool clear_err,
+                            const float *x, int F, float *xpad, int Fp, hipStream_t s) {
+  if (clear_err) k_set_dims<<<1, 64, 0, s>>>(nullptr, 0, 0, 0, c.err);
   const int nb = capN > capB ? capN : capB;
   k_csr_init<<<cdiv(nb > 0 ? nb : 1, 256), 256, 0, s>>>(dims, graph_ptr, c.node_graph,
-                                                        c.cnt_in, c.cnt_out, c.err);
+                                                        c.cnt_in, c.cnt_out, c.err, x, F,
+                                                        xpad, Fp);
   if (capE > 0)
     k_csr_count<<<cdiv(capE, 256), 256, 0, s>>>(dims, edge_index, c.node_graph,
                                                 c.cnt_in, c.cnt_out, c.err);

@@ -190,22 +190,27 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   }
 }
 
-// NT split-K: C = act(sum_z P[z] + bias) (* mask), z in order.
+// NT split-K: C = act(sum_z P[z] + bias) (* mask), z = 0, 1, ... in order.
+// One thread per four consecutive outputs (Ncols is a multiple of 4): its
+// loads of the splits are independent 16-byte loads, all in flight at once.
 __global__ void __launch_bounds__(256)
 k_reduce_nt(const Dims *__restrict__ dims, const GemmNT g) {
   const int M = g.M_fixed >= 0 ? g.M_fixed : dims->N;
-  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long t = gt >> 2;
-  const int q = (int)(gt & 3);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long total = (long long)M * g.Ncols;
-  const long long tc = t < total ? t : total - 1;
-  float s = ordered_split_sum(g.P, g.splits, total, tc, q);
-  if (t >= total || q != 0) return;
-  const int m = (int)(t / g.Ncols), n = (int)(t % g.Ncols);
-  if (g.bias) s += g.bias[n];
-  if (g.relu) s = s > 0.f ? s : 0.f;
-  if (g.mask && !(g.mask[(size_t)m * g.ldc + n] > 0.f)) s = 0.f;
-  g.C[(size_t)m * g.ldc + n] = s;
+  if (4 * t >= total) return;
+  const float *src = g.P + 4 * t;
+  f4 sum = *reinterpret_cast<const f4 *>(src);
+  for (int z = 1; z < g.splits; ++z) sum += *reinterpret_cast<const f4 *>(src + z * total);
+  const int m = (int)(4 * t / g.Ncols), n = (int)(4 * t % g.Ncols);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float o = sum[e] + (g.bias ? g.bias[n + e] : 0.f);
+    if (g.relu) o = o > 0.f ? o : 0.f;
+    if (g.mask && !(g.mask[(size_t)m * g.ldc + n + e] > 0.f)) o = 0.f;
+    sum[e] = o;
+  }
+  *reinterpret_cast<f4 *>(g.C + (size_t)m * g.ldc + n) = sum;
 }
 
 constexpr int kNtWGN = 4; // 8 waves per workgroup
@@ -225,7 +230,7 @@ hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
     hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN>, grid, block, 0, s, ev0,
                           ev1, 0, dims, ga, nt);
   if (g.splits > 1)
-    k_reduce_nt<<<cdiv(4LL * capM * g.Ncols, 256), 256, 0, s>>>(dims, g);
+    k_reduce_nt<<<cdiv((long long)capM * g.Ncols / 4, 256), 256, 0, s>>>(dims, g);
   return hipGetLastError();
 }
 

@@ -91,7 +91,8 @@ k_head_bwd_graph(const Dims *__restrict__ dims, int H, const int *__restrict__ g
                  const float *__restrict__ W1, const float *__restrict__ w2,
                  const float *__restrict__ q, const float *__restrict__ pred,
                  const float *__restrict__ target, const float *__restrict__ dpred,
-                 float *__restrict__ dy, float *__restrict__ dq, float *__restrict__ dh) {
+                 float *__restrict__ dy, float *__restrict__ dq, float *__restrict__ dh,
+                 const float *__restrict__ relu_of) {
   __shared__ float dqs[512];
   const int b = blockIdx.x;
   const int B = dims->B;
@@ -111,7 +112,10 @@ k_head_bwd_graph(const Dims *__restrict__ dims, int H, const int *__restrict__ g
     float s = 0.f;
     for (int c = 0; c < H; ++c) s += W1[(size_t)c * H + k] * dqs[c];
     const float v = s * inv_n;
-    for (int i = lo; i < hi; ++i) dh[(size_t)i * H + k] = v;
+    if (relu_of) // fold in the ReLU adjoint of the layer that produced h
+      for (int i = lo; i < hi; ++i) dh[(size_t)i * H + k] = relu_of[(size_t)i * H + k] > 0.f ? v : 0.f;
+    else
+      for (int i = lo; i < hi; ++i) dh[(size_t)i * H + k] = v;
   }
 }
 
@@ -174,10 +178,10 @@ hipError_t launch_head_backward(const Dims *dims, int capB, int H, const int *gr
                                 const float *W1, const float *w2, const float *g,
                                 const float *q, const float *pred, const float *target,
                                 const float *dpred, float *dy, float *dq, float *dh,
-                                float *dw_head, hipStream_t s) {
+                                float *dw_head, const float *relu_of, hipStream_t s) {
   if (capB <= 0) return hipSuccess;
   k_head_bwd_graph<<<capB, kHeadThreads, 0, s>>>(dims, H, graph_ptr, W1, w2, q, pred,
-                                                 target, dpred, dy, dq, dh);
+                                                 target, dpred, dy, dq, dh, relu_of);
   const int n = H * H + 2 * H + 1;
   k_head_bwd_weights<<<cdiv(n, kHeadOut), 256, 0, s>>>(dims, H, g, q, dy, dq, dw_head);
   return hipGetLastError();

@@ -1,6 +1,5 @@
 // Shared pieces of the MFMA GEMMs (gemm_nt.hip, gemm_tn.hip): operand types
-// per precision, the XCD-aware tile order, LDS tile multiply-accumulate and
-// the ordered split-K sum.
+// per precision, the XCD-aware tile order and the LDS tile multiply-accumulate.
 //
 // MFMA GEMMs of the message, update and head-free linears (steps S1, S3 and
 // their adjoints S6, S8).
@@ -12,8 +11,8 @@
 //    [h || A || s+ A || s- A] and the adjoint input [du || s+ du || s- du]
 //    are read in place and scaled while being staged, never materialised.
 //  * gemm_tn:  P[z] = X^T Yv over a fixed chunk z of the node rows (split-K),
-//    reduced afterwards in a fixed order: weight gradients are deterministic
-//    and need no atomics.
+//    reduced afterwards in the fixed order z = 0, 1, ...: weight gradients
+//    are deterministic and need no atomics.
 // Precision 0 runs v_mfma_f32_16x16x4_f32 on FP32 operands; precision 1
 // rounds operands to BF16 (RNE, v_cvt_pk_bf16_f32) while staging and runs
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Weights in BF16 mode come
@@ -120,23 +119,6 @@ __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
   }
 }
 
-
-// Ordered sum over split partials: 4 lanes per output each add a contiguous
-// quarter of the splits in order, then the quarters are added in order
-// (a fixed association, so the result is deterministic).
-__device__ __forceinline__ float ordered_split_sum(const float *__restrict__ P, int splits,
-                                                  long long stride, long long t, int q) {
-  const int per = (splits + 3) / 4;
-  const int z0 = q * per, z1 = min(splits, z0 + per);
-  float s = 0.f;
-  for (int z = z0; z < z1; ++z) s += P[(size_t)z * stride + t];
-  const int lane = threadIdx.x & 63;
-  const float s1 = __shfl(s, (lane & ~3) + 1, 64);
-  const float s2 = __shfl(s, (lane & ~3) + 2, 64);
-  const float s3 = __shfl(s, (lane & ~3) + 3, 64);
-  const float s0 = __shfl(s, lane & ~3, 64);
-  return ((s0 + s1) + s2) + s3;
-}
 
 inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 

@@ -172,13 +172,11 @@ static StageOut stage_out(hgnn_ctx *c, int l) {
   return o;
 }
 
-int stage_all(hgnn_ctx *c, hipStream_t s) {
-  for (int l = 0; l < c->L; ++l) {
-    const LayerDesc &d = c->ld[l];
-    hipError_t e = launch_stage_layer(c->params + d.oWm, c->params + d.oWp, d.F, d.Fp, c->H,
-                                      c->Fe, stage_out(c, l), c->prec, s);
-    if (e != hipSuccess) return hip_fail(c, e, "stage weights");
-  }
+int stage_all(hgnn_ctx *c, hipStream_t s, long long *bump_step) {
+  int maxFp = 0;
+  for (const LayerDesc &d : c->ld) maxFp = std::max(maxFp, d.Fp);
+  hipError_t e = launch_stage_all(c->stage_tab, c->L, maxFp, c->H, c->Fe, c->prec, bump_step, s);
+  if (e != hipSuccess) return hip_fail(c, e, "stage weights");
   c->staged_from_params = true;
   return HGNN_OK;
 }
@@ -223,11 +221,16 @@ int prepare(hgnn_ctx *c, Exec &ex, const hgnn_batch *b, int flags, hipStream_t s
   rc = ensure_work(c, ex, b->num_graphs, b->num_nodes, b->num_edges);
   if (rc) return rc;
   Work &w = ex.w;
-  hipError_t e = launch_set_dims(ex.dims, b->num_graphs, b->num_nodes, b->num_edges, s);
+  // the first layer's padded input is written once here, while the CSR is
+  // built; the batch's arrays are read at prepare time only
+  hipError_t e = launch_set_dims(ex.dims, b->num_graphs, b->num_nodes, b->num_edges,
+                                 w.csr.err, s);
   if (e == hipSuccess)
     e = launch_csr_build(ex.dims, b->num_graphs, b->num_nodes, b->num_edges, b->graph_ptr,
-                         b->edge_index, b->edge_attr, c->Fe, c->maxd, c->table, w.csr, s);
+                         b->edge_index, b->edge_attr, c->Fe, c->maxd, c->table, w.csr,
+                         /*clear_err=*/false, b->x, c->F0, w.xpad, c->F0p, s);
   if (e != hipSuccess) return hip_fail(c, e, "csr build");
+  ex.x_padded = true;
   ex.B = b->num_graphs;
   ex.N = b->num_nodes;
   ex.E = b->num_edges;
@@ -284,8 +287,10 @@ static const float *layer_input(hgnn_ctx *c, Exec &ex, int l, const float *h_in,
                                 hipStream_t s, int *rc) {
   *rc = HGNN_OK;
   if (l == 0) {
-    hipError_t e = launch_pad_copy(ex.dims, ex.N, h_in, c->F0, ex.w.xpad, c->F0p, s);
-    if (e != hipSuccess) *rc = hip_fail(c, e, "pad input");
+    if (!(ex.x_padded && h_in == ex.xin)) {
+      hipError_t e = launch_pad_copy(ex.dims, ex.N, h_in, c->F0, ex.w.xpad, c->F0p, s);
+      if (e != hipSuccess) *rc = hip_fail(c, e, "pad input");
+    }
     *ldh = c->F0p;
     return ex.w.xpad;
   }
@@ -507,12 +512,12 @@ int head_forward(hgnn_ctx *c, Exec &ex, const float *wh, const float *h, const f
 }
 
 int head_backward(hgnn_ctx *c, Exec &ex, const float *wh, const float *target, const float *dpred,
-                  float *dh, float *dwh, hipStream_t s) {
+                  float *dh, float *dwh, hipStream_t s, const float *relu_of = nullptr) {
   const int H = c->H;
   Work &w = ex.w;
   hipError_t e = launch_head_backward(ex.dims, ex.B, H, ex.graph_ptr, wh, wh + H * H + H,
                                       w.g, w.q, w.ypred, target, dpred, w.dy, w.dq, dh, dwh,
-                                      s);
+                                      relu_of, s);
   if (e != hipSuccess) return hip_fail(c, e, "head backward");
   return HGNN_OK;
 }
@@ -615,7 +620,6 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
   HGNN_CALLOC(c->adam_m, c->P);
   HGNN_CALLOC(c->adam_v, c->P);
   HGNN_CALLOC(c->step_dev, 1);
-  HGNN_CALLOC(c->corr, 2);
   HGNN_CALLOC(c->table, 2 * (c->maxd + 1));
   HGNN_CALLOC(c->ex.dims, 1);
   HGNN_CALLOC(c->ex.w.csr.err, 1);
@@ -639,6 +643,19 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
     float *we = nullptr;
     if (c->Fe > 0) HGNN_CALLOC(we, (size_t)c->Fe * H);
     c->WeT.push_back(we);
+  }
+  {
+    std::vector<StageDesc> tab(c->L);
+    for (int l = 0; l < c->L; ++l) {
+      const LayerDesc &d = c->ld[l];
+      tab[l] = StageDesc{c->params + d.oWm, c->params + d.oWp, d.F, d.Fp, stage_out(c, l)};
+    }
+    HGNN_CALLOC(c->stage_tab, c->L);
+    if (hipMemcpy(c->stage_tab, tab.data(), tab.size() * sizeof(StageDesc),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      hgnn_destroy(c);
+      return fail(HGNN_EDEVICE, "copying the staging table failed");
+    }
   }
 #undef HGNN_CALLOC
   // Degree-scaler table: s+(d) = ln(d+1)/delta, s-(d) = delta/ln(d+1) in FP64,
@@ -688,7 +705,7 @@ void hgnn_destroy(hgnn_ctx *c) {
     if (ev) (void)hipEventDestroy(ev);
   if (c->aux) (void)hipStreamDestroy(c->aux);
   void **ptrs[] = {(void **)&c->params, (void **)&c->grads, (void **)&c->adam_m,
-                   (void **)&c->adam_v, (void **)&c->step_dev, (void **)&c->corr,
+                   (void **)&c->adam_v, (void **)&c->step_dev, (void **)&c->stage_tab,
                    (void **)&c->table, (void **)&c->ex.dims, (void **)&c->ex.w.csr.err,
                    (void **)&c->part};
   for (void **p : ptrs) dfree(*p);
@@ -766,14 +783,16 @@ int hgnn_backward(hgnn_ctx *c, const float *dpred, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   Work &w = c->ex.w;
   float *cur = w.dh0, *nxt = w.dh1;
+  // the head adjoint already applies the last layer's ReLU adjoint, and each
+  // input gradient GEMM applies the one below it
   int rc = head_backward(c, c->ex, c->params + c->off_head, c->ex.target, dpred, cur,
-                         c->grads + c->off_head, s);
+                         c->grads + c->off_head, s, w.hbuf[c->L - 1]);
   if (rc) return rc;
   for (int l = c->L - 1; l >= 0; --l) {
     const float *h_in = l ? w.hbuf[l - 1] : c->ex.xin;
     rc = layer_backward(c, c->ex, l, c->params + c->ld[l].off, h_in, w.hbuf[l], cur,
                         l ? nxt : nullptr, c->grads + c->ld[l].off, s,
-                        /*dh_out_masked=*/l < c->L - 1, /*mask_dh_in=*/true);
+                        /*dh_out_masked=*/true, /*mask_dh_in=*/true);
     if (rc) return rc;
     std::swap(cur, nxt);
   }
@@ -788,9 +807,9 @@ int hgnn_adam_step(hgnn_ctx *c, float lr, float beta1, float beta2, float eps, f
     return fail(HGNN_EINVAL, "bad AdamW hyperparameters");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_adamw(c->params, c->grads, c->adam_m, c->adam_v, c->P, lr,
-                              (double)beta1, (double)beta2, eps, wd, c->step_dev, c->corr, s);
+                              (double)beta1, (double)beta2, eps, wd, c->step_dev, s);
   if (e != hipSuccess) return hip_fail(c, e, "adamw");
-  return stage_all(c, s);
+  return stage_all(c, s, c->step_dev); // also advances the step counter
 }
 
 // ---- checkpoint -----------------------------------------------------------

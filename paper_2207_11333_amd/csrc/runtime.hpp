@@ -43,6 +43,7 @@ struct Exec {
   const int *graph_ptr = nullptr;
   const float *xin = nullptr, *target = nullptr;
   bool prepared = false;
+  bool x_padded = false;        // w.xpad holds xin, zero-padded (written at prepare)
   bool inference_only = false;  // no backward buffers, two rotating h slots
 };
 
@@ -77,7 +78,7 @@ struct hgnn_ctx {
   std::vector<hgnn::LayerDesc> ld;
   float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
   long long *step_dev = nullptr;
-  float *corr = nullptr;
+  hgnn::StageDesc *stage_tab = nullptr; // device table for the one-launch weight staging
   float *table = nullptr;
   std::vector<void *> Wds, Wpp, WpTA, WhdsT; // GEMM-layout weight copies per layer
   std::vector<void *> Wds_lo, Wpp_lo, WpTA_lo, WhdsT_lo; // BF16 low halves
@@ -109,7 +110,9 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
                   float *h_out, hipStream_t s);
 int head_forward(hgnn_ctx *c, Exec &ex, const float *wh, const float *h,
                  const float *target, float *pred, float *loss, hipStream_t s);
-int stage_all(hgnn_ctx *c, hipStream_t s);
+// Refresh every layer's GEMM-layout weight copies from the parameters in one
+// launch; bump_step (AdamW's step counter) is advanced when non-null.
+int stage_all(hgnn_ctx *c, hipStream_t s, long long *bump_step = nullptr);
 
 // Records an event pair around one launch when the timer watches `site`.
 // Only the training path's launches are timed (serving lanes never are).

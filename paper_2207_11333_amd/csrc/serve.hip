@@ -160,7 +160,7 @@ int run_batch(Server &S, Lane &ln, const Bucket &bk) {
   const float *x = reinterpret_cast<const float *>(ln.d_stage + S.lay.off_x);
   const float *ea = c->Fe ? reinterpret_cast<const float *>(ln.d_stage + S.lay.off_ea) : nullptr;
   e = launch_csr_build(ex.dims, bk.B, bk.N, bk.E, ln.d_graph_ptr, ln.d_ei, ea, c->Fe, c->maxd,
-                       c->table, ex.w.csr, s);
+                       c->table, ex.w.csr, /*clear_err=*/true, nullptr, 0, nullptr, 0, s);
   if (e != hipSuccess) return hip_fail(c, e, "serve csr build");
   const float *h = x;
   for (int l = 0; l < c->L; ++l) {
