@@ -30,14 +30,14 @@ def _log(msg):
 
 # Counter-derived HBM traffic per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
 # scaled by a plain copy kernel), kept as short text summaries in profiles/.
-# Each names a digest of the kernel's sources; a summary taken before the
-# sources changed no longer describes the kernel and is not used.
+# Each names a digest of the file that defines the kernel (and its tile
+# header); a summary taken before that source changed no longer describes the
+# kernel and is not used.
 UPDATE_GEMM_TRAFFIC = ("update_gemm_c1_fp32_traffic.txt",
-                       ["csrc/gemm_nt.hip", "csrc/mfma_tile.hpp", "csrc/common.hpp"])
+                       ["csrc/gemm_nt.hip", "csrc/mfma_tile.hpp"])
 AGGREGATE_TRAFFIC = {
-    "aggregate": ("aggregate_c3_traffic.txt", ["csrc/aggregate.hip", "csrc/common.hpp"]),
-    "aggregate_bwd": ("aggregate_bwd_c3_traffic.txt", ["csrc/aggregate.hip",
-                                                       "csrc/common.hpp"]),
+    "aggregate": ("aggregate_c3_traffic.txt", ["csrc/aggregate.hip"]),
+    "aggregate_bwd": ("aggregate_bwd_c3_traffic.txt", ["csrc/aggregate.hip"]),
 }
 
 

@@ -153,7 +153,9 @@ int nt_splits(int capM, int Ncols, int Ktot, int precision);
 size_t nt_partial_floats(int capM, int Ncols, int Ktot, int precision);
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
                           hipStream_t s);
+// reduce.hip
 hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s);
+hipError_t launch_reduce_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s);
 
 // aggregate.hip
 hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,

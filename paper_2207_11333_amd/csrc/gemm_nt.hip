@@ -1,5 +1,6 @@
 // NT-form MFMA GEMM (steps S1, S3 and the input-gradient products of S6 and
-// S8) and its split-K reduction.  Shared tile code: mfma_tile.hpp.
+// S8); split-K partials are added by reduce.hip.  Shared tile code:
+// mfma_tile.hpp.
 #include "mfma_tile.hpp"
 
 namespace hgnn {
@@ -190,29 +191,6 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   }
 }
 
-// NT split-K: C = act(sum_z P[z] + bias) (* mask), z = 0, 1, ... in order.
-// One thread per four consecutive outputs (Ncols is a multiple of 4): its
-// loads of the splits are independent 16-byte loads, all in flight at once.
-__global__ void __launch_bounds__(256)
-k_reduce_nt(const Dims *__restrict__ dims, const GemmNT g) {
-  const int M = g.M_fixed >= 0 ? g.M_fixed : dims->N;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long total = (long long)M * g.Ncols;
-  if (4 * t >= total) return;
-  const float *src = g.P + 4 * t;
-  f4 sum = *reinterpret_cast<const f4 *>(src);
-  for (int z = 1; z < g.splits; ++z) sum += *reinterpret_cast<const f4 *>(src + z * total);
-  const int m = (int)(4 * t / g.Ncols), n = (int)(4 * t % g.Ncols);
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    float o = sum[e] + (g.bias ? g.bias[n + e] : 0.f);
-    if (g.relu) o = o > 0.f ? o : 0.f;
-    if (g.mask && !(g.mask[(size_t)m * g.ldc + n + e] > 0.f)) o = 0.f;
-    sum[e] = o;
-  }
-  *reinterpret_cast<f4 *>(g.C + (size_t)m * g.ldc + n) = sum;
-}
-
 constexpr int kNtWGN = 4; // 8 waves per workgroup
 
 template <int PREC, int BM, int BN, int TAG>
@@ -229,9 +207,9 @@ hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
   else
     hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN>, grid, block, 0, s, ev0,
                           ev1, 0, dims, ga, nt);
-  if (g.splits > 1)
-    k_reduce_nt<<<cdiv((long long)capM * g.Ncols / 4, 256), 256, 0, s>>>(dims, g);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && g.splits > 1) e = launch_reduce_nt(dims, capM, g, s);
+  return e;
 }
 
 // Output tiles are 64 rows x 128 columns: one tile spans the whole hidden

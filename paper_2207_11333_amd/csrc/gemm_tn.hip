@@ -1,6 +1,6 @@
 // TN-form MFMA GEMM (the weight gradients of S6 and S8, split-K over node
-// chunks) and the ordered reduction that scatters it into the packed
-// gradient.  Shared tile code: mfma_tile.hpp.
+// chunks; reduce.hip adds the splits in order and scatters the result into
+// the packed gradient).  Shared tile code: mfma_tile.hpp.
 #include "mfma_tile.hpp"
 
 namespace hgnn {
@@ -151,38 +151,6 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   }
 }
 
-
-// Sum the split-K partials in order and scatter them into the packed
-// gradient layout (routes: see ReduceMap).
-__global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long total = (long long)r.M * r.Ncols;
-  if (4 * t >= total) return;
-  // four consecutive columns of one row (Ncols is a multiple of 4); the
-  // splits are added in order z = 0, 1, ...
-  const float *src = r.P + 4 * t;
-  f4 sum = *reinterpret_cast<const f4 *>(src);
-  for (int z = 1; z < r.splits; ++z) sum += *reinterpret_cast<const f4 *>(src + z * total);
-  const int m = (int)(4 * t / r.Ncols), c0 = (int)(4 * t % r.Ncols);
-  for (int k = 0; k < r.nroute; ++k) {
-    const ReduceRoute &ro = r.route[k];
-    if (m < ro.r0 || m >= ro.r1) continue;
-    const int u = m - ro.r0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int c = c0 + e;
-      if (c < r.main_cols) {
-        if (!ro.main || (c >= r.F && c < r.Fp)) continue;
-        const int oc = c < r.F ? c : c - (r.Fp - r.F);
-        ro.main[(size_t)u * ro.main_ld + ro.main_coloff + oc] = sum[e];
-      } else if (c == r.main_cols && ro.ones) {
-        ro.ones[(size_t)(u % ro.ones_split) * ro.ones_stride + u / ro.ones_split] = sum[e];
-      }
-    }
-    return;
-  }
-}
-
 } // namespace
 
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
@@ -194,13 +162,6 @@ hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
     k_gemm_tn<0, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
   else
     k_gemm_tn<1, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s) {
-  const long long total = (long long)r.M * r.Ncols;
-  if (total <= 0) return hipSuccess;
-  k_reduce_map<<<cdiv(total / 4, 256), 256, 0, s>>>(r);
   return hipGetLastError();
 }
 
