@@ -264,7 +264,7 @@ def update_gemm_bytes(w, N):
     H, L = w.hidden, w.num_layers
     tot = 0.0
     for l in range(L):
-        F = 12 if l == 0 else H      # the first layer's 9 features are padded to 12
+        F = 9 if l == 0 else H
         tot += 4.0 * (N * (F + 4 * H + 2) + (F + 12 * H) * H + N * H)
     return tot / L
 
