@@ -179,6 +179,7 @@ def serve_bench(qps=500.0, warm_s=2.0, measure_s=10.0, pool=48):
         if now > total + 30:
             break
     stats = m.serve_stats()
+    sat = serve_saturation(m, reqs)
     m.serve_stop()
     m.close()
     lat = np.sort(np.asarray(lat)) * 1e3
@@ -188,7 +189,50 @@ def serve_bench(qps=500.0, warm_s=2.0, measure_s=10.0, pool=48):
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "graphs_per_s": graphs_done / measure_s, "batches": stats["batches"],
-            "graph_replays": stats["graph_replays"]}
+            "graph_replays": stats["graph_replays"], "saturation": sat}
+
+
+def serve_saturation(m, reqs, inflight=64, warm_s=1.0, measure_s=5.0):
+    """Closed loop: keep `inflight` requests submitted at all times; the
+    completion rate is the server's capacity at this request mix."""
+    import numpy as np
+    pending, lat, graphs_done, reqs_done = {}, [], 0, 0
+    t0 = time.perf_counter()
+    i = 0
+    while True:
+        now = time.perf_counter() - t0
+        if now > warm_s + measure_s:
+            break
+        while len(pending) < inflight:
+            r = reqs[i % len(reqs)]
+            t = m.serve_submit(r)
+            if t < 0:
+                break
+            pending[t] = (time.perf_counter() - t0, r.num_graphs)
+            i += 1
+        done = []
+        for t, (ts, nb) in pending.items():
+            if m.serve_poll(t, nb) is not None:
+                fin = time.perf_counter() - t0
+                if ts >= warm_s:
+                    lat.append(fin - ts)
+                    graphs_done += nb
+                    reqs_done += 1
+                done.append(t)
+        for t in done:
+            del pending[t]
+    t_drain = time.perf_counter()
+    while pending and time.perf_counter() - t_drain < 30.0:  # drain
+        for t, (ts, nb) in list(pending.items()):
+            if m.serve_poll(t, nb) is not None:
+                del pending[t]
+    if pending:
+        raise RuntimeError(f"{len(pending)} serving requests did not complete")
+    lat = np.sort(np.asarray(lat)) * 1e3
+    return {"inflight": inflight, "graphs_per_s": graphs_done / measure_s,
+            "requests_per_s": reqs_done / measure_s,
+            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None}
 
 
 def aggregate_bytes(N, E, H, Fe):
@@ -403,7 +447,8 @@ def main():
              f"{line['c3']['aggregate_bwd']['achieved']:.0f} GB/s")
         _log("bench: serving")
         line["serve"] = serve_bench(qps=args.qps)
-        _log(f"bench: serve p50 {line['serve']['p50_ms']} ms p99 {line['serve']['p99_ms']} ms")
+        _log(f"bench: serve p50 {line['serve']['p50_ms']} ms p99 {line['serve']['p99_ms']} ms; "
+             f"capacity {line['serve']['saturation']['graphs_per_s']:.0f} molecules/s")
     if not args.no_cpu_baseline:
         _log("bench: timing the FP64 oracle on the host")
         line["cpu_baseline"] = cpu_baseline(w)
