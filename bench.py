@@ -235,6 +235,64 @@ def serve_saturation(m, reqs, inflight=64, warm_s=1.0, measure_s=5.0):
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None}
 
 
+def loader_bench(steps=100, warmup=10, nbatches=16):
+    """Training fed from the packed graph store on local disk (reader threads
+    into pinned buffers, copy overlapped with compute) against the same
+    batches already resident in HBM; plus the reader alone."""
+    import tempfile
+    import torch
+    from paper_2207_11333_amd import graphstore, hgnn, synth
+    w = synth.WORKLOADS["c1_train_fp32"]
+    batches = [synth.make_batch(w.data_seed + 1000 + i, w.num_graphs, w.n_lo, w.n_hi,
+                                w.edge_feat) for i in range(nbatches)]
+    fd, path = tempfile.mkstemp(suffix=".hgnnstore")
+    os.close(fd)
+    try:
+        entries = graphstore.write_store(path, batches, edge_feat=w.edge_feat)
+        m = hgnn.Model(w.num_layers, w.hidden, 9, w.edge_feat, 4, w.precision, w.recompute,
+                       w.delta)
+        m.set_params(w.params())
+        pred = torch.empty(w.num_graphs, device="cuda")
+        loss = torch.empty(1, device="cuda")
+
+        def run(get):
+            for i in range(warmup):
+                m.forward(get(i), pred, loss)
+                m.backward()
+                m.adam_step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                m.forward(get(warmup + i), pred, loss)
+                m.backward()
+                m.adam_step()
+            torch.cuda.synchronize()
+            return w.num_graphs * steps / (time.perf_counter() - t0)
+
+        dbs = [hgnn.DeviceBatch.from_host(b) for b in batches]
+        resident = run(lambda i: dbs[i % nbatches])
+        store = hgnn.GraphStore(path, io_threads=4, host_slots=4)
+        streamed = run(lambda i: store.next())
+        # the reader alone: records per second through pinned memory to HBM
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nread = 4 * nbatches
+        for _ in range(nread):
+            store.next()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        store.close()
+        m.close()
+        rec = sum(e["bytes"] for e in entries) / nbatches
+        return {"workload": f"c1 shapes, {nbatches} distinct batches in one store file",
+                "resident_graphs_per_s": resident, "store_graphs_per_s": streamed,
+                "store_vs_resident": streamed / resident,
+                "reader_batches_per_s": nread / dt, "reader_MB_per_s": nread * rec / dt / 1e6,
+                "record_bytes": rec}
+    finally:
+        os.unlink(path)
+
+
 def aggregate_bytes(N, E, H, Fe):
     """Algorithmic bytes of one forward aggregation launch (S2): gathered Q
     rows (E x H), own P rows (N x H), CSR arrays and edge attributes read; the
@@ -449,6 +507,11 @@ def main():
         line["serve"] = serve_bench(qps=args.qps)
         _log(f"bench: serve p50 {line['serve']['p50_ms']} ms p99 {line['serve']['p99_ms']} ms; "
              f"capacity {line['serve']['saturation']['graphs_per_s']:.0f} molecules/s")
+        _log("bench: training fed from the packed graph store")
+        line["loader"] = loader_bench()
+        _log(f"bench: store {line['loader']['store_graphs_per_s']:.1f} graphs/s vs resident "
+             f"{line['loader']['resident_graphs_per_s']:.1f}; reader "
+             f"{line['loader']['reader_MB_per_s']:.0f} MB/s")
     if not args.no_cpu_baseline:
         _log("bench: timing the FP64 oracle on the host")
         line["cpu_baseline"] = cpu_baseline(w)

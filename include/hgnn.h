@@ -233,6 +233,41 @@ int hgnn_serve_stats_get(hgnn_ctx *ctx, hgnn_serve_stats *out);
 /* Drain in-flight work and stop the thread. */
 int hgnn_serve_stop(hgnn_ctx *ctx);
 
+/* ---- packed graph store (Section 3.3: I/O; Table 1: graph layout) ------ */
+/* A binary file of batches in the Table 1 layout, one contiguous record per
+ * batch (graph_ptr, x, edge_index, edge_attr, y), read by host threads into
+ * pinned buffers and copied to the device on the store's own stream, so the
+ * copy of the next batch overlaps the caller's compute.  File format: a
+ * 64-byte header ("HGNNSTR1", version 1, num_batches, node_feat, edge_feat,
+ * has_y, index offset), an index of {offset, bytes, B, N, E} per batch, and
+ * 4096-aligned records whose sections start 256-byte aligned in the order
+ * graph_ptr i32 [B+1], x f32 [N, F], edge_index i32 [2, E], edge_attr f32
+ * [E, Fe], y f32 [B].  The writer is paper_2207_11333_amd/graphstore.py. */
+typedef struct hgnn_store hgnn_store;
+
+typedef struct {
+  int32_t num_batches, node_feat, edge_feat, has_y;
+  int32_t max_graphs, max_nodes, max_edges, reserved;
+  int64_t max_record_bytes;
+} hgnn_store_info;
+
+/* Open a store on the current device: io_threads (1..64) reader threads,
+ * host_slots (2..64) pinned record buffers, two device record buffers.
+ * EINVAL for a missing or malformed file, ENOMEM when buffers fail. */
+int hgnn_store_open(const char *path, int32_t io_threads, int32_t host_slots,
+                    hgnn_store **out);
+int hgnn_store_info_get(const hgnn_store *store, hgnn_store_info *info);
+/* The next batch in file order, cycling over the file: fills *out with
+ * device pointers (owned by the store) and *index (may be NULL) with its
+ * position in the file.  `stream` is made to wait for the batch's copy; the
+ * pointers stay valid for all work enqueued on that stream until the next
+ * call, which releases them.  Blocks while the batch is still being read.
+ * EINVAL after a read error, EDEVICE when a HIP call fails. */
+int hgnn_store_next(hgnn_store *store, void *stream, hgnn_batch *out,
+                    int64_t *index);
+/* Stop the readers, wait for copies in flight, free everything. */
+int hgnn_store_close(hgnn_store *store);
+
 const char *hgnn_last_error(void);
 
 #ifdef __cplusplus

@@ -53,6 +53,14 @@ class ServeConfig(ctypes.Structure):
                 ("use_graphs", ctypes.c_int32)]
 
 
+class StoreInfo(ctypes.Structure):
+    _fields_ = [("num_batches", ctypes.c_int32), ("node_feat", ctypes.c_int32),
+                ("edge_feat", ctypes.c_int32), ("has_y", ctypes.c_int32),
+                ("max_graphs", ctypes.c_int32), ("max_nodes", ctypes.c_int32),
+                ("max_edges", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_record_bytes", ctypes.c_int64)]
+
+
 class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
@@ -91,6 +99,10 @@ _SIGS = {
     "hgnn_timer_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)], _I),
     "hgnn_calib_copy": ([_P, _P, ctypes.c_int64, _P], _I),
     "hgnn_last_error": ([], ctypes.c_char_p),
+    "hgnn_store_open": ([ctypes.c_char_p, _I, _I, ctypes.POINTER(_P)], _I),
+    "hgnn_store_info_get": ([_P, _P], _I),
+    "hgnn_store_next": ([_P, _P, ctypes.POINTER(CBatch), ctypes.POINTER(ctypes.c_int64)], _I),
+    "hgnn_store_close": ([_P], _I),
 }
 
 
@@ -157,6 +169,54 @@ class DeviceBatch:
                       self.edge_index.data_ptr() if self.num_edges else None,
                       None if self.edge_attr is None else self.edge_attr.data_ptr(),
                       None if (self.y is None or not with_y) else self.y.data_ptr())
+
+
+class StoreBatch:
+    """A batch handed out by GraphStore.next(): device pointers owned by the
+    store, valid for work enqueued on the stream until the next call."""
+
+    def __init__(self, cb: CBatch, index: int):
+        self._cb = cb
+        self.index = index
+        self.num_graphs, self.num_nodes, self.num_edges = cb.num_graphs, cb.num_nodes, cb.num_edges
+
+    def cstruct(self, with_y: bool = True) -> CBatch:
+        if with_y:
+            return self._cb
+        cb = CBatch.from_buffer_copy(self._cb)
+        cb.y = None
+        return cb
+
+
+class GraphStore:
+    """Reader of a packed graph store file (see graphstore.py): io_threads
+    host threads read records into pinned buffers; next() returns the next
+    batch on the device, its copy overlapped with the caller's compute."""
+
+    def __init__(self, path: str, io_threads: int = 4, host_slots: int = 4):
+        h = ctypes.c_void_p()
+        _check(lib().hgnn_store_open(path.encode(), io_threads, host_slots, ctypes.byref(h)))
+        self.handle = h
+        info = StoreInfo()
+        _check(lib().hgnn_store_info_get(self.handle, ctypes.byref(info)))
+        self.info = {k: int(getattr(info, k)) for k, _ in StoreInfo._fields_}
+
+    def next(self) -> StoreBatch:
+        cb = CBatch()
+        idx = ctypes.c_int64()
+        _check(lib().hgnn_store_next(self.handle, _stream(), ctypes.byref(cb), ctypes.byref(idx)))
+        return StoreBatch(cb, int(idx.value))
+
+    def close(self):
+        if self.handle:
+            _check(lib().hgnn_store_close(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def host_cbatch(b):
