@@ -356,6 +356,16 @@ def backward(rec: ForwardRecord, dpred: Optional[np.ndarray] = None,
     dh = np.zeros((N, H))
     for b in range(B):
         dh[gp[b]:gp[b + 1]] = dg[b] / (gp[b + 1] - gp[b])
+    dh = layers_backward(rec, dh, G, hint, tau, stats)
+    return pack(G, L), dh, stats
+
+
+def layers_backward(rec, dh, G, hint: Optional[Decisions], tau: float, stats):
+    """Adjoint of the GC stack: from dL/dh of the last layer's output, fill the
+    layer gradients into G and return dL/dx (Section 3.2, backward phase)."""
+    cfg, P, csr = rec.cfg, rec.P, rec.csr
+    L, H = cfg["num_layers"], cfg["hidden"]
+    N = rec.layers[0].h_in.shape[0]
     src, dst = rec.edge_index
     for l in reversed(range(L)):
         lr = rec.layers[l]
@@ -397,7 +407,7 @@ def backward(rec: ForwardRecord, dpred: Optional[np.ndarray] = None,
         np.add.at(dh_prev, dst, dz[:, 0:F])
         np.add.at(dh_prev, src, dz[:, F:2 * F])
         dh = dh_prev
-    return pack(G, L), dh, stats
+    return dh
 
 
 # --------------------------------------------------------------------------
