@@ -103,6 +103,28 @@ typedef struct {
  * Parameters start at zero: set them with hgnn_set_params.  EINVAL for a bad
  * config (checked before any device call), EDEVICE/ENOMEM otherwise. */
 int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out);
+
+/* Multitask heads (HydraGNN's multi-headed outputs; the paper's model has one
+ * graph-level head, which is what hgnn_create builds).  graph_heads Tg in 1..8
+ * graph-level heads on the pooled embedding, node_heads Tn in 0..4
+ * node-level heads on every node's last-layer embedding, each head
+ * Linear(H,H)-ReLU-Linear(H,1).  Loss = sum_t graph_weights[t] mean_b
+ * (y[b,t] - Y[b,t])^2 + sum_s node_weights[s] mean_i (z[i,s] - Z[i,s])^2
+ * (weight arrays are host memory, >= 0, NULL = all 1).  Packed parameters:
+ * the layers, then the Tg graph heads, then the Tn node heads, each head
+ * W1 [H,H], b1 [H], w2 [1,H], b2 [1].  Such a model is trained through
+ * hgnn_forward_multitask, hgnn_backward (no dpred) and hgnn_adam_step;
+ * serving and the per-operation head entries take single-head models only.
+ * The config's `reserved` field records (Tg, Tn) and is part of a
+ * checkpoint's identity. */
+typedef struct {
+  int32_t graph_heads, node_heads;
+  int32_t reserved[2];
+  const float *graph_weights; /* host [graph_heads] or NULL */
+  const float *node_weights;  /* host [node_heads] or NULL */
+} hgnn_heads;
+int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads,
+                          hgnn_ctx **out);
 void hgnn_destroy(hgnn_ctx *ctx); /* synchronises; NULL is ignored */
 int hgnn_num_params(const hgnn_ctx *ctx, int64_t *out);
 /* Copy the packed parameters in (device [P]) and refresh the internal GEMM
@@ -122,6 +144,14 @@ int hgnn_check(hgnn_ctx *ctx, void *stream);
  * buffers: keep them alive until hgnn_backward is done). */
 int hgnn_forward(hgnn_ctx *ctx, const hgnn_batch *batch, float *pred_dev,
                  float *loss_dev, int32_t flags, void *stream);
+/* Forward of a multitask model: batch->y is [B, Tg] (row-major), y_node_dev
+ * [N, Tn] (device; NULL when no loss is wanted), pred_dev [B, Tg],
+ * pred_node_dev [N, Tn] (required when Tn > 0).  The targets must stay
+ * valid until hgnn_backward.  hgnn_forward is this call with Tn = 0. */
+int hgnn_forward_multitask(hgnn_ctx *ctx, const hgnn_batch *batch,
+                           const float *y_node_dev, float *pred_dev,
+                           float *pred_node_dev, float *loss_dev, int32_t flags,
+                           void *stream);
 /* Gradients of the loss of the last forward (dpred_dev == NULL, needs
  * batch->y) or of sum(dpred * y) (dpred_dev [B]) into the context's packed
  * gradient vector. */
@@ -177,9 +207,10 @@ int hgnn_op_head_backward(hgnn_ctx *ctx, const float *w_head_dev,
  *   4 srcptr [N+1]  5 t2csr [E]    6 node_graph [N]          (int32)
  *   7 aggregates A of `layer` [N, 4H] (float32)
  *   8 arg decisions of `layer` [N, 2H] (uint8: argmin offsets then argmax)
- *   9 head hidden activations ReLU(W1 g + b1) [B, H] (float32)
+ *   9 hidden activations ReLU(W1 g + b1) of graph head `layer` [B, H] (float32)
  *  10 pooled features g [B, H] (float32)
  *  11 output of `layer` from the last hgnn_forward [N, H] (float32)
+ *  12 hidden activations ReLU(W1 h + b1) of node head `layer` [N, H] (float32)
  * Copies into dst_dev (capacity bytes); EINVAL if too small or not stored. */
 int hgnn_op_fetch(hgnn_ctx *ctx, int32_t which, int32_t layer, void *dst_dev,
                   size_t capacity, void *stream);

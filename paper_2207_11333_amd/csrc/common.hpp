@@ -180,25 +180,37 @@ hipError_t launch_transpose_sum(const Dims *dims, int capN, int H,
                                 const int *srcptr, const int *t2csr,
                                 const float *dm, float *D, int ldD, hipStream_t s);
 // head.hip
-hipError_t launch_head_forward(const Dims *dims, int capB, int H,
-                               const int *graph_ptr, const float *h,
-                               const float *W1, const float *b1,
-                               const float *w2, const float *b2, float *g,
-                               float *q, float *pred, float *pred2,
+// Graph heads (Tg, packed head after head: W1 [H,H], b1, w2, b2): pooled
+// embedding g [B, H], q [Tg][B][H], predictions pred (and pred2 if non-null)
+// [B, Tg].
+hipError_t launch_head_forward(const Dims *dims, int capB, int H, int Tg,
+                               const int *graph_ptr, const float *h, const float *wh,
+                               float *g, float *q, float *pred, float *pred2,
                                hipStream_t s);
-hipError_t launch_loss(const Dims *dims, const float *pred, const float *t,
-                       float *loss, hipStream_t s);
-// dw_head receives [dW1 (H*H), db1 (H), dw2 (H), db2 (1)].
+// loss = sum_t gw_t mean_b (pred - t)^2 + sum_s nw_s mean_i (z - zt)^2
+// (gw, nw nullable: weight 1).
+hipError_t launch_loss(const Dims *dims, int Tg, const float *pred, const float *t,
+                       const float *gw, int Tn, const float *z, const float *zt,
+                       const float *nw, float *loss, hipStream_t s);
+// dw_head receives, per graph head, [dW1 (H*H), db1 (H), dw2 (H), db2 (1)].
 // relu_of (nullable): write dh masked by relu_of > 0 (the ReLU adjoint of the
-// layer whose output was pooled).
-hipError_t launch_head_backward(const Dims *dims, int capB, int H,
-                                const int *graph_ptr, const float *W1,
-                                const float *w2, const float *g, const float *q,
-                                const float *pred, const float *target,
-                                const float *dpred, float *dy, float *dq,
+// layer whose output was pooled); add (nullable) [N, H] is added to dh first.
+hipError_t launch_head_backward(const Dims *dims, int capB, int H, int Tg,
+                                const int *graph_ptr, const float *wh, const float *g,
+                                const float *q, const float *pred, const float *target,
+                                const float *dpred, const float *gw, float *dy, float *dq,
                                 float *dh, float *dw_head, const float *relu_of,
-                                hipStream_t s);
-
+                                const float *add, hipStream_t s);
+// Node heads (Tn): aligned weight copies, outputs, errors and small gradients.
+hipError_t launch_stage_node_heads(int H, int Tn, const float *wn, float *W1n, float *W1nT,
+                                   hipStream_t s);
+hipError_t launch_node_head_out(const Dims *dims, int capN, int H, int Tn, const float *Qn,
+                                const float *wn, float *z, float *z2, hipStream_t s);
+hipError_t launch_node_head_err(const Dims *dims, int capN, int H, int Tn, const float *Qn,
+                                const float *wn, const float *z, const float *zt,
+                                const float *nw, float *e, float *dQ, hipStream_t s);
+hipError_t launch_node_head_small(const Dims *dims, int capN, int H, int Tn, const float *Qn,
+                                  const float *e, float *gwn, hipStream_t s);
 // adam.hip
 hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_t n,
                         float lr, double b1, double b2, float eps, float wd,

@@ -1,6 +1,8 @@
 // Steps S4 and S5: global mean pooling over each graph's nodes (Section 3.1),
 // the fully connected head Linear(H,H)-ReLU-Linear(H,1), the MSE loss
-// (Section 3.2) and their adjoint.  One workgroup per graph; every reduction
+// (Section 3.2) and their adjoint; generalised to several graph-level heads
+// and to node-level heads (HydraGNN's multi-headed outputs) with a weighted
+// sum of the heads' losses.  One workgroup per graph; every reduction
 // runs in a fixed order, so results are deterministic and a graph's
 // prediction does not depend on the other graphs of the batch.
 #include "common.hpp"
@@ -11,6 +13,7 @@ namespace {
 
 inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 constexpr int kHeadThreads = 256;
+constexpr int kMaxGraphHeads = 8;
 
 // Node range of graph b, clamped to [0, N] so that an unvalidated malformed
 // graph_ptr (reported through the error word) never leads out of bounds.
@@ -33,17 +36,21 @@ __device__ float block_sum(float v, float *red) {
   return r;
 }
 
+// Graph head t of Tg (blockIdx.y): head weights at wh + t (H^2 + 2H + 1) as
+// W1 [H, H], b1 [H], w2 [H], b2 [1]; q of head t at q + (t B + b) H; the
+// prediction goes to pred[b Tg + t].
 __global__ void __launch_bounds__(kHeadThreads)
-k_head_forward(const Dims *__restrict__ dims, int H, const int *__restrict__ gptr,
-               const float *__restrict__ h, const float *__restrict__ W1,
-               const float *__restrict__ b1, const float *__restrict__ w2,
-               const float *__restrict__ b2, float *__restrict__ g,
-               float *__restrict__ q, float *__restrict__ pred,
+k_head_forward(const Dims *__restrict__ dims, int H, int Tg, const int *__restrict__ gptr,
+               const float *__restrict__ h, const float *__restrict__ wh,
+               float *__restrict__ g, float *__restrict__ q, float *__restrict__ pred,
                float *__restrict__ pred2) {
   __shared__ float gs[512];
   __shared__ float red[kHeadThreads];
-  const int b = blockIdx.x;
-  if (b >= dims->B) return;
+  const int b = blockIdx.x, t = blockIdx.y;
+  const int B = dims->B;
+  if (b >= B) return;
+  const float *W1 = wh + (size_t)t * (H * H + 2 * H + 1);
+  const float *b1 = W1 + H * H, *w2 = b1 + H, *b2 = w2 + H;
   int lo, hi;
   graph_range(gptr, b, dims->N, lo, hi);
   const float inv_n = 1.0f / (float)(hi - lo);
@@ -52,57 +59,83 @@ k_head_forward(const Dims *__restrict__ dims, int H, const int *__restrict__ gpt
     for (int i = lo; i < hi; ++i) s += h[(size_t)i * H + c];
     const float gv = s * inv_n;
     gs[c] = gv;
-    g[(size_t)b * H + c] = gv;
+    if (t == 0) g[(size_t)b * H + c] = gv;
   }
   __syncthreads();
+  float *qt = q + ((size_t)t * B + b) * H;
   float part = 0.f;
   for (int c = threadIdx.x; c < H; c += kHeadThreads) {
     float s = b1[c];
     const float *row = W1 + (size_t)c * H;
     for (int k = 0; k < H; ++k) s += row[k] * gs[k];
     const float qv = s > 0.f ? s : 0.f;
-    q[(size_t)b * H + c] = qv;
+    qt[c] = qv;
     part += w2[c] * qv;
   }
   const float y = block_sum(part, red) + b2[0];
   if (threadIdx.x == 0) {
-    pred[b] = y;
-    if (pred2) pred2[b] = y;
+    pred[(size_t)b * Tg + t] = y;
+    if (pred2) pred2[(size_t)b * Tg + t] = y;
   }
 }
 
+// loss = sum_t gw_t mean_b (pred - y)^2 + sum_s nw_s mean_i (z - z_target)^2,
+// each mean a fixed-order workgroup sum (weights default to 1).
 __global__ void __launch_bounds__(kHeadThreads)
-k_loss(const Dims *__restrict__ dims, const float *__restrict__ pred,
-       const float *__restrict__ t, float *__restrict__ loss) {
+k_loss(const Dims *__restrict__ dims, int Tg, const float *__restrict__ pred,
+       const float *__restrict__ t, const float *__restrict__ gw, int Tn,
+       const float *__restrict__ z, const float *__restrict__ zt,
+       const float *__restrict__ nw, float *__restrict__ loss) {
   __shared__ float red[kHeadThreads];
-  const int B = dims->B;
-  float s = 0.f;
-  for (int b = threadIdx.x; b < B; b += kHeadThreads) {
-    const float d = pred[b] - t[b];
-    s += d * d;
+  const int B = dims->B, N = dims->N;
+  float acc = 0.f;
+  for (int k = 0; k < Tg; ++k) {
+    float s = 0.f;
+    for (int b = threadIdx.x; b < B; b += kHeadThreads) {
+      const float d = pred[(size_t)b * Tg + k] - t[(size_t)b * Tg + k];
+      s += d * d;
+    }
+    acc += (gw ? gw[k] : 1.0f) * (block_sum(s, red) / (float)B);
   }
-  const float tot = block_sum(s, red);
-  if (threadIdx.x == 0) *loss = tot / (float)B;
+  for (int k = 0; k < Tn; ++k) {
+    float s = 0.f;
+    for (int i = threadIdx.x; i < N; i += kHeadThreads) {
+      const float d = z[(size_t)i * Tn + k] - zt[(size_t)i * Tn + k];
+      s += d * d;
+    }
+    acc += (nw ? nw[k] : 1.0f) * (block_sum(s, red) / (float)N);
+  }
+  if (threadIdx.x == 0) *loss = acc;
 }
 
-// Per graph: dy, dq = dy w2 * [q > 0], dg = W1^T dq, dh_i = dg / n_b.
+// Per graph, for every graph head t: dy, dq_t = dy w2_t * [q_t > 0]; then
+// dg = sum_t W1_t^T dq_t and dh_i = dg / n_b (+ add_i, the node heads' share),
+// masked by relu_of > 0 when given.
 __global__ void __launch_bounds__(kHeadThreads)
-k_head_bwd_graph(const Dims *__restrict__ dims, int H, const int *__restrict__ gptr,
-                 const float *__restrict__ W1, const float *__restrict__ w2,
-                 const float *__restrict__ q, const float *__restrict__ pred,
-                 const float *__restrict__ target, const float *__restrict__ dpred,
+k_head_bwd_graph(const Dims *__restrict__ dims, int H, int Tg, const int *__restrict__ gptr,
+                 const float *__restrict__ wh, const float *__restrict__ q,
+                 const float *__restrict__ pred, const float *__restrict__ target,
+                 const float *__restrict__ dpred, const float *__restrict__ gw,
                  float *__restrict__ dy, float *__restrict__ dq, float *__restrict__ dh,
-                 const float *__restrict__ relu_of) {
-  __shared__ float dqs[512];
+                 const float *__restrict__ relu_of, const float *__restrict__ add) {
+  __shared__ float dqs[kMaxGraphHeads * 512];
   const int b = blockIdx.x;
   const int B = dims->B;
   if (b >= B) return;
-  const float dyb = dpred ? dpred[b] : 2.0f * (pred[b] - target[b]) / (float)B;
-  if (threadIdx.x == 0) dy[b] = dyb;
-  for (int c = threadIdx.x; c < H; c += kHeadThreads) {
-    const float v = q[(size_t)b * H + c] > 0.f ? dyb * w2[c] : 0.f;
-    dqs[c] = v;
-    dq[(size_t)b * H + c] = v;
+  const size_t HS = (size_t)H * H + 2 * H + 1;
+  for (int t = 0; t < Tg; ++t) {
+    const size_t o = (size_t)b * Tg + t;
+    const float dyb = dpred ? dpred[o]
+                            : (2.0f * (pred[o] - target[o]) / (float)B) * (gw ? gw[t] : 1.0f);
+    if (threadIdx.x == 0) dy[o] = dyb;
+    const float *w2 = wh + t * HS + H * H + H;
+    const float *qt = q + ((size_t)t * B + b) * H;
+    float *dqt = dq + ((size_t)t * B + b) * H;
+    for (int c = threadIdx.x; c < H; c += kHeadThreads) {
+      const float v = qt[c] > 0.f ? dyb * w2[c] : 0.f;
+      dqs[t * H + c] = v;
+      dqt[c] = v;
+    }
   }
   __syncthreads();
   int lo, hi;
@@ -110,12 +143,17 @@ k_head_bwd_graph(const Dims *__restrict__ dims, int H, const int *__restrict__ g
   const float inv_n = 1.0f / (float)(hi - lo);
   for (int k = threadIdx.x; k < H; k += kHeadThreads) {
     float s = 0.f;
-    for (int c = 0; c < H; ++c) s += W1[(size_t)c * H + k] * dqs[c];
+    for (int t = 0; t < Tg; ++t) {
+      const float *W1 = wh + t * HS;
+      for (int c = 0; c < H; ++c) s += W1[(size_t)c * H + k] * dqs[t * H + c];
+    }
     const float v = s * inv_n;
-    if (relu_of) // fold in the ReLU adjoint of the layer that produced h
-      for (int i = lo; i < hi; ++i) dh[(size_t)i * H + k] = relu_of[(size_t)i * H + k] > 0.f ? v : 0.f;
-    else
-      for (int i = lo; i < hi; ++i) dh[(size_t)i * H + k] = v;
+    for (int i = lo; i < hi; ++i) {
+      float o = add ? v + add[(size_t)i * H + k] : v;
+      // fold in the ReLU adjoint of the layer that produced h
+      if (relu_of && !(relu_of[(size_t)i * H + k] > 0.f)) o = 0.f;
+      dh[(size_t)i * H + k] = o;
+    }
   }
 }
 
@@ -126,14 +164,23 @@ k_head_bwd_graph(const Dims *__restrict__ dims, int H, const int *__restrict__ g
 constexpr int kHeadOut = 32, kHeadParts = 8;
 
 __global__ void __launch_bounds__(256)
-k_head_bwd_weights(const Dims *__restrict__ dims, int H, const float *__restrict__ g,
-                   const float *__restrict__ q, const float *__restrict__ dy,
-                   const float *__restrict__ dq, float *__restrict__ out) {
+k_head_bwd_weights(const Dims *__restrict__ dims, int H, int Tg, const float *__restrict__ g,
+                   const float *__restrict__ qall, const float *__restrict__ dyall,
+                   const float *__restrict__ dqall, float *__restrict__ outall) {
   __shared__ float red[kHeadParts][kHeadOut];
   const int o = threadIdx.x % kHeadOut, p = threadIdx.x / kHeadOut;
   const int t = blockIdx.x * kHeadOut + o;
   const int B = dims->B;
   const int n1 = H * H, total = n1 + 2 * H + 1;
+  // graph head blockIdx.y: its q, dq, dy column and output block
+  const int hd = blockIdx.y;
+  const float *q = qall + (size_t)hd * B * H, *dq = dqall + (size_t)hd * B * H;
+  float *out = outall + (size_t)hd * total;
+  struct Col {
+    const float *p;
+    int s;
+    __device__ float operator[](int b) const { return p[(size_t)b * s]; }
+  } dy{dyall + hd, Tg};
   float s = 0.f;
   if (t < n1) {
     const int c = t / H, k = t % H;
@@ -156,34 +203,149 @@ k_head_bwd_weights(const Dims *__restrict__ dims, int H, const float *__restrict
   }
 }
 
+// ---- node-level heads (Tn of them; head s at wn + s (H^2 + 2H + 1)) ------
+// Their hidden layer Q_s = ReLU(h W1_s^T + b1_s) [N, H] comes from the NT
+// GEMM (Q_s at Qn + s capN H); these kernels do the rest.
+
+// 16-byte-aligned copies of W1_s for the GEMMs: W1n [Tn][H][H] as stored and
+// W1nT [H][Tn H] with W1nT[n][s H + c] = W1_s[c][n].
+__global__ void __launch_bounds__(256)
+k_stage_node_heads(int H, int Tn, const float *__restrict__ wn, float *__restrict__ W1n,
+                   float *__restrict__ W1nT) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n = (long long)Tn * H * H;
+  if (t >= n) return;
+  const int sh = (int)(t / ((long long)H * H)), r = (int)((t / H) % H), k = (int)(t % H);
+  const float v = wn[(size_t)sh * (H * H + 2 * H + 1) + (size_t)r * H + k];
+  W1n[t] = v;
+  W1nT[(size_t)k * Tn * H + (size_t)sh * H + r] = v;
+}
+
+// z[i, s] = w2_s . Q_s[i] + b2_s (one thread per node and head).
+__global__ void __launch_bounds__(256)
+k_node_head_out(const Dims *__restrict__ dims, int H, int Tn, size_t capN,
+                const float *__restrict__ Qn, const float *__restrict__ wn,
+                float *__restrict__ z, float *__restrict__ z2) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = dims->N;
+  if (t >= (long long)N * Tn) return;
+  const int i = (int)(t / Tn), sh = (int)(t % Tn);
+  const float *w2 = wn + (size_t)sh * (H * H + 2 * H + 1) + H * H + H;
+  const float *q = Qn + (size_t)sh * capN * H + (size_t)i * H;
+  float acc = w2[H];
+  for (int c = 0; c < H; ++c) acc += w2[c] * q[c];
+  z[t] = acc;
+  if (z2) z2[t] = acc;
+}
+
+// e[i, s] = 2 nw_s (z - z_target) / N and dQ_s[i, c] = e w2_s[c] [Q_s[i, c] > 0].
+__global__ void __launch_bounds__(256)
+k_node_head_err(const Dims *__restrict__ dims, int H, int Tn, size_t capN,
+                const float *__restrict__ Qn, const float *__restrict__ wn,
+                const float *__restrict__ z, const float *__restrict__ zt,
+                const float *__restrict__ nw, float *__restrict__ e, float *__restrict__ dQ) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = dims->N;
+  if (t >= (long long)N * Tn * H) return;
+  const int c = (int)(t % H);
+  const long long is = t / H;
+  const int i = (int)(is / Tn), sh = (int)(is % Tn);
+  const float ev = (2.0f * (z[is] - zt[is]) / (float)N) * (nw ? nw[sh] : 1.0f);
+  if (c == 0) e[is] = ev;
+  const size_t o = (size_t)sh * capN * H + (size_t)i * H + c;
+  const float w2 = wn[(size_t)sh * (H * H + 2 * H + 1) + H * H + H + c];
+  dQ[o] = Qn[o] > 0.f ? ev * w2 : 0.f;
+}
+
+// dw2_s[c] = sum_i e[i, s] Q_s[i, c] and db2_s = sum_i e[i, s], in a fixed
+// order: 4 row groups x 64 columns per pass, the 4 partials added in order.
+__global__ void __launch_bounds__(256)
+k_node_head_small(const Dims *__restrict__ dims, int H, int Tn, size_t capN,
+                  const float *__restrict__ Qn, const float *__restrict__ e,
+                  float *__restrict__ gwn) {
+  __shared__ float red[4][64];
+  const int sh = blockIdx.x;
+  const int N = dims->N;
+  const int col = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const float *Q = Qn + (size_t)sh * capN * H;
+  float *dw2 = gwn + (size_t)sh * (H * H + 2 * H + 1) + H * H + H;
+  for (int c0 = 0; c0 <= H; c0 += 64) {
+    const int c = c0 + col;
+    float s = 0.f;
+    if (c < H)
+      for (int i = rg; i < N; i += 4) s += e[(size_t)i * Tn + sh] * Q[(size_t)i * H + c];
+    else if (c == H)
+      for (int i = rg; i < N; i += 4) s += e[(size_t)i * Tn + sh];
+    red[rg][col] = s;
+    __syncthreads();
+    if (rg == 0 && c <= H) dw2[c] = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
+    __syncthreads();
+  }
+}
+
 } // namespace
 
-hipError_t launch_head_forward(const Dims *dims, int capB, int H, const int *graph_ptr,
-                               const float *h, const float *W1, const float *b1,
-                               const float *w2, const float *b2, float *g, float *q,
+hipError_t launch_stage_node_heads(int H, int Tn, const float *wn, float *W1n, float *W1nT,
+                                   hipStream_t s) {
+  const long long n = (long long)Tn * H * H;
+  if (n <= 0) return hipSuccess;
+  k_stage_node_heads<<<cdiv(n, 256), 256, 0, s>>>(H, Tn, wn, W1n, W1nT);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_head_out(const Dims *dims, int capN, int H, int Tn, const float *Qn,
+                                const float *wn, float *z, float *z2, hipStream_t s) {
+  if (capN <= 0 || Tn <= 0) return hipSuccess;
+  k_node_head_out<<<cdiv((long long)capN * Tn, 256), 256, 0, s>>>(dims, H, Tn, (size_t)capN,
+                                                                  Qn, wn, z, z2);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_head_err(const Dims *dims, int capN, int H, int Tn, const float *Qn,
+                                const float *wn, const float *z, const float *zt,
+                                const float *nw, float *e, float *dQ, hipStream_t s) {
+  if (capN <= 0 || Tn <= 0) return hipSuccess;
+  k_node_head_err<<<cdiv((long long)capN * Tn * H, 256), 256, 0, s>>>(
+      dims, H, Tn, (size_t)capN, Qn, wn, z, zt, nw, e, dQ);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_head_small(const Dims *dims, int capN, int H, int Tn, const float *Qn,
+                                  const float *e, float *gwn, hipStream_t s) {
+  if (Tn <= 0) return hipSuccess;
+  k_node_head_small<<<Tn, 256, 0, s>>>(dims, H, Tn, (size_t)capN, Qn, e, gwn);
+  return hipGetLastError();
+}
+
+hipError_t launch_head_forward(const Dims *dims, int capB, int H, int Tg, const int *graph_ptr,
+                               const float *h, const float *wh, float *g, float *q,
                                float *pred, float *pred2, hipStream_t s) {
   if (capB <= 0) return hipSuccess;
-  k_head_forward<<<capB, kHeadThreads, 0, s>>>(dims, H, graph_ptr, h, W1, b1, w2, b2, g,
-                                               q, pred, pred2);
+  k_head_forward<<<dim3(capB, Tg), kHeadThreads, 0, s>>>(dims, H, Tg, graph_ptr, h, wh, g, q,
+                                                         pred, pred2);
   return hipGetLastError();
 }
 
-hipError_t launch_loss(const Dims *dims, const float *pred, const float *t, float *loss,
-                       hipStream_t s) {
-  k_loss<<<1, kHeadThreads, 0, s>>>(dims, pred, t, loss);
+hipError_t launch_loss(const Dims *dims, int Tg, const float *pred, const float *t,
+                       const float *gw, int Tn, const float *z, const float *zt,
+                       const float *nw, float *loss, hipStream_t s) {
+  k_loss<<<1, kHeadThreads, 0, s>>>(dims, Tg, pred, t, gw, Tn, z, zt, nw, loss);
   return hipGetLastError();
 }
 
-hipError_t launch_head_backward(const Dims *dims, int capB, int H, const int *graph_ptr,
-                                const float *W1, const float *w2, const float *g,
-                                const float *q, const float *pred, const float *target,
-                                const float *dpred, float *dy, float *dq, float *dh,
-                                float *dw_head, const float *relu_of, hipStream_t s) {
+hipError_t launch_head_backward(const Dims *dims, int capB, int H, int Tg, const int *graph_ptr,
+                                const float *wh, const float *g, const float *q,
+                                const float *pred, const float *target, const float *dpred,
+                                const float *gw, float *dy, float *dq, float *dh,
+                                float *dw_head, const float *relu_of, const float *add,
+                                hipStream_t s) {
   if (capB <= 0) return hipSuccess;
-  k_head_bwd_graph<<<capB, kHeadThreads, 0, s>>>(dims, H, graph_ptr, W1, w2, q, pred,
-                                                 target, dpred, dy, dq, dh, relu_of);
+  if (Tg < 1 || Tg > kMaxGraphHeads || H > 512) return hipErrorInvalidValue;
+  k_head_bwd_graph<<<capB, kHeadThreads, 0, s>>>(dims, H, Tg, graph_ptr, wh, q, pred, target,
+                                                 dpred, gw, dy, dq, dh, relu_of, add);
   const int n = H * H + 2 * H + 1;
-  k_head_bwd_weights<<<cdiv(n, kHeadOut), 256, 0, s>>>(dims, H, g, q, dy, dq, dw_head);
+  k_head_bwd_weights<<<dim3(cdiv(n, kHeadOut), Tg), 256, 0, s>>>(dims, H, Tg, g, q, dy, dq,
+                                                                 dw_head);
   return hipGetLastError();
 }
 

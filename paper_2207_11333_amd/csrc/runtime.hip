@@ -69,7 +69,8 @@ void free_work(Exec &ex) {
                    (void **)&w.csr.sm, (void **)&w.xpad, (void **)&w.g, (void **)&w.q,
                    (void **)&w.ypred, (void **)&w.dy, (void **)&w.dq, (void **)&w.du,
                    (void **)&w.dA, (void **)&w.dm, (void **)&w.D, (void **)&w.dh0,
-                   (void **)&w.dh1, (void **)&w.ntpart};
+                   (void **)&w.dh1, (void **)&w.ntpart, (void **)&w.zn, (void **)&w.Qn,
+                   (void **)&w.dQn, (void **)&w.en, (void **)&w.dhn};
   for (void **p : ptrs) dfree(*p);
   for (auto &p : w.hbuf) dfree(reinterpret_cast<void *&>(p));
   for (auto &p : w.PQ) dfree(reinterpret_cast<void *&>(p));
@@ -109,13 +110,19 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
   for (int l = 0; l < nstore && ok; ++l)
     ok = f(w.PQ[l], (size_t)capN * 2 * H) && f(w.A[l], (size_t)capN * 4 * H) &&
          f(w.args[l], (size_t)capN * 2 * H);
-  ok = ok && f(w.g, (size_t)capB * H) && f(w.q, (size_t)capB * H) && f(w.ypred, (size_t)capB);
+  const int Tg = c->Tg, Tn = c->Tn;
+  ok = ok && f(w.g, (size_t)capB * H) && f(w.q, (size_t)Tg * capB * H) &&
+       f(w.ypred, (size_t)capB * Tg);
+  if (Tn > 0) ok = ok && f(w.zn, (size_t)capN * Tn) && f(w.Qn, (size_t)Tn * capN * H);
   {
     const size_t np = nt_partial_floats(capN, H, 12 * H, c->prec);
     ok = ok && f(w.ntpart, np);
   }
   if (!inference) {
-    ok = ok && f(w.dq, (size_t)capB * H) && f(w.dy, (size_t)capB);
+    ok = ok && f(w.dq, (size_t)Tg * capB * H) && f(w.dy, (size_t)capB * Tg);
+    if (Tn > 0)
+      ok = ok && f(w.dQn, (size_t)Tn * capN * H) && f(w.en, (size_t)capN * Tn) &&
+           f(w.dhn, (size_t)capN * H);
     ok = ok && f(w.du, (size_t)capN * H) && f(w.dA, (size_t)capN * 4 * H) &&
          f(w.dm, (size_t)capE * H) && f(w.D, (size_t)capN * (2 + c->Fe) * H) &&
          f(w.dh0, (size_t)capN * H) && f(w.dh1, (size_t)capN * H);
@@ -499,25 +506,109 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   return HGNN_OK;
 }
 
+// Graph heads (and, in the fused path, node heads) and the weighted loss.
 int head_forward(hgnn_ctx *c, Exec &ex, const float *wh, const float *h, const float *target,
-                 float *pred, float *loss, hipStream_t s) {
-  const int H = c->H;
+                 float *pred, float *loss, hipStream_t s, float *pred_node,
+                 const float *ynode) {
+  const int H = c->H, Tn = c->Tn;
   Work &w = ex.w;
-  hipError_t e = launch_head_forward(ex.dims, ex.B, H, ex.graph_ptr, h, wh, wh + H * H,
-                                     wh + H * H + H, wh + H * H + 2 * H, w.g, w.q, w.ypred,
-                                     pred, s);
-  if (e == hipSuccess && loss && target) e = launch_loss(ex.dims, w.ypred, target, loss, s);
+  hipError_t e = launch_head_forward(ex.dims, ex.B, H, c->Tg, ex.graph_ptr, h, wh, w.g, w.q,
+                                     w.ypred, pred, s);
+  if (e == hipSuccess && Tn > 0) {
+    const float *wn = c->params + c->off_node;
+    e = launch_stage_node_heads(H, Tn, wn, c->W1n, c->W1nT, s);
+    for (int k = 0; k < Tn && e == hipSuccess; ++k) {
+      GemmNT g{};
+      g.nseg = 1;
+      g.seg[0] = SegA{h, nullptr, H, H, 0};
+      g.B = c->W1n + (size_t)k * H * H;
+      g.ldb = H;
+      g.Ncols = H;
+      g.bias = wn + (size_t)k * node_head_size(H) + (size_t)H * H;
+      g.relu = 1;
+      g.C = w.Qn + (size_t)k * ex.N * H;
+      g.ldc = H;
+      g.M_fixed = -1;
+      e = launch_gemm_nt(ex.dims, ex.N, g, /*precision=*/0, w.ntpart, s);
+    }
+    if (e == hipSuccess) e = launch_node_head_out(ex.dims, ex.N, H, Tn, w.Qn, wn, w.zn,
+                                                  pred_node, s);
+  }
+  if (e == hipSuccess && loss && target)
+    e = launch_loss(ex.dims, c->Tg, w.ypred, target, c->gw_dev, Tn, w.zn, ynode, c->nw_dev,
+                    loss, s);
   if (e != hipSuccess) return hip_fail(c, e, "head forward");
   return HGNN_OK;
 }
 
+// Node heads' adjoint (fused path): their weight gradients and their share
+// of dL/dh (into w.dhn).  h: the last layer's output.
+static int node_heads_backward(hgnn_ctx *c, Exec &ex, const float *h, hipStream_t s) {
+  const int H = c->H, Tn = c->Tn;
+  Work &w = ex.w;
+  const float *wn = c->params + c->off_node;
+  float *gwn = c->grads + c->off_node;
+  hipError_t e = launch_node_head_err(ex.dims, ex.N, H, Tn, w.Qn, wn, w.zn, ex.ynode,
+                                      c->nw_dev, w.en, w.dQn, s);
+  for (int k = 0; k < Tn && e == hipSuccess; ++k) {
+    float *dW1 = gwn + (size_t)k * node_head_size(H);
+    GemmTN t{};
+    t.X = w.dQn + (size_t)k * ex.N * H;
+    t.ldx = H;
+    t.M = H;
+    t.seg[0] = SegY{h, nullptr, H, H};
+    t.seg[1] = SegY{nullptr, nullptr, 0, 4}; // sum column: db1
+    t.nseg = 2;
+    t.Ncols = H + 4;
+    t.P = c->part;
+    t.splits = c->split_node;
+    e = launch_gemm_tn(ex.dims, t, /*precision=*/0, s);
+    if (e == hipSuccess) {
+      ReduceMap r{};
+      r.P = c->part;
+      r.splits = c->split_node;
+      r.M = H;
+      r.Ncols = H + 4;
+      r.main_cols = H;
+      r.F = H;
+      r.Fp = H;
+      r.route[0] = ReduceRoute{0, H, dW1, H, 0, dW1 + (size_t)H * H, 1, H};
+      r.nroute = 1;
+      e = launch_reduce_map(r, s);
+    }
+  }
+  if (e == hipSuccess) e = launch_node_head_small(ex.dims, ex.N, H, Tn, w.Qn, w.en, gwn, s);
+  if (e == hipSuccess) {
+    GemmNT g{};
+    g.nseg = Tn;
+    for (int k = 0; k < Tn; ++k)
+      g.seg[k] = SegA{w.dQn + (size_t)k * ex.N * H, nullptr, H, H, k * H};
+    g.B = c->W1nT;
+    g.ldb = Tn * H;
+    g.Ncols = H;
+    g.C = w.dhn;
+    g.ldc = H;
+    g.M_fixed = -1;
+    e = launch_gemm_nt(ex.dims, ex.N, g, /*precision=*/0, w.ntpart, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "node heads backward");
+  return HGNN_OK;
+}
+
 int head_backward(hgnn_ctx *c, Exec &ex, const float *wh, const float *target, const float *dpred,
-                  float *dh, float *dwh, hipStream_t s, const float *relu_of = nullptr) {
+                  float *dh, float *dwh, hipStream_t s, const float *relu_of = nullptr,
+                  const float *h_last = nullptr) {
   const int H = c->H;
   Work &w = ex.w;
-  hipError_t e = launch_head_backward(ex.dims, ex.B, H, ex.graph_ptr, wh, wh + H * H + H,
-                                      w.g, w.q, w.ypred, target, dpred, w.dy, w.dq, dh, dwh,
-                                      relu_of, s);
+  const float *add = nullptr;
+  if (c->Tn > 0) {
+    int rc = node_heads_backward(c, ex, h_last, s);
+    if (rc) return rc;
+    add = w.dhn;
+  }
+  hipError_t e = launch_head_backward(ex.dims, ex.B, H, c->Tg, ex.graph_ptr, wh, w.g, w.q,
+                                      w.ypred, target, dpred, c->gw_dev, w.dy, w.dq, dh, dwh,
+                                      relu_of, add, s);
   if (e != hipSuccess) return hip_fail(c, e, "head backward");
   return HGNN_OK;
 }
@@ -541,8 +632,22 @@ extern "C" {
 const char *hgnn_last_error(void) { return g_err.c_str(); }
 
 int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
+  return hgnn_create_multitask(cfg, nullptr, out);
+}
+
+int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_ctx **out) {
   if (!cfg || !out) return fail(HGNN_EINVAL, "cfg and out are required");
   *out = nullptr;
+  const int Tg = heads ? heads->graph_heads : 1, Tn = heads ? heads->node_heads : 0;
+  if (Tg < 1 || Tg > 8) return fail(HGNN_EINVAL, "graph_heads must be in 1..8");
+  if (Tn < 0 || Tn > 4) return fail(HGNN_EINVAL, "node_heads must be in 0..4");
+  std::vector<float> gw(Tg, 1.0f), nw(Tn, 1.0f);
+  for (int k = 0; heads && heads->graph_weights && k < Tg; ++k) gw[k] = heads->graph_weights[k];
+  for (int k = 0; heads && heads->node_weights && k < Tn; ++k) nw[k] = heads->node_weights[k];
+  for (float v : gw)
+    if (!(v >= 0.f) || !std::isfinite(v)) return fail(HGNN_EINVAL, "loss weights must be >= 0");
+  for (float v : nw)
+    if (!(v >= 0.f) || !std::isfinite(v)) return fail(HGNN_EINVAL, "loss weights must be >= 0");
   if (cfg->num_layers < 1 || cfg->num_layers > 64)
     return fail(HGNN_EINVAL, "num_layers must be in 1..64");
   if (cfg->hidden < 16 || cfg->hidden > 512 || cfg->hidden % 16)
@@ -597,9 +702,18 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
     part_max = std::max(part_max, std::max(a, b));
     c->ld.push_back(d);
   }
+  c->Tg = Tg;
+  c->Tn = Tn;
+  c->cfg.reserved = Tg + 256 * Tn; // part of the checkpoint's identity
   c->off_head = off;
-  off += (int64_t)H * H + H + H + 1;
+  off += (int64_t)Tg * node_head_size(H);
+  c->off_node = off;
+  off += (int64_t)Tn * node_head_size(H);
   c->P = off;
+  if (Tn > 0) {
+    c->split_node = tn_splits(H, H + 4);
+    part_max = std::max(part_max, (size_t)c->split_node * H * (H + 4));
+  }
 
   hipError_t e = hipGetDevice(&c->dev);
   int ndev = 0;
@@ -624,6 +738,18 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
   HGNN_CALLOC(c->ex.dims, 1);
   HGNN_CALLOC(c->ex.w.csr.err, 1);
   HGNN_CALLOC(c->part, part_max);
+  HGNN_CALLOC(c->gw_dev, Tg);
+  if (Tn > 0) {
+    HGNN_CALLOC(c->nw_dev, Tn);
+    HGNN_CALLOC(c->W1n, (size_t)Tn * H * H);
+    HGNN_CALLOC(c->W1nT, (size_t)Tn * H * H);
+  }
+  if (hipMemcpy(c->gw_dev, gw.data(), Tg * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      (Tn > 0 && hipMemcpy(c->nw_dev, nw.data(), Tn * sizeof(float), hipMemcpyHostToDevice) !=
+                     hipSuccess)) {
+    hgnn_destroy(c);
+    return fail(HGNN_EDEVICE, "copying the loss weights failed");
+  }
   const size_t esz = c->prec ? 2 : 4;
   for (int l = 0; l < c->L; ++l) {
     const LayerDesc &d = c->ld[l];
@@ -706,6 +832,8 @@ void hgnn_destroy(hgnn_ctx *c) {
   if (c->aux) (void)hipStreamDestroy(c->aux);
   void **ptrs[] = {(void **)&c->params, (void **)&c->grads, (void **)&c->adam_m,
                    (void **)&c->adam_v, (void **)&c->step_dev, (void **)&c->stage_tab,
+                   (void **)&c->gw_dev, (void **)&c->nw_dev, (void **)&c->W1n,
+                   (void **)&c->W1nT,
                    (void **)&c->table, (void **)&c->ex.dims, (void **)&c->ex.w.csr.err,
                    (void **)&c->part};
   for (void **p : ptrs) dfree(*p);
@@ -759,12 +887,23 @@ int hgnn_check(hgnn_ctx *c, void *stream) {
 int hgnn_forward(hgnn_ctx *c, const hgnn_batch *b, float *pred, float *loss, int32_t flags,
                  void *stream) {
   HGNN_GUARD(c);
-  if (!pred) return fail(HGNN_EINVAL, "pred_dev is NULL");
-  if (loss && !b->y) return fail(HGNN_EINVAL, "loss requested without targets");
+  if (c->Tn > 0) return fail(HGNN_EINVAL, "node heads present: use hgnn_forward_multitask");
+  return hgnn_forward_multitask(c, b, nullptr, pred, nullptr, loss, flags, stream);
+}
+
+int hgnn_forward_multitask(hgnn_ctx *c, const hgnn_batch *b, const float *y_node,
+                           float *pred, float *pred_node, float *loss, int32_t flags,
+                           void *stream) {
+  HGNN_GUARD(c);
+  if (!pred || !b) return fail(HGNN_EINVAL, "batch and pred_dev are required");
+  if (c->Tn > 0 && !pred_node) return fail(HGNN_EINVAL, "pred_node_dev is NULL");
+  if (loss && (!b->y || (c->Tn > 0 && !y_node)))
+    return fail(HGNN_EINVAL, "loss requested without targets");
   hipStream_t s = (hipStream_t)stream;
   Exec &ex = c->ex;
   int rc = prepare(c, ex, b, flags, s);
   if (rc) return rc;
+  ex.ynode = y_node;
   if (!c->staged_from_params && (rc = stage_all(c, s))) return rc;
   const float *h = b->x;
   for (int l = 0; l < c->L; ++l) {
@@ -772,13 +911,17 @@ int hgnn_forward(hgnn_ctx *c, const hgnn_batch *b, float *pred, float *loss, int
     if (rc) return rc;
     h = c->ex.w.hbuf[l];
   }
-  return head_forward(c, ex, c->params + c->off_head, h, b->y, pred, loss, s);
+  return head_forward(c, ex, c->params + c->off_head, h, b->y, pred, loss, s, pred_node,
+                      y_node);
 }
 
 int hgnn_backward(hgnn_ctx *c, const float *dpred, void *stream) {
   HGNN_GUARD(c);
   if (!c->ex.prepared) return fail(HGNN_EINVAL, "no forward to differentiate");
   if (!dpred && !c->ex.target) return fail(HGNN_EINVAL, "no targets and no dpred");
+  if (dpred && (c->Tg != 1 || c->Tn != 0))
+    return fail(HGNN_EINVAL, "dpred_dev needs a single graph head and no node head");
+  if (c->Tn > 0 && !c->ex.ynode) return fail(HGNN_EINVAL, "no node targets in the forward");
   if (!c->staged_from_params) return fail(HGNN_EINVAL, "weights changed since the forward");
   hipStream_t s = (hipStream_t)stream;
   Work &w = c->ex.w;
@@ -786,7 +929,7 @@ int hgnn_backward(hgnn_ctx *c, const float *dpred, void *stream) {
   // the head adjoint already applies the last layer's ReLU adjoint, and each
   // input gradient GEMM applies the one below it
   int rc = head_backward(c, c->ex, c->params + c->off_head, c->ex.target, dpred, cur,
-                         c->grads + c->off_head, s, w.hbuf[c->L - 1]);
+                         c->grads + c->off_head, s, w.hbuf[c->L - 1], w.hbuf[c->L - 1]);
   if (rc) return rc;
   for (int l = c->L - 1; l >= 0; --l) {
     const float *h_in = l ? w.hbuf[l - 1] : c->ex.xin;
@@ -857,7 +1000,8 @@ int hgnn_set_state(hgnn_ctx *c, const void *buf, size_t bytes) {
   if (bytes < sizeof(h)) return fail(HGNN_EINVAL, "state buffer too small");
   std::memcpy(&h, buf, sizeof(h));
   if (std::memcmp(h.magic, "HGNNST01", 8) != 0) return fail(HGNN_EINVAL, "not an hgnn state");
-  if (h.P != c->P || h.cfg.num_layers != c->cfg.num_layers || h.cfg.hidden != c->cfg.hidden ||
+  if (h.P != c->P || h.cfg.reserved != c->cfg.reserved ||
+      h.cfg.num_layers != c->cfg.num_layers || h.cfg.hidden != c->cfg.hidden ||
       h.cfg.node_feat != c->cfg.node_feat || h.cfg.edge_feat != c->cfg.edge_feat)
     return fail(HGNN_EINVAL, "state belongs to a different model shape");
   const size_t n = (size_t)c->P * sizeof(float);
@@ -917,6 +1061,8 @@ int hgnn_op_head_forward(hgnn_ctx *c, const float *wh, const float *h, const flo
   if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
   if (!wh || !h || !pred) return fail(HGNN_EINVAL, "NULL buffer");
   if (loss && !target) return fail(HGNN_EINVAL, "loss requested without targets");
+  if (c->Tg != 1 || c->Tn != 0)
+    return fail(HGNN_EINVAL, "the per-operation head entries take one graph head only");
   return head_forward(c, c->ex, wh, h, target, pred, loss, (hipStream_t)stream);
 }
 
@@ -927,6 +1073,8 @@ int hgnn_op_head_backward(hgnn_ctx *c, const float *wh, const float *h, const fl
   if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
   if (!wh || !dh || !dwh) return fail(HGNN_EINVAL, "NULL buffer");
   if (!dpred && !target) return fail(HGNN_EINVAL, "need dpred or targets");
+  if (c->Tg != 1 || c->Tn != 0)
+    return fail(HGNN_EINVAL, "the per-operation head entries take one graph head only");
   return head_backward(c, c->ex, wh, target, dpred, dh, dwh, (hipStream_t)stream);
 }
 
@@ -1004,7 +1152,16 @@ int hgnn_op_fetch(hgnn_ctx *c, int32_t which, int32_t layer, void *dst, size_t c
     else { src = w.args[slot]; bytes = (size_t)N * 2 * H; }
     break;
   }
-  case 9: src = w.q; bytes = (size_t)B * H * 4; break;
+  case 9: // q of graph head `layer`
+    if (layer < 0 || layer >= c->Tg) return fail(HGNN_EINVAL, "graph head out of range");
+    src = w.q + (size_t)layer * B * H;
+    bytes = (size_t)B * H * 4;
+    break;
+  case 12: // hidden layer of node head `layer`
+    if (layer < 0 || layer >= c->Tn) return fail(HGNN_EINVAL, "node head out of range");
+    src = w.Qn + (size_t)layer * N * H;
+    bytes = (size_t)N * H * 4;
+    break;
   case 10: src = w.g; bytes = (size_t)B * H * 4; break;
   case 11:
     if (layer < 0 || layer >= c->L) return fail(HGNN_EINVAL, "layer out of range");

@@ -31,6 +31,9 @@ struct Work {
   float *D = nullptr;                    // [N, (2 + Fe) H] = [D_in | D_out | De]
   float *dh0 = nullptr, *dh1 = nullptr;
   float *ntpart = nullptr;               // split-K partials of the NT GEMMs
+  // node heads: outputs [N, Tn], hidden [Tn][N][H], its adjoint, errors
+  // [N, Tn], and their share of dL/dh [N, H]
+  float *zn = nullptr, *Qn = nullptr, *dQn = nullptr, *en = nullptr, *dhn = nullptr;
 };
 
 // Batch-local execution state: device size header, CSR, activations and
@@ -42,12 +45,16 @@ struct Exec {
   int B = 0, N = 0, E = 0;
   const int *graph_ptr = nullptr;
   const float *xin = nullptr, *target = nullptr;
+  const float *ynode = nullptr;  // node-level targets [N, Tn] of the last forward
   bool prepared = false;
   bool x_padded = false;        // w.xpad holds xin, zero-padded (written at prepare)
   bool inference_only = false;  // no backward buffers, two rotating h slots
 };
 
 struct Server;
+
+// packed size of one head: W1 [H, H], b1 [H], w2 [H], b2 [1]
+inline size_t node_head_size(int H) { return (size_t)H * H + 2 * (size_t)H + 1; }
 
 // Launch sites that the opt-in event timer can bracket.
 enum Site : int {
@@ -79,6 +86,14 @@ struct hgnn_ctx {
   float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
   long long *step_dev = nullptr;
   hgnn::StageDesc *stage_tab = nullptr; // device table for the one-launch weight staging
+  // heads: Tg graph-level (packed from off_head), Tn node-level (from
+  // off_node); loss weights on the device (null = all 1); aligned node-head
+  // weight copies for the GEMMs
+  int Tg = 1, Tn = 0;
+  int64_t off_node = 0;
+  int split_node = 1; // split-K count of a node head's weight-gradient GEMM
+  float *gw_dev = nullptr, *nw_dev = nullptr;
+  float *W1n = nullptr, *W1nT = nullptr;
   float *table = nullptr;
   std::vector<void *> Wds, Wpp, WpTA, WhdsT; // GEMM-layout weight copies per layer
   std::vector<void *> Wds_lo, Wpp_lo, WpTA_lo, WhdsT_lo; // BF16 low halves
@@ -108,8 +123,10 @@ void free_work(Exec &ex);
 size_t work_bytes(const hgnn_ctx *c, int B, int N, int E, bool inference_only);
 int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_in,
                   float *h_out, hipStream_t s);
+// graph heads, node heads (fused path: pred_node/ynode), weighted loss
 int head_forward(hgnn_ctx *c, Exec &ex, const float *wh, const float *h,
-                 const float *target, float *pred, float *loss, hipStream_t s);
+                 const float *target, float *pred, float *loss, hipStream_t s,
+                 float *pred_node = nullptr, const float *ynode = nullptr);
 // Refresh every layer's GEMM-layout weight copies from the parameters in one
 // launch; bump_step (AdamW's step counter) is advanced when non-null.
 int stage_all(hgnn_ctx *c, hipStream_t s, long long *bump_step = nullptr);

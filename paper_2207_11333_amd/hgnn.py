@@ -53,6 +53,12 @@ class ServeConfig(ctypes.Structure):
                 ("use_graphs", ctypes.c_int32)]
 
 
+class Heads(ctypes.Structure):
+    _fields_ = [("graph_heads", ctypes.c_int32), ("node_heads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2), ("graph_weights", ctypes.c_void_p),
+                ("node_weights", ctypes.c_void_p)]
+
+
 class StoreInfo(ctypes.Structure):
     _fields_ = [("num_batches", ctypes.c_int32), ("node_feat", ctypes.c_int32),
                 ("edge_feat", ctypes.c_int32), ("has_y", ctypes.c_int32),
@@ -72,6 +78,9 @@ _P = ctypes.c_void_p
 _I = ctypes.c_int32
 _SIGS = {
     "hgnn_create": ([ctypes.POINTER(Config), ctypes.POINTER(_P)], _I),
+    "hgnn_create_multitask": ([ctypes.POINTER(Config), ctypes.POINTER(Heads),
+                               ctypes.POINTER(_P)], _I),
+    "hgnn_forward_multitask": ([_P, ctypes.POINTER(CBatch), _P, _P, _P, _P, _I, _P], _I),
     "hgnn_destroy": ([_P], None),
     "hgnn_num_params": ([_P, ctypes.POINTER(ctypes.c_int64)], _I),
     "hgnn_set_params": ([_P, _P, _P], _I),
@@ -241,11 +250,24 @@ class Model:
 
     def __init__(self, num_layers: int, hidden: int, node_feat: int = 9, edge_feat: int = 1,
                  max_degree: int = 4, precision: int = PREC_FP32, recompute: int = 0,
-                 delta: float = 1.0, std_eps: float = 1e-5):
+                 delta: float = 1.0, std_eps: float = 1e-5, graph_heads: int = 1,
+                 node_heads: int = 0, graph_weights=None, node_weights=None):
+        """graph_heads / node_heads > 1 / > 0 build a multitask model (several
+        graph-level heads, node-level heads, weighted loss; see the header)."""
         self.cfg = Config(num_layers, hidden, node_feat, edge_feat, max_degree, precision,
                           recompute, 0, delta, std_eps)
         h = ctypes.c_void_p()
-        _check(lib().hgnn_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self.Tg, self.Tn = graph_heads, node_heads
+        if graph_heads == 1 and node_heads == 0 and graph_weights is None:
+            _check(lib().hgnn_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        else:
+            gw = None if graph_weights is None else np.asarray(graph_weights, np.float32)
+            nw = None if node_weights is None else np.asarray(node_weights, np.float32)
+            hd = Heads(graph_heads, node_heads, (ctypes.c_int32 * 2)(0, 0),
+                       None if gw is None else gw.ctypes.data,
+                       None if nw is None else nw.ctypes.data)
+            _check(lib().hgnn_create_multitask(ctypes.byref(self.cfg), ctypes.byref(hd),
+                                               ctypes.byref(h)))
         self.handle = h
         n = ctypes.c_int64()
         _check(lib().hgnn_num_params(self.handle, ctypes.byref(n)))
@@ -297,11 +319,21 @@ class Model:
         _check(lib().hgnn_check(self.handle, _stream()))
 
     def forward(self, batch: DeviceBatch, pred: torch.Tensor, loss: Optional[torch.Tensor] = None,
-                validate: bool = False):
+                validate: bool = False, y_node: Optional[torch.Tensor] = None,
+                pred_node: Optional[torch.Tensor] = None):
+        """pred [B] (or [B, graph_heads]); a multitask model also takes the node
+        targets y_node [N, node_heads] (kept until backward) and pred_node."""
         cb = batch.cstruct()
         self._batch_keep = batch
-        _check(lib().hgnn_forward(self.handle, ctypes.byref(cb), _ptr(pred), _ptr(loss),
-                                  VALIDATE if validate else 0, _stream()))
+        self._ynode_keep = y_node
+        flags = VALIDATE if validate else 0
+        if self.Tn == 0 and y_node is None and pred_node is None:
+            _check(lib().hgnn_forward(self.handle, ctypes.byref(cb), _ptr(pred), _ptr(loss),
+                                      flags, _stream()))
+        else:
+            _check(lib().hgnn_forward_multitask(self.handle, ctypes.byref(cb), _ptr(y_node),
+                                                _ptr(pred), _ptr(pred_node), _ptr(loss), flags,
+                                                _stream()))
 
     def backward(self, dpred: Optional[torch.Tensor] = None):
         _check(lib().hgnn_backward(self.handle, _ptr(dpred), _stream()))

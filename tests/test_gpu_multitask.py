@@ -1,0 +1,141 @@
+"""Multitask heads on the GPU against the FP64 multitask oracle: several
+graph-level heads and node-level heads with a weighted loss, FP32 1e-5 on the
+outputs, the loss and every gradient tensor (head ReLU decisions replayed)."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from oracle import multitask as mt
+from paper_2207_11333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, r):
+    a, r = np.asarray(a, np.float64), np.asarray(r, np.float64)
+    n = np.linalg.norm(r)
+    return float(np.linalg.norm(a - r) / (n if n > 0 else 1.0))
+
+
+def _case(seed, Tg, Tn, L, H, B=24):
+    b = synth.make_batch(seed, B, 5, 30, 1)
+    rng = np.random.default_rng(seed)
+    layers = synth.init_params(synth.ModelShape(L, H, 9, 1), seed)
+    nl = layers.shape[0] - mt.head_size(H)
+    lim = np.sqrt(6.0 / (2 * H))
+    heads = []
+    for _ in range(Tg + Tn):
+        heads += [rng.uniform(-lim, lim, H * H), rng.uniform(-0.1, 0.1, H),
+                  rng.uniform(-lim, lim, H), rng.uniform(-0.1, 0.1, 1)]
+    params = np.concatenate([layers[:nl]] + heads).astype(np.float32)
+    y = rng.normal(5.0, 1.5, size=(B, Tg)).astype(np.float32)
+    yn = rng.normal(0.0, 1.0, size=(b.num_nodes, Tn)).astype(np.float32)
+    return synth.Batch(b.graph_ptr, b.x, b.edge_index, b.edge_attr, y), params, yn
+
+
+@pytest.mark.parametrize("Tg,Tn,L,H", [(2, 2, 2, 32), (3, 1, 3, 64), (1, 4, 2, 48), (4, 0, 2, 16)])
+def test_multitask_parity(Tg, Tn, L, H):
+    from paper_2207_11333_amd import hgnn
+    b, params, yn = _case(200 + Tg * 10 + Tn, Tg, Tn, L, H)
+    gw = [0.5, 2.0, 1.0, 0.25][:Tg]
+    nw = [1.5, 0.75, 1.0, 3.0][:Tn]
+    delta = 1.1
+    m = hgnn.Model(L, H, 9, 1, 4, 0, 0, delta, graph_heads=Tg, node_heads=Tn,
+                   graph_weights=gw, node_weights=nw)
+    assert m.num_params == params.shape[0]
+    m.set_params(params)
+    db = hgnn.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, Tg, device="cuda")
+    pn = torch.empty(b.num_nodes, max(Tn, 1), device="cuda")
+    loss = torch.empty(1, device="cuda")
+    ynd = torch.tensor(yn, device="cuda") if Tn else None
+    m.forward(db, pred, loss, validate=True, y_node=ynd, pred_node=pn if Tn else None)
+    m.backward()
+    grads = m.grads().cpu().numpy()
+    torch.cuda.synchronize()
+    rec = mt.forward(params, b, L, H, delta, Tg, Tn, gw, nw, yn if Tn else None)
+    r_pred = rel(pred.cpu().numpy(), rec.y)
+    r_node = rel(pn.cpu().numpy()[:, :Tn], rec.z) if Tn else 0.0
+    r_loss = rel([loss.item()], [rec.loss])
+    N = b.num_nodes
+    dec = oracle.Decisions(
+        [m.fetch(8, l, (N, 2 * H), torch.uint8).cpu().numpy().astype(np.int64)[:, :H]
+         for l in range(L)],
+        [m.fetch(8, l, (N, 2 * H), torch.uint8).cpu().numpy().astype(np.int64)[:, H:]
+         for l in range(L)],
+        [m.fetch(11, l, (N, H), torch.float32).cpu().numpy() > 0 for l in range(L)])
+    grelu = [m.fetch(9, t, (b.num_graphs, H), torch.float32).cpu().numpy() > 0
+             for t in range(Tg)]
+    nrelu = [m.fetch(12, s, (N, H), torch.float32).cpu().numpy() > 0 for s in range(Tn)]
+    g_ref, _, stats = mt.backward(rec, dec, grelu, nrelu, tau=1e-4)
+    say(f"multitask Tg={Tg} Tn={Tn} L={L} H={H}: pred rel {r_pred:.2e} node rel {r_node:.2e} "
+        f"loss rel {r_loss:.2e}; adopted {stats}")
+    assert r_pred <= 1e-5 and r_node <= 1e-5 and r_loss <= 1e-5
+    shape = synth.ModelShape(L, H, 9, 1)
+    offs = shape.offsets()
+    worst = 0.0
+    for name, (off, shp) in offs.items():
+        if name in ("W1", "b1", "w2", "b2"):
+            continue
+        n = int(np.prod(shp))
+        worst = max(worst, rel(grads[off:off + n], g_ref[off:off + n]))
+    nl = params.shape[0] - (Tg + Tn) * mt.head_size(H)
+    hs = mt.head_size(H)
+    for k in range(Tg + Tn):
+        sl = slice(nl + k * hs, nl + (k + 1) * hs)
+        worst = max(worst, rel(grads[sl], g_ref[sl]))
+    say(f"  worst gradient tensor rel {worst:.2e}")
+    assert worst <= 1e-5
+    m.close()
+
+
+def test_single_head_model_unchanged_by_the_multitask_entry():
+    """A one-graph-head model built through the multitask entry point gives
+    bitwise the predictions, loss and gradients of the plain one."""
+    from paper_2207_11333_amd import hgnn
+    w = synth.WORKLOADS["c0_small_fp32"]
+    b, params = w.batch(), w.params()
+    outs = []
+    for multi in (False, True):
+        kw = dict(graph_heads=1, node_heads=0, graph_weights=[1.0]) if multi else {}
+        m = hgnn.Model(w.num_layers, w.hidden, 9, w.edge_feat, 4, 0, 0, w.delta, **kw)
+        m.set_params(params)
+        pred = torch.empty(b.num_graphs, device="cuda")
+        loss = torch.empty(1, device="cuda")
+        m.forward(hgnn.DeviceBatch.from_host(b), pred, loss)
+        m.backward()
+        outs.append((pred.clone(), loss.clone(), m.grads()))
+        torch.cuda.synchronize()
+        m.close()
+    for a, c in zip(outs[0], outs[1]):
+        assert torch.equal(a, c)
+
+
+def test_multitask_argument_errors():
+    from paper_2207_11333_amd import hgnn
+    with pytest.raises(hgnn.HgnnError):
+        hgnn.Model(2, 16, graph_heads=0, node_heads=1)
+    with pytest.raises(hgnn.HgnnError):
+        hgnn.Model(2, 16, graph_heads=1, node_heads=5)
+    with pytest.raises(hgnn.HgnnError):
+        hgnn.Model(2, 16, graph_heads=2, node_heads=0, graph_weights=[1.0, -1.0])
+    m = hgnn.Model(2, 16, graph_heads=1, node_heads=1)
+    b = synth.make_batch(3, 4, 5, 9, 1)
+    pred = torch.empty(4, device="cuda")
+    with pytest.raises(hgnn.HgnnError):          # node heads need the multitask forward
+        from paper_2207_11333_amd.hgnn import lib, _ptr, _stream, _check
+        import ctypes
+        cb = hgnn.DeviceBatch.from_host(b).cstruct()
+        _check(lib().hgnn_forward(m.handle, ctypes.byref(cb), _ptr(pred), None, 0, _stream()))
+    with pytest.raises(hgnn.HgnnError):          # serving takes single-head models
+        m.serve_start(hbm_budget_bytes=1 << 30)
+    m.close()
