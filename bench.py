@@ -135,6 +135,53 @@ def train_rate_graph(workload, steps, warmup):
     return {"graphs_per_s": b.num_graphs * steps / dt, "ms_per_step": 1e3 * dt / steps}
 
 
+def multitask_rate(workload, steps, warmup, Tg=2, Tn=2):
+    """Training step of the same GC stack with Tg graph-level and Tn node-level
+    heads and a weighted loss (seeded synthetic targets)."""
+    import numpy as np
+    import torch
+    from paper_2207_11333_amd import hgnn, synth
+    b = workload.batch()
+    rng = np.random.default_rng(workload.data_seed + 77)
+    H = workload.hidden
+    layers = workload.params()[:-(H * H + 2 * H + 1)]
+    lim = np.sqrt(6.0 / (2 * H))
+    heads = []
+    for _ in range(Tg + Tn):
+        heads += [rng.uniform(-lim, lim, H * H), rng.uniform(-0.1, 0.1, H),
+                  rng.uniform(-lim, lim, H), rng.uniform(-0.1, 0.1, 1)]
+    params = np.concatenate([layers] + heads).astype(np.float32)
+    y = rng.normal(5.0, 1.5, size=(b.num_graphs, Tg)).astype(np.float32)
+    yn = torch.tensor(rng.normal(0.0, 1.0, size=(b.num_nodes, Tn)).astype(np.float32),
+                      device="cuda")
+    m = hgnn.Model(workload.num_layers, H, 9, workload.edge_feat, 4, workload.precision,
+                   workload.recompute, workload.delta, graph_heads=Tg, node_heads=Tn,
+                   graph_weights=[1.0] + [0.5] * (Tg - 1), node_weights=[0.25] * Tn)
+    m.set_params(params)
+    db = hgnn.DeviceBatch.from_host(synth.Batch(b.graph_ptr, b.x, b.edge_index, b.edge_attr, y))
+    pred = torch.empty(b.num_graphs, Tg, device="cuda")
+    pn = torch.empty(b.num_nodes, Tn, device="cuda")
+    loss = torch.empty(1, device="cuda")
+
+    def step():
+        m.forward(db, pred, loss, y_node=yn, pred_node=pn)
+        m.backward()
+        m.adam_step(lr=1e-3)
+
+    m.forward(db, pred, loss, validate=True, y_node=yn, pred_node=pn)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    m.close()
+    return {"graph_heads": Tg, "node_heads": Tn, "graphs_per_s": b.num_graphs * steps / dt,
+            "ms_per_step": 1e3 * dt / steps}
+
+
 def serve_bench(qps=500.0, warm_s=2.0, measure_s=10.0, pool=48):
     """Open-loop Poisson arrivals at a fixed rate; latency is measured from the
     scheduled arrival time to the poll that observes completion."""
@@ -498,6 +545,11 @@ def main():
                         "ratio_vs_fp32": rb["graphs_per_s"] / r["graphs_per_s"],
                         "graph_replay_value": rbg["graphs_per_s"],
                         "graph_replay_ratio_vs_fp32": rbg["graphs_per_s"] / rg["graphs_per_s"]}
+        mt = multitask_rate(w, args.steps, args.warmup)
+        mt["ratio_vs_single_head"] = mt["graphs_per_s"] / r["graphs_per_s"]
+        line["multitask"] = mt
+        _log(f"bench: multitask ({mt['graph_heads']} graph + {mt['node_heads']} node heads) "
+             f"{mt['graphs_per_s']:.1f} graphs/s")
         _log("bench: large configuration")
         line["c3"] = c3_measure()
         _log(f"bench: c3 {line['c3']['graphs_per_s']:.1f} graphs/s; aggregation "

@@ -209,8 +209,10 @@ hipError_t launch_node_head_out(const Dims *dims, int capN, int H, int Tn, const
 hipError_t launch_node_head_err(const Dims *dims, int capN, int H, int Tn, const float *Qn,
                                 const float *wn, const float *z, const float *zt,
                                 const float *nw, float *e, float *dQ, hipStream_t s);
+// dw2/db2 of every node head; part holds node_head_small_floats(H, Tn) floats.
+size_t node_head_small_floats(int H, int Tn);
 hipError_t launch_node_head_small(const Dims *dims, int capN, int H, int Tn, const float *Qn,
-                                  const float *e, float *gwn, hipStream_t s);
+                                  const float *e, float *part, float *gwn, hipStream_t s);
 // adam.hip
 hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_t n,
                         float lr, double b1, double b2, float eps, float wd,

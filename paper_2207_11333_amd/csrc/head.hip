@@ -56,6 +56,7 @@ k_head_forward(const Dims *__restrict__ dims, int H, int Tg, const int *__restri
   const float inv_n = 1.0f / (float)(hi - lo);
   for (int c = threadIdx.x; c < H; c += kHeadThreads) {
     float s = 0.f;
+#pragma unroll 8
     for (int i = lo; i < hi; ++i) s += h[(size_t)i * H + c];
     const float gv = s * inv_n;
     gs[c] = gv;
@@ -67,6 +68,7 @@ k_head_forward(const Dims *__restrict__ dims, int H, int Tg, const int *__restri
   for (int c = threadIdx.x; c < H; c += kHeadThreads) {
     float s = b1[c];
     const float *row = W1 + (size_t)c * H;
+#pragma unroll 8
     for (int k = 0; k < H; ++k) s += row[k] * gs[k];
     const float qv = s > 0.f ? s : 0.f;
     qt[c] = qv;
@@ -110,7 +112,9 @@ k_loss(const Dims *__restrict__ dims, int Tg, const float *__restrict__ pred,
 
 // Per graph, for every graph head t: dy, dq_t = dy w2_t * [q_t > 0]; then
 // dg = sum_t W1_t^T dq_t and dh_i = dg / n_b (+ add_i, the node heads' share),
-// masked by relu_of > 0 when given.
+// masked by relu_of > 0 when given.  The sums over c are split into P
+// contiguous ranges (P = 256 / H threads per output when H < 256) whose
+// partials are added in range order.
 __global__ void __launch_bounds__(kHeadThreads)
 k_head_bwd_graph(const Dims *__restrict__ dims, int H, int Tg, const int *__restrict__ gptr,
                  const float *__restrict__ wh, const float *__restrict__ q,
@@ -119,7 +123,9 @@ k_head_bwd_graph(const Dims *__restrict__ dims, int H, int Tg, const int *__rest
                  float *__restrict__ dy, float *__restrict__ dq, float *__restrict__ dh,
                  const float *__restrict__ relu_of, const float *__restrict__ add) {
   __shared__ float dqs[kMaxGraphHeads * 512];
-  const int b = blockIdx.x;
+  __shared__ float red[kHeadThreads];
+  __shared__ float dgs[512];
+  const int b = blockIdx.x, tid = threadIdx.x;
   const int B = dims->B;
   if (b >= B) return;
   const size_t HS = (size_t)H * H + 2 * H + 1;
@@ -127,33 +133,60 @@ k_head_bwd_graph(const Dims *__restrict__ dims, int H, int Tg, const int *__rest
     const size_t o = (size_t)b * Tg + t;
     const float dyb = dpred ? dpred[o]
                             : (2.0f * (pred[o] - target[o]) / (float)B) * (gw ? gw[t] : 1.0f);
-    if (threadIdx.x == 0) dy[o] = dyb;
+    if (tid == 0) dy[o] = dyb;
     const float *w2 = wh + t * HS + H * H + H;
     const float *qt = q + ((size_t)t * B + b) * H;
     float *dqt = dq + ((size_t)t * B + b) * H;
-    for (int c = threadIdx.x; c < H; c += kHeadThreads) {
+    for (int c = tid; c < H; c += kHeadThreads) {
       const float v = qt[c] > 0.f ? dyb * w2[c] : 0.f;
       dqs[t * H + c] = v;
       dqt[c] = v;
     }
   }
   __syncthreads();
+  if (H < kHeadThreads) {
+    const int P = kHeadThreads / H;
+    if (tid < P * H) {
+      const int k = tid % H, p = tid / H;
+      const int c0 = (p * H) / P, c1 = ((p + 1) * H) / P;
+      float s = 0.f;
+      for (int t = 0; t < Tg; ++t) {
+        const float *W1 = wh + t * HS;
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) s += W1[(size_t)c * H + k] * dqs[t * H + c];
+      }
+      red[tid] = s;
+    }
+    __syncthreads();
+    if (tid < H) {
+      float s = red[tid];
+      for (int p = 1; p < P; ++p) s += red[p * H + tid];
+      dgs[tid] = s;
+    }
+  } else {
+    for (int k = tid; k < H; k += kHeadThreads) {
+      float s = 0.f;
+      for (int t = 0; t < Tg; ++t) {
+        const float *W1 = wh + t * HS;
+#pragma unroll 8
+        for (int c = 0; c < H; ++c) s += W1[(size_t)c * H + k] * dqs[t * H + c];
+      }
+      dgs[k] = s;
+    }
+  }
+  __syncthreads();
   int lo, hi;
   graph_range(gptr, b, dims->N, lo, hi);
   const float inv_n = 1.0f / (float)(hi - lo);
-  for (int k = threadIdx.x; k < H; k += kHeadThreads) {
-    float s = 0.f;
-    for (int t = 0; t < Tg; ++t) {
-      const float *W1 = wh + t * HS;
-      for (int c = 0; c < H; ++c) s += W1[(size_t)c * H + k] * dqs[t * H + c];
-    }
-    const float v = s * inv_n;
-    for (int i = lo; i < hi; ++i) {
-      float o = add ? v + add[(size_t)i * H + k] : v;
-      // fold in the ReLU adjoint of the layer that produced h
-      if (relu_of && !(relu_of[(size_t)i * H + k] > 0.f)) o = 0.f;
-      dh[(size_t)i * H + k] = o;
-    }
+  const long long n = (long long)(hi - lo) * H;
+  for (long long idx = tid; idx < n; idx += kHeadThreads) {
+    const int k = (int)(idx % H);
+    const size_t at = (size_t)lo * H + idx;
+    float o = dgs[k] * inv_n;
+    if (add) o += add[at];
+    // fold in the ReLU adjoint of the layer that produced h
+    if (relu_of && !(relu_of[at] > 0.f)) o = 0.f;
+    dh[at] = o;
   }
 }
 
@@ -233,6 +266,7 @@ k_node_head_out(const Dims *__restrict__ dims, int H, int Tn, size_t capN,
   const float *w2 = wn + (size_t)sh * (H * H + 2 * H + 1) + H * H + H;
   const float *q = Qn + (size_t)sh * capN * H + (size_t)i * H;
   float acc = w2[H];
+#pragma unroll 8
   for (int c = 0; c < H; ++c) acc += w2[c] * q[c];
   z[t] = acc;
   if (z2) z2[t] = acc;
@@ -257,29 +291,41 @@ k_node_head_err(const Dims *__restrict__ dims, int H, int Tn, size_t capN,
   dQ[o] = Qn[o] > 0.f ? ev * w2 : 0.f;
 }
 
-// dw2_s[c] = sum_i e[i, s] Q_s[i, c] and db2_s = sum_i e[i, s], in a fixed
-// order: 4 row groups x 64 columns per pass, the 4 partials added in order.
+// dw2_s[c] = sum_i e[i, s] Q_s[i, c] and db2_s = sum_i e[i, s] (column c = H),
+// in a fixed order: the nodes are cut into kNodeChunks contiguous chunks
+// (blockIdx.x), each chunk's sum goes to part[s][chunk][c], and
+// k_node_head_small_sum adds the chunks in order.
+constexpr int kNodeChunks = 128;
+
 __global__ void __launch_bounds__(256)
 k_node_head_small(const Dims *__restrict__ dims, int H, int Tn, size_t capN,
                   const float *__restrict__ Qn, const float *__restrict__ e,
-                  float *__restrict__ gwn) {
-  __shared__ float red[4][64];
-  const int sh = blockIdx.x;
+                  float *__restrict__ part) {
+  const int r = blockIdx.x, sh = blockIdx.y;
   const int N = dims->N;
-  const int col = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int rows = (N + kNodeChunks - 1) / kNodeChunks;
+  const int i0 = min(r * rows, N), i1 = min(i0 + rows, N);
   const float *Q = Qn + (size_t)sh * capN * H;
-  float *dw2 = gwn + (size_t)sh * (H * H + 2 * H + 1) + H * H + H;
-  for (int c0 = 0; c0 <= H; c0 += 64) {
-    const int c = c0 + col;
+  float *out = part + ((size_t)sh * kNodeChunks + r) * (H + 1);
+  for (int c = threadIdx.x; c <= H; c += 256) {
     float s = 0.f;
     if (c < H)
-      for (int i = rg; i < N; i += 4) s += e[(size_t)i * Tn + sh] * Q[(size_t)i * H + c];
-    else if (c == H)
-      for (int i = rg; i < N; i += 4) s += e[(size_t)i * Tn + sh];
-    red[rg][col] = s;
-    __syncthreads();
-    if (rg == 0 && c <= H) dw2[c] = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
-    __syncthreads();
+      for (int i = i0; i < i1; ++i) s += e[(size_t)i * Tn + sh] * Q[(size_t)i * H + c];
+    else
+      for (int i = i0; i < i1; ++i) s += e[(size_t)i * Tn + sh];
+    out[c] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_node_head_small_sum(int H, const float *__restrict__ part, float *__restrict__ gwn) {
+  const int sh = blockIdx.x;
+  const float *p = part + (size_t)sh * kNodeChunks * (H + 1);
+  float *dw2 = gwn + (size_t)sh * (H * H + 2 * H + 1) + H * H + H;
+  for (int c = threadIdx.x; c <= H; c += 256) {
+    float s = 0.f;
+    for (int r = 0; r < kNodeChunks; ++r) s += p[(size_t)r * (H + 1) + c];
+    dw2[c] = s;
   }
 }
 
@@ -310,10 +356,14 @@ hipError_t launch_node_head_err(const Dims *dims, int capN, int H, int Tn, const
   return hipGetLastError();
 }
 
+size_t node_head_small_floats(int H, int Tn) { return (size_t)Tn * kNodeChunks * (H + 1); }
+
 hipError_t launch_node_head_small(const Dims *dims, int capN, int H, int Tn, const float *Qn,
-                                  const float *e, float *gwn, hipStream_t s) {
+                                  const float *e, float *part, float *gwn, hipStream_t s) {
   if (Tn <= 0) return hipSuccess;
-  k_node_head_small<<<Tn, 256, 0, s>>>(dims, H, Tn, (size_t)capN, Qn, e, gwn);
+  k_node_head_small<<<dim3(kNodeChunks, Tn), 256, 0, s>>>(dims, H, Tn, (size_t)capN, Qn, e,
+                                                          part);
+  k_node_head_small_sum<<<Tn, 256, 0, s>>>(H, part, gwn);
   return hipGetLastError();
 }
 

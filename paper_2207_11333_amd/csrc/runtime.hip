@@ -577,7 +577,7 @@ static int node_heads_backward(hgnn_ctx *c, Exec &ex, const float *h, hipStream_
       e = launch_reduce_map(r, s);
     }
   }
-  if (e == hipSuccess) e = launch_node_head_small(ex.dims, ex.N, H, Tn, w.Qn, w.en, gwn, s);
+  if (e == hipSuccess) e = launch_node_head_small(ex.dims, ex.N, H, Tn, w.Qn, w.en, c->nh_part, gwn, s);
   if (e == hipSuccess) {
     GemmNT g{};
     g.nseg = Tn;
@@ -743,6 +743,7 @@ int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_
     HGNN_CALLOC(c->nw_dev, Tn);
     HGNN_CALLOC(c->W1n, (size_t)Tn * H * H);
     HGNN_CALLOC(c->W1nT, (size_t)Tn * H * H);
+    HGNN_CALLOC(c->nh_part, node_head_small_floats(H, Tn));
   }
   if (hipMemcpy(c->gw_dev, gw.data(), Tg * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       (Tn > 0 && hipMemcpy(c->nw_dev, nw.data(), Tn * sizeof(float), hipMemcpyHostToDevice) !=
@@ -833,7 +834,7 @@ void hgnn_destroy(hgnn_ctx *c) {
   void **ptrs[] = {(void **)&c->params, (void **)&c->grads, (void **)&c->adam_m,
                    (void **)&c->adam_v, (void **)&c->step_dev, (void **)&c->stage_tab,
                    (void **)&c->gw_dev, (void **)&c->nw_dev, (void **)&c->W1n,
-                   (void **)&c->W1nT,
+                   (void **)&c->W1nT, (void **)&c->nh_part,
                    (void **)&c->table, (void **)&c->ex.dims, (void **)&c->ex.w.csr.err,
                    (void **)&c->part};
   for (void **p : ptrs) dfree(*p);

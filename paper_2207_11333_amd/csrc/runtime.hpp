@@ -94,6 +94,7 @@ struct hgnn_ctx {
   int split_node = 1; // split-K count of a node head's weight-gradient GEMM
   float *gw_dev = nullptr, *nw_dev = nullptr;
   float *W1n = nullptr, *W1nT = nullptr;
+  float *nh_part = nullptr; // node heads' per-chunk dw2/db2 partials
   float *table = nullptr;
   std::vector<void *> Wds, Wpp, WpTA, WhdsT; // GEMM-layout weight copies per layer
   std::vector<void *> Wds_lo, Wpp_lo, WpTA_lo, WhdsT_lo; // BF16 low halves
