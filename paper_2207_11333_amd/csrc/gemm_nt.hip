@@ -52,6 +52,15 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   const int KT_all = cum[kMaxSeg];
   const int t_lo = (int)((long long)KT_all * z / g.splits);
   const int KT = (int)((long long)KT_all * (z + 1) / g.splits) - t_lo;
+  // interleaved trailing segments: tiles from il_start on cycle through them
+  const int il_n = g.ileave_n > 1 ? g.ileave_n : 1;
+  const int il_first = g.nseg - il_n;
+  int il_start = 0x7fffffff;
+  if (il_n > 1) {
+#pragma unroll
+    for (int q = 0; q < kMaxSeg; ++q)
+      if (q == il_first) il_start = cum[q];
+  }
 
   f4 acc[TM][TN];
 #pragma unroll
@@ -93,10 +102,16 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     int q = 0;
 #pragma unroll
     for (int u = 1; u < kMaxSeg; ++u) q += (t >= cum[u]) ? 1 : 0;
+    int kt = t - cum[q];
+    if (t >= il_start) {
+      const int r = t - il_start;
+      q = il_first + r % il_n;
+      kt = r / il_n;
+    }
     const float *aptr = g.seg[q].ptr;
     const float *scale = g.seg[q].scale;
     const int lda = g.seg[q].ld, ks = g.seg[q].k, boff = g.seg[q].boff;
-    const int k0 = (t - cum[q]) * BK;
+    const int k0 = kt * BK;
     const float *sbase = scale ? scale : aptr;
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
@@ -252,6 +267,11 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
                           float *partials, hipStream_t s, int tag, hipEvent_t ev0,
                           hipEvent_t ev1) {
   if (capM <= 0 || g.Ncols <= 0) return hipSuccess;
+  if (g.ileave_n > 1) {
+    if (g.ileave_n > g.nseg) return hipErrorInvalidValue;
+    for (int q = g.nseg - g.ileave_n + 1; q < g.nseg; ++q)
+      if (g.seg[q].k != g.seg[g.nseg - g.ileave_n].k) return hipErrorInvalidValue;
+  }
   int Ktot = 0;
   for (int q = 0; q < g.nseg; ++q) Ktot += g.seg[q].k > 0 ? ((g.seg[q].k + 15) / 16) * 16 : 0;
   // segment tiles are counted per segment; bound the split by the sum

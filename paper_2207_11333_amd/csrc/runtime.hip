@@ -325,6 +325,7 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
   g.seg[1] = SegA{A, nullptr, 4 * H, 4 * H, d.Fp};
   g.seg[2] = SegA{A, w.csr.sp, 4 * H, 4 * H, d.Fp + 4 * H};
   g.seg[3] = SegA{A, w.csr.sm, 4 * H, 4 * H, d.Fp + 8 * H};
+  g.ileave_n = 3;
   g.B = c->Wpp[l];
   g.B_lo = c->prec ? c->Wpp_lo[l] : nullptr;
   g.ldb = d.Fp + 12 * H;
@@ -420,6 +421,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     g.seg[0] = SegA{du, nullptr, H, H, 0};
     g.seg[1] = SegA{du, w.csr.sp, H, H, H};
     g.seg[2] = SegA{du, w.csr.sm, H, H, 2 * H};
+    g.ileave_n = 3;
     g.B = c->WpTA[l];
     g.B_lo = c->prec ? c->WpTA_lo[l] : nullptr;
     g.ldb = 3 * H;
