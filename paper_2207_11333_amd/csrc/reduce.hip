@@ -1,8 +1,11 @@
 // Ordered split-K reductions of the MFMA GEMMs (gemm_nt.hip, gemm_tn.hip):
-// the partial sums P[z] are added in the fixed order z = 0, 1, ... so the
-// result does not depend on scheduling.  One thread owns four consecutive
-// outputs (every Ncols here is a multiple of 4) and issues the 16-byte loads
-// of up to kBatch splits before adding them, so they are in flight together.
+// the partial sums P[z] are added in a fixed order, so the result does not
+// depend on scheduling.  Each output float4 (every Ncols here is a multiple
+// of 4) is owned by a group of G adjacent lanes: lane g adds the contiguous
+// splits [g per, (g + 1) per) in order, issuing all of its 16-byte loads
+// before adding them, and the G lane sums are combined by a fixed pairwise
+// tree of wave shuffles.  G grows with the split count so that no lane waits
+// on more than kPerLane loads.
 #include "common.hpp"
 
 namespace hgnn {
@@ -11,33 +14,51 @@ namespace {
 
 inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
 
-constexpr int kBatch = 4;
+constexpr int kPerLane = 4;
 
+template <int G>
 __device__ __forceinline__ f4 ordered_sum(const float *__restrict__ src, int splits,
-                                          long long stride) {
-  f4 sum = *reinterpret_cast<const f4 *>(src);
-  for (int z0 = 1; z0 < splits; z0 += kBatch) {
-    f4 v[kBatch];
+                                          long long stride, int g) {
+  const int per = (splits + G - 1) / G;
+  const int z_lo = g * per, z_hi = min(splits, z_lo + per);
+  f4 sum = f4{0.f, 0.f, 0.f, 0.f};
+  for (int z0 = z_lo; z0 < z_hi; z0 += kPerLane) {
+    f4 v[kPerLane];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < kPerLane; ++u) {
       const int z = min(z0 + u, splits - 1);
       v[u] = *reinterpret_cast<const f4 *>(src + z * stride);
     }
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (z0 + u < splits) sum += v[u];
+    for (int u = 0; u < kPerLane; ++u)
+      if (z0 + u < z_hi) sum += v[u];
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sum[e] += __shfl_down(sum[e], off, G);
   }
   return sum;
 }
 
+int pick_group(int splits) {
+  int G = 1;
+  while (G < 16 && G * kPerLane < splits) G <<= 1;
+  return G;
+}
+
 // NT: C = act(sum_z P[z] + bias) (* mask).
+template <int G>
 __global__ void __launch_bounds__(256)
 k_reduce_nt(const Dims *__restrict__ dims, const GemmNT g) {
   const int M = g.M_fixed >= 0 ? g.M_fixed : dims->N;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = gt / G;
   const long long total = (long long)M * g.Ncols;
-  if (4 * t >= total) return;
-  f4 sum = ordered_sum(g.P + 4 * t, g.splits, total);
+  // lanes past the end still take part in their group's shuffles
+  const bool live = 4 * t < total;
+  f4 sum = ordered_sum<G>(g.P + (live ? 4 * t : 0), g.splits, total, (int)(gt % G));
+  if (!live || gt % G != 0) return;
   const int m = (int)(4 * t / g.Ncols), n = (int)(4 * t % g.Ncols);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -50,11 +71,14 @@ k_reduce_nt(const Dims *__restrict__ dims, const GemmNT g) {
 }
 
 // TN: sum, then scatter into the packed gradient layout (routes: see ReduceMap).
+template <int G>
 __global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = gt / G;
   const long long total = (long long)r.M * r.Ncols;
-  if (4 * t >= total) return;
-  const f4 sum = ordered_sum(r.P + 4 * t, r.splits, total);
+  const bool live = 4 * t < total;
+  const f4 sum = ordered_sum<G>(r.P + (live ? 4 * t : 0), r.splits, total, (int)(gt % G));
+  if (!live || gt % G != 0) return;
   const int m = (int)(4 * t / r.Ncols), c0 = (int)(4 * t % r.Ncols);
   for (int k = 0; k < r.nroute; ++k) {
     const ReduceRoute &ro = r.route[k];
@@ -80,14 +104,30 @@ __global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
 hipError_t launch_reduce_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s) {
   const long long total = (long long)capM * g.Ncols;
   if (total <= 0) return hipSuccess;
-  k_reduce_nt<<<cdiv(total / 4, 256), 256, 0, s>>>(dims, g);
+  const int G = pick_group(g.splits);
+  const int grid = cdiv(total / 4 * G, 256);
+  switch (G) {
+  case 1: k_reduce_nt<1><<<grid, 256, 0, s>>>(dims, g); break;
+  case 2: k_reduce_nt<2><<<grid, 256, 0, s>>>(dims, g); break;
+  case 4: k_reduce_nt<4><<<grid, 256, 0, s>>>(dims, g); break;
+  case 8: k_reduce_nt<8><<<grid, 256, 0, s>>>(dims, g); break;
+  default: k_reduce_nt<16><<<grid, 256, 0, s>>>(dims, g); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s) {
   const long long total = (long long)r.M * r.Ncols;
   if (total <= 0) return hipSuccess;
-  k_reduce_map<<<cdiv(total / 4, 256), 256, 0, s>>>(r);
+  const int G = pick_group(r.splits);
+  const int grid = cdiv(total / 4 * G, 256);
+  switch (G) {
+  case 1: k_reduce_map<1><<<grid, 256, 0, s>>>(r); break;
+  case 2: k_reduce_map<2><<<grid, 256, 0, s>>>(r); break;
+  case 4: k_reduce_map<4><<<grid, 256, 0, s>>>(r); break;
+  case 8: k_reduce_map<8><<<grid, 256, 0, s>>>(r); break;
+  default: k_reduce_map<16><<<grid, 256, 0, s>>>(r); break;
+  }
   return hipGetLastError();
 }
 
