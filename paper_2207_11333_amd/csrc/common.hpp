@@ -68,10 +68,10 @@ struct GemmNT {
   // optional: zero C[m, n] where mask[m * ldc + n] <= 0 (ReLU adjoint of the
   // layer that produced `mask`)
   const float *mask;
-  // > 1: the last ileave_n segments read the same rows (equal k, differing
-  // only in scale and boff) and their K tiles are taken interleaved -- tile j
-  // of each in turn -- so a workgroup rereads a tile while it is still cached
-  // instead of streaming the operand once per segment.  0 or 1: in order.
+  // 3: the last three segments read the same rows (equal k, differing only
+  // in scale and boff) and their K tiles are taken interleaved -- tile j of
+  // each in turn -- so a workgroup rereads a tile while it is still cached
+  // instead of streaming the operand once per segment.  0: in order.
   int ileave_n;
 };
 

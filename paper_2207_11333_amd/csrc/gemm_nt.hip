@@ -14,9 +14,12 @@ namespace {
 // Waves form a 2 x WGN grid over the BM x BN tile (NTH = 128 WGN threads).
 template <int PREC, int BM, int BN, bool SPLIT, int TAG, int WGN>
 // FP32: four waves per SIMD (the compiler fits the kernel in 128 registers;
-// measured 1.7% faster end to end).  BF16 keeps two: at four it loses on
-// the large workload.
-__global__ void __launch_bounds__(128 * WGN, PREC == 0 ? 4 : 2)
+// measured 1.7% faster end to end).  BF16: five, which holds the kernel to
+// 96 registers (one spilled).  Left to itself the compiler takes 125, and
+// the weight-gradient GEMM that runs beside this kernel on the second stream
+// then slows by 40% on the 8-layer hidden-256 workload (measured 63k vs 75k
+// graphs/s end to end).
+__global__ void __launch_bounds__(128 * WGN, PREC == 0 ? 4 : 5)
 k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   using P = Prec<PREC>;
   using T = typename P::T;
@@ -52,11 +55,11 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   const int KT_all = cum[kMaxSeg];
   const int t_lo = (int)((long long)KT_all * z / g.splits);
   const int KT = (int)((long long)KT_all * (z + 1) / g.splits) - t_lo;
-  // interleaved trailing segments: tiles from il_start on cycle through them
-  const int il_n = g.ileave_n > 1 ? g.ileave_n : 1;
-  const int il_first = g.nseg - il_n;
+  // interleaved trailing segments (three: the host accepts no other count):
+  // tiles from il_start on cycle through them
+  const int il_first = g.nseg - 3;
   int il_start = 0x7fffffff;
-  if (il_n > 1) {
+  if (g.ileave_n == 3) {
 #pragma unroll
     for (int q = 0; q < kMaxSeg; ++q)
       if (q == il_first) il_start = cum[q];
@@ -104,9 +107,9 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     for (int u = 1; u < kMaxSeg; ++u) q += (t >= cum[u]) ? 1 : 0;
     int kt = t - cum[q];
     if (t >= il_start) {
-      const int r = t - il_start;
-      q = il_first + r % il_n;
-      kt = r / il_n;
+      const unsigned r = (unsigned)(t - il_start);
+      kt = (int)(r / 3u);
+      q = il_first + (int)(r - 3u * (unsigned)kt);
     }
     const float *aptr = g.seg[q].ptr;
     const float *scale = g.seg[q].scale;
@@ -267,10 +270,10 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
                           float *partials, hipStream_t s, int tag, hipEvent_t ev0,
                           hipEvent_t ev1) {
   if (capM <= 0 || g.Ncols <= 0) return hipSuccess;
-  if (g.ileave_n > 1) {
-    if (g.ileave_n > g.nseg) return hipErrorInvalidValue;
-    for (int q = g.nseg - g.ileave_n + 1; q < g.nseg; ++q)
-      if (g.seg[q].k != g.seg[g.nseg - g.ileave_n].k) return hipErrorInvalidValue;
+  if (g.ileave_n != 0) {
+    if (g.ileave_n != 3 || g.nseg < 3) return hipErrorInvalidValue;
+    for (int q = g.nseg - 2; q < g.nseg; ++q)
+      if (g.seg[q].k != g.seg[g.nseg - 3].k) return hipErrorInvalidValue;
   }
   int Ktot = 0;
   for (int q = 0; q < g.nseg; ++q) Ktot += g.seg[q].k > 0 ? ((g.seg[q].k + 15) / 16) * 16 : 0;
