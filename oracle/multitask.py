@@ -61,11 +61,12 @@ def unpack_heads(params, num_layers: int, hidden: int, node_feat: int, edge_feat
 
 
 @dataclasses.dataclass
-class MTRecord:
-    base: pna.ForwardRecord       # GC stack, pooling; its head fields unused
+class HeadsRecord:
     graph: List[dict]
     node: List[dict]
-    g: np.ndarray                 # [B, H]
+    g: np.ndarray                 # [B, H] pooled embeddings
+    h: np.ndarray                 # [N, H] last GC layer's output
+    gp: np.ndarray                # graph_ptr
     gpre: List[np.ndarray]        # per graph head [B, H]
     npre: List[np.ndarray]        # per node head [N, H]
     y: np.ndarray                 # [B, Tg]
@@ -75,6 +76,102 @@ class MTRecord:
     gw: np.ndarray
     nw: np.ndarray
     loss: Optional[float]
+
+
+def heads_forward(h, graph_ptr, graph: List[dict], node: List[dict],
+                  graph_weights=None, node_weights=None, y=None,
+                  y_node=None) -> HeadsRecord:
+    """Mean pooling, every head and the weighted loss, from the last GC
+    layer's node embeddings h [N, H]."""
+    h = np.asarray(h, np.float64)
+    N, H = h.shape
+    gp = np.asarray(graph_ptr, np.int64)
+    B = gp.shape[0] - 1
+    Tg, Tn = len(graph), len(node)
+    g = np.zeros((B, H))
+    for b in range(B):
+        g[b] = h[gp[b]:gp[b + 1]].sum(0) / (gp[b + 1] - gp[b])
+    gpre, ys = [], []
+    for hd in graph:
+        pre = g @ hd["W1"].T + hd["b1"]
+        gpre.append(pre)
+        ys.append((np.maximum(pre, 0.0) @ hd["w2"].T)[:, 0] + hd["b2"][0])
+    npre, zs = [], []
+    for hd in node:
+        pre = h @ hd["W1"].T + hd["b1"]
+        npre.append(pre)
+        zs.append((np.maximum(pre, 0.0) @ hd["w2"].T)[:, 0] + hd["b2"][0])
+    yv = np.stack(ys, 1)
+    z = np.stack(zs, 1) if Tn else np.zeros((N, 0))
+    gw = np.ones(Tg) if graph_weights is None else np.asarray(graph_weights, np.float64)
+    nw = np.ones(Tn) if node_weights is None else np.asarray(node_weights, np.float64)
+    yt = None if y is None else np.asarray(y, np.float64).reshape(-1, Tg)
+    zt = None if y_node is None else np.asarray(y_node, np.float64).reshape(N, Tn)
+    loss = None
+    if yt is not None and (Tn == 0 or zt is not None):
+        loss = float(sum(gw[t] * ((yv[:, t] - yt[:, t]) ** 2).sum() / B for t in range(Tg)))
+        loss += float(sum(nw[s] * ((z[:, s] - zt[:, s]) ** 2).sum() / N for s in range(Tn)))
+    return HeadsRecord(graph, node, g, h, gp, gpre, npre, yv, z, yt, zt, gw, nw, loss)
+
+
+def heads_backward(hr: HeadsRecord, graph_relu=None, node_relu=None, tau: float = 0.0,
+                   stats=None):
+    """Adjoint of heads_forward: (dL/dh [N, H], [per-head gradient dicts])."""
+    if stats is None:
+        stats = {"relu": 0, "argmin": 0, "argmax": 0}
+    B, Tg = hr.y.shape
+    N, H = hr.h.shape
+    gp = hr.gp
+    dg = np.zeros((B, H))
+    gheads = []
+    for t, hd in enumerate(hr.graph):
+        dy = 2.0 * hr.gw[t] * (hr.y[:, t] - hr.y_target[:, t]) / B
+        pre = hr.gpre[t]
+        mask = pna._replay_relu(pre, pre > 0, None if graph_relu is None else graph_relu[t],
+                                tau, stats, f"graph head {t}")
+        q = np.maximum(pre, 0.0) * mask
+        dpre = dy[:, None] * hd["w2"][0][None, :] * mask
+        gheads.append({"W1": dpre.T @ hr.g, "b1": dpre.sum(0), "w2": (dy @ q)[None, :],
+                       "b2": np.array([dy.sum()])})
+        dg += dpre @ hd["W1"]
+    dh = np.zeros((N, H))
+    for b in range(B):
+        dh[gp[b]:gp[b + 1]] = dg[b] / (gp[b + 1] - gp[b])
+    nheads = []
+    for s, hd in enumerate(hr.node):
+        e = 2.0 * hr.nw[s] * (hr.z[:, s] - hr.z_target[:, s]) / N
+        pre = hr.npre[s]
+        mask = pna._replay_relu(pre, pre > 0, None if node_relu is None else node_relu[s],
+                                tau, stats, f"node head {s}")
+        q = np.maximum(pre, 0.0) * mask
+        dpre = e[:, None] * hd["w2"][0][None, :] * mask
+        nheads.append({"W1": dpre.T @ hr.h, "b1": dpre.sum(0), "w2": (e @ q)[None, :],
+                       "b2": np.array([e.sum()])})
+        dh += dpre @ hd["W1"]
+    return dh, gheads + nheads
+
+
+@dataclasses.dataclass
+class MTRecord:
+    base: pna.ForwardRecord       # GC stack, pooling; its head fields unused
+    heads: HeadsRecord
+
+    # the head fields under their earlier names
+    @property
+    def y(self):
+        return self.heads.y
+
+    @property
+    def z(self):
+        return self.heads.z
+
+    @property
+    def loss(self):
+        return self.heads.loss
+
+    @property
+    def g(self):
+        return self.heads.g
 
 
 def forward(params, batch, num_layers: int, hidden: int, delta: float, Tg: int, Tn: int,
@@ -90,30 +187,9 @@ def forward(params, batch, num_layers: int, hidden: int, delta: float, Tg: int, 
     single = pna.pack({**layers, "W1": np.zeros((hidden, hidden)), "b1": np.zeros(hidden),
                        "w2": np.zeros((1, hidden)), "b2": np.zeros(1)}, num_layers)
     base = pna.forward(single, batch, num_layers, hidden, delta, eps, with_loss=False)
-    h = base.layers[-1].h_out
-    g = base.g
-    gpre, ys = [], []
-    for hd in graph:
-        pre = g @ hd["W1"].T + hd["b1"]
-        gpre.append(pre)
-        ys.append((np.maximum(pre, 0.0) @ hd["w2"].T)[:, 0] + hd["b2"][0])
-    npre, zs = [], []
-    for hd in node:
-        pre = h @ hd["W1"].T + hd["b1"]
-        npre.append(pre)
-        zs.append((np.maximum(pre, 0.0) @ hd["w2"].T)[:, 0] + hd["b2"][0])
-    y = np.stack(ys, 1)
-    z = np.stack(zs, 1) if Tn else np.zeros((N, 0))
-    gw = np.ones(Tg) if graph_weights is None else np.asarray(graph_weights, np.float64)
-    nw = np.ones(Tn) if node_weights is None else np.asarray(node_weights, np.float64)
-    yt = None if batch.y is None else np.asarray(batch.y, np.float64).reshape(-1, Tg)
-    zt = None if y_node is None else np.asarray(y_node, np.float64).reshape(N, Tn)
-    loss = None
-    if yt is not None and (Tn == 0 or zt is not None):
-        B = y.shape[0]
-        loss = float(sum(gw[t] * ((y[:, t] - yt[:, t]) ** 2).sum() / B for t in range(Tg)))
-        loss += float(sum(nw[s] * ((z[:, s] - zt[:, s]) ** 2).sum() / N for s in range(Tn)))
-    return MTRecord(base, graph, node, g, gpre, npre, y, z, yt, zt, gw, nw, loss)
+    hr = heads_forward(base.layers[-1].h_out, batch.graph_ptr, graph, node, graph_weights,
+                       node_weights, batch.y, y_node)
+    return MTRecord(base, hr)
 
 
 def backward(rec: MTRecord, hint: Optional[pna.Decisions] = None,
@@ -126,44 +202,15 @@ def backward(rec: MTRecord, hint: Optional[pna.Decisions] = None,
     Returns (packed gradient, dx, adopted-decision counts).
     """
     base = rec.base
-    L, H = base.cfg["num_layers"], base.cfg["hidden"]
-    B, Tg = rec.y.shape
-    N, Tn = rec.z.shape
-    gp = base.graph_ptr
-    h = base.layers[-1].h_out
+    L = base.cfg["num_layers"]
     stats = {"relu": 0, "argmin": 0, "argmax": 0}
-    dg = np.zeros((B, H))
-    gheads = []
-    for t, hd in enumerate(rec.graph):
-        dy = 2.0 * rec.gw[t] * (rec.y[:, t] - rec.y_target[:, t]) / B
-        pre = rec.gpre[t]
-        mask = pna._replay_relu(pre, pre > 0, None if graph_relu is None else graph_relu[t],
-                                tau, stats, f"graph head {t}")
-        q = np.maximum(pre, 0.0) * mask
-        dpre = dy[:, None] * hd["w2"][0][None, :] * mask
-        gheads.append({"W1": dpre.T @ rec.g, "b1": dpre.sum(0), "w2": (dy @ q)[None, :],
-                       "b2": np.array([dy.sum()])})
-        dg += dpre @ hd["W1"]
-    dh = np.zeros((N, H))
-    for b in range(B):
-        dh[gp[b]:gp[b + 1]] = dg[b] / (gp[b + 1] - gp[b])
-    nheads = []
-    for s, hd in enumerate(rec.node):
-        e = 2.0 * rec.nw[s] * (rec.z[:, s] - rec.z_target[:, s]) / N
-        pre = rec.npre[s]
-        mask = pna._replay_relu(pre, pre > 0, None if node_relu is None else node_relu[s],
-                                tau, stats, f"node head {s}")
-        q = np.maximum(pre, 0.0) * mask
-        dpre = e[:, None] * hd["w2"][0][None, :] * mask
-        nheads.append({"W1": dpre.T @ h, "b1": dpre.sum(0), "w2": (e @ q)[None, :],
-                       "b2": np.array([e.sum()])})
-        dh += dpre @ hd["W1"]
+    dh, hgrads = heads_backward(rec.heads, graph_relu, node_relu, tau, stats)
     G: Dict[str, np.ndarray] = {}
     dx = pna.layers_backward(base, dh, G, hint, tau, stats)
     keys = []
     for l in range(L):
         keys += [f"l{l}.Wm", f"l{l}.bm", f"l{l}.Wp", f"l{l}.bp"]
     parts = [G[k].ravel() for k in keys]
-    for hd in gheads + nheads:
+    for hd in hgrads:
         parts += [hd[k].ravel() for k in ("W1", "b1", "w2", "b2")]
     return np.concatenate(parts), dx, stats

@@ -231,6 +231,44 @@ def init_params(shape: ModelShape, seed: int) -> np.ndarray:
     return np.concatenate(chunks).astype(np.float32)
 
 
+def gc_tensor_shapes(kind: str, num_layers: int, hidden: int, node_feat: int = NODE_FEAT,
+                     edge_feat: int = 1, graph_heads: int = 1, node_heads: int = 0):
+    """[(name, shape)] of a GraphSAGE ("sage") or CGCNN ("cgcnn") model in
+    packing order: the GC stack, then the graph heads, then the node heads."""
+    H, Fe = hidden, edge_feat
+    out = []
+    if kind == "sage":
+        for l in range(num_layers):
+            F = node_feat if l == 0 else H
+            out += [(f"l{l}.W", (H, 2 * F)), (f"l{l}.b", (H,))]
+    elif kind == "cgcnn":
+        out += [("emb.W", (H, node_feat)), ("emb.b", (H,))]
+        for l in range(num_layers):
+            out += [(f"l{l}.W", (2 * H, 2 * H + Fe)), (f"l{l}.b", (2 * H,))]
+    else:
+        raise ValueError(f"unknown layer kind {kind!r}")
+    for t in range(graph_heads + node_heads):
+        out += [(f"h{t}.W1", (H, H)), (f"h{t}.b1", (H,)), (f"h{t}.w2", (1, H)),
+                (f"h{t}.b2", (1,))]
+    return out
+
+
+def init_gc_params(kind: str, num_layers: int, hidden: int, seed: int,
+                   node_feat: int = NODE_FEAT, edge_feat: int = 1, graph_heads: int = 1,
+                   node_heads: int = 0) -> np.ndarray:
+    """Seeded Xavier-uniform matrices, U(+-0.1) biases, in packing order (float32)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    chunks = []
+    for _, shp in gc_tensor_shapes(kind, num_layers, hidden, node_feat, edge_feat,
+                                   graph_heads, node_heads):
+        if len(shp) == 2:
+            a = np.sqrt(6.0 / (shp[0] + shp[1]))
+            chunks.append(rng.uniform(-a, a, size=shp).ravel())
+        else:
+            chunks.append(rng.uniform(-0.1, 0.1, size=shp))
+    return np.concatenate(chunks).astype(np.float32)
+
+
 # ---------------------------------------------------------------------------
 # Workload presets.  ``delta`` is the PNA degree normaliser: the mean of
 # ln(d+1) over every node of 10,000 generator graphs (seed 3000 + c), written

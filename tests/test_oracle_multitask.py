@@ -43,7 +43,7 @@ def test_single_graph_head_is_the_plain_oracle():
 
 
 def _decisions(rec):
-    out = [p > 0 for p in rec.gpre] + [p > 0 for p in rec.npre]
+    out = [p > 0 for p in rec.heads.gpre] + [p > 0 for p in rec.heads.npre]
     for lr in rec.base.layers:
         out += [lr.u > 0, lr.argmin, lr.argmax]
     return out
