@@ -66,6 +66,9 @@ enum {
 
 enum { HGNN_VALIDATE = 1 }; /* forward flag: synchronise and check content */
 enum { HGNN_PREC_FP32 = 0, HGNN_PREC_BF16 = 1 };
+/* GC layer kinds (Section 2 names PNA, CGCNN and GraphSAGE as the kinds
+ * HydraGNN implements; the paper's runs use PNA). */
+enum { HGNN_GC_PNA = 0, HGNN_GC_SAGE = 1, HGNN_GC_CGCNN = 2 };
 
 typedef struct hgnn_ctx hgnn_ctx;
 
@@ -125,6 +128,26 @@ typedef struct {
 } hgnn_heads;
 int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads,
                           hgnn_ctx **out);
+
+/* A model whose GC layers are of another kind (heads NULL: one graph head).
+ * HGNN_GC_PNA is hgnn_create_multitask.  The others (cfg->delta is unused;
+ * recompute must be 0; serving and the per-operation layer entries reject
+ * them; hgnn_op_fetch ids 7 and 8 are PNA-only):
+ *  HGNN_GC_SAGE   GraphSAGE, mean aggregator (Hamilton et al., 2017):
+ *                 M_i = mean of h_j over the in-edges j -> i (0 without
+ *                 in-edges), h'_i = ReLU(W_self h_i + W_nbr M_i + b).
+ *                 Packed per layer: W [H, 2F] = [W_self | W_nbr], b [H].
+ *  HGNN_GC_CGCNN  CGCNN (Xie and Grossman, 2018): h0 = W_emb x + b_emb, then
+ *                 per layer, for every in-edge j -> i with z = [h_i || h_j ||
+ *                 e_ij]: f = W_f z + b_f, s = W_s z + b_s, and h'_i =
+ *                 ReLU(h_i + sum sigmoid(f) * softplus(s)).  Packed: W_emb
+ *                 [H, F0], b_emb [H], then per layer W [2H, 2H + Fe] (rows
+ *                 0..H-1 the filter f, H..2H-1 the core s) and b [2H].
+ * Every layer ends in ReLU; batch normalisation is not applied.  The heads
+ * follow the layers as for PNA.  The kind is part of a checkpoint's
+ * identity (recorded in the config's `reserved` field). */
+int hgnn_create_gc(const hgnn_config *cfg, int32_t kind, const hgnn_heads *heads,
+                   hgnn_ctx **out);
 void hgnn_destroy(hgnn_ctx *ctx); /* synchronises; NULL is ignored */
 int hgnn_num_params(const hgnn_ctx *ctx, int64_t *out);
 /* Copy the packed parameters in (device [P]) and refresh the internal GEMM

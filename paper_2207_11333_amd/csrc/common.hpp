@@ -68,6 +68,9 @@ struct GemmNT {
   // optional: zero C[m, n] where mask[m * ldc + n] <= 0 (ReLU adjoint of the
   // layer that produced `mask`)
   const float *mask;
+  // optional: added to the product before bias/ReLU: C = act(A B^T + bias + addend)
+  const float *addend;
+  int ld_add;
   // 3: the last three segments read the same rows (equal k, differing only
   // in scale and boff) and their K tiles are taken interleaved -- tile j of
   // each in turn -- so a workgroup rereads a tile while it is still cached
@@ -98,9 +101,10 @@ struct GemmTN {
 };
 
 // Scatter of reduced partials into the packed gradient vector.  Columns
-// [0, main_cols) are the weight columns, with cmap(c) = c < F ? c :
-// (c < Fp ? skip : c - (Fp - F)); column main_cols is the sum column (from a
-// constant-one segment); later columns are padding.  Up to three row ranges
+// [0, main_cols) are the weight columns; the first npad blocks of Fp columns
+// hold F real columns each (the rest is skipped), later columns shift down
+// by npad (Fp - F); column main_cols is the sum column (from a constant-one
+// segment); later columns are padding.  Up to three row ranges
 // route rows m in [r0, r1) (local row u = m - r0):
 //   weight columns -> main[u * main_ld + main_coloff + cmap(c)] (main may be null)
 //   sum column     -> ones[(u % ones_split) * ones_stride + u / ones_split] (or null)
@@ -115,6 +119,9 @@ struct ReduceMap {
   const float *P;
   int splits, M, Ncols;
   int main_cols, F, Fp;
+  // number of leading Fp-wide column blocks padded from F (0 counts as 1):
+  // block b, column w < F maps to b F + w; later columns shift by npad (Fp - F)
+  int npad;
   ReduceRoute route[3];
   int nroute;
 };
@@ -126,6 +133,7 @@ struct ReduceMap {
 // csr.hip
 struct CsrBufs {
   int *rowptr, *csr_src, *csr_eid, *deg, *srcptr, *t2csr, *node_graph;
+  int *csr_dst;       // destination of each CSR position
   int *cnt_in, *cnt_out, *tmp_out, *csr_pos;
   float *csr_e;       // [E, Fe] edge attributes in CSR order
   float *sp, *sm;     // per-node degree scalers
@@ -241,5 +249,35 @@ hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp,
                               int H, int Fe, const StageOut &o, int to_bf16,
                               hipStream_t s);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
+
+// gc.hip: GraphSAGE and CGCNN layer kinds
+constexpr int kMaxFe = 4;
+hipError_t launch_sage_mean(const Dims *dims, int capN, int F, const int *rowptr,
+                            const int *csr_src, const float *h, int ldh, float *M,
+                            hipStream_t s);
+// G [N, 2F] = du [W_self | W_nbr]; dh = G_self + neighbour scatter, masked
+hipError_t launch_sage_scatter(const Dims *dims, int capN, int F, const int *srcptr,
+                               const int *t2csr, const int *csr_dst, const int *rowptr,
+                               const float *G, const float *mask, float *dh, hipStream_t s);
+hipError_t launch_cg_aggregate(const Dims *dims, int capN, int H, int Fe, const int *rowptr,
+                               const int *csr_src, const float *csr_e, const float *PQ,
+                               const float *weT, const float *b, const float *h_in,
+                               float *h_out, hipStream_t s);
+hipError_t launch_cg_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
+                                   const int *rowptr, const int *csr_src, const float *csr_e,
+                                   const float *PQ, const float *weT, const float *b,
+                                   const float *du, float *dm, float *D, int ldD,
+                                   hipStream_t s);
+// One block copy of a weight staging: dst[r ld + c] = src[r rs + c cs] inside
+// the valid vrows x vcols corner, 0 outside; BF16 hi + lo when bf16.
+struct GcStageJob {
+  const float *src;
+  long long rs, cs;
+  int rows, cols, vrows, vcols;
+  void *hi, *lo;
+  int ld, bf16;
+};
+hipError_t launch_gc_stage(const GcStageJob *jobs, int njobs, long long max_elems,
+                           long long *bump, hipStream_t s);
 
 } // namespace hgnn

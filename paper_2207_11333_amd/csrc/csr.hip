@@ -184,7 +184,7 @@ __global__ void k_csr_sort_in(const Dims *__restrict__ dims,
                               const int *__restrict__ ei,
                               const int *__restrict__ rowptr,
                               int *__restrict__ csr_eid, int *__restrict__ csr_src,
-                              int *__restrict__ csr_pos,
+                              int *__restrict__ csr_dst, int *__restrict__ csr_pos,
                               const float *__restrict__ edge_attr, int Fe,
                               float *__restrict__ csr_e, int max_degree) {
   const int N = dims->N;
@@ -209,6 +209,7 @@ __global__ void k_csr_sort_in(const Dims *__restrict__ dims,
   for (int q = lo; q < hi; ++q) {
     const int k = csr_eid[q];
     csr_src[q] = ei[k];
+    csr_dst[q] = i;
     csr_pos[k] = q;
     for (int f = 0; f < Fe; ++f) csr_e[(size_t)q * Fe + f] = edge_attr[(size_t)k * Fe + f];
   }
@@ -276,7 +277,7 @@ hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
                                                c.tmp_out);
   if (capN > 0) {
     k_csr_sort_in<<<cdiv(capN, 128), 128, 0, s>>>(dims, edge_index, c.rowptr, c.csr_eid,
-                                                  c.csr_src, c.csr_pos, edge_attr, Fe,
+                                                  c.csr_src, c.csr_dst, c.csr_pos, edge_attr, Fe,
                                                   c.csr_e, max_degree);
     k_csr_sort_out<<<cdiv(capN, 128), 128, 0, s>>>(dims, c.srcptr, c.tmp_out, c.csr_pos,
                                                    c.t2csr, max_degree);

@@ -203,6 +203,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
         const int m = m0 + wm0 + i * 16 + cr + v;
         if (m < M) {
           float o = acc[i][j][v] + bias;
+          if (g.addend) o += g.addend[(size_t)m * g.ld_add + n];
           if (g.relu) o = o > 0.f ? o : 0.f;
           if (g.mask && !(g.mask[(size_t)m * g.ldc + n] > 0.f)) o = 0.f;
           g.C[(size_t)m * g.ldc + n] = o;

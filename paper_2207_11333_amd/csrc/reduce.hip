@@ -63,6 +63,7 @@ k_reduce_nt(const Dims *__restrict__ dims, const GemmNT g) {
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     float o = sum[e] + (g.bias ? g.bias[n + e] : 0.f);
+    if (g.addend) o += g.addend[(size_t)m * g.ld_add + n + e];
     if (g.relu) o = o > 0.f ? o : 0.f;
     if (g.mask && !(g.mask[(size_t)m * g.ldc + n + e] > 0.f)) o = 0.f;
     sum[e] = o;
@@ -88,8 +89,16 @@ __global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
     for (int e = 0; e < 4; ++e) {
       const int c = c0 + e;
       if (c < r.main_cols) {
-        if (!ro.main || (c >= r.F && c < r.Fp)) continue;
-        const int oc = c < r.F ? c : c - (r.Fp - r.F);
+        if (!ro.main) continue;
+        const int nb = r.npad > 1 ? r.npad : 1;
+        int oc;
+        if (c < nb * r.Fp) {
+          const int blk = c / r.Fp, w = c - blk * r.Fp;
+          if (w >= r.F) continue;
+          oc = blk * r.F + w;
+        } else {
+          oc = c - nb * (r.Fp - r.F);
+        }
         ro.main[(size_t)u * ro.main_ld + ro.main_coloff + oc] = sum[e];
       } else if (c == r.main_cols && ro.ones) {
         ro.ones[(size_t)(u % ro.ones_split) * ro.ones_stride + u / ro.ones_split] = sum[e];

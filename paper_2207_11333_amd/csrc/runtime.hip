@@ -73,8 +73,12 @@ void free_work(Exec &ex) {
                    (void **)&w.ypred, (void **)&w.dy, (void **)&w.dq, (void **)&w.du,
                    (void **)&w.dA, (void **)&w.dm, (void **)&w.D, (void **)&w.dh0,
                    (void **)&w.dh1, (void **)&w.ntpart, (void **)&w.zn, (void **)&w.Qn,
-                   (void **)&w.dQn, (void **)&w.en, (void **)&w.dhn};
+                   (void **)&w.dQn, (void **)&w.en, (void **)&w.dhn,
+                   (void **)&w.csr.csr_dst, (void **)&w.h0, (void **)&w.gcG,
+                   (void **)&w.gcD, (void **)&w.gcdm};
   for (void **p : ptrs) dfree(*p);
+  for (auto &p : w.gcA) dfree(reinterpret_cast<void *&>(p));
+  w.gcA.clear();
   for (auto &p : w.hbuf) dfree(reinterpret_cast<void *&>(p));
   for (auto &p : w.PQ) dfree(reinterpret_cast<void *&>(p));
   for (auto &p : w.A) dfree(reinterpret_cast<void *&>(p));
@@ -98,21 +102,31 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
   ok = ok && f(w.csr.rowptr, (size_t)capN + 1) && f(w.csr.srcptr, (size_t)capN + 1);
   ok = ok && f(w.csr.csr_src, (size_t)capE) && f(w.csr.csr_eid, (size_t)capE) &&
        f(w.csr.t2csr, (size_t)capE) && f(w.csr.tmp_out, (size_t)capE) &&
-       f(w.csr.csr_pos, (size_t)capE);
+       f(w.csr.csr_pos, (size_t)capE) && f(w.csr.csr_dst, (size_t)capE);
   ok = ok && f(w.csr.deg, (size_t)capN) && f(w.csr.node_graph, (size_t)capN) &&
        f(w.csr.cnt_in, (size_t)capN) && f(w.csr.cnt_out, (size_t)capN);
   ok = ok && f(w.csr.csr_e, (size_t)capE * Fe) && f(w.csr.sp, (size_t)capN) &&
        f(w.csr.sm, (size_t)capN) && f(w.xpad, (size_t)capN * c->F0p);
   if (w.hbuf.size() != (size_t)nh) w.hbuf.assign(nh, nullptr);
   for (int l = 0; l < nh && ok; ++l) ok = f(w.hbuf[l], (size_t)capN * H);
-  if (w.PQ.size() != (size_t)nstore) {
-    w.PQ.assign(nstore, nullptr);
-    w.A.assign(nstore, nullptr);
-    w.args.assign(nstore, nullptr);
+  const bool pna = c->kind == HGNN_GC_PNA;
+  if (pna) {
+    if (w.PQ.size() != (size_t)nstore) {
+      w.PQ.assign(nstore, nullptr);
+      w.A.assign(nstore, nullptr);
+      w.args.assign(nstore, nullptr);
+    }
+    for (int l = 0; l < nstore && ok; ++l)
+      ok = f(w.PQ[l], (size_t)capN * 2 * H) && f(w.A[l], (size_t)capN * 4 * H) &&
+           f(w.args[l], (size_t)capN * 2 * H);
+  } else {
+    if (w.gcA.size() != (size_t)L) w.gcA.assign(L, nullptr);
+    for (int l = 0; l < L && ok; ++l) {
+      const size_t width = c->kind == HGNN_GC_SAGE ? (size_t)c->ld[l].Fp : 4 * (size_t)H;
+      ok = f(w.gcA[l], (size_t)capN * width);
+    }
+    if (c->kind == HGNN_GC_CGCNN) ok = ok && f(w.h0, (size_t)capN * H);
   }
-  for (int l = 0; l < nstore && ok; ++l)
-    ok = f(w.PQ[l], (size_t)capN * 2 * H) && f(w.A[l], (size_t)capN * 4 * H) &&
-         f(w.args[l], (size_t)capN * 2 * H);
   const int Tg = c->Tg, Tn = c->Tn;
   ok = ok && f(w.g, (size_t)capB * H) && f(w.q, (size_t)Tg * capB * H) &&
        f(w.ypred, (size_t)capB * Tg);
@@ -126,9 +140,16 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
     if (Tn > 0)
       ok = ok && f(w.dQn, (size_t)Tn * capN * H) && f(w.en, (size_t)capN * Tn) &&
            f(w.dhn, (size_t)capN * H);
-    ok = ok && f(w.du, (size_t)capN * H) && f(w.dA, (size_t)capN * 4 * H) &&
-         f(w.dm, (size_t)capE * H) && f(w.D, (size_t)capN * (2 + c->Fe) * H) &&
-         f(w.dh0, (size_t)capN * H) && f(w.dh1, (size_t)capN * H);
+    ok = ok && f(w.du, (size_t)capN * H) && f(w.dh0, (size_t)capN * H) &&
+         f(w.dh1, (size_t)capN * H);
+    if (pna)
+      ok = ok && f(w.dA, (size_t)capN * 4 * H) && f(w.dm, (size_t)capE * H) &&
+           f(w.D, (size_t)capN * (2 + c->Fe) * H);
+    else if (c->kind == HGNN_GC_SAGE)
+      ok = ok && f(w.gcG, (size_t)capN * 2 * H);
+    else
+      ok = ok && f(w.gcD, (size_t)capN * (4 + 2 * c->Fe) * H) &&
+           f(w.gcdm, (size_t)capE * 2 * H);
   }
   return ok;
 }
@@ -183,6 +204,12 @@ static StageOut stage_out(hgnn_ctx *c, int l) {
 }
 
 int stage_all(hgnn_ctx *c, hipStream_t s, long long *bump_step) {
+  if (c->kind != HGNN_GC_PNA) {
+    hipError_t e = launch_gc_stage(c->gc_jobs, c->gc_njobs, c->gc_max_elems, bump_step, s);
+    if (e != hipSuccess) return hip_fail(c, e, "stage weights");
+    c->staged_from_params = true;
+    return HGNN_OK;
+  }
   int maxFp = 0;
   for (const LayerDesc &d : c->ld) maxFp = std::max(maxFp, d.Fp);
   hipError_t e = launch_stage_all(c->stage_tab, c->L, maxFp, c->H, c->Fe, c->prec, bump_step, s);
@@ -618,6 +645,310 @@ int head_backward(hgnn_ctx *c, Exec &ex, const float *wh, const float *target, c
   return HGNN_OK;
 }
 
+// ---- GraphSAGE and CGCNN layer kinds ---------------------------------------
+
+// The block copies that refresh their GEMM-layout weights (one launch).
+static std::vector<GcStageJob> gc_stage_jobs(hgnn_ctx *c) {
+  std::vector<GcStageJob> jobs;
+  const int H = c->H, bf = c->prec;
+  const size_t esz = bf ? 2 : 4;
+  auto at = [&](void *base, size_t elems) {
+    return base ? static_cast<void *>(static_cast<uint8_t *>(base) + esz * elems) : nullptr;
+  };
+  auto job = [&](const float *src, long long rs, long long cs, int rows, int cols, int vrows,
+                 int vcols, void *hi, void *lo, int ld, int to_bf16) {
+    jobs.push_back(GcStageJob{src, rs, cs, rows, cols, vrows, vcols, hi, lo, ld, to_bf16});
+  };
+  for (int l = 0; l < c->L; ++l) {
+    const LayerDesc &d = c->ld[l];
+    const float *W = c->params + d.oWm;
+    void *g1 = c->Wg1[l], *g2 = c->Wg2[l];
+    void *g1l = bf ? c->Wg1_lo[l] : nullptr, *g2l = bf ? c->Wg2_lo[l] : nullptr;
+    if (c->kind == HGNN_GC_SAGE) {
+      const int F = d.F, Fp = d.Fp;
+      // Wg1 [H, 2Fp] = [W_self | W_nbr], each half zero-padded from F to Fp
+      job(W, 2 * F, 1, H, Fp, H, F, g1, g1l, 2 * Fp, bf);
+      job(W + F, 2 * F, 1, H, Fp, H, F, at(g1, Fp), at(g1l, Fp), 2 * Fp, bf);
+      // Wg2 [2Fp, H] = [W_self^T; W_nbr^T], rows past F zero
+      job(W, 1, 2 * F, Fp, H, F, H, g2, g2l, H, bf);
+      job(W + F, 1, 2 * F, Fp, H, F, H, at(g2, (size_t)Fp * H), at(g2l, (size_t)Fp * H), H, bf);
+    } else {
+      const int ldw = 2 * H + c->Fe;
+      // Wg1 [4H, H] = [W[:, 0:H]; W[:, H:2H]] (destination rows, then source rows)
+      job(W, ldw, 1, 2 * H, H, 2 * H, H, g1, g1l, H, bf);
+      job(W + H, ldw, 1, 2 * H, H, 2 * H, H, at(g1, (size_t)2 * H * H),
+          at(g1l, (size_t)2 * H * H), H, bf);
+      // Wg2 [H, 4H]: row n = [W[:, n] | W[:, H + n]]
+      job(W, 1, ldw, H, 2 * H, H, 2 * H, g2, g2l, 4 * H, bf);
+      job(W + H, 1, ldw, H, 2 * H, H, 2 * H, at(g2, 2 * H), at(g2l, 2 * H), 4 * H, bf);
+      // edge-feature columns, FP32 in both precisions: weT[k, r] = W[r, 2H + k]
+      if (c->Fe > 0)
+        job(W + 2 * H, 1, ldw, c->Fe, 2 * H, c->Fe, 2 * H, c->WeT[l], nullptr, 2 * H, 0);
+    }
+  }
+  if (c->kind == HGNN_GC_CGCNN)
+    job(c->params + c->off_emb, c->F0, 1, H, c->F0p, H, c->F0, c->Wemb, c->Wemb_lo, c->F0p, bf);
+  return jobs;
+}
+
+static void fork_to_aux(hgnn_ctx *c, int k, hipStream_t s, hipError_t &e) {
+  if (e == hipSuccess) e = hipEventRecord(c->fork_ev[k], s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->fork_ev[k], 0);
+}
+
+static void join_aux(hgnn_ctx *c, hipStream_t s, hipError_t &e) {
+  if (e == hipSuccess) e = hipEventRecord(c->join_ev, c->aux);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join_ev, 0);
+}
+
+// Forward of the GC stack; *last receives the last layer's output.
+static int gc_forward(hgnn_ctx *c, Exec &ex, hipStream_t s, const float **last) {
+  Work &w = ex.w;
+  const int H = c->H;
+  hipError_t e = hipSuccess;
+  const float *h = w.xpad;
+  int ldh = c->F0p;
+  if (c->kind == HGNN_GC_CGCNN) { // h0 = x W_emb^T + b_emb
+    GemmNT g{};
+    g.nseg = 1;
+    g.seg[0] = SegA{w.xpad, nullptr, c->F0p, c->F0p, 0};
+    g.B = c->Wemb;
+    g.B_lo = c->prec ? c->Wemb_lo : nullptr;
+    g.ldb = c->F0p;
+    g.Ncols = H;
+    g.bias = c->params + c->off_emb + (size_t)H * c->F0;
+    g.C = w.h0;
+    g.ldc = H;
+    g.M_fixed = -1;
+    e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
+    if (e != hipSuccess) return hip_fail(c, e, "embedding GEMM");
+    h = w.h0;
+    ldh = H;
+  }
+  for (int l = 0; l < c->L; ++l) {
+    const LayerDesc &d = c->ld[l];
+    const float *b = c->params + d.obm;
+    if (c->kind == HGNN_GC_SAGE) {
+      e = launch_sage_mean(ex.dims, ex.N, d.Fp, w.csr.rowptr, w.csr.csr_src, h, ldh, w.gcA[l],
+                           s);
+      if (e != hipSuccess) return hip_fail(c, e, "neighbour mean");
+      GemmNT g{};
+      g.nseg = 2;
+      g.seg[0] = SegA{h, nullptr, ldh, d.Fp, 0};
+      g.seg[1] = SegA{w.gcA[l], nullptr, d.Fp, d.Fp, d.Fp};
+      g.B = c->Wg1[l];
+      g.B_lo = c->prec ? c->Wg1_lo[l] : nullptr;
+      g.ldb = 2 * d.Fp;
+      g.Ncols = H;
+      g.bias = b;
+      g.relu = 1;
+      g.C = w.hbuf[l];
+      g.ldc = H;
+      g.M_fixed = -1;
+      {
+        TimedLaunch tl(c, ex, SITE_UPDATE_GEMM, s, /*manual=*/true);
+        hipEvent_t e0 = tl.start(), e1 = tl.stop();
+        e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s, /*tag=*/1, e0, e1);
+      }
+      if (e != hipSuccess) return hip_fail(c, e, "GraphSAGE GEMM");
+    } else {
+      GemmNT g{};
+      g.nseg = 1;
+      g.seg[0] = SegA{h, nullptr, ldh, H, 0};
+      g.B = c->Wg1[l];
+      g.B_lo = c->prec ? c->Wg1_lo[l] : nullptr;
+      g.ldb = H;
+      g.Ncols = 4 * H;
+      g.C = w.gcA[l];
+      g.ldc = 4 * H;
+      g.M_fixed = -1;
+      e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
+      if (e != hipSuccess) return hip_fail(c, e, "CGCNN gate GEMM");
+      {
+        TimedLaunch tl(c, ex, SITE_AGGREGATE, s);
+        e = launch_cg_aggregate(ex.dims, ex.N, H, c->Fe, w.csr.rowptr, w.csr.csr_src,
+                                w.csr.csr_e, w.gcA[l], static_cast<const float *>(c->WeT[l]),
+                                b, h, w.hbuf[l], s);
+      }
+      if (e != hipSuccess) return hip_fail(c, e, "CGCNN aggregation");
+    }
+    h = w.hbuf[l];
+    ldh = H;
+  }
+  *last = h;
+  return HGNN_OK;
+}
+
+// Backward of the GC stack from cur = dL/du of the last layer (its ReLU
+// adjoint applied); nxt is the second [N, H] buffer of the ping-pong.
+static int gc_backward(hgnn_ctx *c, Exec &ex, float *cur, float *nxt, hipStream_t s) {
+  Work &w = ex.w;
+  const int H = c->H, Fe = c->Fe;
+  hipError_t e = hipSuccess;
+  for (int l = c->L - 1; l >= 0; --l) {
+    const LayerDesc &d = c->ld[l];
+    float *dW = c->grads + d.oWm, *db = c->grads + d.obm;
+    const float *hin = l ? w.hbuf[l - 1] : (c->kind == HGNN_GC_CGCNN ? w.h0 : w.xpad);
+    const int ldh = l ? H : (c->kind == HGNN_GC_CGCNN ? H : c->F0p);
+    const float *du = cur;
+    if (c->kind == HGNN_GC_SAGE) {
+      fork_to_aux(c, 0, s, e);
+      if (e != hipSuccess) return hip_fail(c, e, "fork");
+      // dW = du^T [h || M], db = sum du
+      GemmTN t{};
+      t.X = du;
+      t.ldx = H;
+      t.M = H;
+      t.seg[0] = SegY{hin, nullptr, ldh, d.Fp};
+      t.seg[1] = SegY{w.gcA[l], nullptr, d.Fp, d.Fp};
+      t.seg[2] = SegY{nullptr, nullptr, 0, 4};
+      t.nseg = 3;
+      t.Ncols = 2 * d.Fp + 4;
+      t.P = c->part;
+      t.splits = d.split_p;
+      {
+        TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, c->aux);
+        e = launch_gemm_tn(ex.dims, t, c->prec, c->aux);
+      }
+      if (e == hipSuccess) {
+        ReduceMap r{};
+        r.P = c->part;
+        r.splits = d.split_p;
+        r.M = H;
+        r.Ncols = 2 * d.Fp + 4;
+        r.main_cols = 2 * d.Fp;
+        r.F = d.F;
+        r.Fp = d.Fp;
+        r.npad = 2;
+        r.route[0] = ReduceRoute{0, H, dW, 2 * d.F, 0, db, 1, H};
+        r.nroute = 1;
+        e = launch_reduce_map(r, c->aux);
+      }
+      if (e != hipSuccess) return hip_fail(c, e, "GraphSAGE weight gradient");
+      if (l > 0) { // G = du [W_self | W_nbr]; dh_in = G_self + neighbour scatter
+        GemmNT g{};
+        g.nseg = 1;
+        g.seg[0] = SegA{du, nullptr, H, H, 0};
+        g.B = c->Wg2[l];
+        g.B_lo = c->prec ? c->Wg2_lo[l] : nullptr;
+        g.ldb = H;
+        g.Ncols = 2 * H;
+        g.C = w.gcG;
+        g.ldc = 2 * H;
+        g.M_fixed = -1;
+        e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
+        if (e == hipSuccess)
+          e = launch_sage_scatter(ex.dims, ex.N, H, w.csr.srcptr, w.csr.t2csr, w.csr.csr_dst,
+                                  w.csr.rowptr, w.gcG, hin, nxt, s);
+        if (e != hipSuccess) return hip_fail(c, e, "GraphSAGE input gradient");
+      }
+    } else {
+      const int ldD = (4 + 2 * Fe) * H;
+      {
+        TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s);
+        e = launch_cg_aggregate_bwd(ex.dims, ex.N, H, Fe, w.csr.rowptr, w.csr.csr_src,
+                                    w.csr.csr_e, w.gcA[l], static_cast<const float *>(c->WeT[l]),
+                                    c->params + d.obm, du, w.gcdm, w.gcD, ldD, s);
+      }
+      if (e == hipSuccess)
+        e = launch_transpose_sum(ex.dims, ex.N, 2 * H, w.csr.srcptr, w.csr.t2csr, w.gcdm, w.gcD,
+                                 ldD, s);
+      if (e != hipSuccess) return hip_fail(c, e, "CGCNN aggregation adjoint");
+      fork_to_aux(c, 0, s, e);
+      if (e != hipSuccess) return hip_fail(c, e, "fork");
+      // [dW_dst | dW_src] = [D_in | D_out]^T h; db and the edge columns from
+      // the constant-one column
+      GemmTN t{};
+      t.X = w.gcD;
+      t.ldx = ldD;
+      t.M = ldD;
+      t.seg[0] = SegY{hin, nullptr, ldh, H};
+      t.seg[1] = SegY{nullptr, nullptr, 0, 4};
+      t.nseg = 2;
+      t.Ncols = H + 4;
+      t.P = c->part;
+      t.splits = d.split_p;
+      {
+        TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, c->aux);
+        e = launch_gemm_tn(ex.dims, t, c->prec, c->aux);
+      }
+      if (e == hipSuccess) {
+        const int ldw = 2 * H + Fe;
+        ReduceMap r{};
+        r.P = c->part;
+        r.splits = d.split_p;
+        r.M = ldD;
+        r.Ncols = H + 4;
+        r.main_cols = H;
+        r.F = H;
+        r.Fp = H;
+        r.route[0] = ReduceRoute{0, 2 * H, dW, ldw, 0, db, 1, 2 * H};
+        r.route[1] = ReduceRoute{2 * H, 4 * H, dW, ldw, H, nullptr, 0, 1};
+        r.route[2] = ReduceRoute{4 * H, ldD, nullptr, 0, 0, dW + 2 * H, ldw, 2 * H};
+        r.nroute = Fe > 0 ? 3 : 2;
+        e = launch_reduce_map(r, c->aux);
+      }
+      if (e != hipSuccess) return hip_fail(c, e, "CGCNN weight gradient");
+      // dh_in = du (residual) + [D_in | D_out] [W_dst; W_src], masked by the
+      // ReLU of the layer below (the embedding below layer 0 has none)
+      GemmNT g{};
+      g.nseg = 2;
+      g.seg[0] = SegA{w.gcD, nullptr, ldD, 2 * H, 0};
+      g.seg[1] = SegA{w.gcD + 2 * H, nullptr, ldD, 2 * H, 2 * H};
+      g.B = c->Wg2[l];
+      g.B_lo = c->prec ? c->Wg2_lo[l] : nullptr;
+      g.ldb = 4 * H;
+      g.Ncols = H;
+      g.addend = du;
+      g.ld_add = H;
+      g.mask = l ? hin : nullptr;
+      g.C = nxt;
+      g.ldc = H;
+      g.M_fixed = -1;
+      {
+        TimedLaunch tl(c, ex, SITE_INPUT_GEMM, s);
+        e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
+      }
+      if (e != hipSuccess) return hip_fail(c, e, "CGCNN input gradient");
+    }
+    join_aux(c, s, e);
+    if (e != hipSuccess) return hip_fail(c, e, "join");
+    std::swap(cur, nxt);
+  }
+  if (c->kind == HGNN_GC_CGCNN) { // embedding: dW_emb = dh0^T x, db_emb = sum dh0
+    GemmTN t{};
+    t.X = cur;
+    t.ldx = H;
+    t.M = H;
+    t.seg[0] = SegY{w.xpad, nullptr, c->F0p, c->F0p};
+    t.seg[1] = SegY{nullptr, nullptr, 0, 4};
+    t.nseg = 2;
+    t.Ncols = c->F0p + 4;
+    t.P = c->part;
+    t.splits = c->split_emb;
+    e = launch_gemm_tn(ex.dims, t, c->prec, s);
+    if (e == hipSuccess) {
+      float *dWe = c->grads + c->off_emb;
+      ReduceMap r{};
+      r.P = c->part;
+      r.splits = c->split_emb;
+      r.M = H;
+      r.Ncols = c->F0p + 4;
+      r.main_cols = c->F0p;
+      r.F = c->F0;
+      r.Fp = c->F0p;
+      r.route[0] = ReduceRoute{0, H, dWe, c->F0, 0, dWe + (size_t)H * c->F0, 1, H};
+      r.nroute = 1;
+      e = launch_reduce_map(r, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "embedding weight gradient");
+  }
+  return HGNN_OK;
+}
+
+static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
+                      hgnn_ctx **out);
+
 } // namespace hgnn
 
 // ===========================================================================
@@ -641,8 +972,27 @@ int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
 }
 
 int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_ctx **out) {
+  return create_ctx(cfg, HGNN_GC_PNA, heads, out);
+}
+
+int hgnn_create_gc(const hgnn_config *cfg, int32_t kind, const hgnn_heads *heads,
+                   hgnn_ctx **out) {
+  if (kind != HGNN_GC_PNA && kind != HGNN_GC_SAGE && kind != HGNN_GC_CGCNN) {
+    if (out) *out = nullptr;
+    return fail(HGNN_EINVAL, "kind must be HGNN_GC_PNA, HGNN_GC_SAGE or HGNN_GC_CGCNN");
+  }
+  return create_ctx(cfg, kind, heads, out);
+}
+
+} // extern "C"
+
+namespace hgnn {
+
+static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
+                      hgnn_ctx **out) {
   if (!cfg || !out) return fail(HGNN_EINVAL, "cfg and out are required");
   *out = nullptr;
+  const bool pna = kind == HGNN_GC_PNA;
   const int Tg = heads ? heads->graph_heads : 1, Tn = heads ? heads->node_heads : 0;
   if (Tg < 1 || Tg > 8) return fail(HGNN_EINVAL, "graph_heads must be in 1..8");
   if (Tn < 0 || Tn > 4) return fail(HGNN_EINVAL, "node_heads must be in 0..4");
@@ -667,7 +1017,8 @@ int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_
     return fail(HGNN_EINVAL, "precision must be HGNN_PREC_FP32 or HGNN_PREC_BF16");
   if (cfg->recompute != 0 && cfg->recompute != 1)
     return fail(HGNN_EINVAL, "recompute must be 0 or 1");
-  if (!(cfg->delta > 0.0) || !std::isfinite(cfg->delta))
+  if (!pna && cfg->recompute) return fail(HGNN_EINVAL, "recompute is PNA-only");
+  if (pna && (!(cfg->delta > 0.0) || !std::isfinite(cfg->delta)))
     return fail(HGNN_EINVAL, "delta must be positive and finite");
   if (!(cfg->std_eps >= 0.0) || !std::isfinite(cfg->std_eps))
     return fail(HGNN_EINVAL, "std_eps must be >= 0");
@@ -683,10 +1034,44 @@ int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_
   c->maxd = cfg->max_degree;
   c->prec = cfg->precision;
   c->recompute = cfg->recompute;
+  c->kind = kind;
   const int H = c->H;
   int64_t off = 0;
   size_t part_max = 0;
-  for (int l = 0; l < c->L; ++l) {
+  if (kind == HGNN_GC_SAGE) {
+    for (int l = 0; l < c->L; ++l) {
+      LayerDesc d{};
+      d.F = l == 0 ? c->F0 : H;
+      d.Fp = l == 0 ? c->F0p : H;
+      d.off = d.oWm = off;
+      off += (int64_t)H * 2 * d.F;
+      d.obm = off;
+      off += H;
+      d.size = off - d.off;
+      d.split_p = tn_splits(H, 2 * d.Fp + 4, cfg->precision);
+      part_max = std::max(part_max, (size_t)d.split_p * H * (2 * d.Fp + 4));
+      c->ld.push_back(d);
+    }
+  } else if (kind == HGNN_GC_CGCNN) {
+    c->off_emb = 0;
+    off += (int64_t)H * c->F0 + H;
+    c->split_emb = tn_splits(H, c->F0p + 4, cfg->precision);
+    part_max = std::max(part_max, (size_t)c->split_emb * H * (c->F0p + 4));
+    const int ldD = (4 + 2 * c->Fe) * H;
+    for (int l = 0; l < c->L; ++l) {
+      LayerDesc d{};
+      d.F = d.Fp = H;
+      d.off = d.oWm = off;
+      off += (int64_t)2 * H * (2 * H + c->Fe);
+      d.obm = off;
+      off += 2 * H;
+      d.size = off - d.off;
+      d.split_p = tn_splits(ldD, H + 4, cfg->precision);
+      part_max = std::max(part_max, (size_t)d.split_p * ldD * (H + 4));
+      c->ld.push_back(d);
+    }
+  }
+  for (int l = 0; pna && l < c->L; ++l) {
     LayerDesc d;
     d.F = l == 0 ? c->F0 : H;
     d.Fp = l == 0 ? c->F0p : H;
@@ -709,7 +1094,7 @@ int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_
   }
   c->Tg = Tg;
   c->Tn = Tn;
-  c->cfg.reserved = Tg + 256 * Tn; // part of the checkpoint's identity
+  c->cfg.reserved = Tg + 256 * Tn + 65536 * kind; // part of the checkpoint's identity
   c->off_head = off;
   off += (int64_t)Tg * node_head_size(H);
   c->off_node = off;
@@ -757,7 +1142,50 @@ int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_
     return fail(HGNN_EDEVICE, "copying the loss weights failed");
   }
   const size_t esz = c->prec ? 2 : 4;
-  for (int l = 0; l < c->L; ++l) {
+  if (!pna) {
+    // GEMM-layout copies: forward operand Wg1, input-gradient operand Wg2
+    // (SAGE: [H, 2Fp] and [2Fp, H]; CGCNN: [4H, H] and [H, 4H]), the CGCNN
+    // edge-feature weights [Fe, 2H] (FP32) and embedding [H, F0p]
+    for (int l = 0; l < c->L; ++l) {
+      const LayerDesc &d = c->ld[l];
+      const size_t n = kind == HGNN_GC_SAGE ? (size_t)2 * H * d.Fp : (size_t)4 * H * H;
+      uint8_t *p;
+      HGNN_CALLOC(p, esz * n);
+      c->Wg1.push_back(p);
+      HGNN_CALLOC(p, esz * n);
+      c->Wg2.push_back(p);
+      if (c->prec) {
+        HGNN_CALLOC(p, esz * n);
+        c->Wg1_lo.push_back(p);
+        HGNN_CALLOC(p, esz * n);
+        c->Wg2_lo.push_back(p);
+      }
+      float *we = nullptr;
+      if (kind == HGNN_GC_CGCNN && c->Fe > 0) HGNN_CALLOC(we, (size_t)c->Fe * 2 * H);
+      c->WeT.push_back(we);
+    }
+    if (kind == HGNN_GC_CGCNN) {
+      uint8_t *p;
+      HGNN_CALLOC(p, esz * H * c->F0p);
+      c->Wemb = p;
+      if (c->prec) {
+        HGNN_CALLOC(p, esz * H * c->F0p);
+        c->Wemb_lo = p;
+      }
+    }
+    std::vector<GcStageJob> jobs = gc_stage_jobs(c);
+    c->gc_njobs = (int)jobs.size();
+    c->gc_max_elems = 0;
+    for (const GcStageJob &j : jobs)
+      c->gc_max_elems = std::max(c->gc_max_elems, (long long)j.rows * j.cols);
+    HGNN_CALLOC(c->gc_jobs, jobs.size());
+    if (hipMemcpy(c->gc_jobs, jobs.data(), jobs.size() * sizeof(GcStageJob),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      hgnn_destroy(c);
+      return fail(HGNN_EDEVICE, "copying the staging table failed");
+    }
+  }
+  for (int l = 0; pna && l < c->L; ++l) {
     const LayerDesc &d = c->ld[l];
     const size_t n[4] = {(size_t)2 * H * d.Fp, (size_t)H * (d.Fp + 12 * H), (size_t)12 * H * H,
                          (size_t)3 * H * d.Fp};
@@ -776,7 +1204,7 @@ int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_
     if (c->Fe > 0) HGNN_CALLOC(we, (size_t)c->Fe * H);
     c->WeT.push_back(we);
   }
-  {
+  if (pna) {
     std::vector<StageDesc> tab(c->L);
     for (int l = 0; l < c->L; ++l) {
       const LayerDesc &d = c->ld[l];
@@ -825,6 +1253,10 @@ int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_
   return HGNN_OK;
 }
 
+} // namespace hgnn
+
+extern "C" {
+
 void hgnn_destroy(hgnn_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->dev);
@@ -844,8 +1276,9 @@ void hgnn_destroy(hgnn_ctx *c) {
                    (void **)&c->part};
   for (void **p : ptrs) dfree(*p);
   for (auto *v : {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT, &c->Wds_lo, &c->Wpp_lo, &c->WpTA_lo,
-                  &c->WhdsT_lo, &c->WeT})
+                  &c->WhdsT_lo, &c->WeT, &c->Wg1, &c->Wg1_lo, &c->Wg2, &c->Wg2_lo})
     for (auto &p : *v) dfree(reinterpret_cast<void *&>(p));
+  for (void **p : {(void **)&c->Wemb, (void **)&c->Wemb_lo, (void **)&c->gc_jobs}) dfree(*p);
   delete c;
 }
 
@@ -912,10 +1345,15 @@ int hgnn_forward_multitask(hgnn_ctx *c, const hgnn_batch *b, const float *y_node
   ex.ynode = y_node;
   if (!c->staged_from_params && (rc = stage_all(c, s))) return rc;
   const float *h = b->x;
-  for (int l = 0; l < c->L; ++l) {
-    rc = layer_forward(c, ex, l, c->params + c->ld[l].off, h, c->ex.w.hbuf[l], s);
+  if (c->kind != HGNN_GC_PNA) {
+    rc = gc_forward(c, ex, s, &h);
     if (rc) return rc;
-    h = c->ex.w.hbuf[l];
+  } else {
+    for (int l = 0; l < c->L; ++l) {
+      rc = layer_forward(c, ex, l, c->params + c->ld[l].off, h, c->ex.w.hbuf[l], s);
+      if (rc) return rc;
+      h = c->ex.w.hbuf[l];
+    }
   }
   return head_forward(c, ex, c->params + c->off_head, h, b->y, pred, loss, s, pred_node,
                       y_node);
@@ -937,6 +1375,7 @@ int hgnn_backward(hgnn_ctx *c, const float *dpred, void *stream) {
   int rc = head_backward(c, c->ex, c->params + c->off_head, c->ex.target, dpred, cur,
                          c->grads + c->off_head, s, w.hbuf[c->L - 1], w.hbuf[c->L - 1]);
   if (rc) return rc;
+  if (c->kind != HGNN_GC_PNA) return gc_backward(c, c->ex, cur, nxt, s);
   for (int l = c->L - 1; l >= 0; --l) {
     const float *h_in = l ? w.hbuf[l - 1] : c->ex.xin;
     rc = layer_backward(c, c->ex, l, c->params + c->ld[l].off, h_in, w.hbuf[l], cur,
@@ -1039,6 +1478,7 @@ int hgnn_op_prepare(hgnn_ctx *c, const hgnn_batch *b, int32_t flags, void *strea
 int hgnn_op_layer_forward(hgnn_ctx *c, int32_t l, const float *wl, const float *h_in,
                           float *h_out, void *stream) {
   HGNN_GUARD(c);
+  if (c->kind != HGNN_GC_PNA) return fail(HGNN_EINVAL, "per-operation layer entries are PNA-only");
   if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
   if (l < 0 || l >= c->L) return fail(HGNN_EINVAL, "layer out of range");
   if (!wl || !h_in || !h_out) return fail(HGNN_EINVAL, "NULL buffer");
@@ -1052,6 +1492,7 @@ int hgnn_op_layer_backward(hgnn_ctx *c, int32_t l, const float *wl, const float 
                            const float *h_out, const float *dh_out, float *dh_in,
                            float *dwl, void *stream) {
   HGNN_GUARD(c);
+  if (c->kind != HGNN_GC_PNA) return fail(HGNN_EINVAL, "per-operation layer entries are PNA-only");
   if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
   if (l < 0 || l >= c->L) return fail(HGNN_EINVAL, "layer out of range");
   if (!wl || !h_in || !h_out || !dh_out || !dwl) return fail(HGNN_EINVAL, "NULL buffer");
@@ -1148,6 +1589,7 @@ int hgnn_op_fetch(hgnn_ctx *c, int32_t which, int32_t layer, void *dst, size_t c
   case 6: src = w.csr.node_graph; bytes = (size_t)N * 4; break;
   case 7:
   case 8: {
+    if (c->kind != HGNN_GC_PNA) return fail(HGNN_EINVAL, "fetch ids 7 and 8 are PNA-only");
     if (layer < 0 || layer >= c->L) return fail(HGNN_EINVAL, "layer out of range");
     int slot = layer;
     if (c->recompute) {

@@ -34,6 +34,12 @@ struct Work {
   // node heads: outputs [N, Tn], hidden [Tn][N][H], its adjoint, errors
   // [N, Tn], and their share of dL/dh [N, H]
   float *zn = nullptr, *Qn = nullptr, *dQn = nullptr, *en = nullptr, *dhn = nullptr;
+  // GraphSAGE / CGCNN: per layer the neighbour means M [N, Fp] (SAGE) or the
+  // gate halves PQ [N, 4H] (CGCNN); the CGCNN embedding h0 [N, H]; SAGE's
+  // input-gradient product G [N, 2H]; CGCNN's D [N, (4 + 2Fe) H] and per-edge
+  // gate gradients dm [E, 2H]
+  std::vector<float *> gcA;
+  float *h0 = nullptr, *gcG = nullptr, *gcD = nullptr, *gcdm = nullptr;
 };
 
 // Batch-local execution state: device size header, CSR, activations and
@@ -80,6 +86,7 @@ struct SiteTimer {
 struct hgnn_ctx {
   hgnn_config cfg{};
   int dev = 0;
+  int kind = HGNN_GC_PNA; // GC layer kind
   int L = 0, H = 0, F0 = 0, F0p = 0, Fe = 0, maxd = 0, prec = 0, recompute = 0;
   int64_t P = 0, off_head = 0;
   std::vector<hgnn::LayerDesc> ld;
@@ -98,7 +105,17 @@ struct hgnn_ctx {
   float *table = nullptr;
   std::vector<void *> Wds, Wpp, WpTA, WhdsT; // GEMM-layout weight copies per layer
   std::vector<void *> Wds_lo, Wpp_lo, WpTA_lo, WhdsT_lo; // BF16 low halves
-  std::vector<void *> WeT; // per layer [Fe, H] edge-feature weights (FP32), or null
+  std::vector<void *> WeT; // per layer [Fe, H] (CGCNN [Fe, 2H]) edge-feature weights (FP32)
+  // GraphSAGE / CGCNN GEMM-layout copies per layer (forward B operand and
+  // input-gradient B operand; BF16 low halves), the CGCNN embedding, and the
+  // one-launch staging table that refreshes them
+  std::vector<void *> Wg1, Wg1_lo, Wg2, Wg2_lo;
+  void *Wemb = nullptr, *Wemb_lo = nullptr;
+  int64_t off_emb = 0;
+  int split_emb = 1;
+  hgnn::GcStageJob *gc_jobs = nullptr;
+  int gc_njobs = 0;
+  long long gc_max_elems = 0;
   bool staged_from_params = false;
   float *part = nullptr;
   hgnn::Exec ex; // the training path's batch state

@@ -428,6 +428,7 @@ int hgnn_serve_start(hgnn_ctx *c, const hgnn_serve_config *cfg) {
   if (c->server) return set_error(HGNN_EINVAL, "serving already started");
   if (c->Tg != 1 || c->Tn != 0)
     return set_error(HGNN_EINVAL, "serving takes a model with one graph head and no node head");
+  if (c->kind != HGNN_GC_PNA) return set_error(HGNN_EINVAL, "serving takes PNA models only");
   if (cfg->max_batch_nodes < 16 || cfg->max_batch_graphs < 1 || cfg->max_batch_edges < 0 ||
       cfg->num_lanes < 1 || cfg->num_lanes > 64 || cfg->queue_capacity < 1 ||
       cfg->hbm_budget_bytes <= 0)

@@ -81,6 +81,8 @@ _SIGS = {
     "hgnn_create_multitask": ([ctypes.POINTER(Config), ctypes.POINTER(Heads),
                                ctypes.POINTER(_P)], _I),
     "hgnn_forward_multitask": ([_P, ctypes.POINTER(CBatch), _P, _P, _P, _P, _I, _P], _I),
+    "hgnn_create_gc": ([ctypes.POINTER(Config), _I, ctypes.POINTER(Heads),
+                        ctypes.POINTER(_P)], _I),
     "hgnn_destroy": ([_P], None),
     "hgnn_num_params": ([_P, ctypes.POINTER(ctypes.c_int64)], _I),
     "hgnn_set_params": ([_P, _P, _P], _I),
@@ -245,20 +247,36 @@ def host_cbatch(b):
 # the context
 # ---------------------------------------------------------------------------
 
+KINDS = {"pna": 0, "sage": 1, "cgcnn": 2}
+
+
 class Model:
     """Owns an hgnn context: weights, gradients, AdamW state, workspaces."""
 
     def __init__(self, num_layers: int, hidden: int, node_feat: int = 9, edge_feat: int = 1,
                  max_degree: int = 4, precision: int = PREC_FP32, recompute: int = 0,
                  delta: float = 1.0, std_eps: float = 1e-5, graph_heads: int = 1,
-                 node_heads: int = 0, graph_weights=None, node_weights=None):
+                 node_heads: int = 0, graph_weights=None, node_weights=None,
+                 kind: str = "pna"):
         """graph_heads / node_heads > 1 / > 0 build a multitask model (several
-        graph-level heads, node-level heads, weighted loss; see the header)."""
+        graph-level heads, node-level heads, weighted loss); kind "sage" or
+        "cgcnn" selects the GraphSAGE or CGCNN layer kind (see the header)."""
+        if kind not in KINDS:
+            raise ValueError(f"kind must be one of {sorted(KINDS)}")
+        self.kind = kind
         self.cfg = Config(num_layers, hidden, node_feat, edge_feat, max_degree, precision,
                           recompute, 0, delta, std_eps)
         h = ctypes.c_void_p()
         self.Tg, self.Tn = graph_heads, node_heads
-        if graph_heads == 1 and node_heads == 0 and graph_weights is None:
+        if kind != "pna":
+            gw = None if graph_weights is None else np.asarray(graph_weights, np.float32)
+            nw = None if node_weights is None else np.asarray(node_weights, np.float32)
+            hd = Heads(graph_heads, node_heads, (ctypes.c_int32 * 2)(0, 0),
+                       None if gw is None else gw.ctypes.data,
+                       None if nw is None else nw.ctypes.data)
+            _check(lib().hgnn_create_gc(ctypes.byref(self.cfg), KINDS[kind], ctypes.byref(hd),
+                                        ctypes.byref(h)))
+        elif graph_heads == 1 and node_heads == 0 and graph_weights is None:
             _check(lib().hgnn_create(ctypes.byref(self.cfg), ctypes.byref(h)))
         else:
             gw = None if graph_weights is None else np.asarray(graph_weights, np.float32)
@@ -275,7 +293,7 @@ class Model:
         self.L, self.H, self.F0, self.Fe = num_layers, hidden, node_feat, edge_feat
         self._batch_keep = None
 
-    # layout of the packed vector (mirrors the header's packing order)
+    # layout of the packed vector of a PNA model (mirrors the header's packing order)
     def layer_slices(self) -> List[slice]:
         out, off = [], 0
         H, Fe = self.H, self.Fe

@@ -1,0 +1,224 @@
+"""GraphSAGE and CGCNN layer kinds on the GPU against the FP64 oracle
+(oracle/gclayers.py): FP32 within 1e-5 relative on predictions, loss and
+every gradient tensor (ReLU decisions of the GPU replayed inside the tie
+window), BF16 within 2e-2 on the outputs, and the error paths."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import gclayers as gcl
+from paper_2207_11333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TAU_FP32 = 1e-4
+TAU_BF16 = 3e-2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, r):
+    a, r = np.asarray(a, np.float64), np.asarray(r, np.float64)
+    n = np.linalg.norm(r)
+    return float(np.linalg.norm(a - r) / (n if n > 0 else 1.0))
+
+
+def _batch(seed, B, n_lo, n_hi, Fe, Tg=1):
+    b = synth.make_batch(seed, B, n_lo, n_hi, Fe)
+    if Tg > 1:
+        y = np.random.default_rng(seed).normal(5.0, 1.5, size=(B, Tg)).astype(np.float32)
+        b = synth.Batch(b.graph_ptr, b.x, b.edge_index, b.edge_attr, y)
+    return b
+
+
+def _run(kind, b, params, L, H, Fe, prec=0, Tg=1, Tn=0, yn=None, gw=None, nw=None):
+    from paper_2207_11333_amd import hgnn
+    m = hgnn.Model(L, H, 9, Fe, 4, prec, 0, 1.0, graph_heads=Tg, node_heads=Tn,
+                   graph_weights=gw, node_weights=nw, kind=kind)
+    assert m.num_params == params.shape[0]
+    m.set_params(params)
+    db = hgnn.DeviceBatch.from_host(b)
+    pred = torch.empty((b.num_graphs, Tg) if Tg > 1 else b.num_graphs, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    if Tn:
+        pn = torch.empty(b.num_nodes, Tn, device="cuda")
+        m.forward(db, pred, loss, validate=True, y_node=torch.tensor(yn, device="cuda"),
+                  pred_node=pn)
+    else:
+        pn = None
+        m.forward(db, pred, loss, validate=True)
+    m.backward()
+    out = {"pred": pred.cpu().numpy(), "loss": loss.item(), "grads": m.grads().cpu().numpy(),
+           "pn": None if pn is None else pn.cpu().numpy()}
+    N = b.num_nodes
+    out["relu"] = [m.fetch(11, l, (N, H), torch.float32).cpu().numpy() > 0 for l in range(L)]
+    out["grelu"] = [m.fetch(9, t, (b.num_graphs, H), torch.float32).cpu().numpy() > 0
+                    for t in range(Tg)]
+    out["nrelu"] = [m.fetch(12, s, (N, H), torch.float32).cpu().numpy() > 0 for s in range(Tn)]
+    torch.cuda.synchronize()
+    return m, out
+
+
+def _tensor_report(kind, L, H, Fe, Tg, Tn, g_gpu, g_ref):
+    shapes = synth.gc_tensor_shapes(kind, L, H, 9, Fe, Tg, Tn)
+    off, rep = 0, {}
+    for name, shp in shapes:
+        n = int(np.prod(shp))
+        rep[name] = rel(g_gpu[off:off + n], g_ref[off:off + n])
+        off += n
+    assert off == g_gpu.shape[0]
+    return rep
+
+
+CASES = [
+    # kind, L, H, Fe, B, n_lo, n_hi, seed
+    ("sage", 3, 64, 1, 40, 5, 30, 300),
+    ("sage", 2, 32, 0, 24, 1, 12, 301),     # no edge features; single-atom graphs
+    ("sage", 2, 48, 2, 16, 3, 20, 302),
+    ("cgcnn", 3, 64, 1, 40, 5, 30, 310),
+    ("cgcnn", 2, 32, 0, 24, 1, 12, 311),
+    ("cgcnn", 2, 48, 4, 16, 3, 20, 312),
+]
+
+
+@pytest.mark.parametrize("kind,L,H,Fe,B,n_lo,n_hi,seed", CASES)
+def test_gc_fp32_parity(kind, L, H, Fe, B, n_lo, n_hi, seed):
+    b = _batch(seed, B, n_lo, n_hi, Fe)
+    params = synth.init_gc_params(kind, L, H, seed + 1, edge_feat=Fe)
+    say(f"case {kind} L={L} H={H} Fe={Fe} N={b.num_nodes} E={b.num_edges}")
+    m, out = _run(kind, b, params, L, H, Fe)
+    rec = gcl.forward(params, b, kind, L, H)
+    r_pred = rel(out["pred"], rec.y[:, 0])
+    r_loss = rel([out["loss"]], [rec.loss])
+    g_ref, stats = gcl.backward(rec, out["relu"], out["grelu"], None, tau=TAU_FP32)
+    rep = _tensor_report(kind, L, H, Fe, 1, 0, out["grads"], g_ref)
+    worst = max(rep, key=rep.get)
+    say(f"  pred rel {r_pred:.2e} loss rel {r_loss:.2e}; worst grad {worst} {rep[worst]:.2e}; "
+        f"adopted {stats}")
+    assert r_pred <= 1e-5 and r_loss <= 1e-5
+    assert rep[worst] <= 1e-5
+    m.close()
+
+
+@pytest.mark.parametrize("kind", ["sage", "cgcnn"])
+def test_gc_multitask_parity(kind):
+    L, H, Fe, Tg, Tn = 2, 32, 1, 2, 2
+    b = _batch(320, 20, 4, 18, Fe, Tg)
+    params = synth.init_gc_params(kind, L, H, 321, edge_feat=Fe, graph_heads=Tg,
+                                  node_heads=Tn)
+    yn = np.random.default_rng(5).normal(size=(b.num_nodes, Tn)).astype(np.float32)
+    gw, nw = [1.0, 0.5], [0.25, 2.0]
+    m, out = _run(kind, b, params, L, H, Fe, 0, Tg, Tn, yn, gw, nw)
+    rec = gcl.forward(params, b, kind, L, H, Tg, Tn, gw, nw, yn)
+    g_ref, stats = gcl.backward(rec, out["relu"], out["grelu"], out["nrelu"], tau=TAU_FP32)
+    r = {"pred": rel(out["pred"], rec.y), "node": rel(out["pn"], rec.z),
+         "loss": rel([out["loss"]], [rec.loss]),
+         "grad": max(_tensor_report(kind, L, H, Fe, Tg, Tn, out["grads"], g_ref).values())}
+    say(f"multitask {kind}: {r}; adopted {stats}")
+    assert max(r.values()) <= 1e-5
+    m.close()
+
+
+@pytest.mark.parametrize("kind", ["sage", "cgcnn"])
+def test_gc_bf16_outputs_within_2e2(kind):
+    L, H, Fe = 6, 128, 1
+    b = _batch(330, 64, 10, 60, Fe)
+    params = synth.init_gc_params(kind, L, H, 331)
+    m, out = _run(kind, b, params, L, H, Fe, prec=1)
+    rec = gcl.forward(params, b, kind, L, H)
+    r_pred = rel(out["pred"], rec.y[:, 0])
+    r_loss = rel([out["loss"]], [rec.loss])
+    g_ref, stats = gcl.backward(rec, out["relu"], out["grelu"], None, tau=TAU_BF16)
+    rep = _tensor_report(kind, L, H, Fe, 1, 0, out["grads"], g_ref)
+    say(f"bf16 {kind}: pred rel {r_pred:.2e} loss rel {r_loss:.2e}; grad median "
+        f"{np.median(list(rep.values())):.2e} worst {max(rep.values()):.2e}; adopted {stats}")
+    assert r_pred <= 2e-2 and r_loss <= 2e-2
+    m.close()
+
+
+@pytest.mark.parametrize("kind", ["sage", "cgcnn"])
+def test_gc_full_size_sampled_graphs(kind):
+    """The benchmark's configuration (6 layers, H = 128, 128 molecules of
+    10-60 atoms, FP32): graphs are independent, so the oracle checks a
+    sample of them one at a time."""
+    from paper_2207_11333_amd import hgnn
+    w = synth.WORKLOADS["c1_train_fp32"]
+    b = w.batch()
+    params = synth.init_gc_params(kind, w.num_layers, w.hidden, 2101)
+    m, out = _run(kind, b, params, w.num_layers, w.hidden, w.edge_feat)
+    assert np.isfinite(out["grads"]).all()
+    sample = [0, 63, 127]
+    sub = synth.select_graphs(b, sample)
+    rec = gcl.forward(params, sub, kind, w.num_layers, w.hidden)
+    r = rel(out["pred"][sample], rec.y[:, 0])
+    say(f"{kind} full size: sampled pred rel {r:.2e}")
+    assert r <= 1e-5
+    m.close()
+
+
+@pytest.mark.parametrize("kind", ["sage", "cgcnn"])
+def test_gc_bitwise_reproducible_and_trains(kind):
+    from paper_2207_11333_amd import hgnn
+    L, H, Fe = 2, 32, 1
+    b = _batch(340, 24, 4, 20, Fe)
+    params = synth.init_gc_params(kind, L, H, 341)
+    m = hgnn.Model(L, H, 9, Fe, 4, 0, 0, 1.0, kind=kind)
+    m.set_params(params)
+    db = hgnn.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    runs = []
+    for _ in range(2):
+        m.set_params(params)
+        m.forward(db, pred, loss)
+        m.backward()
+        runs.append((pred.clone(), m.grads()))
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    losses = []
+    for _ in range(30):
+        m.forward(db, pred, loss)
+        m.backward()
+        m.adam_step(lr=3e-3)
+        losses.append(loss.item())
+    torch.cuda.synchronize()
+    say(f"{kind} training loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert losses[-1] < 0.5 * losses[0]
+    # a checkpoint of one kind does not restore into another
+    other = hgnn.Model(L, H, 9, Fe, 4, 0, 0, 1.0, kind="cgcnn" if kind == "sage" else "sage")
+    with pytest.raises(hgnn.HgnnError):
+        other.set_state(m.get_state())
+    other.close()
+    m.close()
+
+
+def test_gc_error_paths():
+    from paper_2207_11333_amd import hgnn
+    from paper_2207_11333_amd.hgnn import _check, _ptr, _stream, lib
+    with pytest.raises(hgnn.HgnnError):                # recompute is PNA-only
+        hgnn.Model(2, 32, recompute=1, kind="sage")
+    cfg = hgnn.Config(2, 32, 9, 1, 4, 0, 0, 0, 1.0, 1e-5)
+    h = ctypes.c_void_p()
+    with pytest.raises(hgnn.HgnnError):                # unknown kind
+        _check(lib().hgnn_create_gc(ctypes.byref(cfg), 7, None, ctypes.byref(h)))
+    m = hgnn.Model(2, 32, kind="cgcnn")
+    b = synth.make_batch(350, 4, 3, 8, 1)
+    db = hgnn.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+    m.forward(db, pred)
+    with pytest.raises(hgnn.HgnnError):                # aggregates are PNA-only
+        m.fetch(7, 0, (b.num_nodes, 4 * 32), torch.float32)
+    with pytest.raises(hgnn.HgnnError):                # serving takes PNA models
+        m.serve_start(hbm_budget_bytes=1 << 30)
+    buf = torch.empty(1, device="cuda")
+    with pytest.raises(hgnn.HgnnError):                # per-operation layers are PNA-only
+        _check(lib().hgnn_op_layer_forward(m.handle, 0, _ptr(buf), _ptr(buf), _ptr(buf),
+                                           _stream()))
+    torch.cuda.synchronize()
+    m.close()
