@@ -182,6 +182,49 @@ def multitask_rate(workload, steps, warmup, Tg=2, Tn=2):
             "ms_per_step": 1e3 * dt / steps}
 
 
+def gc_rate(kind, workload, steps, warmup, precision=0):
+    """Training step (CSR build, forward, backward, AdamW) of a GraphSAGE or
+    CGCNN model of the workload's depth and width on the same batch."""
+    import torch
+    from paper_2207_11333_amd import hgnn, synth
+    b = workload.batch()
+    m = hgnn.Model(workload.num_layers, workload.hidden, 9, workload.edge_feat, 4, precision,
+                   0, 1.0, kind=kind)
+    m.set_params(synth.init_gc_params(kind, workload.num_layers, workload.hidden, 2100))
+    db = hgnn.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+    loss = torch.empty(1, device="cuda")
+
+    def step():
+        m.forward(db, pred, loss)
+        m.backward()
+        m.adam_step(lr=1e-3)
+
+    m.forward(db, pred, loss, validate=True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    m.close()
+    return {"graphs_per_s": b.num_graphs * steps / dt, "ms_per_step": 1e3 * dt / steps}
+
+
+def gc_measure(workload, steps, warmup):
+    out = {"workload": (f"{workload.num_layers} layers, hidden {workload.hidden}, "
+                        f"{workload.num_graphs} molecules of {workload.n_lo}-{workload.n_hi} "
+                        "atoms (the FP32 headline batch)")}
+    for kind in ("sage", "cgcnn"):
+        r32 = gc_rate(kind, workload, steps, warmup, 0)
+        r16 = gc_rate(kind, workload, steps, warmup, 1)
+        out[kind] = {"fp32_graphs_per_s": r32["graphs_per_s"], "fp32_ms_per_step": r32["ms_per_step"],
+                     "bf16_graphs_per_s": r16["graphs_per_s"], "bf16_ms_per_step": r16["ms_per_step"]}
+    return out
+
+
 def serve_bench(qps=500.0, warm_s=2.0, measure_s=10.0, pool=48):
     """Open-loop Poisson arrivals at a fixed rate; latency is measured from the
     scheduled arrival time to the poll that observes completion."""
@@ -475,6 +518,9 @@ def main():
     ap.add_argument("--only-large", action="store_true",
                     help="run only the large-configuration measurement (for profiling) "
                          "and print its JSON")
+    ap.add_argument("--only-gc", choices=["sage", "cgcnn"], default=None,
+                    help="run only the training step of that layer kind on the headline "
+                         "batch (for profiling) and print its JSON")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -495,6 +541,11 @@ def main():
         hgnn.calib_copy(src, dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_gc:
+        _log(f"bench: {args.only_gc} only")
+        print(json.dumps({args.only_gc: gc_rate(args.only_gc, w, args.steps, args.warmup,
+                                                w.precision)}), flush=True)
+        return
     if args.only_large:
         _log("bench: large configuration only")
         print(json.dumps({"c3": c3_measure()}), flush=True)
@@ -550,6 +601,12 @@ def main():
         line["multitask"] = mt
         _log(f"bench: multitask ({mt['graph_heads']} graph + {mt['node_heads']} node heads) "
              f"{mt['graphs_per_s']:.1f} graphs/s")
+        _log("bench: GraphSAGE and CGCNN layer kinds")
+        line["gc_layers"] = gc_measure(w, args.steps, args.warmup)
+        _log("bench: " + ", ".join(
+            f"{k} {line['gc_layers'][k]['fp32_graphs_per_s']:.0f} (bf16 "
+            f"{line['gc_layers'][k]['bf16_graphs_per_s']:.0f})" for k in ("sage", "cgcnn"))
+            + " graphs/s")
         _log("bench: large configuration")
         line["c3"] = c3_measure()
         _log(f"bench: c3 {line['c3']['graphs_per_s']:.1f} graphs/s; aggregation "
