@@ -151,10 +151,18 @@ int hgnn_create_gc(const hgnn_config *cfg, int32_t kind, const hgnn_heads *heads
 void hgnn_destroy(hgnn_ctx *ctx); /* synchronises; NULL is ignored */
 int hgnn_num_params(const hgnn_ctx *ctx, int64_t *out);
 /* Copy the packed parameters in (device [P]) and refresh the internal GEMM
- * copies (padded, transposed, BF16 when precision is BF16). */
+ * copies (padded, transposed, BF16 when precision is BF16).  Given the
+ * context's own parameter vector (from hgnn_param_views) it copies nothing
+ * and only refreshes the copies. */
 int hgnn_set_params(hgnn_ctx *ctx, const float *params_dev, void *stream);
 int hgnn_get_params(hgnn_ctx *ctx, float *params_dev, void *stream);
 int hgnn_get_grads(hgnn_ctx *ctx, float *grads_dev, void *stream);
+/* The context's own packed parameter and gradient vectors (device [P] each,
+ * owned by the context, valid until hgnn_destroy; either output may be
+ * NULL).  Gradients are rewritten by every hgnn_backward.  Parameters written
+ * through the pointer reach the layers only after hgnn_set_params(ctx,
+ * *params, stream); until then the forward pass uses the previous values. */
+int hgnn_param_views(hgnn_ctx *ctx, float **params_dev, float **grads_dev);
 /* Synchronise the stream and report the device error word (EINVAL with a
  * message naming the first failed check) or a sticky ESTATE. */
 int hgnn_check(hgnn_ctx *ctx, void *stream);

@@ -1292,9 +1292,19 @@ int hgnn_set_params(hgnn_ctx *c, const float *src, void *stream) {
   HGNN_GUARD(c);
   if (!src) return fail(HGNN_EINVAL, "params_dev is NULL");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(c->params, src, c->P * sizeof(float), hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return hip_fail(c, e, "copy params");
+  if (src != c->params) {
+    hipError_t e =
+        hipMemcpyAsync(c->params, src, c->P * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "copy params");
+  }
   return stage_all(c, s);
+}
+
+int hgnn_param_views(hgnn_ctx *c, float **params, float **grads) {
+  if (!c) return fail(HGNN_EINVAL, "context is NULL");
+  if (params) *params = c->params;
+  if (grads) *grads = c->grads;
+  return HGNN_OK;
 }
 
 int hgnn_get_params(hgnn_ctx *c, float *dst, void *stream) {

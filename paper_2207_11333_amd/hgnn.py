@@ -83,6 +83,7 @@ _SIGS = {
     "hgnn_forward_multitask": ([_P, ctypes.POINTER(CBatch), _P, _P, _P, _P, _I, _P], _I),
     "hgnn_create_gc": ([ctypes.POINTER(Config), _I, ctypes.POINTER(Heads),
                         ctypes.POINTER(_P)], _I),
+    "hgnn_param_views": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I),
     "hgnn_destroy": ([_P], None),
     "hgnn_num_params": ([_P, ctypes.POINTER(ctypes.c_int64)], _I),
     "hgnn_set_params": ([_P, _P, _P], _I),
@@ -250,6 +251,19 @@ def host_cbatch(b):
 KINDS = {"pna": 0, "sage": 1, "cgcnn": 2}
 
 
+class _DeviceView:
+    """A float32 [n] device vector owned by a context, exposed to torch through
+    the CUDA array interface (torch.as_tensor(view, device="cuda") aliases it)."""
+
+    def __init__(self, ptr: int, n: int, owner):
+        self._owner = owner
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<f4", "data": (ptr, False),
+                                         "version": 2, "strides": None}
+
+    def tensor(self) -> torch.Tensor:
+        return torch.as_tensor(self, device="cuda")
+
+
 class Model:
     """Owns an hgnn context: weights, gradients, AdamW state, workspaces."""
 
@@ -318,6 +332,8 @@ class Model:
             pass
 
     def set_params(self, params):
+        if isinstance(params, _DeviceView):
+            params = params.tensor()
         p = torch.as_tensor(params, dtype=torch.float32).cuda().contiguous()
         assert p.numel() == self.num_params
         _check(lib().hgnn_set_params(self.handle, _ptr(p), _stream()))
@@ -332,6 +348,13 @@ class Model:
         out = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
         _check(lib().hgnn_get_grads(self.handle, _ptr(out), _stream()))
         return out
+
+    def param_views(self):
+        """(params, grads): torch views of the context's own [P] vectors (no
+        copy).  Writes to params reach the layers after set_params(params)."""
+        p, g = _P(), _P()
+        _check(lib().hgnn_param_views(self.handle, ctypes.byref(p), ctypes.byref(g)))
+        return _DeviceView(p.value, self.num_params, self), _DeviceView(g.value, self.num_params, self)
 
     def check(self):
         _check(lib().hgnn_check(self.handle, _stream()))

@@ -508,3 +508,30 @@ def test_config_sweep_fp32_parity(L, H, Fe, maxd, recompute, p_edge):
     for k, v in rep.items():
         assert v <= 1e-5, (k, v)
     m.close()
+
+
+def test_param_views_alias_the_context_vectors():
+    """hgnn_param_views: the gradient view holds what hgnn_get_grads copies;
+    a write through the parameter view reaches the layers after
+    set_params(view), which then copies nothing."""
+    from paper_2207_11333_amd import hgnn
+    w = synth.WORKLOADS["c0_small_fp32"]
+    b, params = w.batch(), w.params()
+    m = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+    out = run_train_step(m, b, params)
+    pv, gv = m.param_views()
+    p_t, g_t = pv.tensor(), gv.tensor()
+    assert torch.equal(g_t, out["grads"]) and torch.equal(p_t, m.params())
+    p_t.mul_(0.5)                                   # in place, through the view
+    m.set_params(pv)
+    db = hgnn.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+    m.forward(db, pred)
+    m2 = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+    m2.set_params(params * 0.5)
+    pred2 = torch.empty(b.num_graphs, device="cuda")
+    m2.forward(db, pred2)
+    torch.cuda.synchronize()
+    assert torch.equal(pred, pred2)
+    m.close()
+    m2.close()
