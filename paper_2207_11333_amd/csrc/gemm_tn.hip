@@ -19,8 +19,16 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
   constexpr int NA = BM * BK / 4 / 256;
   constexpr int NB = BN * BK / 4 / 256;
-  __shared__ __attribute__((aligned(16))) T As[BM * LDA];
-  __shared__ __attribute__((aligned(16))) T Bs[BN * LDA];
+  // FP32 keeps the tiles in LDS as they lie in memory, k-major ([k][m] and
+  // [k][n], rows padded by 4 floats), written with 16-byte stores; the MFMA
+  // operands are read one k-slot at a time.  With a 68-float row pitch the
+  // lane groups of a read fall in distinct banks, whereas transposing on the
+  // way in (the BF16 form, which needs 8 consecutive k per lane) puts a
+  // wave's 64 scalar stores into 8 banks.
+  constexpr bool KMAJ = PREC == 0;
+  constexpr int LDKA = BM + 4, LDKB = BN + 4;
+  __shared__ __attribute__((aligned(16))) T As[KMAJ ? BK * LDKA : BM * LDA];
+  __shared__ __attribute__((aligned(16))) T Bs[KMAJ ? BK * LDKB : BN * LDA];
 
   const int rows = dims->N;
   const int mtiles = (g.M + BM - 1) / BM;
@@ -106,16 +114,47 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     for (int j = 0; j < NA; ++j) {
       const int v = tid + j * 256;
       const int il = v / (BM / 4), mc = (v % (BM / 4)) * 4;
+      if constexpr (KMAJ) {
+        store4(As + il * LDKA + mc, ra[S][j]);
+      } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) store1(As + (mc + e) * LDA + il, ra[S][j][e]);
+        for (int e = 0; e < 4; ++e) store1(As + (mc + e) * LDA + il, ra[S][j][e]);
+      }
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int v = tid + j * 256;
       const int il = v / (BN / 4), nc = (v % (BN / 4)) * 4;
       const f4 val = rb[S][j] * rsc[S][j];
+      if constexpr (KMAJ) {
+        store4(Bs + il * LDKB + nc, val);
+      } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) store1(Bs + (nc + e) * LDA + il, val[e]);
+        for (int e = 0; e < 4; ++e) store1(Bs + (nc + e) * LDA + il, val[e]);
+      }
+    }
+  };
+  // k-major multiply: lane group g supplies k = kc + 4 g + s in instruction
+  // s, the assignment mma_tile uses, so the sum runs in the same order.
+  auto mma_kmajor = [&]() {
+    const int lane = tid & 63;
+    const int r = lane & 15, gq = lane >> 4;
+#pragma unroll
+    for (int kc = 0; kc < BK; kc += 16) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = kc + 4 * gq + s4;
+        float a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = As[k * LDKA + wm0 + i * 16 + r];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = Bs[k * LDKB + wn0 + j * 16 + r];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
     }
   };
   auto step = [&](auto st, int t) {
@@ -123,7 +162,8 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     stash(st);
     __syncthreads();
     load(st, min(t + 2, KT - 1));
-    mma_tile<PREC, TM, TN, LDA, BK>(As, Bs, wm0, wn0, acc);
+    if constexpr (KMAJ) mma_kmajor();
+    else mma_tile<PREC, TM, TN, LDA, BK>(As, Bs, wm0, wn0, acc);
   };
 
   if (KT > 0) load(IC<0>{}, 0);
