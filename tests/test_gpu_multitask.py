@@ -139,3 +139,48 @@ def test_multitask_argument_errors():
     with pytest.raises(hgnn.HgnnError):          # serving takes single-head models
         m.serve_start(hbm_budget_bytes=1 << 30)
     m.close()
+
+
+@pytest.mark.parametrize("prec,recompute", [(0, 1), (1, 0), (1, 1)])
+def test_multitask_with_recompute_and_bf16(prec, recompute):
+    """Multitask heads on top of recomputed layers (FP32: 1e-5 on everything)
+    and on BF16 layers (2e-2 on the outputs and the loss)."""
+    from paper_2207_11333_amd import hgnn
+    Tg, Tn, L, H = 2, 1, 3, 64
+    b, params, yn = _case(260 + 2 * prec + recompute, Tg, Tn, L, H, B=32)
+    gw, nw = [1.0, 0.5], [2.0]
+    delta = 1.1
+    m = hgnn.Model(L, H, 9, 1, 4, prec, recompute, delta, graph_heads=Tg, node_heads=Tn,
+                   graph_weights=gw, node_weights=nw)
+    m.set_params(params)
+    db = hgnn.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, Tg, device="cuda")
+    pn = torch.empty(b.num_nodes, Tn, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    m.forward(db, pred, loss, validate=True, y_node=torch.tensor(yn, device="cuda"), pred_node=pn)
+    m.backward()
+    grads = m.grads().cpu().numpy()
+    torch.cuda.synchronize()
+    rec = mt.forward(params, b, L, H, delta, Tg, Tn, gw, nw, yn)
+    r = {"pred": rel(pred.cpu().numpy(), rec.y), "node": rel(pn.cpu().numpy(), rec.z),
+         "loss": rel([loss.item()], [rec.loss])}
+    say(f"multitask prec={prec} recompute={recompute}: {r}")
+    if prec == 1:
+        assert max(r.values()) <= 2e-2
+        assert np.isfinite(grads).all()
+    else:
+        assert max(r.values()) <= 1e-5
+        N = b.num_nodes
+        # with recomputation only the last recomputed layer's decisions are
+        # held; replay the ReLU decisions of every layer (kept outputs)
+        dec = oracle.Decisions([None] * L, [None] * L,
+                               [m.fetch(11, l, (N, H), torch.float32).cpu().numpy() > 0
+                                for l in range(L)])
+        grelu = [m.fetch(9, t, (b.num_graphs, H), torch.float32).cpu().numpy() > 0
+                 for t in range(Tg)]
+        nrelu = [m.fetch(12, s, (N, H), torch.float32).cpu().numpy() > 0 for s in range(Tn)]
+        g_ref, _, stats = mt.backward(rec, dec, grelu, nrelu, tau=1e-4)
+        worst = rel(grads, g_ref)
+        say(f"  gradient rel {worst:.2e}; adopted {stats}")
+        assert worst <= 1e-5
+    m.close()
