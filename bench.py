@@ -524,9 +524,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the data-parallel "
-                          "gradient all-reduce across GPUs is not part of it; run with "
-                          "--gpus 1"}))
+        print(json.dumps({"error": "hgnn runs on one GPU: the data-parallel gradient "
+                          "all-reduce across GPUs is not implemented; run with --gpus 1"}))
         sys.exit(2)
 
     import torch
