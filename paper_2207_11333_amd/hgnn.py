@@ -533,3 +533,41 @@ class PNANet(torch.nn.Module):
         for l, w in enumerate(self.layers):
             h = PNALayerFunction.apply(h, w, self.model, l)
         return PoolHeadFunction.apply(h, self.head, self.model)
+
+
+class ModelFunction(torch.autograd.Function):
+    """pred = the whole model (any layer kind, one graph head) as a function of
+    its packed parameter vector: the forward loads the parameters and runs
+    hgnn_forward, the backward runs hgnn_backward with dpred and returns the
+    packed gradient.  Lets torch optimisers drive GraphSAGE / CGCNN / PNA
+    models through one parameter tensor."""
+
+    @staticmethod
+    def forward(ctx, params, model: Model, batch: DeviceBatch):
+        if model.Tg != 1 or model.Tn != 0:
+            raise ValueError("ModelFunction takes a model with one graph head and no node head")
+        params = params.detach().contiguous()
+        model.set_params(params)
+        pred = torch.empty(batch.num_graphs, dtype=torch.float32, device=params.device)
+        model.forward(batch, pred)
+        ctx.model = model
+        return pred
+
+    @staticmethod
+    def backward(ctx, dpred):
+        model = ctx.model
+        model.backward(dpred.contiguous())
+        return model.grads(), None, None
+
+
+class GCNet(torch.nn.Module):
+    """One packed parameter tensor and the whole model of any layer kind
+    (forward and backward through the library's fused entry points)."""
+
+    def __init__(self, model: Model, params):
+        super().__init__()
+        self.model = model
+        self.params = torch.nn.Parameter(torch.as_tensor(params, dtype=torch.float32).cuda().clone())
+
+    def forward(self, batch: DeviceBatch):
+        return ModelFunction.apply(self.params, self.model, batch)

@@ -277,3 +277,44 @@ def test_gc_training_step_graph_replay_matches_eager(kind, Tn):
         assert torch.equal(bufs["a"][0], bufs["b"][0]) and torch.equal(bufs["a"][1], bufs["b"][1])
     ma.close()
     mb.close()
+
+
+@pytest.mark.parametrize("kind", ["sage", "cgcnn", "pna"])
+def test_gcnet_autograd_matches_fused_entries_and_trains(kind):
+    """GCNet (one packed parameter tensor behind a torch.autograd.Function):
+    the gradient of sum(w * pred) equals hgnn_backward with dpred = w, and a
+    torch optimiser on it lowers the loss."""
+    from paper_2207_11333_amd import hgnn
+    L, H, Fe = 2, 32, 1
+    b = _batch(370, 16, 4, 18, Fe)
+    if kind == "pna":
+        params = synth.init_params(synth.ModelShape(L, H, 9, Fe), 371)
+    else:
+        params = synth.init_gc_params(kind, L, H, 371)
+    db = hgnn.DeviceBatch.from_host(b)
+    m = hgnn.Model(L, H, 9, Fe, 4, 0, 0, 1.1, kind=kind)
+    net = hgnn.GCNet(m, params)
+    wv = torch.linspace(-1.0, 1.0, b.num_graphs, device="cuda")
+    pred = net(db)
+    (pred * wv).sum().backward()
+    ref = hgnn.Model(L, H, 9, Fe, 4, 0, 0, 1.1, kind=kind)
+    ref.set_params(params)
+    p2 = torch.empty(b.num_graphs, device="cuda")
+    ref.forward(db, p2)
+    ref.backward(wv)
+    torch.cuda.synchronize()
+    assert torch.equal(pred.detach(), p2)
+    assert torch.equal(net.params.grad, ref.grads())
+    y = torch.as_tensor(b.y, device="cuda")
+    opt = torch.optim.Adam(net.parameters(), lr=3e-3)
+    losses = []
+    for _ in range(25):
+        opt.zero_grad()
+        loss = ((net(db) - y) ** 2).mean()
+        loss.backward()
+        opt.step()
+        losses.append(loss.item())
+    say(f"GCNet {kind}: loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert losses[-1] < 0.5 * losses[0]
+    ref.close()
+    m.close()
