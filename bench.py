@@ -182,9 +182,25 @@ def multitask_rate(workload, steps, warmup, Tg=2, Tn=2):
             "ms_per_step": 1e3 * dt / steps}
 
 
-def gc_rate(kind, workload, steps, warmup, precision=0):
+def sage_gemm_flops(workload, N):
+    """FLOPs of one GraphSAGE layer GEMM ([h || M] W^T), averaged over the
+    layers (layer 0 reads the padded 16-wide input)."""
+    H, L = workload.hidden, workload.num_layers
+    ks = [2 * 16] + [2 * H] * (L - 1)
+    return sum(2.0 * N * k * H for k in ks) / L
+
+
+def cgcnn_aggregate_bytes(N, E, H, Fe):
+    """Algorithmic bytes of one CGCNN gated aggregation: own gate halves
+    (N x 2H) and gathered source halves (E x 2H), the layer input and output
+    (N x H each), CSR arrays and edge attributes; FP32."""
+    return 4 * (2 * H * N + 2 * H * E + 2 * H * N + (N + 1) + E + E * Fe)
+
+
+def gc_rate(kind, workload, steps, warmup, precision=0, site=None):
     """Training step (CSR build, forward, backward, AdamW) of a GraphSAGE or
-    CGCNN model of the workload's depth and width on the same batch."""
+    CGCNN model of the workload's depth and width on the same batch; with a
+    timer site, a second pass times that site's launches."""
     import torch
     from paper_2207_11333_amd import hgnn, synth
     b = workload.batch()
@@ -209,19 +225,44 @@ def gc_rate(kind, workload, steps, warmup, precision=0):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    out = {"graphs_per_s": b.num_graphs * steps / dt, "ms_per_step": 1e3 * dt / steps,
+           "N": b.num_nodes, "E": b.num_edges}
+    if site:
+        m.timer_start(site, steps * workload.num_layers + 16)
+        torch.cuda.synchronize()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        out["site_ms_total"], out["site_launches"] = m.timer_read()
     m.close()
-    return {"graphs_per_s": b.num_graphs * steps / dt, "ms_per_step": 1e3 * dt / steps}
+    return out
 
 
 def gc_measure(workload, steps, warmup):
     out = {"workload": (f"{workload.num_layers} layers, hidden {workload.hidden}, "
                         f"{workload.num_graphs} molecules of {workload.n_lo}-{workload.n_hi} "
                         "atoms (the FP32 headline batch)")}
-    for kind in ("sage", "cgcnn"):
-        r32 = gc_rate(kind, workload, steps, warmup, 0)
+    for kind, site in (("sage", "update_gemm"), ("cgcnn", "aggregate")):
+        r32 = gc_rate(kind, workload, steps, warmup, 0, site)
         r16 = gc_rate(kind, workload, steps, warmup, 1)
         out[kind] = {"fp32_graphs_per_s": r32["graphs_per_s"], "fp32_ms_per_step": r32["ms_per_step"],
                      "bf16_graphs_per_s": r16["graphs_per_s"], "bf16_ms_per_step": r16["ms_per_step"]}
+        avg = r32["site_ms_total"] / 1e3 / max(1, r32["site_launches"])
+        if kind == "sage":
+            fl = sage_gemm_flops(workload, r32["N"])
+            ach = fl / avg / 1e12
+            out[kind]["roofline"] = {"kernel": "GraphSAGE layer GEMM, FP32", "bound": "mfma",
+                                     "achieved": ach, "peak": FP32_PEAK_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
+                                     "avg_us": avg * 1e6, "flops_per_launch": fl}
+        else:
+            nb = cgcnn_aggregate_bytes(r32["N"], r32["E"], workload.hidden, workload.edge_feat)
+            ach = nb / avg / 1e9
+            out[kind]["roofline"] = {"kernel": "CGCNN gated aggregation, FP32", "bound": "hbm",
+                                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": ach / HBM_PEAK_GBS, "avg_us": avg * 1e6,
+                                     "bytes_per_launch": nb,
+                                     "note": "cache-resident at this size"}
     return out
 
 
