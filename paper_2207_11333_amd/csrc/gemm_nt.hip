@@ -241,7 +241,7 @@ hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
 
 // Output tiles are 64 rows x 128 columns: one tile spans the whole hidden
 // width, so each weight tile is staged once per 64 rows.  When the tiles
-// alone cannot cover the 256 CUs, K is split (at least three K tiles per
+// alone cannot cover the 256 CUs, K is split (at least two K tiles per
 // split, at most 8 splits).  Measured: more splits lose to their partial
 // traffic at these sizes.
 constexpr int kNtBM = 64, kNtBN = 128;
@@ -257,7 +257,7 @@ int nt_splits(int capM, int Ncols, int Ktot, int precision) {
   const int tiles = cdiv(capM, kNtBM) * cdiv(Ncols, kNtBN);
   const int kt = nt_ktiles(Ktot, precision);
   int sp = 256 / (tiles > 0 ? tiles : 1);
-  if (sp > kt / 3) sp = kt / 3;
+  if (sp > kt / 2) sp = kt / 2;
   if (sp > 8) sp = 8;
   return sp < 1 ? 1 : sp;
 }
