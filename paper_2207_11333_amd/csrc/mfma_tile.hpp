@@ -4,15 +4,18 @@
 // MFMA GEMMs of the message, update and head-free linears (steps S1, S3 and
 // their adjoints S6, S8).
 //
-// Two forms, both tiled for 256-thread workgroups (4 wave64s in a 2x2 grid)
-// with operands staged through LDS in [row][k] order (k contiguous):
+// Two forms:
 //  * gemm_nt:  C = act(sum_seg diag(scale_seg) A_seg B_seg^T + bias).  The
 //    K dimension is a list of segments so that the update input
 //    [h || A || s+ A || s- A] and the adjoint input [du || s+ du || s- du]
 //    are read in place and scaled while being staged, never materialised.
+//    512-thread workgroups (8 wave64s in a 2x4 grid) on 64 x 128 tiles,
+//    operands staged through LDS in [row][k] order (k contiguous).
 //  * gemm_tn:  P[z] = X^T Yv over a fixed chunk z of the node rows (split-K),
 //    reduced afterwards in the fixed order z = 0, 1, ...: weight gradients
-//    are deterministic and need no atomics.
+//    are deterministic and need no atomics.  256-thread workgroups (4
+//    wave64s in a 2x2 grid) on 64 x 64 tiles; FP32 keeps the node-row tiles
+//    k-major in LDS, BF16 transposes them to [row][k] while staging.
 // Precision 0 runs v_mfma_f32_16x16x4_f32 on FP32 operands; precision 1
 // rounds operands to BF16 (RNE, v_cvt_pk_bf16_f32) while staging and runs
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Weights in BF16 mode come
