@@ -37,9 +37,10 @@
  *    hgnn_last_error() returns a thread-local message for the last failure.
  *    Size and pointer checks are done on the host and return HGNN_EINVAL
  *    synchronously.  Content checks (edge endpoint out of range, edge across
- *    graphs, in- or out-degree above max_degree, empty graph) are done on the
- *    device and set the context's error word: with HGNN_VALIDATE the call
- *    synchronises and returns HGNN_EINVAL; otherwise hgnn_check() reports it.
+ *    graphs, in- or out-degree above max_degree, empty graph, a NaN or
+ *    infinity in x or edge_attr) are done on the device and set the
+ *    context's error word: with HGNN_VALIDATE the call synchronises and
+ *    returns HGNN_EINVAL; otherwise hgnn_check() reports it.
  *    A failed HIP call puts the context in HGNN_ESTATE until hgnn_set_state.
  *  - Gradients overwrite (never accumulate) and refer to the last forward.
  *  - Train calls on one context are not thread-safe; serve calls are.
@@ -163,6 +164,11 @@ int hgnn_get_grads(hgnn_ctx *ctx, float *grads_dev, void *stream);
  * through the pointer reach the layers only after hgnn_set_params(ctx,
  * *params, stream); until then the forward pass uses the previous values. */
 int hgnn_param_views(hgnn_ctx *ctx, float **params_dev, float **grads_dev);
+/* Test hook for the failure path: the n-th layer call (forward or backward,
+ * any layer kind) from now on returns HGNN_EDEVICE without launching, as a
+ * failed launch would, and the context stays in HGNN_ESTATE until
+ * hgnn_set_state.  n = 0 disables it.  For tests of callers' recovery. */
+int hgnn_debug_fail_after(hgnn_ctx *ctx, int32_t n);
 /* Synchronise the stream and report the device error word (EINVAL with a
  * message naming the first failed check) or a sticky ESTATE. */
 int hgnn_check(hgnn_ctx *ctx, void *stream);

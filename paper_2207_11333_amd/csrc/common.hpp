@@ -24,6 +24,7 @@ enum : int32_t {
   ERR_EDGE_CROSS = 2,   // edge joins two graphs
   ERR_DEGREE = 4,       // in- or out-degree above max_degree
   ERR_GRAPH_PTR = 8,    // graph_ptr not 0..N or a graph without nodes
+  ERR_NONFINITE = 16,   // a NaN or infinity in x or edge_attr
 };
 
 typedef float f4 __attribute__((ext_vector_type(4)));

@@ -51,8 +51,15 @@ __global__ void k_csr_init(const Dims *__restrict__ dims,
     node_graph[i] = lo;
     cnt_in[i] = 0;
     cnt_out[i] = 0;
-    if (x) // the first layer's input, zero-padded from F to Fp columns
-      for (int c = 0; c < Fp; ++c) xpad[(size_t)i * Fp + c] = c < F ? x[(size_t)i * F + c] : 0.f;
+    if (x) { // the first layer's input, zero-padded from F to Fp columns
+      bool finite = true;
+      for (int c = 0; c < Fp; ++c) {
+        const float v = c < F ? x[(size_t)i * F + c] : 0.f;
+        finite = finite && isfinite(v);
+        xpad[(size_t)i * Fp + c] = v;
+      }
+      if (!finite) atomicOr(err, ERR_NONFINITE);
+    }
   }
 }
 
@@ -186,7 +193,8 @@ __global__ void k_csr_sort_in(const Dims *__restrict__ dims,
                               int *__restrict__ csr_eid, int *__restrict__ csr_src,
                               int *__restrict__ csr_dst, int *__restrict__ csr_pos,
                               const float *__restrict__ edge_attr, int Fe,
-                              float *__restrict__ csr_e, int max_degree) {
+                              float *__restrict__ csr_e, int max_degree,
+                              int *__restrict__ err) {
   const int N = dims->N;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -206,13 +214,19 @@ __global__ void k_csr_sort_in(const Dims *__restrict__ dims,
       csr_eid[b + 1] = ka;
     }
   }
+  bool finite = true;
   for (int q = lo; q < hi; ++q) {
     const int k = csr_eid[q];
     csr_src[q] = ei[k];
     csr_dst[q] = i;
     csr_pos[k] = q;
-    for (int f = 0; f < Fe; ++f) csr_e[(size_t)q * Fe + f] = edge_attr[(size_t)k * Fe + f];
+    for (int f = 0; f < Fe; ++f) {
+      const float v = edge_attr[(size_t)k * Fe + f];
+      finite = finite && isfinite(v);
+      csr_e[(size_t)q * Fe + f] = v;
+    }
   }
+  if (!finite) atomicOr(err, ERR_NONFINITE);
 }
 
 // Per source: CSR positions of its out-edges, ascending.
@@ -278,7 +292,7 @@ hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
   if (capN > 0) {
     k_csr_sort_in<<<cdiv(capN, 128), 128, 0, s>>>(dims, edge_index, c.rowptr, c.csr_eid,
                                                   c.csr_src, c.csr_dst, c.csr_pos, edge_attr, Fe,
-                                                  c.csr_e, max_degree);
+                                                  c.csr_e, max_degree, c.err);
     k_csr_sort_out<<<cdiv(capN, 128), 128, 0, s>>>(dims, c.srcptr, c.tmp_out, c.csr_pos,
                                                    c.t2csr, max_degree);
   }

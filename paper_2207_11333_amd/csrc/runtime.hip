@@ -36,6 +36,15 @@ int hip_fail(hgnn_ctx *c, hipError_t e, const char *what) {
   return fail(HGNN_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Test-only failure injection (hgnn_debug_fail_after): the n-th layer call
+// from now reports a launch failure instead of launching, which puts the
+// context into HGNN_ESTATE exactly as a real device failure would.
+static int injected_failure(hgnn_ctx *c) {
+  if (c->fail_after > 0 && --c->fail_after == 0)
+    return hip_fail(c, hipErrorLaunchFailure, "injected failure (hgnn_debug_fail_after)");
+  return 0;
+}
+
 static void dfree(void *&p) {
   if (p) (void)hipFree(p);
   p = nullptr;
@@ -249,6 +258,7 @@ std::string decode_err(int bits) {
   if (bits & ERR_EDGE_RANGE) m += " edge endpoint out of range;";
   if (bits & ERR_EDGE_CROSS) m += " edge crosses graphs;";
   if (bits & ERR_DEGREE) m += " node degree above max_degree;";
+  if (bits & ERR_NONFINITE) m += " non-finite value in x or edge_attr;";
   return m;
 }
 
@@ -337,6 +347,7 @@ static const float *layer_input(hgnn_ctx *c, Exec &ex, int l, const float *h_in,
 
 int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_in, float *h_out,
                   hipStream_t s) {
+  if (int rc = injected_failure(c)) return rc;
   const LayerDesc &d = c->ld[l];
   const int H = c->H;
   Work &w = ex.w;
@@ -380,6 +391,7 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
 int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_in,
                    const float *h_out, const float *dh_out, float *dh_in, float *dwl,
                    hipStream_t s, bool dh_out_masked = false, bool mask_dh_in = false) {
+  if (int rc = injected_failure(c)) return rc;
   const LayerDesc &d = c->ld[l];
   const int H = c->H, Fe = c->Fe, ldD = (2 + Fe) * H;
   Work &w = ex.w;
@@ -726,6 +738,7 @@ static int gc_forward(hgnn_ctx *c, Exec &ex, hipStream_t s, const float **last) 
     ldh = H;
   }
   for (int l = 0; l < c->L; ++l) {
+    if (int rc = injected_failure(c)) return rc;
     const LayerDesc &d = c->ld[l];
     const float *b = c->params + d.obm;
     if (c->kind == HGNN_GC_SAGE) {
@@ -786,6 +799,7 @@ static int gc_backward(hgnn_ctx *c, Exec &ex, float *cur, float *nxt, hipStream_
   const int H = c->H, Fe = c->Fe;
   hipError_t e = hipSuccess;
   for (int l = c->L - 1; l >= 0; --l) {
+    if (int rc = injected_failure(c)) return rc;
     const LayerDesc &d = c->ld[l];
     float *dW = c->grads + d.oWm, *db = c->grads + d.obm;
     const float *hin = l ? w.hbuf[l - 1] : (c->kind == HGNN_GC_CGCNN ? w.h0 : w.xpad);
@@ -1298,6 +1312,12 @@ int hgnn_set_params(hgnn_ctx *c, const float *src, void *stream) {
     if (e != hipSuccess) return hip_fail(c, e, "copy params");
   }
   return stage_all(c, s);
+}
+
+int hgnn_debug_fail_after(hgnn_ctx *c, int32_t n) {
+  if (!c || n < 0) return fail(HGNN_EINVAL, "context is NULL or n < 0");
+  c->fail_after = n;
+  return HGNN_OK;
 }
 
 int hgnn_param_views(hgnn_ctx *c, float **params, float **grads) {

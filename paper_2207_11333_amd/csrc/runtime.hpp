@@ -120,6 +120,7 @@ struct hgnn_ctx {
   float *part = nullptr;
   hgnn::Exec ex; // the training path's batch state
   int sticky = 0;
+  int fail_after = 0; // test-only failure injection (hgnn_debug_fail_after)
   hgnn::Server *server = nullptr;
   hgnn::SiteTimer timer;
   // The backward pass runs the weight-gradient GEMMs on this stream,

@@ -84,6 +84,7 @@ _SIGS = {
     "hgnn_create_gc": ([ctypes.POINTER(Config), _I, ctypes.POINTER(Heads),
                         ctypes.POINTER(_P)], _I),
     "hgnn_param_views": ([_P, ctypes.POINTER(_P), ctypes.POINTER(_P)], _I),
+    "hgnn_debug_fail_after": ([_P, _I], _I),
     "hgnn_destroy": ([_P], None),
     "hgnn_num_params": ([_P, ctypes.POINTER(ctypes.c_int64)], _I),
     "hgnn_set_params": ([_P, _P, _P], _I),
@@ -355,6 +356,10 @@ class Model:
         p, g = _P(), _P()
         _check(lib().hgnn_param_views(self.handle, ctypes.byref(p), ctypes.byref(g)))
         return _DeviceView(p.value, self.num_params, self), _DeviceView(g.value, self.num_params, self)
+
+    def debug_fail_after(self, n: int):
+        """Test hook: the n-th layer call from now fails as a launch would."""
+        _check(lib().hgnn_debug_fail_after(self.handle, n))
 
     def check(self):
         _check(lib().hgnn_check(self.handle, _stream()))
