@@ -535,3 +535,30 @@ def test_param_views_alias_the_context_vectors():
     assert torch.equal(pred, pred2)
     m.close()
     m2.close()
+
+
+def test_same_step_on_another_stream_is_bitwise_equal():
+    """The library runs on whatever stream the caller passes: the same
+    training step on a side stream gives bitwise the same outputs."""
+    hg = _hgnn()
+    w = synth.WORKLOADS["c0_small_fp32"]
+    b, params = w.batch(), w.params()
+    db = hg.DeviceBatch.from_host(b)
+    outs = []
+    for use_side in (False, True):
+        m = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+        m.set_params(params)
+        pred = torch.empty(b.num_graphs, device="cuda")
+        loss = torch.empty(1, device="cuda")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side if use_side else torch.cuda.current_stream()):
+            m.forward(db, pred, loss)
+            m.backward()
+            m.adam_step()
+            p = m.params()
+        torch.cuda.synchronize()
+        outs.append((pred, loss, p))
+        m.close()
+    for a, c in zip(outs[0], outs[1]):
+        assert torch.equal(a, c)
