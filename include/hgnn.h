@@ -258,7 +258,10 @@ int hgnn_op_fetch(hgnn_ctx *ctx, int32_t which, int32_t layer, void *dst_dev,
  * HIP events recorded on that launch's stream, for up to max_launches
  * launches.  Sites: 1 message GEMM, 2 aggregation, 3 update GEMM, 4 update
  * weight-gradient GEMM, 5 aggregate-gradient GEMM, 6 aggregation adjoint,
- * 7 input-gradient GEMM.  Synchronises the device. */
+ * 7 input-gradient GEMM.  For GraphSAGE models site 3 is the layer GEMM and
+ * 4 its weight gradient; for CGCNN models 2 is the gated aggregation, 4 the
+ * layer weight gradient, 6 the aggregation adjoint and 7 the input-gradient
+ * GEMM.  Synchronises the device. */
 int hgnn_timer_start(hgnn_ctx *ctx, int32_t site, int32_t max_launches);
 /* Sum of the bracketed durations (ms) and the number of launches; stops the
  * timer.  Waits for the recorded events. */
