@@ -12,14 +12,17 @@ namespace {
 // --------------------------------------------------------------------------
 // TAG only distinguishes launch sites in profiles (1: the update linear).
 // Waves form a 2 x WGN grid over the BM x BN tile (NTH = 128 WGN threads).
-template <int PREC, int BM, int BN, bool SPLIT, int TAG, int WGN>
+// DB doubles the LDS tiles: tile t+1 is staged while tile t computes, with one
+// barrier per K step.  It needs 102 KB of LDS (FP32), so it is taken only
+// where the grid holds at most one workgroup per CU anyway.
+template <int PREC, int BM, int BN, bool SPLIT, int TAG, int WGN, bool DB>
 // FP32: four waves per SIMD (the compiler fits the kernel in 128 registers;
 // measured 1.7% faster end to end).  BF16: five, which holds the kernel to
 // 96 registers (one spilled).  Left to itself the compiler takes 125, and
 // the weight-gradient GEMM that runs beside this kernel on the second stream
 // then slows by 40% on the 8-layer hidden-256 workload (measured 63k vs 75k
-// graphs/s end to end).
-__global__ void __launch_bounds__(128 * WGN, PREC == 0 ? 4 : 5)
+// graphs/s end to end).  DB: two, all that its LDS allows.
+__global__ void __launch_bounds__(128 * WGN, DB ? 2 : (PREC == 0 ? 4 : 5))
 k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   using P = Prec<PREC>;
   using T = typename P::T;
@@ -32,9 +35,14 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   constexpr int BVEC = (PREC == 0) ? 4 : 8;
   constexpr int NB = BN * BK / BVEC / NTH;
   static_assert(NA >= 1 && NB >= 1, "tile too small for 256 threads");
+  // With DB the second buffer is a separate set of arrays, so the compiler
+  // can tell the stash into one buffer from the reads of the other.
   __shared__ __attribute__((aligned(16))) T As[BM * LDA];
   __shared__ __attribute__((aligned(16))) T Bs[BN * LDA];
   __shared__ __attribute__((aligned(16))) T Bl[SPLIT ? BN * LDA : 1];
+  __shared__ __attribute__((aligned(16))) T As1[DB ? BM * LDA : 1];
+  __shared__ __attribute__((aligned(16))) T Bs1[DB ? BN * LDA : 1];
+  __shared__ __attribute__((aligned(16))) T Bl1[DB && SPLIT ? BN * LDA : 1];
 
   const int M = g.M_fixed >= 0 ? g.M_fixed : dims->N;
   const int mtiles = (M + BM - 1) / BM;
@@ -74,10 +82,15 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   const T *Bg = reinterpret_cast<const T *>(g.B);
   const T *Blg = reinterpret_cast<const T *>(g.B_lo);
   // two register stages: tiles t and t+1 are in flight while t-1 computes.
-  // Loads are unconditional from clamped (in-bounds) addresses and masked
-  // by a select, so no branch forces the compiler to drain the load queue.
+  // Loads are unconditional from clamped (in-bounds) addresses.  With DB the
+  // stages keep the raw values and the row/column masks are applied only
+  // when a stage is written to LDS (a select right after the load makes the
+  // compiler wait for that load at once); the single-buffer form masks at
+  // the load, which needs fewer registers.
   f4 ra[2][NA], rb[2][NB], rl[2][SPLIT ? NB : 1];
   float rs[2][NA];
+  unsigned am[2], bm[2]; // bit j: element vector j is inside the matrix
+  bool hs[2];            // the stage's segment has a row scale
   int a_row[NA], a_col[NA];
   bool a_ok[NA];
 #pragma unroll
@@ -99,18 +112,64 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     b_col[j] = (v % (BK / BVEC)) * BVEC;
   }
 
-  auto load = [&](auto st, int t) {
-    constexpr int S = decltype(st)::value;
+  // Segment and K offset of tile t (of this split's range).
+  auto locate = [&](int t, int &q, int &kt) {
     t = t_lo + min(t, KT - 1);
-    int q = 0;
+    q = 0;
 #pragma unroll
     for (int u = 1; u < kMaxSeg; ++u) q += (t >= cum[u]) ? 1 : 0;
-    int kt = t - cum[q];
-    if (t >= il_start) {
+    kt = t - cum[q];
+    if constexpr (DB) {
+      // selects, not a branch: the loop body stays one block
+      const unsigned r = (unsigned)(t - il_start);
+      const int kt_il = (int)(r / 3u);
+      const bool il = t >= il_start;
+      q = il ? il_first + (int)(r - 3u * (unsigned)kt_il) : q;
+      kt = il ? kt_il : kt;
+    } else if (t >= il_start) {
       const unsigned r = (unsigned)(t - il_start);
       kt = (int)(r / 3u);
       q = il_first + (int)(r - 3u * (unsigned)kt);
     }
+  };
+  // DB: loads of tile t into stage S; the stage keeps the raw values, the
+  // bits of the K-tail and edge masks and whether the segment has a row
+  // scale, all applied when it is stashed.
+  auto dload = [&](auto st, int t) {
+    constexpr int S = decltype(st)::value;
+    int q, kt;
+    locate(t, q, kt);
+    const float *aptr = g.seg[q].ptr;
+    const float *scale = g.seg[q].scale;
+    const int lda = g.seg[q].ld, ks = g.seg[q].k, boff = g.seg[q].boff;
+    const int k0 = kt * BK;
+    const float *sbase = scale ? scale : aptr; // a readable word either way
+    unsigned mk = 0;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int k = k0 + a_col[j];
+      ra[S][j] = *reinterpret_cast<const f4 *>(aptr + (size_t)a_row[j] * lda + min(k, ks - 4));
+      rs[S][j] = sbase[a_row[j]];
+      mk |= (a_ok[j] && k < ks) ? 1u << j : 0u;
+    }
+    am[S] = mk;
+    hs[S] = scale != nullptr;
+    mk = 0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int k = k0 + b_col[j];
+      const size_t off = (size_t)b_row[j] * g.ldb + boff + min(k, ks - BVEC);
+      rb[S][j] = *reinterpret_cast<const f4 *>(Bg + off);
+      if constexpr (SPLIT) rl[S][j] = *reinterpret_cast<const f4 *>(Blg + off);
+      mk |= (b_ok[j] && k < ks) ? 1u << j : 0u;
+    }
+    bm[S] = mk;
+  };
+  // single buffer: segment lookup and loads together, masks applied at once
+  auto load = [&](auto st, int t) {
+    constexpr int S = decltype(st)::value;
+    int q, kt;
+    locate(t, q, kt);
     const float *aptr = g.seg[q].ptr;
     const float *scale = g.seg[q].scale;
     const int lda = g.seg[q].ld, ks = g.seg[q].k, boff = g.seg[q].boff;
@@ -139,38 +198,115 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
         rl[S][j] = ok ? vlo : f4{0.f, 0.f, 0.f, 0.f};
       }
     }
+    am[S] = ~0u;
+    bm[S] = ~0u;
+    hs[S] = true; // rs already holds 1 where there is no scale
   };
-  auto stash = [&](auto st) {
+  // register stage S goes to LDS buffer b (b = S when DB, else 0)
+  auto stash_a = [&](auto st, auto buf) {
     constexpr int S = decltype(st)::value;
+    T *Ad = decltype(buf)::value ? As1 : As;
+    const f4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       const int v = tid + j * NTH;
       const int r = v / (BK / 4), c = (v % (BK / 4)) * 4;
-      store4(As + r * LDA + c, ra[S][j] * rs[S][j]);
+      const float sc = hs[S] ? rs[S][j] : 1.0f;
+      store4(Ad + r * LDA + c, (am[S] >> j & 1u) ? ra[S][j] * sc : zero);
     }
+  };
+  auto stash_b = [&](auto st, auto buf) {
+    constexpr int S = decltype(st)::value;
+    T *Bd = decltype(buf)::value ? Bs1 : Bs, *Ld = decltype(buf)::value ? Bl1 : Bl;
+    const f4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int v = tid + j * NTH;
       const int r = v / (BK / BVEC), c = (v % (BK / BVEC)) * BVEC;
-      *reinterpret_cast<f4 *>(Bs + r * LDA + c) = rb[S][j]; // 16 raw bytes
-      if constexpr (SPLIT) *reinterpret_cast<f4 *>(Bl + r * LDA + c) = rl[S][j];
+      const bool ok = bm[S] >> j & 1u;
+      *reinterpret_cast<f4 *>(Bd + r * LDA + c) = ok ? rb[S][j] : zero; // 16 raw bytes
+      if constexpr (SPLIT) *reinterpret_cast<f4 *>(Ld + r * LDA + c) = ok ? rl[S][j] : zero;
     }
   };
+  auto stash = [&](auto st, auto buf) {
+    stash_a(st, buf);
+    stash_b(st, buf);
+  };
+  auto mma = [&](auto buf) {
+    constexpr int b = decltype(buf)::value;
+    const T *Ad = b ? As1 : As, *Bd = b ? Bs1 : Bs;
+    mma_tile<PREC, TM, TN, LDA, BK>(Ad, Bd, wm0, wn0, acc);
+    if constexpr (SPLIT) mma_tile<PREC, TM, TN, LDA, BK>(Ad, b ? Bl1 : Bl, wm0, wn0, acc);
+  };
+  // single buffer: the tile is staged between two barriers, then computed
+  // (several workgroups share a CU here and cover each other's waits)
   auto step = [&](auto st, int t) {
     __syncthreads();
-    stash(st);
+    stash(st, IC<0>{});
     __syncthreads();
     load(st, t + 2);
-    mma_tile<PREC, TM, TN, LDA, BK>(As, Bs, wm0, wn0, acc);
-    if constexpr (SPLIT) mma_tile<PREC, TM, TN, LDA, BK>(As, Bl, wm0, wn0, acc);
+    mma(IC<0>{});
+  };
+  // double buffer, on entry: LDS buffer S holds tile t, register stage 1-S
+  // holds tile t+1.  Stage S is free (its tile is in LDS) and takes tile t+2;
+  // tile t+1 goes to the other buffer, last read by tile t-1's products,
+  // which the previous step's barrier has retired.  With one workgroup per
+  // CU nothing else covers a wave's waits, so the step is pipelined by hand
+  // in chunks of MFMAs (one K chunk of one weight half each, in the order
+  // mma_tile uses: the same sums in the same order as the single buffer,
+  // bitwise equal for the non-negative finite row scales used here):
+  // chunk c reads chunk c+1's fragments, the first chunk also issues tile
+  // t+2's loads and the last ones write tile t+1 to LDS.  Scheduling
+  // barriers between chunks keep the compiler from regrouping them.
+  constexpr int KC = Frag<PREC>::KC, NKC = BK / KC, NCH = NKC * (SPLIT ? 2 : 1);
+  constexpr int CH_SA = NCH >= 3 ? NCH - 2 : NCH - 1; // chunk that stashes A
+  auto dstep = [&](auto st, int t) {
+    constexpr int S = decltype(st)::value;
+    const T *Ad = S ? As1 : As, *Bd = S ? Bs1 : Bs, *Ld = S ? Bl1 : Bl;
+    typename Frag<PREC>::V fa[2][TM], fb[2][TN];
+    read_frags<PREC, TM, TN, LDA>(Ad, Bd, wm0, wn0, 0, fa[0], fb[0]);
+    static_for<NCH>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if constexpr (c + 1 < NCH) {
+        constexpr int n = c + 1;
+        read_frags<PREC, TM, TN, LDA>(Ad, n >= NKC ? Ld : Bd, wm0, wn0, (n % NKC) * KC,
+                                      fa[n & 1], fb[n & 1]);
+      }
+      if constexpr (c == 0) dload(st, t + 2);
+      if constexpr (c == CH_SA) stash_a(IC<1 - S>{}, IC<1 - S>{});
+      if constexpr (c == NCH - 1) stash_b(IC<1 - S>{}, IC<1 - S>{});
+      mma_frags<PREC, TM, TN>(fa[c & 1], fb[c & 1], acc);
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    __syncthreads();
   };
 
-  if (KT > 0) load(IC<0>{}, 0);
-  if (KT > 1) load(IC<1>{}, 1);
-  for (int t = 0; t < KT; t += 2) {
-    step(IC<0>{}, t);
-    if (t + 1 >= KT) break;
-    step(IC<1>{}, t + 1);
+  if constexpr (DB) {
+    // tiles past the range clamp to its last one (KT = 1: tile 0 again)
+    if (KT > 0) {
+      dload(IC<0>{}, 0);
+      dload(IC<1>{}, 1);
+      stash(IC<0>{}, IC<0>{});
+    }
+    // drain tile 1's loads once here: otherwise the compiler carries their
+    // pending register writes into the loop head and waits there every step
+    __builtin_amdgcn_s_waitcnt(0x0f70); // vmcnt(0)
+    __syncthreads();
+    // pairs of steps, then an odd last tile: no branch inside the loop body
+    int t = 0;
+    for (; t + 1 < KT; t += 2) {
+      dstep(IC<0>{}, t);
+      dstep(IC<1>{}, t + 1);
+    }
+    if (t < KT) dstep(IC<0>{}, t);
+  } else {
+    if (KT > 0) load(IC<0>{}, 0);
+    if (KT > 1) load(IC<1>{}, 1);
+    for (int t = 0; t < KT; t += 2) {
+      step(IC<0>{}, t);
+      if (t + 1 >= KT) break;
+      step(IC<1>{}, t + 1);
+    }
   }
 
   const int lane = tid & 63;
@@ -214,6 +350,8 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
 }
 
 constexpr int kNtWGN = 4; // 8 waves per workgroup
+// grids up to this many workgroups use the double-buffered tiles
+constexpr long long kNtDbMaxGrid = 256;
 
 template <int PREC, int BM, int BN, int TAG>
 hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
@@ -226,13 +364,22 @@ hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
   // the hi + lo weight form exists only for BF16 (no FP32 instance of it)
   bool split_weights = false;
   if constexpr (PREC == 1) split_weights = g.B_lo != nullptr;
+  const bool db = (long long)grid.x * grid.y <= kNtDbMaxGrid;
   if (split_weights) {
-    if constexpr (PREC == 1)
-      hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, true, TAG, kNtWGN>, grid, block, 0, s, ev0,
-                            ev1, 0, dims, ga, nt);
+    if constexpr (PREC == 1) {
+      if (db)
+        hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, true, TAG, kNtWGN, true>, grid, block, 0,
+                              s, ev0, ev1, 0, dims, ga, nt);
+      else
+        hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, true, TAG, kNtWGN, false>, grid, block, 0,
+                              s, ev0, ev1, 0, dims, ga, nt);
+    }
+  } else if (db) {
+    hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN, true>, grid, block, 0, s,
+                          ev0, ev1, 0, dims, ga, nt);
   } else {
-    hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN>, grid, block, 0, s, ev0,
-                          ev1, 0, dims, ga, nt);
+    hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN, false>, grid, block, 0, s,
+                          ev0, ev1, 0, dims, ga, nt);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && g.splits > 1) e = launch_reduce_nt(dims, capM, g, s);

@@ -34,6 +34,7 @@
 #include "common.hpp"
 
 #include <type_traits>
+#include <utility>
 
 namespace hgnn {
 
@@ -78,7 +79,61 @@ __device__ __forceinline__ void store4(__bf16 *dst, f4 v) {
 __device__ __forceinline__ void store1(float *dst, float v) { *dst = v; }
 __device__ __forceinline__ void store1(__bf16 *dst, float v) { *dst = (__bf16)v; }
 
-// Multiply-accumulate one BK-deep LDS tile into the wave's accumulators.
+// One K chunk of a wave's operands: FP32 16 k (four per lane, one 16-byte
+// LDS read per 16-row block), BF16 32 k (eight per lane).
+template <int PREC> struct Frag;
+template <> struct Frag<0> {
+  using V = f4;
+  static constexpr int KC = 16;
+};
+template <> struct Frag<1> {
+  using V = bf16x8;
+  static constexpr int KC = 32;
+};
+
+// Read the A and B fragments of the K chunk starting at kc.
+template <int PREC, int TM, int TN, int LDA>
+__device__ __forceinline__ void read_frags(const typename Prec<PREC>::T *As,
+                                           const typename Prec<PREC>::T *Bs, int wm0, int wn0,
+                                           int kc, typename Frag<PREC>::V (&a)[TM],
+                                           typename Frag<PREC>::V (&b)[TN]) {
+  using V = typename Frag<PREC>::V;
+  constexpr int PER = PREC == 0 ? 4 : 8; // k per lane group
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+    a[i] = *reinterpret_cast<const V *>(As + (wm0 + i * 16 + r) * LDA + kc + PER * g);
+#pragma unroll
+  for (int j = 0; j < TN; ++j)
+    b[j] = *reinterpret_cast<const V *>(Bs + (wn0 + j * 16 + r) * LDA + kc + PER * g);
+}
+
+// Multiply-accumulate one K chunk: FP32 issues four k-slots s per 16-byte
+// read, each over every (i, j) block; BF16 one instruction per block.
+template <int PREC, int TM, int TN>
+__device__ __forceinline__ void mma_frags(const typename Frag<PREC>::V (&a)[TM],
+                                          const typename Frag<PREC>::V (&b)[TN],
+                                          f4 (&acc)[TM][TN]) {
+  if constexpr (PREC == 0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+// Multiply-accumulate one BK-deep LDS tile into the wave's accumulators:
+// read_frags then mma_frags per K chunk, written out (the same order).
 template <int PREC, int TM, int TN, int LDA, int BK>
 __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
                                          const typename Prec<PREC>::T *Bs,
@@ -120,6 +175,15 @@ __device__ __forceinline__ void mma_tile(const typename Prec<PREC>::T *As,
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
+}
+
+// Call f(IC<0>{}), ..., f(IC<N-1>{}) in order.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &f, std::integer_sequence<int, I...>) {
+  (f(IC<I>{}), ...);
+}
+template <int N, typename F> __device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 
