@@ -598,7 +598,15 @@ def main():
     avg_s = r["site_ms_total"] / 1e3 / max(1, r["site_launches"])
     achieved = flops / avg_s / 1e12
     peak = BF16_PEAK_TFLOPS if bf16 else FP32_PEAK_TFLOPS
-    kname = f"update GEMM (S3) k_gemm_nt<{w.precision}, 64, 128, {'true' if bf16 else 'false'}, 1, 4>"
+    # the launch rule of the NT GEMM (64 x 128 tiles, K tiles of 64): the K
+    # split, then the double-buffered form for grids of at most 256 workgroups
+    # whose splits run at least four K tiles (hidden layers' K: H + 3 x 4H)
+    tiles = -(-r["N"] // 64) * -(-w.hidden // 128)
+    kt = -(-w.hidden // 64) + 3 * -(-4 * w.hidden // 64)
+    splits = max(1, min(256 // tiles, kt // 2, 8))
+    db = tiles * splits <= 256 and kt >= 4 * splits
+    kname = (f"update GEMM (S3) k_gemm_nt<{w.precision}, 64, 128, {'true' if bf16 else 'false'}, "
+             f"1, 4, {'true' if db else 'false'}>")
     wdesc = (f"{w.name}: {w.num_layers}-layer PNA GCNN, hidden {w.hidden}, {w.num_graphs} "
              f"synthetic molecules of {w.n_lo}-{w.n_hi} atoms, {w.edge_feat} edge feature, "
              f"{'BF16 linears, FP32 aggregation' if bf16 else 'FP32'}, "

@@ -350,11 +350,15 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
 }
 
 constexpr int kNtWGN = 4; // 8 waves per workgroup
-// grids up to this many workgroups use the double-buffered tiles
+// The double-buffered form: grids of at most this many workgroups (one per
+// CU) whose splits each run at least kNtDbMinKt K tiles.  Shorter K ranges
+// leave it little to overlap, and its LDS and registers then mostly slow the
+// weight-gradient GEMM beside it on the second stream.
 constexpr long long kNtDbMaxGrid = 256;
+constexpr int kNtDbMinKt = 4;
 
 template <int PREC, int BM, int BN, int TAG>
-hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
+hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, bool db, hipStream_t s,
                   hipEvent_t ev0, hipEvent_t ev1) {
   const int nt = cdiv(g.Ncols, BN);
   dim3 grid(cdiv(capM, BM) * nt, g.splits);
@@ -364,7 +368,6 @@ hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s,
   // the hi + lo weight form exists only for BF16 (no FP32 instance of it)
   bool split_weights = false;
   if constexpr (PREC == 1) split_weights = g.B_lo != nullptr;
-  const bool db = (long long)grid.x * grid.y <= kNtDbMaxGrid;
   if (split_weights) {
     if constexpr (PREC == 1) {
       if (db)
@@ -435,12 +438,14 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
   if (g.splits > 1 && !partials) g.splits = 1;
   while (g.splits > 1 && (size_t)g.splits * capM * g.Ncols > nt_partial_floats(0, 0, 0, 0))
     --g.splits;
+  const long long grid = (long long)cdiv(capM, kNtBM) * cdiv(g.Ncols, kNtBN) * g.splits;
+  const bool db = grid <= kNtDbMaxGrid && kt >= kNtDbMinKt * g.splits;
   if (tag == 1) {
-    if (precision == 0) return run_nt<0, kNtBM, kNtBN, 1>(dims, capM, g, s, ev0, ev1);
-    return run_nt<1, kNtBM, kNtBN, 1>(dims, capM, g, s, ev0, ev1);
+    if (precision == 0) return run_nt<0, kNtBM, kNtBN, 1>(dims, capM, g, db, s, ev0, ev1);
+    return run_nt<1, kNtBM, kNtBN, 1>(dims, capM, g, db, s, ev0, ev1);
   }
-  if (precision == 0) return run_nt<0, kNtBM, kNtBN, 0>(dims, capM, g, s, ev0, ev1);
-  return run_nt<1, kNtBM, kNtBN, 0>(dims, capM, g, s, ev0, ev1);
+  if (precision == 0) return run_nt<0, kNtBM, kNtBN, 0>(dims, capM, g, db, s, ev0, ev1);
+  return run_nt<1, kNtBM, kNtBN, 0>(dims, capM, g, db, s, ev0, ev1);
 }
 
 } // namespace hgnn
