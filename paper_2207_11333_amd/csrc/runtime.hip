@@ -388,9 +388,16 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
 
 // dh_out_masked: dh_out already carries this layer's ReLU adjoint (it is du).
 // mask_dh_in: fold the previous layer's ReLU adjoint (h_in > 0) into dh_in.
+// defer_join: leave the main stream's wait for this layer's weight-gradient
+// work to the next layer_backward call, which takes it just before its
+// aggregation adjoint, the first of its launches that overwrites a buffer the
+// weight gradients read (D; the next input gradient GEMM then overwrites this
+// layer's du).  Not with recomputation, which rewrites the stored A and PQ at
+// the start of the next layer.
 int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_in,
                    const float *h_out, const float *dh_out, float *dh_in, float *dwl,
-                   hipStream_t s, bool dh_out_masked = false, bool mask_dh_in = false) {
+                   hipStream_t s, bool dh_out_masked = false, bool mask_dh_in = false,
+                   bool defer_join = false) {
   if (int rc = injected_failure(c)) return rc;
   const LayerDesc &d = c->ld[l];
   const int H = c->H, Fe = c->Fe, ldD = (2 + Fe) * H;
@@ -477,6 +484,12 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     }
     if (e != hipSuccess) return hip_fail(c, e, "aggregate-input gradient GEMM");
   }
+  // the previous layer's weight gradients read D: wait for them now
+  if (c->join_pending) {
+    c->join_pending = false;
+    e = hipStreamWaitEvent(s, c->join_ev, 0);
+    if (e != hipSuccess) return hip_fail(c, e, "join");
+  }
   // S7: per-edge dm, D_in, De; then D_out through the transpose
   {
     TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s, /*manual=*/true);
@@ -543,10 +556,11 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     }
     if (e != hipSuccess) return hip_fail(c, e, "input gradient GEMM");
   }
-  // join
+  // join (now, or deferred to the next layer's aggregation adjoint)
   e = hipEventRecord(c->join_ev, a);
-  if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join_ev, 0);
+  if (e == hipSuccess && !defer_join) e = hipStreamWaitEvent(s, c->join_ev, 0);
   if (e != hipSuccess) return hip_fail(c, e, "join");
+  c->join_pending = defer_join;
   return HGNN_OK;
 }
 
@@ -1406,11 +1420,18 @@ int hgnn_backward(hgnn_ctx *c, const float *dpred, void *stream) {
                          c->grads + c->off_head, s, w.hbuf[c->L - 1], w.hbuf[c->L - 1]);
   if (rc) return rc;
   if (c->kind != HGNN_GC_PNA) return gc_backward(c, c->ex, cur, nxt, s);
+  if (c->join_pending) { // left by a backward that failed part-way
+    c->join_pending = false;
+    if (hipError_t e = hipStreamWaitEvent(s, c->join_ev, 0); e != hipSuccess)
+      return hip_fail(c, e, "join");
+  }
   for (int l = c->L - 1; l >= 0; --l) {
     const float *h_in = l ? w.hbuf[l - 1] : c->ex.xin;
+    // the last call (l = 0) joins, which orders all weight-gradient work
     rc = layer_backward(c, c->ex, l, c->params + c->ld[l].off, h_in, w.hbuf[l], cur,
                         l ? nxt : nullptr, c->grads + c->ld[l].off, s,
-                        /*dh_out_masked=*/true, /*mask_dh_in=*/true);
+                        /*dh_out_masked=*/true, /*mask_dh_in=*/true,
+                        /*defer_join=*/l > 0 && !c->recompute);
     if (rc) return rc;
     std::swap(cur, nxt);
   }

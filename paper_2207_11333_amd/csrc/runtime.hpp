@@ -127,6 +127,8 @@ struct hgnn_ctx {
   // concurrently with the input-gradient chain (event fork/join).
   hipStream_t aux = nullptr;
   hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev = nullptr;
+  // the main stream has not yet waited for join_ev (a deferred layer join)
+  bool join_pending = false;
 };
 
 namespace hgnn {
