@@ -84,7 +84,7 @@ void free_work(Exec &ex) {
                    (void **)&w.dh1, (void **)&w.ntpart, (void **)&w.zn, (void **)&w.Qn,
                    (void **)&w.dQn, (void **)&w.en, (void **)&w.dhn,
                    (void **)&w.csr.csr_dst, (void **)&w.h0, (void **)&w.gcG,
-                   (void **)&w.gcD, (void **)&w.gcdm};
+                   (void **)&w.gcD, (void **)&w.gcdm, (void **)&w.gcD1};
   for (void **p : ptrs) dfree(*p);
   for (auto &p : w.gcA) dfree(reinterpret_cast<void *&>(p));
   w.gcA.clear();
@@ -158,7 +158,7 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
       ok = ok && f(w.gcG, (size_t)capN * 2 * H);
     else
       ok = ok && f(w.gcD, (size_t)capN * (4 + 2 * c->Fe) * H) &&
-           f(w.gcdm, (size_t)capE * 2 * H);
+           f(w.gcD1, (size_t)capN * (4 + 2 * c->Fe) * H) && f(w.gcdm, (size_t)capE * 2 * H);
   }
   return ok;
 }
@@ -808,10 +808,25 @@ static int gc_forward(hgnn_ctx *c, Exec &ex, hipStream_t s, const float **last) 
 
 // Backward of the GC stack from cur = dL/du of the last layer (its ReLU
 // adjoint applied); nxt is the second [N, H] buffer of the ping-pong.
+// The main stream waits for a layer's weight-gradient stream (join_ev) only
+// at the next layer's first launch that overwrites a buffer those GEMMs read:
+// GraphSAGE's neighbour scatter (it rewrites this layer's du) and CGCNN's
+// input-gradient GEMM (CGCNN's D alternates between two buffers by layer
+// parity, so the next layer's aggregation adjoint leaves this layer's D
+// alone).  Layer 0 joins at once.
+static void wait_pending_join(hgnn_ctx *c, hipStream_t s, hipError_t &e) {
+  if (e == hipSuccess && c->join_pending) {
+    c->join_pending = false;
+    e = hipStreamWaitEvent(s, c->join_ev, 0);
+  }
+}
+
 static int gc_backward(hgnn_ctx *c, Exec &ex, float *cur, float *nxt, hipStream_t s) {
   Work &w = ex.w;
   const int H = c->H, Fe = c->Fe;
   hipError_t e = hipSuccess;
+  wait_pending_join(c, s, e); // left by a backward that failed part-way
+  if (e != hipSuccess) return hip_fail(c, e, "join");
   for (int l = c->L - 1; l >= 0; --l) {
     if (int rc = injected_failure(c)) return rc;
     const LayerDesc &d = c->ld[l];
@@ -865,6 +880,7 @@ static int gc_backward(hgnn_ctx *c, Exec &ex, float *cur, float *nxt, hipStream_
         g.ldc = 2 * H;
         g.M_fixed = -1;
         e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
+        wait_pending_join(c, s, e);
         if (e == hipSuccess)
           e = launch_sage_scatter(ex.dims, ex.N, H, w.csr.srcptr, w.csr.t2csr, w.csr.csr_dst,
                                   w.csr.rowptr, w.gcG, hin, nxt, s);
@@ -872,14 +888,15 @@ static int gc_backward(hgnn_ctx *c, Exec &ex, float *cur, float *nxt, hipStream_
       }
     } else {
       const int ldD = (4 + 2 * Fe) * H;
+      float *gcD = (l & 1) ? w.gcD1 : w.gcD;
       {
         TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s);
         e = launch_cg_aggregate_bwd(ex.dims, ex.N, H, Fe, w.csr.rowptr, w.csr.csr_src,
                                     w.csr.csr_e, w.gcA[l], static_cast<const float *>(c->WeT[l]),
-                                    c->params + d.obm, du, w.gcdm, w.gcD, ldD, s);
+                                    c->params + d.obm, du, w.gcdm, gcD, ldD, s);
       }
       if (e == hipSuccess)
-        e = launch_transpose_sum(ex.dims, ex.N, 2 * H, w.csr.srcptr, w.csr.t2csr, w.gcdm, w.gcD,
+        e = launch_transpose_sum(ex.dims, ex.N, 2 * H, w.csr.srcptr, w.csr.t2csr, w.gcdm, gcD,
                                  ldD, s);
       if (e != hipSuccess) return hip_fail(c, e, "CGCNN aggregation adjoint");
       fork_to_aux(c, 0, s, e);
@@ -887,7 +904,7 @@ static int gc_backward(hgnn_ctx *c, Exec &ex, float *cur, float *nxt, hipStream_
       // [dW_dst | dW_src] = [D_in | D_out]^T h; db and the edge columns from
       // the constant-one column
       GemmTN t{};
-      t.X = w.gcD;
+      t.X = gcD;
       t.ldx = ldD;
       t.M = ldD;
       t.seg[0] = SegY{hin, nullptr, ldh, H};
@@ -921,8 +938,8 @@ static int gc_backward(hgnn_ctx *c, Exec &ex, float *cur, float *nxt, hipStream_
       // ReLU of the layer below (the embedding below layer 0 has none)
       GemmNT g{};
       g.nseg = 2;
-      g.seg[0] = SegA{w.gcD, nullptr, ldD, 2 * H, 0};
-      g.seg[1] = SegA{w.gcD + 2 * H, nullptr, ldD, 2 * H, 2 * H};
+      g.seg[0] = SegA{gcD, nullptr, ldD, 2 * H, 0};
+      g.seg[1] = SegA{gcD + 2 * H, nullptr, ldD, 2 * H, 2 * H};
       g.B = c->Wg2[l];
       g.B_lo = c->prec ? c->Wg2_lo[l] : nullptr;
       g.ldb = 4 * H;
@@ -933,13 +950,21 @@ static int gc_backward(hgnn_ctx *c, Exec &ex, float *cur, float *nxt, hipStream_
       g.C = nxt;
       g.ldc = H;
       g.M_fixed = -1;
+      wait_pending_join(c, s, e);
+      if (e != hipSuccess) return hip_fail(c, e, "join");
       {
         TimedLaunch tl(c, ex, SITE_INPUT_GEMM, s);
         e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
       }
       if (e != hipSuccess) return hip_fail(c, e, "CGCNN input gradient");
     }
-    join_aux(c, s, e);
+    if (l > 0) { // deferred to the next layer
+      if (e == hipSuccess) e = hipEventRecord(c->join_ev, c->aux);
+      c->join_pending = e == hipSuccess;
+    } else {
+      wait_pending_join(c, s, e);
+      join_aux(c, s, e);
+    }
     if (e != hipSuccess) return hip_fail(c, e, "join");
     std::swap(cur, nxt);
   }
@@ -1504,6 +1529,7 @@ int hgnn_set_state(hgnn_ctx *c, const void *buf, size_t bytes) {
   if (bytes < sizeof(h) + 3 * n) return fail(HGNN_EINVAL, "state buffer truncated");
   (void)hipSetDevice(c->dev);
   hipError_t e = hipDeviceSynchronize();
+  c->join_pending = false; // the synchronisation retired any deferred join
   if (e != hipSuccess) (void)hipGetLastError(); // clear a sticky launch error if possible
   const char *p = reinterpret_cast<const char *>(buf) + sizeof(h);
   long long step = h.step;

@@ -40,6 +40,7 @@ struct Work {
   // gate gradients dm [E, 2H]
   std::vector<float *> gcA;
   float *h0 = nullptr, *gcG = nullptr, *gcD = nullptr, *gcdm = nullptr;
+  float *gcD1 = nullptr; // CGCNN: D of odd layers (even layers use gcD)
 };
 
 // Batch-local execution state: device size header, CSR, activations and
