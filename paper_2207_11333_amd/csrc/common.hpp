@@ -66,6 +66,7 @@ struct GemmNT {
   // order z = 0..splits-1 and applies bias and ReLU.
   int splits;
   float *P;
+  int max_splits;    // > 0: cap on the split count chosen by the launcher
   // optional: zero C[m, n] where mask[m * ldc + n] <= 0 (ReLU adjoint of the
   // layer that produced `mask`)
   const float *mask;

@@ -434,6 +434,7 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
     if (g.seg[q].k > 0) kt += nt_ktiles(g.seg[q].k, precision);
   g.splits = nt_splits(capM, g.Ncols, Ktot, precision);
   if (g.splits > kt / 2) g.splits = kt / 2 > 0 ? kt / 2 : 1;
+  if (g.max_splits > 0 && g.splits > g.max_splits) g.splits = g.max_splits;
   g.P = partials;
   if (g.splits > 1 && !partials) g.splits = 1;
   while (g.splits > 1 && (size_t)g.splits * capM * g.Ncols > nt_partial_floats(0, 0, 0, 0))

@@ -550,6 +550,11 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     g.ldc = d.F;
     g.M_fixed = -1;
     g.mask = (mask_dh_in && l > 0) ? h_in : nullptr;
+    // BF16: unsplit, so the CUs a K split would take are left to the message
+    // weight-gradient GEMM running beside this one and no reduction follows
+    // (C2 169k -> 172k graphs/s; FP32, whose unsplit GEMM is slower, loses:
+    // C1 131k -> 126k)
+    g.max_splits = c->prec ? 1 : 0;
     {
       TimedLaunch tl(c, ex, SITE_INPUT_GEMM, s);
       e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
