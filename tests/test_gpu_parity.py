@@ -235,6 +235,35 @@ def test_autograd_functions_match_fused_entry_points():
     m.close()
 
 
+@pytest.mark.parametrize("name", ["c1_train_fp32", "c2_train_bf16"])
+def test_deferred_joins_match_per_layer_joins(name):
+    """The fused backward leaves each layer's weight-gradient stream to be
+    joined at the next layer's aggregation adjoint; the per-operation layer
+    entries (driven here by PNANet) join every layer at once.  At the full
+    headline size, where the weight-gradient GEMMs run long beside the
+    input-gradient chain, both give the same gradients (the loss gradient is
+    formed by torch on one side and by the head kernel on the other, hence a
+    tolerance instead of bitwise equality; in BF16 that difference can move a
+    few operand roundings).  A missed wait would show as a far larger error."""
+    hg = _hgnn()
+    w = synth.WORKLOADS[name]
+    b, params = w.batch(), w.params()
+    say(f"deferred joins: {name} N={b.num_nodes} E={b.num_edges}")
+    m = make_model(w.num_layers, w.hidden, w.edge_feat, w.precision, w.recompute, w.delta)
+    out = run_train_step(m, b, params)
+    net = hg.PNANet(m, params)
+    db = hg.DeviceBatch.from_host(b)
+    pred = net(db)
+    loss = ((pred - db.y) ** 2).mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert torch.equal(pred.detach(), out["pred"])
+    r = rel(net.packed_grad().cpu().numpy(), out["grads"].cpu().numpy())
+    say(f"  gradient rel {r:.2e}")
+    assert r <= (1e-5 if w.precision else 1e-6)
+    m.close()
+
+
 def test_gpu_path_central_differences():
     """FP32 finite differences through the GPU forward (loose: FP32 noise)."""
     hg = _hgnn()
