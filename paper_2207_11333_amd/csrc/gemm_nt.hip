@@ -14,7 +14,8 @@ namespace {
 // Waves form a 2 x WGN grid over the BM x BN tile (NTH = 128 WGN threads).
 // DB doubles the LDS tiles: tile t+1 is staged while tile t computes, with one
 // barrier per K step.  It needs 102 KB of LDS (FP32), so it is taken only
-// where the grid holds at most one workgroup per CU anyway.
+// where the grid holds at most one workgroup per CU anyway and each K split
+// runs at least four K tiles (launch_gemm_nt).
 template <int PREC, int BM, int BN, bool SPLIT, int TAG, int WGN, bool DB>
 // FP32: four waves per SIMD (the compiler fits the kernel in 128 registers;
 // measured 1.7% faster end to end).  BF16: five, which holds the kernel to
@@ -34,7 +35,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   // B tile: BN x BK elements loaded 16 bytes at a time
   constexpr int BVEC = (PREC == 0) ? 4 : 8;
   constexpr int NB = BN * BK / BVEC / NTH;
-  static_assert(NA >= 1 && NB >= 1, "tile too small for 256 threads");
+  static_assert(NA >= 1 && NB >= 1, "tile too small for the workgroup");
   // With DB the second buffer is a separate set of arrays, so the compiler
   // can tell the stash into one buffer from the reads of the other.
   __shared__ __attribute__((aligned(16))) T As[BM * LDA];

@@ -1,5 +1,7 @@
 // Shared pieces of the MFMA GEMMs (gemm_nt.hip, gemm_tn.hip): operand types
-// per precision, the XCD-aware tile order and the LDS tile multiply-accumulate.
+// per precision, the XCD-aware tile order and the LDS tile multiply-accumulate
+// (whole, or as per-chunk fragment reads and products for loops pipelined
+// by hand).
 //
 // MFMA GEMMs of the message, update and head-free linears (steps S1, S3 and
 // their adjoints S6, S8).
@@ -10,7 +12,8 @@
 //    [h || A || s+ A || s- A] and the adjoint input [du || s+ du || s- du]
 //    are read in place and scaled while being staged, never materialised.
 //    512-thread workgroups (8 wave64s in a 2x4 grid) on 64 x 128 tiles,
-//    operands staged through LDS in [row][k] order (k contiguous).
+//    operands staged through LDS in [row][k] order (k contiguous); small
+//    grids with long K ranges double-buffer the LDS tiles.
 //  * gemm_tn:  P[z] = X^T Yv over a fixed chunk z of the node rows (split-K),
 //    reduced afterwards in the fixed order z = 0, 1, ...: weight gradients
 //    are deterministic and need no atomics.  256-thread workgroups (4
