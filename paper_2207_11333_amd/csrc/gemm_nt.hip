@@ -240,12 +240,15 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     if constexpr (SPLIT) mma_tile<PREC, TM, TN, LDA, BK>(Ad, b ? Bl1 : Bl, wm0, wn0, acc);
   };
   // single buffer: the tile is staged between two barriers, then computed
-  // (several workgroups share a CU here and cover each other's waits)
+  // (several workgroups share a CU here and cover each other's waits).
+  // FP32 skips the clamped reloads past the range (a short K range, as in
+  // the message linear's two K tiles, otherwise loads twice what it uses);
+  // BF16 keeps them, since the branch makes its hi + lo form spill.
   auto step = [&](auto st, int t) {
     __syncthreads();
     stash(st, IC<0>{});
     __syncthreads();
-    load(st, t + 2);
+    if (PREC == 1 || t + 2 < KT) load(st, t + 2);
     mma(IC<0>{});
   };
   // double buffer, on entry: LDS buffer S holds tile t, register stage 1-S
