@@ -294,8 +294,9 @@ def _replay_relu(u, own, hint, tau, stats, what):
     diff = hint != own
     if not diff.any():
         return own
-    win = tau * np.maximum(np.abs(u), _rms(u))
-    bad = diff & (np.abs(u) > win)
+    # a ReLU decision is a tie of u against 0, so the window is measured on
+    # the scale of u's own tensor: |u| <= tau * rms(u)
+    bad = diff & (np.abs(u) > tau * _rms(u))
     if bad.any():
         idx = np.argwhere(bad)[0]
         raise DecisionMismatch(f"{what}: ReLU decision differs at {tuple(idx)} with "

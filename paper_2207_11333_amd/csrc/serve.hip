@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -394,6 +395,17 @@ std::string check_request(const hgnn_ctx *c, const hgnn_batch *r) {
     if (s < 0 || s >= N || d < 0 || d >= N) return "edge endpoint out of range";
     if (ng[s] != ng[d]) return "edge crosses graphs";
     if (++din[d] > c->maxd || ++dout[s] > c->maxd) return "degree above max_degree";
+  }
+  // Content is checked here as well: a batch shares one device error word,
+  // so a non-finite value found on the device would fail every request
+  // packed beside this one.
+  const size_t nx = (size_t)N * c->F0;
+  for (size_t i = 0; i < nx; ++i)
+    if (!std::isfinite(r->x[i])) return "non-finite value in x";
+  if (c->Fe > 0 && E > 0) {
+    const size_t ne = (size_t)E * c->Fe;
+    for (size_t i = 0; i < ne; ++i)
+      if (!std::isfinite(r->edge_attr[i])) return "non-finite value in edge_attr";
   }
   return "";
 }

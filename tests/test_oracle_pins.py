@@ -475,3 +475,73 @@ def test_decision_replay_window():
     hm = rec2.layers[0].argmax.copy(); hm[1, 0] = 0
     with pytest.raises(oracle.DecisionMismatch):
         oracle.backward(rec2, hint=oracle.Decisions([None], [hm], [None]), tau=1e-4)
+
+
+def _relu_replay_case():
+    """A 2-layer model on three small molecules with one pre-activation of
+    layer 0 moved (through its bias) to +-delta of the ReLU kink."""
+    b = synth.make_batch(41, 3, 5, 9, 1)
+    shape = synth.ModelShape(2, 8, 9, 1)
+    params = synth.init_params(shape, 42).astype(np.float64)
+    o, _ = shape.offsets()["l0.bp"]
+    rec = oracle.forward(params, b, 2, 8, 1.1)
+    u = rec.layers[0].u
+    i, c = 4, 3
+    scale = pna._rms(u)
+
+    def at(sign):
+        p = params.copy()
+        p[o + c] += sign * 1e-9 * scale - u[i, c]
+        r = oracle.forward(p, b, 2, 8, 1.1)
+        assert np.sign(r.layers[0].u[i, c]) == sign
+        return r
+
+    return at(+1), at(-1), (i, c)
+
+
+def _own_relu(rec):
+    return [lr.u > 0 for lr in rec.layers]
+
+
+def test_relu_replay_adopts_a_near_tie():
+    """Flipping a ReLU decision whose u is 1e-9 rms(u) from the kink is
+    adopted, counted, and gives the gradient of the other side of the kink."""
+    pos, neg, (i, c) = _relu_replay_case()
+    relu = _own_relu(pos)
+    relu[0] = relu[0].copy()
+    relu[0][i, c] = False
+    hint = oracle.Decisions([None, None], [None, None], relu, pos.pre > 0)
+    g_rep, dx_rep, st = oracle.backward(pos, hint=hint, tau=1e-4)
+    assert st == {"relu": 1, "argmin": 0, "argmax": 0}
+    g_pos, _, _ = oracle.backward(pos)
+    g_neg, dx_neg, _ = oracle.backward(neg)
+    # the adopted mask matters (the two sides of the kink differ) ...
+    assert np.linalg.norm(g_pos - g_neg) > 1e-6 * np.linalg.norm(g_neg)
+    # ... and replay lands on the other side: equal up to the 1e-9 offset
+    np.testing.assert_allclose(g_rep, g_neg, rtol=1e-6, atol=1e-9 * np.abs(g_neg).max())
+    np.testing.assert_allclose(dx_rep, dx_neg, rtol=1e-6, atol=1e-9 * np.abs(dx_neg).max())
+
+
+def test_relu_replay_rejects_a_far_flip():
+    """A ReLU decision flipped where |u| is far above tau rms(u) is an error,
+    in a GC layer and in the head."""
+    pos, _, _ = _relu_replay_case()
+    u = pos.layers[1].u
+    j = np.unravel_index(np.argmax(np.abs(u)), u.shape)
+    relu = _own_relu(pos)
+    relu[1] = relu[1].copy()
+    relu[1][j] = not relu[1][j]
+    with pytest.raises(oracle.DecisionMismatch):
+        oracle.backward(pos, hint=oracle.Decisions([None, None], [None, None], relu), tau=1e-4)
+    head = pos.pre > 0
+    k = np.unravel_index(np.argmax(np.abs(pos.pre)), pos.pre.shape)
+    head = head.copy()
+    head[k] = not head[k]
+    with pytest.raises(oracle.DecisionMismatch):
+        oracle.backward(pos, hint=oracle.Decisions([None, None], [None, None],
+                                                   [None, None], head), tau=1e-4)
+    # an unchanged hint adopts nothing
+    _, _, st = oracle.backward(pos, hint=oracle.Decisions([None, None], [None, None],
+                                                          _own_relu(pos), pos.pre > 0),
+                               tau=1e-4)
+    assert st == {"relu": 0, "argmin": 0, "argmax": 0}
