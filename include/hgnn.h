@@ -103,10 +103,25 @@ typedef struct {
 
 /* ---- context ------------------------------------------------------------ */
 
-/* Validate cfg, select the current HIP device and allocate the context.
- * Parameters start at zero: set them with hgnn_set_params.  EINVAL for a bad
- * config (checked before any device call), EDEVICE/ENOMEM otherwise. */
-int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out);
+/* Validate cfg, select the current HIP device, allocate the context and set
+ * the parameters (the trainable weights of the layers, pooling head and loss
+ * of Sections 3.1-3.2): from init_params_dev (device [P] in packing order,
+ * copied; the caller keeps ownership) or, when it is NULL, by
+ * hgnn_init_params(seed).  The parameter work runs on `stream`.  *out is NULL
+ * after any failure.  EINVAL for a bad config (checked before any device
+ * call), EDEVICE/ENOMEM otherwise. */
+int hgnn_create(const hgnn_config *cfg, const float *init_params_dev, uint64_t seed,
+                void *stream, hgnn_ctx **out);
+/* Seeded initialisation of the packed parameters on the device, in packing
+ * order: weights [rows, cols] Xavier-uniform with bound sqrt(6/(rows+cols)),
+ * biases with bound 0.1.  Element j (index into the packed vector) takes
+ * bound * k * 2^-23, k = (z >> 40) - 2^23, z the j-th output of SplitMix64
+ * from `seed` (Steele, Lea and Flood, 2014): z = mix(seed + (j + 1) *
+ * 0x9E3779B97F4A7C15) with mix(z) = z ^= z >> 30, z *= 0xBF58476D1CE4E5B9,
+ * z ^= z >> 27, z *= 0x94D049BB133111EB, z ^= z >> 31 -- a counter
+ * generator, reproducible on the host bit for bit.  Moments and the step
+ * count are left as they are; the GEMM copies are refreshed. */
+int hgnn_init_params(hgnn_ctx *ctx, uint64_t seed, void *stream);
 
 /* Multitask heads (HydraGNN's multi-headed outputs; the paper's model has one
  * graph-level head, which is what hgnn_create builds).  graph_heads Tg in 1..8
@@ -209,32 +224,45 @@ int hgnn_get_state(hgnn_ctx *ctx, void *buf_host, size_t *bytes);
 int hgnn_set_state(hgnn_ctx *ctx, const void *buf_host, size_t bytes);
 
 /* ---- per-operation entries (used by the autograd bindings) -------------- */
-/* These run single steps with explicit buffers.  w_layer_dev points at one
- * layer's packed slice [W^m, b^m, W^p, b^p]; w_head_dev at [W1, b1, w2, b2];
- * dw_* receive gradients in the same packing (overwritten). */
+/* The forward pass of Section 3.1 (message passing, pooling, FC head) and the
+ * backward phase of Section 3.2, one step at a time with explicit buffers.
+ * w_layer_dev points at one layer's packed slice [W^m, b^m, W^p, b^p];
+ * w_head_dev at [W1, b1, w2, b2]; dw_* receive gradients in the same
+ * packing (overwritten).  A backward entry differentiates the forward of the
+ * batch prepared last: it takes the generation that hgnn_op_generation
+ * returned after that prepare and returns EINVAL, writing nothing, if
+ * another batch has been prepared since (a second forward before the first
+ * one's backward). */
 
-/* Step S0: validate sizes, copy x into the padded layer-0 input and build the
- * destination-sorted CSR, its by-source transpose and the per-node scalers. */
+/* Step S0 (Table 1 layout in; node degree for the PNA scalers, Section 3.1):
+ * validate sizes, copy x into the padded layer-0 input and build the
+ * destination-sorted CSR, its by-source transpose and the per-node scalers.
+ * Advances the context's batch generation. */
 int hgnn_op_prepare(hgnn_ctx *ctx, const hgnn_batch *batch, int32_t flags,
                     void *stream);
-/* Layer l forward: h_out_dev [N, H] from h_in_dev [N, F_l].  Stores the
- * layer's messages, aggregates and arg decisions (unless recompute is on). */
+/* The batch generation: a count of prepares (hgnn_forward prepares too). */
+int hgnn_op_generation(const hgnn_ctx *ctx, int64_t *out);
+/* Layer l forward (one PNA graph convolution, Section 3.1): h_out_dev [N, H]
+ * from h_in_dev [N, F_l].  Stores the layer's messages, aggregates and arg
+ * decisions (unless recompute is on). */
 int hgnn_op_layer_forward(hgnn_ctx *ctx, int32_t layer,
                           const float *w_layer_dev, const float *h_in_dev,
                           float *h_out_dev, void *stream);
-/* Layer l backward: from dh_out_dev [N, H] (gradient w.r.t. h_out) write
- * dw_layer_dev and, when dh_in_dev is not NULL, dh_in_dev [N, F_l]. */
-int hgnn_op_layer_backward(hgnn_ctx *ctx, int32_t layer,
+/* Layer l backward (Section 3.2): from dh_out_dev [N, H] (gradient w.r.t.
+ * h_out) write dw_layer_dev and, when dh_in_dev is not NULL, dh_in_dev
+ * [N, F_l]. */
+int hgnn_op_layer_backward(hgnn_ctx *ctx, int64_t generation, int32_t layer,
                            const float *w_layer_dev, const float *h_in_dev,
                            const float *h_out_dev, const float *dh_out_dev,
                            float *dh_in_dev, float *dw_layer_dev, void *stream);
-/* Pooling + head (+ loss when target_dev and loss_dev are given). */
+/* Global mean pooling + FC head (Section 3.1), + the MSE loss (Section 3.2)
+ * when target_dev and loss_dev are given.  pred_dev [B]. */
 int hgnn_op_head_forward(hgnn_ctx *ctx, const float *w_head_dev,
                          const float *h_dev, const float *target_dev,
                          float *pred_dev, float *loss_dev, void *stream);
-/* Head adjoint: dpred_dev [B], or the MSE gradient from target_dev when
- * dpred_dev is NULL.  Writes dh_dev [N, H] and dw_head_dev. */
-int hgnn_op_head_backward(hgnn_ctx *ctx, const float *w_head_dev,
+/* Head adjoint (Section 3.2): dpred_dev [B], or the MSE gradient from
+ * target_dev when dpred_dev is NULL.  Writes dh_dev [N, H] and dw_head_dev. */
+int hgnn_op_head_backward(hgnn_ctx *ctx, int64_t generation, const float *w_head_dev,
                           const float *h_dev, const float *target_dev,
                           const float *dpred_dev, float *dh_dev,
                           float *dw_head_dev, void *stream);
@@ -271,6 +299,12 @@ int hgnn_timer_read(hgnn_ctx *ctx, double *total_ms, int32_t *launches);
 int hgnn_calib_copy(const float *src_dev, float *dst_dev, int64_t n, void *stream);
 
 /* ---- serving (continuous batching of inference requests) --------------- */
+/* The use the paper gives the surrogate (Section 1, Fig. 1): a fast screen of
+ * molecules streamed from design workflows, one predicted HOMO-LUMO gap per
+ * molecule.  Requests of any number of molecules are queued, packed into
+ * batches that the forward pass of Section 3.1 runs on the GPU (no loss), and
+ * their predictions handed back per request.  A request's predictions do not
+ * depend on what it was batched with. */
 
 typedef struct {
   int64_t hbm_budget_bytes; /* admission budget for in-flight batches */

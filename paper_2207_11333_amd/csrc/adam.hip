@@ -167,6 +167,35 @@ hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp, i
   return hipGetLastError();
 }
 
+// Seeded initialisation: element j of the packed vector (global index) is
+// bound * k * 2^-23 with k = (z >> 40) - 2^23 in [-2^23, 2^23), where z is
+// the j-th output of SplitMix64 started from `seed` (Steele, Lea and Flood,
+// OOPSLA 2014): z = mix(seed + (j + 1) * 0x9E3779B97F4A7C15).  A counter
+// generator, so every element is computed on its own; k * 2^-23 is exact in
+// FP32 and the product with the FP32 bound is rounded once.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
+  uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256)
+k_init_uniform(float *__restrict__ p, long long off, long long n, float bound, uint64_t seed) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const uint64_t z = splitmix64_at(seed, (uint64_t)(off + t));
+  const int k = (int)(z >> 40) - (1 << 23);
+  p[off + t] = bound * ((float)k * 0x1p-23f);
+}
+
+hipError_t launch_init_uniform(float *p, int64_t off, int64_t n, float bound, uint64_t seed,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_init_uniform<<<cdiv(n, 256), 256, 0, s>>>(p, off, n, bound, seed);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_fill<<<cdiv(n, 256), 256, 0, s>>>(p, n, v);

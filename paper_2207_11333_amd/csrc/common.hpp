@@ -251,6 +251,9 @@ hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp,
                               int H, int Fe, const StageOut &o, int to_bf16,
                               hipStream_t s);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
+// p[off + t] for t < n: bound * U[-1, 1) from SplitMix64(seed) at index off + t
+hipError_t launch_init_uniform(float *p, int64_t off, int64_t n, float bound, uint64_t seed,
+                               hipStream_t s);
 
 // gc.hip: GraphSAGE and CGCNN layer kinds
 constexpr int kMaxFe = 4;

@@ -285,6 +285,7 @@ int prepare(hgnn_ctx *c, Exec &ex, const hgnn_batch *b, int flags, hipStream_t s
   ex.xin = b->x;
   ex.target = b->y;
   ex.prepared = true;
+  ++ex.generation;
   w.stored_layer = -1;
   if (flags & HGNN_VALIDATE) {
     int bits = 0;
@@ -1025,8 +1026,17 @@ extern "C" {
 
 const char *hgnn_last_error(void) { return g_err.c_str(); }
 
-int hgnn_create(const hgnn_config *cfg, hgnn_ctx **out) {
-  return hgnn_create_multitask(cfg, nullptr, out);
+int hgnn_create(const hgnn_config *cfg, const float *init_params, uint64_t seed, void *stream,
+                hgnn_ctx **out) {
+  int rc = hgnn_create_multitask(cfg, nullptr, out);
+  if (rc) return rc;
+  rc = init_params ? hgnn_set_params(*out, init_params, stream)
+                   : hgnn_init_params(*out, seed, stream);
+  if (rc) {
+    hgnn_destroy(*out);
+    *out = nullptr;
+  }
+  return rc;
 }
 
 int hgnn_create_multitask(const hgnn_config *cfg, const hgnn_heads *heads, hgnn_ctx **out) {
@@ -1153,6 +1163,32 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
   c->Tg = Tg;
   c->Tn = Tn;
   c->cfg.reserved = Tg + 256 * Tn + 65536 * kind; // part of the checkpoint's identity
+  // tensors of the packed vector, for the seeded initialisation
+  if (kind == HGNN_GC_CGCNN) {
+    c->init_tab.push_back(InitTensor{0, H, c->F0, false});
+    c->init_tab.push_back(InitTensor{(int64_t)H * c->F0, H, 1, true});
+  }
+  for (const LayerDesc &d : c->ld) {
+    if (kind == HGNN_GC_PNA) {
+      c->init_tab.push_back(InitTensor{d.oWm, H, 2 * d.F + c->Fe, false});
+      c->init_tab.push_back(InitTensor{d.obm, H, 1, true});
+      c->init_tab.push_back(InitTensor{d.oWp, H, d.F + 12 * H, false});
+      c->init_tab.push_back(InitTensor{d.obp, H, 1, true});
+    } else if (kind == HGNN_GC_SAGE) {
+      c->init_tab.push_back(InitTensor{d.oWm, H, 2 * d.F, false});
+      c->init_tab.push_back(InitTensor{d.obm, H, 1, true});
+    } else {
+      c->init_tab.push_back(InitTensor{d.oWm, 2 * H, 2 * H + c->Fe, false});
+      c->init_tab.push_back(InitTensor{d.obm, 2 * H, 1, true});
+    }
+  }
+  for (int t = 0; t < Tg + Tn; ++t) {
+    const int64_t o = off + (int64_t)t * node_head_size(H);
+    c->init_tab.push_back(InitTensor{o, H, H, false});
+    c->init_tab.push_back(InitTensor{o + (int64_t)H * H, H, 1, true});
+    c->init_tab.push_back(InitTensor{o + (int64_t)H * H + H, 1, H, false});
+    c->init_tab.push_back(InitTensor{o + (int64_t)H * H + 2 * H, 1, 1, true});
+  }
   c->off_head = off;
   off += (int64_t)Tg * node_head_size(H);
   c->off_node = off;
@@ -1356,6 +1392,24 @@ int hgnn_set_params(hgnn_ctx *c, const float *src, void *stream) {
     if (e != hipSuccess) return hip_fail(c, e, "copy params");
   }
   return stage_all(c, s);
+}
+
+int hgnn_init_params(hgnn_ctx *c, uint64_t seed, void *stream) {
+  HGNN_GUARD(c);
+  hipStream_t s = (hipStream_t)stream;
+  for (const InitTensor &t : c->init_tab) {
+    const int64_t n = (int64_t)t.rows * t.cols;
+    const float bound = t.bias ? 0.1f : (float)std::sqrt(6.0 / ((double)t.rows + t.cols));
+    hipError_t e = launch_init_uniform(c->params, t.off, n, bound, seed, s);
+    if (e != hipSuccess) return hip_fail(c, e, "init params");
+  }
+  return stage_all(c, s);
+}
+
+int hgnn_op_generation(const hgnn_ctx *c, int64_t *out) {
+  if (!c || !out) return fail(HGNN_EINVAL, "ctx and out are required");
+  *out = c->ex.generation;
+  return HGNN_OK;
 }
 
 int hgnn_debug_fail_after(hgnn_ctx *c, int32_t n) {
@@ -1570,12 +1624,21 @@ int hgnn_op_layer_forward(hgnn_ctx *c, int32_t l, const float *wl, const float *
   return layer_forward(c, c->ex, l, wl, h_in, h_out, s);
 }
 
-int hgnn_op_layer_backward(hgnn_ctx *c, int32_t l, const float *wl, const float *h_in,
-                           const float *h_out, const float *dh_out, float *dh_in,
-                           float *dwl, void *stream) {
+static int check_generation(const hgnn_ctx *c, int64_t generation) {
+  if (generation != c->ex.generation)
+    return fail(HGNN_EINVAL, "the batch changed since this forward (generation " +
+                                 std::to_string(generation) + ", now " +
+                                 std::to_string(c->ex.generation) + "): run the forward again");
+  return HGNN_OK;
+}
+
+int hgnn_op_layer_backward(hgnn_ctx *c, int64_t generation, int32_t l, const float *wl,
+                           const float *h_in, const float *h_out, const float *dh_out,
+                           float *dh_in, float *dwl, void *stream) {
   HGNN_GUARD(c);
   if (c->kind != HGNN_GC_PNA) return fail(HGNN_EINVAL, "per-operation layer entries are PNA-only");
   if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (int rc = check_generation(c, generation)) return rc;
   if (l < 0 || l >= c->L) return fail(HGNN_EINVAL, "layer out of range");
   if (!wl || !h_in || !h_out || !dh_out || !dwl) return fail(HGNN_EINVAL, "NULL buffer");
   hipStream_t s = (hipStream_t)stream;
@@ -1595,11 +1658,13 @@ int hgnn_op_head_forward(hgnn_ctx *c, const float *wh, const float *h, const flo
   return head_forward(c, c->ex, wh, h, target, pred, loss, (hipStream_t)stream);
 }
 
-int hgnn_op_head_backward(hgnn_ctx *c, const float *wh, const float *h, const float *target,
-                          const float *dpred, float *dh, float *dwh, void *stream) {
+int hgnn_op_head_backward(hgnn_ctx *c, int64_t generation, const float *wh, const float *h,
+                          const float *target, const float *dpred, float *dh, float *dwh,
+                          void *stream) {
   HGNN_GUARD(c);
   (void)h;
   if (!c->ex.prepared) return fail(HGNN_EINVAL, "call hgnn_op_prepare first");
+  if (int rc = check_generation(c, generation)) return rc;
   if (!wh || !dh || !dwh) return fail(HGNN_EINVAL, "NULL buffer");
   if (!dpred && !target) return fail(HGNN_EINVAL, "need dpred or targets");
   if (c->Tg != 1 || c->Tn != 0)

@@ -54,11 +54,20 @@ struct Exec {
   const float *xin = nullptr, *target = nullptr;
   const float *ynode = nullptr;  // node-level targets [N, Tn] of the last forward
   bool prepared = false;
+  int64_t generation = 0;       // advanced by every prepare (new batch state)
   bool x_padded = false;        // w.xpad holds xin, zero-padded (written at prepare)
   bool inference_only = false;  // no backward buffers, two rotating h slots
 };
 
 struct Server;
+
+// One tensor of the packed parameter vector, for the seeded initialisation:
+// weights [rows, cols] are Xavier-uniform, biases U(-0.1, 0.1).
+struct InitTensor {
+  int64_t off;
+  int rows, cols;
+  bool bias;
+};
 
 // packed size of one head: W1 [H, H], b1 [H], w2 [H], b2 [1]
 inline size_t node_head_size(int H) { return (size_t)H * H + 2 * (size_t)H + 1; }
@@ -91,6 +100,7 @@ struct hgnn_ctx {
   int L = 0, H = 0, F0 = 0, F0p = 0, Fe = 0, maxd = 0, prec = 0, recompute = 0;
   int64_t P = 0, off_head = 0;
   std::vector<hgnn::LayerDesc> ld;
+  std::vector<hgnn::InitTensor> init_tab; // packing order
   float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
   long long *step_dev = nullptr;
   hgnn::StageDesc *stage_tab = nullptr; // device table for the one-launch weight staging

@@ -77,7 +77,9 @@ class ServeStats(ctypes.Structure):
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 _SIGS = {
-    "hgnn_create": ([ctypes.POINTER(Config), ctypes.POINTER(_P)], _I),
+    "hgnn_create": ([ctypes.POINTER(Config), _P, ctypes.c_uint64, _P, ctypes.POINTER(_P)], _I),
+    "hgnn_init_params": ([_P, ctypes.c_uint64, _P], _I),
+    "hgnn_op_generation": ([_P, ctypes.POINTER(ctypes.c_int64)], _I),
     "hgnn_create_multitask": ([ctypes.POINTER(Config), ctypes.POINTER(Heads),
                                ctypes.POINTER(_P)], _I),
     "hgnn_forward_multitask": ([_P, ctypes.POINTER(CBatch), _P, _P, _P, _P, _I, _P], _I),
@@ -99,9 +101,9 @@ _SIGS = {
     "hgnn_set_state": ([_P, _P, ctypes.c_size_t], _I),
     "hgnn_op_prepare": ([_P, ctypes.POINTER(CBatch), _I, _P], _I),
     "hgnn_op_layer_forward": ([_P, _I, _P, _P, _P, _P], _I),
-    "hgnn_op_layer_backward": ([_P, _I, _P, _P, _P, _P, _P, _P, _P], _I),
+    "hgnn_op_layer_backward": ([_P, ctypes.c_int64, _I, _P, _P, _P, _P, _P, _P, _P], _I),
     "hgnn_op_head_forward": ([_P, _P, _P, _P, _P, _P, _P], _I),
-    "hgnn_op_head_backward": ([_P, _P, _P, _P, _P, _P, _P, _P], _I),
+    "hgnn_op_head_backward": ([_P, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P], _I),
     "hgnn_op_fetch": ([_P, _I, _I, _P, ctypes.c_size_t, _P], _I),
     "hgnn_serve_start": ([_P, ctypes.POINTER(ServeConfig)], _I),
     "hgnn_serve_submit": ([_P, ctypes.POINTER(CBatch), ctypes.POINTER(ctypes.c_uint64)], _I),
@@ -272,10 +274,13 @@ class Model:
                  max_degree: int = 4, precision: int = PREC_FP32, recompute: int = 0,
                  delta: float = 1.0, std_eps: float = 1e-5, graph_heads: int = 1,
                  node_heads: int = 0, graph_weights=None, node_weights=None,
-                 kind: str = "pna"):
+                 kind: str = "pna", init_params=None, seed: int = 0):
         """graph_heads / node_heads > 1 / > 0 build a multitask model (several
         graph-level heads, node-level heads, weighted loss); kind "sage" or
-        "cgcnn" selects the GraphSAGE or CGCNN layer kind (see the header)."""
+        "cgcnn" selects the GraphSAGE or CGCNN layer kind (see the header).
+        A single-head PNA model starts from init_params (packed [P]) or, when
+        it is None, from the library's seeded initialisation (seed); the
+        other kinds start at zero until set_params or init_params."""
         if kind not in KINDS:
             raise ValueError(f"kind must be one of {sorted(KINDS)}")
         self.kind = kind
@@ -292,7 +297,12 @@ class Model:
             _check(lib().hgnn_create_gc(ctypes.byref(self.cfg), KINDS[kind], ctypes.byref(hd),
                                         ctypes.byref(h)))
         elif graph_heads == 1 and node_heads == 0 and graph_weights is None:
-            _check(lib().hgnn_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+            init = None
+            if init_params is not None:
+                init = torch.as_tensor(init_params, dtype=torch.float32).cuda().contiguous()
+            _check(lib().hgnn_create(ctypes.byref(self.cfg), _ptr(init), seed, _stream(),
+                                     ctypes.byref(h)))
+            torch.cuda.current_stream().synchronize()
         else:
             gw = None if graph_weights is None else np.asarray(graph_weights, np.float32)
             nw = None if node_weights is None else np.asarray(node_weights, np.float32)
@@ -356,6 +366,18 @@ class Model:
         p, g = _P(), _P()
         _check(lib().hgnn_param_views(self.handle, ctypes.byref(p), ctypes.byref(g)))
         return _DeviceView(p.value, self.num_params, self), _DeviceView(g.value, self.num_params, self)
+
+    def init_params(self, seed: int):
+        """The library's seeded initialisation (Xavier-uniform weights, U(+-0.1)
+        biases from a SplitMix64 counter generator)."""
+        _check(lib().hgnn_init_params(self.handle, seed, _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def generation(self) -> int:
+        """Count of batches prepared so far (each forward prepares one)."""
+        g = ctypes.c_int64()
+        _check(lib().hgnn_op_generation(self.handle, ctypes.byref(g)))
+        return int(g.value)
 
     def debug_fail_after(self, n: int):
         """Test hook: the n-th layer call from now fails as a launch would."""
@@ -477,6 +499,9 @@ class PNALayerFunction(torch.autograd.Function):
                                            _ptr(h_out), _stream()))
         ctx.save_for_backward(h_in, w_layer, h_out)
         ctx.model, ctx.layer = model, layer
+        # the context's stored messages, aggregates and CSR belong to this
+        # batch; the library refuses the backward once another is prepared
+        ctx.generation = model.generation()
         return h_out
 
     @staticmethod
@@ -486,9 +511,9 @@ class PNALayerFunction(torch.autograd.Function):
         dh_out = dh_out.contiguous()
         dh_in = torch.empty_like(h_in) if ctx.needs_input_grad[0] else None
         dw = torch.empty_like(w_layer)
-        _check(lib().hgnn_op_layer_backward(model.handle, ctx.layer, _ptr(w_layer), _ptr(h_in),
-                                            _ptr(h_out), _ptr(dh_out), _ptr(dh_in), _ptr(dw),
-                                            _stream()))
+        _check(lib().hgnn_op_layer_backward(model.handle, ctx.generation, ctx.layer,
+                                            _ptr(w_layer), _ptr(h_in), _ptr(h_out),
+                                            _ptr(dh_out), _ptr(dh_in), _ptr(dw), _stream()))
         return dh_in, dw, None, None
 
 
@@ -504,6 +529,7 @@ class PoolHeadFunction(torch.autograd.Function):
                                           _ptr(pred), None, _stream()))
         ctx.save_for_backward(h, w_head)
         ctx.model = model
+        ctx.generation = model.generation()
         return pred
 
     @staticmethod
@@ -512,8 +538,9 @@ class PoolHeadFunction(torch.autograd.Function):
         dpred = dpred.contiguous()
         dh = torch.empty_like(h)
         dw = torch.empty_like(w_head)
-        _check(lib().hgnn_op_head_backward(ctx.model.handle, _ptr(w_head), _ptr(h), None,
-                                           _ptr(dpred), _ptr(dh), _ptr(dw), _stream()))
+        _check(lib().hgnn_op_head_backward(ctx.model.handle, ctx.generation, _ptr(w_head),
+                                           _ptr(h), None, _ptr(dpred), _ptr(dh), _ptr(dw),
+                                           _stream()))
         return dh, dw, None
 
 
@@ -556,11 +583,17 @@ class ModelFunction(torch.autograd.Function):
         pred = torch.empty(batch.num_graphs, dtype=torch.float32, device=params.device)
         model.forward(batch, pred)
         ctx.model = model
+        ctx.generation = model.generation()
+        ctx.params = params
         return pred
 
     @staticmethod
     def backward(ctx, dpred):
         model = ctx.model
+        # hgnn_backward differentiates the context's last forward
+        if model.generation() != ctx.generation:
+            raise HgnnError(EINVAL, "another forward ran on this model since this one: "
+                                    "run the forward again before its backward")
         model.backward(dpred.contiguous())
         return model.grads(), None, None
 

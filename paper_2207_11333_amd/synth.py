@@ -231,6 +231,38 @@ def init_params(shape: ModelShape, seed: int) -> np.ndarray:
     return np.concatenate(chunks).astype(np.float32)
 
 
+_SM_GAMMA = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def splitmix64_at(seed: int, j: np.ndarray) -> np.ndarray:
+    """Output j (0-based) of SplitMix64 started from `seed` (Steele, Lea and
+    Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014):
+    mix(seed + (j + 1) * gamma), as uint64 (numpy wraps modulo 2^64)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & _M64) + (np.asarray(j, np.uint64) + np.uint64(1)) * np.uint64(_SM_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def counter_init_params(tensor_shapes, seed: int) -> np.ndarray:
+    """The device-side seeded initialisation, written out on the host: element
+    j of the packed vector is bound * k * 2^-23 (FP32, one rounding) with
+    k = (z >> 40) - 2^23 and z = splitmix64_at(seed, j); bound is
+    sqrt(6 / (rows + cols)) for a weight [rows, cols] (Xavier-uniform) and 0.1
+    for a bias (1-D shape)."""
+    chunks, off = [], 0
+    for _, shp in tensor_shapes:
+        n = int(np.prod(shp))
+        j = np.arange(off, off + n, dtype=np.uint64)
+        k = (splitmix64_at(seed, j) >> np.uint64(40)).astype(np.int64) - (1 << 23)
+        bound = np.float32(np.sqrt(6.0 / (shp[0] + shp[1]))) if len(shp) == 2 else np.float32(0.1)
+        chunks.append(bound * (k.astype(np.float32) * np.float32(2.0 ** -23)))
+        off += n
+    return np.concatenate(chunks).astype(np.float32)
+
+
 def gc_tensor_shapes(kind: str, num_layers: int, hidden: int, node_feat: int = NODE_FEAT,
                      edge_feat: int = 1, graph_heads: int = 1, node_heads: int = 0):
     """[(name, shape)] of a GraphSAGE ("sage") or CGCNN ("cgcnn") model in

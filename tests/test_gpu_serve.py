@@ -193,3 +193,74 @@ def test_training_step_graph_replay_matches_eager():
         assert torch.equal(pred_a, pred_b)
     ma.close()
     mb.close()
+
+
+def test_serving_workload_shapes_match_oracle():
+    """Requests of the serving workload's own shape: 1-256 molecules of 5-70
+    atoms each (plus one of the largest size, 256 molecules of 70 atoms =
+    17,920 atoms), BF16 model, the benchmark's lane and bucket capacities
+    (32,768-atom batches) and captured graphs.  Every request's predictions
+    are checked against the FP64 oracle (2e-2) and equal their alone values
+    when submitted together (packed into the largest bucket)."""
+    m, params, sw = _model(1)
+    rng = np.random.default_rng(sw["request_seed"])
+    reqs = [synth.make_request(rng, sw["mol_lo"], sw["mol_hi"], sw["n_lo"], sw["n_hi"],
+                               sw["edge_feat"]) for _ in range(7)]
+    reqs.append(synth.make_batch(4321, 256, 70, 70, sw["edge_feat"]))
+    say(f"serving shapes: {[r.num_graphs for r in reqs]} molecules, "
+        f"{[r.num_nodes for r in reqs]} atoms")
+    m.serve_start(hbm_budget_bytes=16 << 30, max_batch_nodes=32768, max_batch_edges=73728,
+                  max_batch_graphs=1024, num_lanes=4, use_graphs=1)
+    alone = []
+    for r in reqs:
+        t = m.serve_submit(r)
+        assert t >= 0
+        alone += _wait(m, [t], [r.num_graphs])
+    tickets = [m.serve_submit(r) for r in reqs]
+    assert min(tickets) >= 0
+    mixed = _wait(m, tickets, [r.num_graphs for r in reqs])
+    st = m.serve_stats()
+    say(f"  stats {st}")
+    assert st["graph_replays"] > 0
+    worst = max(rel(a, b) for a, b in zip(mixed, alone))
+    say(f"  alone vs mixed worst rel {worst:.2e}")
+    assert worst <= 2e-2
+    for i, r in enumerate(reqs):
+        rec = oracle.forward(params, r, sw["num_layers"], sw["hidden"], sw["delta"],
+                             with_loss=False)
+        e_mixed, e_alone = rel(mixed[i], rec.y), rel(alone[i], rec.y)
+        say(f"  request {i} ({r.num_graphs} molecules): vs oracle rel {e_mixed:.2e} "
+            f"(alone {e_alone:.2e})")
+        assert e_mixed <= 2e-2 and e_alone <= 2e-2
+    m.serve_stop()
+    m.close()
+
+
+def test_non_finite_request_is_rejected_alone():
+    """A request with a NaN in x or an infinite edge attribute is refused at
+    submit (EINVAL); requests submitted around it complete with their alone
+    results."""
+    hg = _hg()
+    m, _, _ = _model(0)
+    m.serve_start(hbm_budget_bytes=1 << 30, max_batch_nodes=2048, max_batch_edges=4608,
+                  max_batch_graphs=128, num_lanes=2, use_graphs=1)
+    good = _requests(4, 99)
+    alone = []
+    for r in good:
+        t = m.serve_submit(r)
+        alone += _wait(m, [t], [r.num_graphs])
+    bad_x = synth.make_batch(5, 2, 5, 9, 1)
+    bad_x.x[3, 2] = np.nan
+    bad_e = synth.make_batch(6, 2, 5, 9, 1)
+    bad_e.edge_attr[1, 0] = np.inf
+    tickets = [m.serve_submit(good[0]), m.serve_submit(good[1])]
+    for bad in (bad_x, bad_e):
+        with pytest.raises(hg.HgnnError) as e:
+            m.serve_submit(bad)
+        assert e.value.code == hg.EINVAL and "non-finite" in str(e.value)
+    tickets += [m.serve_submit(good[2]), m.serve_submit(good[3])]
+    got = _wait(m, tickets, [r.num_graphs for r in good])
+    for a, b in zip(got, alone):
+        assert rel(a, b) <= 1e-5
+    m.serve_stop()
+    m.close()

@@ -39,7 +39,7 @@ def test_create_rejects_bad_config_before_touching_a_device(field, value, msg):
     cfg = hgnn.Config(3, 64, 9, 1, 4, 0, 0, 0, 1.0, 1e-5)
     setattr(cfg, field, value)
     h = ctypes.c_void_p()
-    rc = hgnn.lib().hgnn_create(ctypes.byref(cfg), ctypes.byref(h))
+    rc = hgnn.lib().hgnn_create(ctypes.byref(cfg), None, 0, None, ctypes.byref(h))
     assert rc == hgnn.EINVAL
     assert msg in hgnn.lib().hgnn_last_error().decode()
     assert not h.value

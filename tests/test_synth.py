@@ -79,3 +79,25 @@ def test_select_and_concat_roundtrip():
     r = synth.select_graphs(b, range(5))
     for k in ("graph_ptr", "x", "edge_index", "edge_attr", "y"):
         assert np.array_equal(getattr(r, k), getattr(b, k))
+
+
+def test_splitmix64_reference_values():
+    """SplitMix64 from seed 0 (published test values of the generator as used
+    to seed xoshiro/xorshift generators)."""
+    got = synth.splitmix64_at(0, np.arange(3, dtype=np.uint64))
+    assert [int(v) for v in got] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                     0x06C45D188009454F]
+
+
+def test_counter_init_bounds_and_moments():
+    shape = synth.ModelShape(2, 32, 9, 1)
+    p = synth.counter_init_params(shape.tensor_shapes(), 7)
+    assert p.dtype == np.float32 and p.shape[0] == shape.num_params()
+    for name, (off, shp) in shape.offsets().items():
+        v = p[off:off + int(np.prod(shp))].astype(np.float64)
+        a = np.sqrt(6.0 / (shp[0] + shp[1])) if len(shp) == 2 else 0.1
+        assert np.all(np.abs(v) <= a * (1 + 1e-7)), name
+        if v.size > 1000:
+            # uniform on [-a, a): mean 0, variance a^2 / 3
+            assert abs(v.mean()) < 0.05 * a and abs(v.var() / (a * a / 3) - 1) < 0.05, name
+    assert not np.array_equal(p, synth.counter_init_params(shape.tensor_shapes(), 8))
