@@ -214,6 +214,31 @@ int hgnn_backward(hgnn_ctx *ctx, const float *dpred_dev, void *stream);
 int hgnn_adam_step(hgnn_ctx *ctx, float lr, float beta1, float beta2,
                    float eps, float weight_decay, void *stream);
 
+/* ---- allocation-free inference forward ---------------------------------- */
+/* For callers that cannot allocate device memory: code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The forward
+ * pass of hgnn_forward (same kernels; no activations are kept for a backward
+ * pass) for a PNA model without node heads, whose whole batch workspace (size
+ * header, error word, CSR, padded input, two rotating layer outputs, one
+ * layer's messages and aggregates, head buffers, split-K partials) lies in one
+ * static device array of the library: hgnn_noalloc_max_bytes() = 64 MiB,
+ * held by each GPU the library runs on until the process ends.  The call
+ * allocates nothing, on the device or the host, outside its error paths.
+ * pred_dev [B] and loss_dev [1] (optional, needs batch->y) as in
+ * hgnn_forward; flags as there (HGNN_VALIDATE synchronises).  EINVAL, with
+ * nothing launched, when the batch needs more than the array holds
+ * (hgnn_noalloc_bytes gives the need: 27.6 MB for 128 molecules of 4.5k atoms
+ * at H = 128, 6 layers).  The array is shared by every call on one GPU
+ * and keeps the last call's contents: calls that overlap on one GPU race,
+ * whatever their context or stream.  The context's training state (the last
+ * hgnn_forward, the gradients) is left alone. */
+int hgnn_forward_noalloc(hgnn_ctx *ctx, const hgnn_batch *batch, float *pred_dev,
+                         float *loss_dev, int32_t flags, void *stream);
+/* Workspace bytes hgnn_forward_noalloc needs for a batch of these sizes. */
+int hgnn_noalloc_bytes(const hgnn_ctx *ctx, int32_t num_graphs, int32_t num_nodes,
+                       int32_t num_edges, int64_t *out);
+int64_t hgnn_noalloc_max_bytes(void);
+
 /* ---- checkpoint --------------------------------------------------------- */
 
 /* Serialise config, step count, parameters and AdamW moments into a host

@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 using namespace hgnn;
@@ -125,9 +126,10 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
       w.A.assign(nstore, nullptr);
       w.args.assign(nstore, nullptr);
     }
+    // the arg decisions are read only by the backward pass
     for (int l = 0; l < nstore && ok; ++l)
       ok = f(w.PQ[l], (size_t)capN * 2 * H) && f(w.A[l], (size_t)capN * 4 * H) &&
-           f(w.args[l], (size_t)capN * 2 * H);
+           (inference || f(w.args[l], (size_t)capN * 2 * H));
   } else {
     if (w.gcA.size() != (size_t)L) w.gcA.assign(L, nullptr);
     for (int l = 0; l < L && ok; ++l) {
@@ -172,6 +174,26 @@ size_t work_bytes(const hgnn_ctx *c, int B, int N, int E, bool inference_only) {
     return true;
   });
   return bytes;
+}
+
+size_t carve_work(const hgnn_ctx *c, Exec &ex, int B, int N, int E, char *base,
+                  size_t bytes) {
+  Work &w = ex.w;
+  size_t off = 0;
+  const bool ok = for_each_buffer(c, w, B, N, E, /*inference=*/true, [&](auto &p, size_t n) {
+    const size_t b = n * sizeof(*p);
+    const size_t step = b < 256 ? 256 : (b + 255) / 256 * 256;
+    if (off + step > bytes) return false;
+    p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + off);
+    off += step;
+    return true;
+  });
+  if (!ok) return 0;
+  w.capB = B;
+  w.capN = N;
+  w.capE = E;
+  w.stored_layer = -1;
+  return off;
 }
 
 int ensure_work(hgnn_ctx *c, Exec &ex, int B, int N, int E) {
@@ -1206,6 +1228,18 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
     delete c;
     return fail(HGNN_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
   }
+  // the allocation-free forward's workspace: this device's scratch array,
+  // looked up once per device; its pointer vectors are sized here so that
+  // carving the workspace allocates nothing on the host either
+  if (int rc = noalloc_init(c->dev)) {
+    delete c;
+    return rc;
+  }
+  c->na.inference_only = true;
+  c->na.w.hbuf.assign(2, nullptr);
+  c->na.w.PQ.assign(1, nullptr);
+  c->na.w.A.assign(1, nullptr);
+  c->na.w.args.assign(1, nullptr);
 #define HGNN_CALLOC(p, n)                                                               \
   do {                                                                                 \
     if (dalloc(p, (size_t)(n)) != hipSuccess) {                                         \

@@ -130,6 +130,9 @@ struct hgnn_ctx {
   bool staged_from_params = false;
   float *part = nullptr;
   hgnn::Exec ex; // the training path's batch state
+  // batch state of hgnn_forward_noalloc: its buffers are carved from the
+  // device's scratch array (noalloc.hip) and never freed
+  hgnn::Exec na;
   int sticky = 0;
   int fail_after = 0; // test-only failure injection (hgnn_debug_fail_after)
   hgnn::Server *server = nullptr;
@@ -151,6 +154,14 @@ void serve_shutdown(hgnn_ctx *c);
 
 // forward-path building blocks shared by training and serving
 int ensure_work(hgnn_ctx *c, Exec &ex, int B, int N, int E);
+// Point every inference buffer of ex into [base, base + bytes) (256-byte
+// aligned pieces, nothing allocated): the bytes used, 0 if they do not fit.
+size_t carve_work(const hgnn_ctx *c, Exec &ex, int B, int N, int E, char *base,
+                  size_t bytes);
+int check_batch_host(hgnn_ctx *c, const hgnn_batch *b);
+// Look up this device's scratch array of the allocation-free forward (once
+// per device; the device must be current).
+int noalloc_init(int dev);
 void free_work(Exec &ex);
 size_t work_bytes(const hgnn_ctx *c, int B, int N, int E, bool inference_only);
 int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_in,

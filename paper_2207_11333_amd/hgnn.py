@@ -113,6 +113,9 @@ _SIGS = {
     "hgnn_timer_start": ([_P, _I, _I], _I),
     "hgnn_timer_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I)], _I),
     "hgnn_calib_copy": ([_P, _P, ctypes.c_int64, _P], _I),
+    "hgnn_forward_noalloc": ([_P, ctypes.POINTER(CBatch), _P, _P, _I, _P], _I),
+    "hgnn_noalloc_bytes": ([_P, _I, _I, _I, ctypes.POINTER(ctypes.c_int64)], _I),
+    "hgnn_noalloc_max_bytes": ([], ctypes.c_int64),
     "hgnn_last_error": ([], ctypes.c_char_p),
     "hgnn_store_open": ([ctypes.c_char_p, _I, _I, ctypes.POINTER(_P)], _I),
     "hgnn_store_info_get": ([_P, _P], _I),
@@ -402,6 +405,20 @@ class Model:
             _check(lib().hgnn_forward_multitask(self.handle, ctypes.byref(cb), _ptr(y_node),
                                                 _ptr(pred), _ptr(pred_node), _ptr(loss), flags,
                                                 _stream()))
+
+    def forward_noalloc(self, batch: DeviceBatch, pred: torch.Tensor,
+                        loss: Optional[torch.Tensor] = None, validate: bool = False):
+        """Inference forward whose workspace is the library's static device
+        array (no allocation); leaves the training state alone."""
+        cb = batch.cstruct()
+        _check(lib().hgnn_forward_noalloc(self.handle, ctypes.byref(cb), _ptr(pred), _ptr(loss),
+                                          VALIDATE if validate else 0, _stream()))
+
+    def noalloc_bytes(self, num_graphs: int, num_nodes: int, num_edges: int) -> int:
+        n = ctypes.c_int64()
+        _check(lib().hgnn_noalloc_bytes(self.handle, num_graphs, num_nodes, num_edges,
+                                        ctypes.byref(n)))
+        return int(n.value)
 
     def backward(self, dpred: Optional[torch.Tensor] = None):
         _check(lib().hgnn_backward(self.handle, _ptr(dpred), _stream()))
