@@ -57,13 +57,30 @@ __device__ __forceinline__ void put(void *dst, void *dst_lo, size_t i, float v) 
 //  WpTA  [4H, 3H]     WpTA[c, j H + m] = W^p[m, F + 4 H j + c]
 //  WhdsT [Fp, 3H]     [W^p[:, c]; W^m[:, c]; W^m[:, F + c]]^T, zero rows c >= F
 //  weT   [Fe, H]      weT[f, c] = W^m[c, 2F + f] (FP32 in both precisions)
+// With nb degree buckets the update copies are per bucket q instead:
+//  Wpp   [nb][H, Fp+4H]  [W_h padded | W_eff(q)]
+//  WpTA  [nb][4H, H]     W_eff(q)^T
+// where W_eff(q)[m, c] = W_0 + s+(q) W_+ + s-(q) W_- (blocks of W^p at
+// columns F + c, F + 4H + c, F + 8H + c), evaluated in FP32 in that order
+// with the FP32 scalers of the table.
+__device__ __forceinline__ float w_eff(const float *__restrict__ Wp, int ldp, int F, int H,
+                                       const float *__restrict__ table, int q, int m, int c) {
+  const float *row = Wp + (size_t)m * ldp + F + c;
+  return fmaf(table[2 * q + 1], row[8 * H], fmaf(table[2 * q], row[4 * H], row[0]));
+}
+
 template <typename T>
 __device__ __forceinline__ void stage_elem(const float *__restrict__ Wm,
                                            const float *__restrict__ Wp, int F, int Fp,
-                                           int H, int Fe, const StageOut &o, long long t) {
+                                           int H, int Fe, int nb,
+                                           const float *__restrict__ table,
+                                           const StageOut &o, long long t) {
   const int ldm = 2 * F + Fe, ldp = F + 12 * H;
-  const long long n1 = 2LL * H * Fp, n2 = (long long)H * (Fp + 12 * H);
-  const long long n3 = 12LL * H * H, n4 = 3LL * Fp * H, n5 = (long long)Fe * H;
+  const int wu = nb ? Fp + 4 * H : Fp + 12 * H; // row width of the update copy
+  const long long n1 = 2LL * H * Fp;
+  const long long n2 = (long long)(nb ? nb : 1) * H * wu;
+  const long long n3 = nb ? 4LL * nb * H * H : 12LL * H * H;
+  const long long n4 = 3LL * Fp * H, n5 = (long long)Fe * H;
   if (t < n1) {
     const int r = (int)(t / Fp), c = (int)(t % Fp);
     float v = 0.f;
@@ -71,16 +88,25 @@ __device__ __forceinline__ void stage_elem(const float *__restrict__ Wm,
     put<T>(o.hi[0], o.lo[0], t, v);
   } else if (t < n1 + n2) {
     const long long u = t - n1;
-    const int r = (int)(u / (Fp + 12 * H)), c = (int)(u % (Fp + 12 * H));
+    const long long rr = u / wu;
+    const int c = (int)(u % wu);
+    const int q = (int)(rr / H), r = (int)(rr % H);
     float v = 0.f;
     if (c < Fp) { if (c < F) v = Wp[(size_t)r * ldp + c]; }
+    else if (nb) v = w_eff(Wp, ldp, F, H, table, q, r, c - Fp);
     else v = Wp[(size_t)r * ldp + F + (c - Fp)];
     put<T>(o.hi[1], o.lo[1], u, v);
   } else if (t < n1 + n2 + n3) {
     const long long u = t - n1 - n2;
-    const int r = (int)(u / (3 * H)), c = (int)(u % (3 * H));
-    const int j = c / H, m = c % H;
-    put<T>(o.hi[2], o.lo[2], u, Wp[(size_t)m * ldp + F + 4 * H * j + r]);
+    if (nb) {
+      const int q = (int)(u / (4LL * H * H));
+      const int r = (int)((u / H) % (4 * H)), m = (int)(u % H);
+      put<T>(o.hi[2], o.lo[2], u, w_eff(Wp, ldp, F, H, table, q, m, r));
+    } else {
+      const int r = (int)(u / (3 * H)), c = (int)(u % (3 * H));
+      const int j = c / H, m = c % H;
+      put<T>(o.hi[2], o.lo[2], u, Wp[(size_t)m * ldp + F + 4 * H * j + r]);
+    }
   } else if (t < n1 + n2 + n3 + n4) {
     const long long u = t - n1 - n2 - n3;
     const int r = (int)(u / (3 * H)), c = (int)(u % (3 * H));
@@ -102,17 +128,19 @@ __device__ __forceinline__ void stage_elem(const float *__restrict__ Wm,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F, int Fp,
-              int H, int Fe, StageOut o) {
-  stage_elem<T>(Wm, Wp, F, Fp, H, Fe, o, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+              int H, int Fe, int nb, const float *__restrict__ table, StageOut o) {
+  stage_elem<T>(Wm, Wp, F, Fp, H, Fe, nb, table, o,
+                (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Every layer in one launch (blockIdx.y = layer); optionally advances the
 // AdamW step counter once the preceding update has been applied.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_stage_all(const StageDesc *__restrict__ tab, int H, int Fe, long long *bump) {
+k_stage_all(const StageDesc *__restrict__ tab, int H, int Fe, int nb,
+            const float *__restrict__ table, long long *bump) {
   const StageDesc &d = tab[blockIdx.y];
-  stage_elem<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, d.o,
+  stage_elem<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, nb, table, d.o,
                 (long long)blockIdx.x * blockDim.x + threadIdx.x);
   if (bump && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *bump += 1;
 }
@@ -141,29 +169,30 @@ hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_
   return hipGetLastError();
 }
 
-static long long stage_total(int F, int Fp, int H, int Fe) {
-  (void)F;
-  return 2LL * H * Fp + (long long)H * (Fp + 12 * H) + 12LL * H * H + 3LL * Fp * H +
-         (long long)Fe * H;
+static long long stage_total(int Fp, int H, int Fe, int nb) {
+  const long long nbk = nb ? nb : 1;
+  return 2LL * H * Fp + nbk * H * (Fp + (nb ? 4 : 12) * H) + (nb ? 4 * nbk : 12LL) * H * H +
+         3LL * Fp * H + (long long)Fe * H;
 }
 
-hipError_t launch_stage_all(const StageDesc *tab, int L, int maxFp, int H, int Fe,
-                            int to_bf16, long long *bump, hipStream_t s) {
-  const dim3 grid(cdiv(stage_total(0, maxFp, H, Fe), 256), L);
+hipError_t launch_stage_all(const StageDesc *tab, int L, int maxFp, int H, int Fe, int nb,
+                            const float *table, int to_bf16, long long *bump, hipStream_t s) {
+  const dim3 grid(cdiv(stage_total(maxFp, H, Fe, nb), 256), L);
   if (to_bf16)
-    k_stage_all<__bf16><<<grid, 256, 0, s>>>(tab, H, Fe, bump);
+    k_stage_all<__bf16><<<grid, 256, 0, s>>>(tab, H, Fe, nb, table, bump);
   else
-    k_stage_all<float><<<grid, 256, 0, s>>>(tab, H, Fe, bump);
+    k_stage_all<float><<<grid, 256, 0, s>>>(tab, H, Fe, nb, table, bump);
   return hipGetLastError();
 }
 
 hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp, int H,
-                              int Fe, const StageOut &o, int to_bf16, hipStream_t s) {
-  const long long total = stage_total(F, Fp, H, Fe);
+                              int Fe, int nb, const float *table, const StageOut &o,
+                              int to_bf16, hipStream_t s) {
+  const long long total = stage_total(Fp, H, Fe, nb);
   if (to_bf16)
-    k_stage_layer<__bf16><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, o);
+    k_stage_layer<__bf16><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
   else
-    k_stage_layer<float><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, o);
+    k_stage_layer<float><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
   return hipGetLastError();
 }
 

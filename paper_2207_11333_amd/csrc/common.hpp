@@ -39,6 +39,20 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 // ------------------------------------------------------------------------
 constexpr int kMaxSeg = 5;
 
+// Degree buckets of the update linear.  The PNA scalers of a node depend on
+// its in-degree d alone, so [A || s+ A || s- A] W^T = A W_eff(d)^T with
+// W_eff(d) = W_0 + s+(d) W_+ + s-(d) W_- (one [H, 4H] matrix per degree).
+// Nodes are grouped by degree (a stable permutation built with the CSR) and
+// every row tile or node chunk of the update GEMMs holds one degree only, so
+// the K range of the update linear and of its input gradient shrinks from
+// F + 12H to F + 4H and from 3H to H.  Models whose max_degree + 1 exceeds
+// kMaxBuckets keep the concatenated form.
+constexpr int kMaxBuckets = 16;
+// ints per block record of the multi-block CSR scan: the in- and out-degree
+// sums and one count per bucket
+constexpr int kScanRec = 2 + kMaxBuckets;
+constexpr int kScanNodes = 1024; // nodes per block of that scan
+
 struct SegA {
   const float *ptr;   // [rows, ld] row-major, k-contiguous
   const float *scale; // per-row scale or nullptr
@@ -78,6 +92,14 @@ struct GemmNT {
   // each in turn -- so a workgroup rereads a tile while it is still cached
   // instead of streaming the operand once per segment.  0: in order.
   int ileave_n;
+  // Degree-bucketed rows (perm non-null): row tiles are taken per bucket q
+  // over the permuted rows [brow[q], brow[q+1]) (brow [nb + 1], device);
+  // a row r reads and writes node perm[r]; bucket q multiplies with
+  // B + q * bstride (and B_lo + q * bstride).
+  const int *perm;
+  const int *brow;
+  int nb;
+  long long bstride;
 };
 
 // Weight-gradient form, reduction over rows i (nodes):
@@ -98,8 +120,29 @@ struct GemmTN {
   SegY seg[kMaxSeg];
   int nseg;
   int Ncols;       // total columns of Yv
-  float *P;        // partials [splits, M, Ncols]
+  float *P;        // partials [splits (+ nb), M, Ncols]
   int splits;
+  // Degree-bucketed chunks (perm non-null): the node chunks are taken per
+  // bucket over the permuted rows (as in GemmNT), nb more partials than
+  // splits; chunk z writes zscale[2 z] = s+(q), zscale[2 z + 1] = s-(q) of
+  // its bucket q from the scaler table (0, 0 for an empty chunk).
+  const int *perm;
+  const int *brow;
+  int nb;
+  const float *table;
+  float *zscale;
+};
+
+// Ordered reduction of the bucketed update weight gradient: P has Z
+// partials of [M = H, Ncols = Fp + 4H + 4] (columns: h block, A block, the
+// sum column, padding); the A block gives W_0, W_+ and W_- as the plain and
+// the s+, s- weighted sums over the chunks.
+struct ReduceUpd {
+  const float *P;
+  const float *zscale; // [Z][2]
+  int Z, M, Ncols, F, Fp, H;
+  float *dWp;          // [H, F + 12H] packed
+  float *dbp;          // [H]
 };
 
 // Scatter of reduced partials into the packed gradient vector.  Columns
@@ -140,6 +183,11 @@ struct CsrBufs {
   float *csr_e;       // [E, Fe] edge attributes in CSR order
   float *sp, *sm;     // per-node degree scalers
   int *err;           // error word
+  // degree buckets (nb > 0): perm [N] nodes in (degree, id) order, brow
+  // [nb + 1] bucket offsets into perm; scan [kScanRec per block] scratch of
+  // the multi-block scan
+  int *perm, *brow, *scan;
+  int nb;
 };
 // sets the batch sizes; also zeroes *err when err is non-null
 hipError_t launch_set_dims(Dims *d, int B, int N, int E, int *err, hipStream_t s);
@@ -166,10 +214,12 @@ hipError_t launch_calib_copy(const float *src, float *dst, long long n, hipStrea
 // Split count launch_gemm_nt will use, and the partial buffer it needs.
 int nt_splits(int capM, int Ncols, int Ktot, int precision);
 size_t nt_partial_floats(int capM, int Ncols, int Ktot, int precision);
+// Grid capacity: g.splits chunks, plus g.nb when bucketed.
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
-                          hipStream_t s);
+                          hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // reduce.hip
 hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s);
+hipError_t launch_reduce_upd(const ReduceUpd &r, hipStream_t s);
 hipError_t launch_reduce_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s);
 
 // aggregate.hip
@@ -245,11 +295,14 @@ struct StageDesc {
   int F, Fp;
   StageOut o;
 };
+// nb > 0: the update-linear copies are per degree bucket (W_eff from the
+// scaler table, see kMaxBuckets), else concatenated.
 hipError_t launch_stage_all(const StageDesc *tab, int L, int maxFp, int H, int Fe,
-                            int to_bf16, long long *bump, hipStream_t s);
+                            int nb, const float *table, int to_bf16, long long *bump,
+                            hipStream_t s);
 hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp,
-                              int H, int Fe, const StageOut &o, int to_bf16,
-                              hipStream_t s);
+                              int H, int Fe, int nb, const float *table, const StageOut &o,
+                              int to_bf16, hipStream_t s);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
 // p[off + t] for t < n: bound * U[-1, 1) from SplitMix64(seed) at index off + t
 hipError_t launch_init_uniform(float *p, int64_t off, int64_t n, float bound, uint64_t seed,

@@ -89,9 +89,14 @@ __global__ void k_csr_count(const Dims *__restrict__ dims,
   atomicAdd(&cnt_out[s], 1);
 }
 
-// One workgroup: exclusive scans of both counters, degrees, scalers, degree
-// check; the counters are reset to zero for use as fill cursors.
-constexpr int kScanThreads = 1024;
+// Exclusive scans of both degree counters (rowptr, srcptr) over all nodes in
+// three passes, no workgroup waiting on another: per block of kScanNodes
+// nodes the counter sums and the node count of every degree bucket
+// (k_scan_count); one workgroup turns those into block offsets and bucket
+// offsets (k_scan_top); every block then scans its own nodes again, adds its
+// offsets and writes rowptr, srcptr, degrees, scalers and, with degree
+// buckets, each node's place in the (degree, node id) order (k_scan_apply).
+constexpr int kScanTop = 1024;
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -103,70 +108,184 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-__global__ void __launch_bounds__(kScanThreads)
-k_csr_scan(const Dims *__restrict__ dims, int *__restrict__ cnt_in,
-           int *__restrict__ cnt_out, int *__restrict__ rowptr,
-           int *__restrict__ srcptr, int *__restrict__ deg,
-           const float *__restrict__ table, float *__restrict__ sp,
-           float *__restrict__ sm, int max_degree, int *__restrict__ err) {
-  __shared__ int wsum[2][kScanThreads / 64];
-  __shared__ int carry[2];
+__device__ __forceinline__ int bucket_of(int d, int max_degree) {
+  return d < max_degree ? d : max_degree; // clamped: a bad degree is flagged elsewhere
+}
+
+__global__ void __launch_bounds__(256)
+k_scan_count(const Dims *__restrict__ dims, const int *__restrict__ cnt_in,
+             const int *__restrict__ cnt_out, int max_degree, int nb,
+             int *__restrict__ scan) {
+  __shared__ int s_b[kMaxBuckets];
+  __shared__ int s_w[2][4];
   const int N = dims->N;
+  const int base = blockIdx.x * kScanNodes;
+  if (base >= N) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid == 0) { carry[0] = 0; carry[1] = 0; }
+  if (tid < kMaxBuckets) s_b[tid] = 0;
   __syncthreads();
-  int bad = 0;
-  for (int base = 0; base < N; base += kScanThreads * 4) {
-    int vi[4], vo[4];
-    int si = 0, so = 0;
+  int si = 0, so = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int i = base + tid * 4 + j;
-      vi[j] = i < N ? cnt_in[i] : 0;
-      vo[j] = i < N ? cnt_out[i] : 0;
-      si += vi[j];
-      so += vo[j];
+  for (int j = 0; j < 4; ++j) {
+    const int i = base + 4 * tid + j;
+    if (i < N) {
+      const int vi = cnt_in[i];
+      si += vi;
+      so += cnt_out[i];
+      if (nb) atomicAdd(&s_b[bucket_of(vi, max_degree)], 1); // an order-free count
     }
-    const int ii = wave_incl_scan(si), io = wave_incl_scan(so);
-    if (lane == 63) { wsum[0][wid] = ii; wsum[1][wid] = io; }
+  }
+  si = wave_incl_scan(si);
+  so = wave_incl_scan(so);
+  if (lane == 63) {
+    s_w[0][wid] = si;
+    s_w[1][wid] = so;
+  }
+  __syncthreads();
+  int *rec = scan + (size_t)blockIdx.x * kScanRec;
+  if (tid == 0) {
+    rec[0] = s_w[0][0] + s_w[0][1] + s_w[0][2] + s_w[0][3];
+    rec[1] = s_w[1][0] + s_w[1][1] + s_w[1][2] + s_w[1][3];
+  }
+  if (tid < nb) rec[2 + tid] = s_b[tid];
+}
+
+// One workgroup: each column of the block records becomes its exclusive
+// prefix over the blocks; the bucket columns then get their bucket's first
+// row added (brow[q] = nodes of lower degree).
+__global__ void __launch_bounds__(kScanTop)
+k_scan_top(const Dims *__restrict__ dims, int nb, int *__restrict__ scan,
+           int *__restrict__ brow, int *__restrict__ rowptr, int *__restrict__ srcptr) {
+  __shared__ int wsum[kScanTop / 64];
+  __shared__ int carry;
+  __shared__ int tot[kScanRec];
+  __shared__ int s_brow[kMaxBuckets + 1];
+  const int N = dims->N;
+  const int nblk = (N + kScanNodes - 1) / kScanNodes;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  constexpr int nw = kScanTop / 64;
+  for (int c = 0; c < 2 + nb; ++c) {
+    if (tid == 0) carry = 0;
     __syncthreads();
-    if (wid == 0) {
-      const int nw = kScanThreads / 64;
-      int a = lane < nw ? wsum[0][lane] : 0;
-      int b = lane < nw ? wsum[1][lane] : 0;
-      a = wave_incl_scan(a);
-      b = wave_incl_scan(b);
-      if (lane < nw) { wsum[0][lane] = a; wsum[1][lane] = b; }
-    }
-    __syncthreads();
-    int ei_ = carry[0] + (wid ? wsum[0][wid - 1] : 0) + ii - si;
-    int eo_ = carry[1] + (wid ? wsum[1][wid - 1] : 0) + io - so;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int i = base + tid * 4 + j;
-      if (i < N) {
-        rowptr[i] = ei_;
-        srcptr[i] = eo_;
-        deg[i] = vi[j];
-        const int dc = vi[j] < max_degree ? vi[j] : max_degree;
-        sp[i] = table[2 * dc];
-        sm[i] = table[2 * dc + 1];
-        if (vi[j] > max_degree || vo[j] > max_degree) bad = 1;
-        cnt_in[i] = 0;
-        cnt_out[i] = 0;
+    for (int b0 = 0; b0 < nblk; b0 += kScanTop) {
+      const int k = b0 + tid;
+      const int v = k < nblk ? scan[(size_t)k * kScanRec + c] : 0;
+      const int inc = wave_incl_scan(v);
+      if (lane == 63) wsum[wid] = inc;
+      __syncthreads();
+      if (wid == 0) {
+        int a = lane < nw ? wsum[lane] : 0;
+        a = wave_incl_scan(a);
+        if (lane < nw) wsum[lane] = a;
       }
-      ei_ += vi[j];
-      eo_ += vo[j];
+      __syncthreads();
+      const int excl = carry + (wid ? wsum[wid - 1] : 0) + inc - v;
+      if (k < nblk) scan[(size_t)k * kScanRec + c] = excl;
+      __syncthreads();
+      if (tid == kScanTop - 1) carry = excl + v;
+      __syncthreads();
     }
+    if (tid == 0) tot[c] = carry;
     __syncthreads();
-    if (tid == kScanThreads - 1) { carry[0] = ei_; carry[1] = eo_; }
-    __syncthreads();
+  }
+  if (tid == 0) {
+    rowptr[N] = tot[0];
+    srcptr[N] = tot[1];
+    int a = 0;
+    for (int q = 0; q < nb; ++q) {
+      s_brow[q] = a;
+      a += tot[2 + q];
+    }
+    s_brow[nb] = a;
+  }
+  __syncthreads();
+  if (nb == 0) return;
+  if (tid <= nb) brow[tid] = s_brow[tid];
+  for (int k = tid; k < nblk; k += kScanTop)
+    for (int q = 0; q < nb; ++q) scan[(size_t)k * kScanRec + 2 + q] += s_brow[q];
+}
+
+// Per block: its own exclusive scans plus the block offsets.  A node's place
+// among the nodes of its degree bucket counts the block's earlier nodes of
+// that bucket (earlier waves, earlier lanes, then the lane's own earlier
+// nodes), so the permutation is stable in node id.
+__global__ void __launch_bounds__(256)
+k_scan_apply(const Dims *__restrict__ dims, int *__restrict__ cnt_in,
+             int *__restrict__ cnt_out, const int *__restrict__ scan,
+             const float *__restrict__ table, int max_degree, int nb,
+             int *__restrict__ rowptr, int *__restrict__ srcptr, int *__restrict__ deg,
+             float *__restrict__ sp, float *__restrict__ sm, int *__restrict__ perm,
+             int *__restrict__ err) {
+  __shared__ int s_w[2][4];
+  __shared__ int s_bw[4][kMaxBuckets];
+  const int N = dims->N;
+  const int base = blockIdx.x * kScanNodes;
+  if (base >= N) return;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int *rec = scan + (size_t)blockIdx.x * kScanRec;
+  int vi[4], vo[4], bq[4];
+  int si = 0, so = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = base + 4 * tid + j;
+    vi[j] = i < N ? cnt_in[i] : 0;
+    vo[j] = i < N ? cnt_out[i] : 0;
+    bq[j] = i < N ? bucket_of(vi[j], max_degree) : -1;
+    si += vi[j];
+    so += vo[j];
+  }
+  const int ii = wave_incl_scan(si), io = wave_incl_scan(so);
+  if (lane == 63) {
+    s_w[0][wid] = ii;
+    s_w[1][wid] = io;
+  }
+  // bucket ranks inside the wave: per bucket, the lane's count and the
+  // exclusive sum over lower lanes
+  int pos[4] = {0, 0, 0, 0};
+  for (int q = 0; q < nb; ++q) {
+    int cq = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cq += bq[j] == q ? 1 : 0;
+    const int inc = wave_incl_scan(cq);
+    if (lane == 63) s_bw[wid][q] = inc;
+    int run = inc - cq;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (bq[j] == q) pos[j] = run++;
+  }
+  __syncthreads();
+  int ei_ = rec[0], eo_ = rec[1];
+  for (int w = 0; w < wid; ++w) {
+    ei_ += s_w[0][w];
+    eo_ += s_w[1][w];
+  }
+  ei_ += ii - si;
+  eo_ += io - so;
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = base + 4 * tid + j;
+    if (i < N) {
+      rowptr[i] = ei_;
+      srcptr[i] = eo_;
+      deg[i] = vi[j];
+      const int dc = bucket_of(vi[j], max_degree);
+      sp[i] = table[2 * dc];
+      sm[i] = table[2 * dc + 1];
+      if (vi[j] > max_degree || vo[j] > max_degree) bad = 1;
+      cnt_in[i] = 0;
+      cnt_out[i] = 0;
+      if (nb) {
+        const int q = bq[j];
+        int p = rec[2 + q] + pos[j];
+        for (int w = 0; w < wid; ++w) p += s_bw[w][q];
+        perm[p] = i;
+      }
+    }
+    ei_ += vi[j];
+    eo_ += vo[j];
   }
   if (bad) atomicOr(err, ERR_DEGREE);
-  if (tid == 0) {
-    rowptr[N] = carry[0];
-    srcptr[N] = carry[1];
-  }
 }
 
 __global__ void k_csr_fill(const Dims *__restrict__ dims,
@@ -283,8 +402,14 @@ hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
   if (capE > 0)
     k_csr_count<<<cdiv(capE, 256), 256, 0, s>>>(dims, edge_index, c.node_graph,
                                                 c.cnt_in, c.cnt_out, c.err);
-  k_csr_scan<<<1, kScanThreads, 0, s>>>(dims, c.cnt_in, c.cnt_out, c.rowptr, c.srcptr,
-                                        c.deg, table, c.sp, c.sm, max_degree, c.err);
+  {
+    const int nsb = cdiv(capN > 0 ? capN : 1, kScanNodes);
+    k_scan_count<<<nsb, 256, 0, s>>>(dims, c.cnt_in, c.cnt_out, max_degree, c.nb, c.scan);
+    k_scan_top<<<1, kScanTop, 0, s>>>(dims, c.nb, c.scan, c.brow, c.rowptr, c.srcptr);
+    k_scan_apply<<<nsb, 256, 0, s>>>(dims, c.cnt_in, c.cnt_out, c.scan, table, max_degree,
+                                     c.nb, c.rowptr, c.srcptr, c.deg, c.sp, c.sm, c.perm,
+                                     c.err);
+  }
   if (capE > 0)
     k_csr_fill<<<cdiv(capE, 256), 256, 0, s>>>(dims, edge_index, c.node_graph, c.rowptr,
                                                c.srcptr, c.cnt_in, c.cnt_out, c.csr_eid,

@@ -46,11 +46,33 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   __shared__ __attribute__((aligned(16))) T Bl1[DB && SPLIT ? BN * LDA : 1];
 
   const int M = g.M_fixed >= 0 ? g.M_fixed : dims->N;
-  const int mtiles = (M + BM - 1) / BM;
+  // Row tiles: plain, or per degree bucket over the permuted rows (each
+  // bucket's last tile may be partial).  The tile covers rows [m0, m_hi) of
+  // the (permuted) row order and multiplies with bucket q's weights.
+  int mtiles = (M + BM - 1) / BM;
+  if (g.perm) {
+    mtiles = 0;
+    for (int q = 0; q < g.nb; ++q) mtiles += (g.brow[q + 1] - g.brow[q] + BM - 1) / BM;
+  }
   const int z = blockIdx.y;
   if ((int)blockIdx.x >= mtiles * ntiles_n) return;
   const int tile = xcd_tile(blockIdx.x, mtiles * ntiles_n);
-  const int m0 = (tile / ntiles_n) * BM, n0 = (tile % ntiles_n) * BN;
+  const int mt = tile / ntiles_n, n0 = (tile % ntiles_n) * BN;
+  int m0 = mt * BM, m_hi = M, bq = 0;
+  if (g.perm) {
+    int first = 0;
+    for (int q = 0; q < g.nb; ++q) {
+      const int r0 = g.brow[q], r1 = g.brow[q + 1];
+      const int nt_q = (r1 - r0 + BM - 1) / BM;
+      if (mt < first + nt_q) {
+        bq = q;
+        m0 = r0 + (mt - first) * BM;
+        m_hi = r1;
+        break;
+      }
+      first += nt_q;
+    }
+  }
   const int tid = threadIdx.x, wid = tid >> 6;
   const int wm0 = (wid / WGN) * WM, wn0 = (wid % WGN) * WN;
 
@@ -80,8 +102,8 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  const T *Bg = reinterpret_cast<const T *>(g.B);
-  const T *Blg = reinterpret_cast<const T *>(g.B_lo);
+  const T *Bg = reinterpret_cast<const T *>(g.B) + (size_t)bq * g.bstride;
+  const T *Blg = g.B_lo ? reinterpret_cast<const T *>(g.B_lo) + (size_t)bq * g.bstride : nullptr;
   // two register stages: tiles t and t+1 are in flight while t-1 computes.
   // Loads are unconditional from clamped (in-bounds) addresses.  With DB the
   // stages keep the raw values and the row/column masks are applied only
@@ -98,8 +120,9 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   for (int j = 0; j < NA; ++j) {
     const int v = tid + j * NTH;
     const int m = m0 + v / (BK / 4);
-    a_ok[j] = m < M;
-    a_row[j] = min(m, M - 1);
+    a_ok[j] = m < m_hi;
+    a_row[j] = min(m, m_hi - 1);
+    if (g.perm) a_row[j] = g.perm[a_row[j]];
     a_col[j] = (v % (BK / 4)) * 4;
   }
   int b_row[NB], b_col[NB];
@@ -325,8 +348,11 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int m = m0 + wm0 + i * 16 + cr + v;
-          if (m < M) Pz[(size_t)m * g.Ncols + n] = acc[i][j][v];
+          const int r = m0 + wm0 + i * 16 + cr + v;
+          if (r < m_hi) {
+            const int m = g.perm ? g.perm[r] : r;
+            Pz[(size_t)m * g.Ncols + n] = acc[i][j][v];
+          }
         }
     }
     return;
@@ -340,8 +366,9 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     for (int i = 0; i < TM; ++i) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm0 + i * 16 + cr + v;
-        if (m < M) {
+        const int r = m0 + wm0 + i * 16 + cr + v;
+        if (r < m_hi) {
+          const int m = g.perm ? g.perm[r] : r;
           float o = acc[i][j][v] + bias;
           if (g.addend) o += g.addend[(size_t)m * g.ld_add + n];
           if (g.relu) o = o > 0.f ? o : 0.f;
@@ -365,7 +392,8 @@ template <int PREC, int BM, int BN, int TAG>
 hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, bool db, hipStream_t s,
                   hipEvent_t ev0, hipEvent_t ev1) {
   const int nt = cdiv(g.Ncols, BN);
-  dim3 grid(cdiv(capM, BM) * nt, g.splits);
+  // bucketed rows: each bucket's last tile may be partial
+  dim3 grid((cdiv(capM, BM) + (g.perm ? g.nb : 0)) * nt, g.splits);
   // A non-null event pair is stamped with the GEMM kernel's own start and end.
   const dim3 block(128 * kNtWGN);
   const GemmNT ga = g;
@@ -443,7 +471,8 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
   if (g.splits > 1 && !partials) g.splits = 1;
   while (g.splits > 1 && (size_t)g.splits * capM * g.Ncols > nt_partial_floats(0, 0, 0, 0))
     --g.splits;
-  const long long grid = (long long)cdiv(capM, kNtBM) * cdiv(g.Ncols, kNtBN) * g.splits;
+  const long long grid =
+      (long long)(cdiv(capM, kNtBM) + (g.perm ? g.nb : 0)) * cdiv(g.Ncols, kNtBN) * g.splits;
   const bool db = grid <= kNtDbMaxGrid && kt >= kNtDbMinKt * g.splits;
   if (tag == 1) {
     if (precision == 0) return run_nt<0, kNtBM, kNtBN, 1>(dims, capM, g, db, s, ev0, ev1);

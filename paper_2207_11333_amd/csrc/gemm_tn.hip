@@ -38,8 +38,30 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   const int m0 = (tile / ntiles_n) * BM, n0 = (tile % ntiles_n) * BN;
   int chunk = (rows + g.splits - 1) / g.splits;
   chunk = (chunk + BK - 1) / BK * BK;
-  const int i_lo = z * chunk;
-  const int i_hi = min(rows, i_lo + chunk);
+  int i_lo = z * chunk;
+  int i_hi = min(rows, i_lo + chunk);
+  if (g.perm) {
+    // bucket-pure chunks over the permuted rows: bucket q holds
+    // ceil(n_q / chunk) chunks, in bucket order; the chunks past the last
+    // are empty and write zero partials
+    int first = 0, bq = -1;
+    i_lo = i_hi = 0;
+    for (int q = 0; q < g.nb; ++q) {
+      const int r0 = g.brow[q], r1 = g.brow[q + 1];
+      const int nc = (r1 - r0 + chunk - 1) / chunk;
+      if (z < first + nc) {
+        bq = q;
+        i_lo = r0 + (z - first) * chunk;
+        i_hi = min(r1, i_lo + chunk);
+        break;
+      }
+      first += nc;
+    }
+    if (blockIdx.x % T2 == 0 && threadIdx.x == 0) {
+      g.zscale[2 * z] = bq >= 0 ? g.table[2 * bq] : 0.f;
+      g.zscale[2 * z + 1] = bq >= 0 ? g.table[2 * bq + 1] : 0.f;
+    }
+  }
   const int KT = i_hi > i_lo ? (i_hi - i_lo + BK - 1) / BK : 0;
   const int tid = threadIdx.x, wid = tid >> 6;
   const int wm0 = (wid >> 1) * WM, wn0 = (wid & 1) * WN;
@@ -93,13 +115,16 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       const int i = i0 + a_il[j];
-      const f4 val = *reinterpret_cast<const f4 *>(g.X + (size_t)min(i, i_last) * g.ldx + a_m[j]);
+      int ic = min(i, i_last);
+      if (g.perm) ic = g.perm[ic];
+      const f4 val = *reinterpret_cast<const f4 *>(g.X + (size_t)ic * g.ldx + a_m[j]);
       ra[S][j] = (a_ok[j] && i < i_hi) ? val : f4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int i = i0 + b_il[j];
-      const int ic = min(i, i_last);
+      int ic = min(i, i_last);
+      if (g.perm) ic = g.perm[ic];
       f4 val = *reinterpret_cast<const f4 *>(b_ptr[j] + (size_t)ic * b_ld[j]);
       const float sv = b_sptr[j][(size_t)ic * b_sstride[j]];
       const float sc = b_has_scale[j] ? sv : 1.0f;
@@ -194,14 +219,17 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
 } // namespace
 
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
-                          hipStream_t s) {
+                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.M <= 0 || g.Ncols <= 0) return hipSuccess;
   const int nt = cdiv(g.Ncols, 64);
-  const int grid = cdiv(g.M, 64) * nt * g.splits;
+  const int grid = cdiv(g.M, 64) * nt * (g.splits + (g.perm ? g.nb : 0));
+  // a non-null event pair is stamped with the kernel's own start and end
   if (precision == 0)
-    k_gemm_tn<0, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
+    hipExtLaunchKernelGGL(k_gemm_tn<0, 64, 64>, dim3(grid), dim3(256), 0, s, ev0, ev1, 0, dims,
+                          g, nt);
   else
-    k_gemm_tn<1, 64, 64><<<grid, 256, 0, s>>>(dims, g, nt);
+    hipExtLaunchKernelGGL(k_gemm_tn<1, 64, 64>, dim3(grid), dim3(256), 0, s, ev0, ev1, 0, dims,
+                          g, nt);
   return hipGetLastError();
 }
 

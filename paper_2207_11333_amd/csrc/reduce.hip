@@ -108,7 +108,84 @@ __global__ void __launch_bounds__(256) k_reduce_map(const ReduceMap r) {
   }
 }
 
+// Bucketed update weight gradient: the chunks of one bucket share its
+// scalers, so sum_z P[z] gives the h block, W_0 and the bias, and the
+// s+ and s- weighted sums give W_+ and W_-.  Same lane grouping and order
+// as ordered_sum.
+template <int G>
+__global__ void __launch_bounds__(256) k_reduce_upd(const ReduceUpd r) {
+  const long long gt = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = gt / G;
+  const long long total = (long long)r.M * r.Ncols;
+  const bool live = 4 * t < total;
+  const float *src = r.P + (live ? 4 * t : 0);
+  const int g = (int)(gt % G);
+  const int per = (r.Z + G - 1) / G;
+  const int z_lo = g * per, z_hi = min(r.Z, z_lo + per);
+  f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0, s2 = s0;
+  for (int z0 = z_lo; z0 < z_hi; z0 += kPerLane) {
+    f4 v[kPerLane];
+    float a[kPerLane], b[kPerLane];
+#pragma unroll
+    for (int u = 0; u < kPerLane; ++u) {
+      const int z = min(z0 + u, r.Z - 1);
+      v[u] = *reinterpret_cast<const f4 *>(src + z * total);
+      a[u] = r.zscale[2 * z];
+      b[u] = r.zscale[2 * z + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kPerLane; ++u)
+      if (z0 + u < z_hi) {
+        s0 += v[u];
+        s1 += a[u] * v[u];
+        s2 += b[u] * v[u];
+      }
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      s0[e] += __shfl_down(s0[e], off, G);
+      s1[e] += __shfl_down(s1[e], off, G);
+      s2[e] += __shfl_down(s2[e], off, G);
+    }
+  }
+  if (!live || g != 0) return;
+  const int m = (int)(4 * t / r.Ncols), c0 = (int)(4 * t % r.Ncols);
+  const int H = r.H, ldp = r.F + 12 * H;
+  float *row = r.dWp + (size_t)m * ldp;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c = c0 + e;
+    if (c < r.Fp) {
+      if (c < r.F) row[c] = s0[e];
+    } else if (c < r.Fp + 4 * H) {
+      const int cc = c - r.Fp;
+      row[r.F + cc] = s0[e];
+      row[r.F + 4 * H + cc] = s1[e];
+      row[r.F + 8 * H + cc] = s2[e];
+    } else if (c == r.Fp + 4 * H) {
+      r.dbp[m] = s0[e];
+    }
+  }
+}
+
 } // namespace
+
+hipError_t launch_reduce_upd(const ReduceUpd &r, hipStream_t s) {
+  const long long total = (long long)r.M * r.Ncols;
+  if (total <= 0) return hipSuccess;
+  const int G = pick_group(r.Z);
+  const int grid = cdiv(total / 4 * G, 256);
+  switch (G) {
+  case 1: k_reduce_upd<1><<<grid, 256, 0, s>>>(r); break;
+  case 2: k_reduce_upd<2><<<grid, 256, 0, s>>>(r); break;
+  case 4: k_reduce_upd<4><<<grid, 256, 0, s>>>(r); break;
+  case 8: k_reduce_upd<8><<<grid, 256, 0, s>>>(r); break;
+  default: k_reduce_upd<16><<<grid, 256, 0, s>>>(r); break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s) {
   const long long total = (long long)capM * g.Ncols;

@@ -84,7 +84,8 @@ void free_work(Exec &ex) {
                    (void **)&w.dA, (void **)&w.dm, (void **)&w.D, (void **)&w.dh0,
                    (void **)&w.dh1, (void **)&w.ntpart, (void **)&w.zn, (void **)&w.Qn,
                    (void **)&w.dQn, (void **)&w.en, (void **)&w.dhn,
-                   (void **)&w.csr.csr_dst, (void **)&w.h0, (void **)&w.gcG,
+                   (void **)&w.csr.csr_dst, (void **)&w.csr.perm, (void **)&w.csr.brow,
+                   (void **)&w.csr.scan, (void **)&w.h0, (void **)&w.gcG,
                    (void **)&w.gcD, (void **)&w.gcdm, (void **)&w.gcD1};
   for (void **p : ptrs) dfree(*p);
   for (auto &p : w.gcA) dfree(reinterpret_cast<void *&>(p));
@@ -117,6 +118,10 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
        f(w.csr.cnt_in, (size_t)capN) && f(w.csr.cnt_out, (size_t)capN);
   ok = ok && f(w.csr.csr_e, (size_t)capE * Fe) && f(w.csr.sp, (size_t)capN) &&
        f(w.csr.sm, (size_t)capN) && f(w.xpad, (size_t)capN * c->F0p);
+  // degree buckets of the update linear (PNA models) and the scan records
+  w.csr.nb = c->kind == HGNN_GC_PNA ? c->nb : 0;
+  ok = ok && f(w.csr.scan, (size_t)((capN + kScanNodes - 1) / kScanNodes) * kScanRec);
+  if (w.csr.nb) ok = ok && f(w.csr.perm, (size_t)capN) && f(w.csr.brow, (size_t)kMaxBuckets + 1);
   if (w.hbuf.size() != (size_t)nh) w.hbuf.assign(nh, nullptr);
   for (int l = 0; l < nh && ok; ++l) ok = f(w.hbuf[l], (size_t)capN * H);
   const bool pna = c->kind == HGNN_GC_PNA;
@@ -243,7 +248,8 @@ int stage_all(hgnn_ctx *c, hipStream_t s, long long *bump_step) {
   }
   int maxFp = 0;
   for (const LayerDesc &d : c->ld) maxFp = std::max(maxFp, d.Fp);
-  hipError_t e = launch_stage_all(c->stage_tab, c->L, maxFp, c->H, c->Fe, c->prec, bump_step, s);
+  hipError_t e = launch_stage_all(c->stage_tab, c->L, maxFp, c->H, c->Fe, c->nb, c->table,
+                                  c->prec, bump_step, s);
   if (e != hipSuccess) return hip_fail(c, e, "stage weights");
   c->staged_from_params = true;
   return HGNN_OK;
@@ -252,7 +258,7 @@ int stage_all(hgnn_ctx *c, hipStream_t s, long long *bump_step) {
 static int stage_layer_from(hgnn_ctx *c, int l, const float *wl, hipStream_t s) {
   const LayerDesc &d = c->ld[l];
   hipError_t e = launch_stage_layer(wl + (d.oWm - d.off), wl + (d.oWp - d.off), d.F, d.Fp,
-                                    c->H, c->Fe, stage_out(c, l), c->prec, s);
+                                    c->H, c->Fe, c->nb, c->table, stage_out(c, l), c->prec, s);
   if (e != hipSuccess) return hip_fail(c, e, "stage layer weights");
   c->staged_from_params = false;
   return HGNN_OK;
@@ -384,15 +390,27 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
   w.stored_layer = l;
   float *A = w.A[slot];
   GemmNT g{};
-  g.nseg = 4;
-  g.seg[0] = SegA{hin, nullptr, ldh, d.Fp, 0};
-  g.seg[1] = SegA{A, nullptr, 4 * H, 4 * H, d.Fp};
-  g.seg[2] = SegA{A, w.csr.sp, 4 * H, 4 * H, d.Fp + 4 * H};
-  g.seg[3] = SegA{A, w.csr.sm, 4 * H, 4 * H, d.Fp + 8 * H};
-  g.ileave_n = 3;
+  if (c->nb) {
+    // degree buckets: u = [h || A] [W_h | W_eff(d)]^T per bucket of rows
+    g.nseg = 2;
+    g.seg[0] = SegA{hin, nullptr, ldh, d.Fp, 0};
+    g.seg[1] = SegA{A, nullptr, 4 * H, 4 * H, d.Fp};
+    g.ldb = d.Fp + 4 * H;
+    g.perm = w.csr.perm;
+    g.brow = w.csr.brow;
+    g.nb = c->nb;
+    g.bstride = (long long)H * g.ldb;
+  } else {
+    g.nseg = 4;
+    g.seg[0] = SegA{hin, nullptr, ldh, d.Fp, 0};
+    g.seg[1] = SegA{A, nullptr, 4 * H, 4 * H, d.Fp};
+    g.seg[2] = SegA{A, w.csr.sp, 4 * H, 4 * H, d.Fp + 4 * H};
+    g.seg[3] = SegA{A, w.csr.sm, 4 * H, 4 * H, d.Fp + 8 * H};
+    g.ileave_n = 3;
+    g.ldb = d.Fp + 12 * H;
+  }
   g.B = c->Wpp[l];
   g.B_lo = c->prec ? c->Wpp_lo[l] : nullptr;
-  g.ldb = d.Fp + 12 * H;
   g.Ncols = H;
   g.bias = wl + (d.obp - d.off);
   g.relu = 1;
@@ -451,8 +469,45 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   e = hipEventRecord(c->fork_ev[0], s);
   if (e == hipSuccess) e = hipStreamWaitEvent(a, c->fork_ev[0], 0);
   if (e != hipSuccess) return hip_fail(c, e, "fork");
-  // S6: dW^p = du^T [h || A || s+ A || s- A]
-  {
+  // S6: dW^p = du^T [h || A || s+ A || s- A]; with degree buckets
+  // du^T [h || A] per bucket-pure chunk, the scalers applied by the reduction
+  if (c->nb) {
+    GemmTN t{};
+    t.X = du;
+    t.ldx = H;
+    t.M = H;
+    t.seg[0] = SegY{hin, nullptr, ldh, d.Fp};
+    t.seg[1] = SegY{A, nullptr, 4 * H, 4 * H};
+    t.seg[2] = SegY{nullptr, nullptr, 0, 4}; // sum column: db^p
+    t.nseg = 3;
+    t.Ncols = d.Fp + 4 * H + 4;
+    t.P = c->part;
+    t.splits = d.split_p;
+    t.perm = w.csr.perm;
+    t.brow = w.csr.brow;
+    t.nb = c->nb;
+    t.table = c->table;
+    t.zscale = c->zscale;
+    {
+      TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, a, /*manual=*/true);
+      e = launch_gemm_tn(ex.dims, t, c->prec, a, tl.start(), tl.stop());
+    }
+    if (e == hipSuccess) {
+      ReduceUpd r{};
+      r.P = c->part;
+      r.zscale = c->zscale;
+      r.Z = d.split_p + c->nb;
+      r.M = H;
+      r.Ncols = t.Ncols;
+      r.F = d.F;
+      r.Fp = d.Fp;
+      r.H = H;
+      r.dWp = dWp;
+      r.dbp = dbp;
+      e = launch_reduce_upd(r, a);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "update weight gradient");
+  } else {
     GemmTN t{};
     t.X = du;
     t.ldx = H;
@@ -468,8 +523,8 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     t.P = c->part;
     t.splits = d.split_p;
     {
-      TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, a);
-      e = launch_gemm_tn(ex.dims, t, c->prec, a);
+      TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, a, /*manual=*/true);
+      e = launch_gemm_tn(ex.dims, t, c->prec, a, tl.start(), tl.stop());
     }
     if (e == hipSuccess) {
       ReduceMap r{};
@@ -486,17 +541,28 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     }
     if (e != hipSuccess) return hip_fail(c, e, "update weight gradient");
   }
-  // S6: dA = [du || s+ du || s- du] [W0; W+; W-]
+  // S6: dA = [du || s+ du || s- du] [W0; W+; W-], with degree buckets
+  // du W_eff(d) per bucket of rows
   {
     GemmNT g{};
-    g.nseg = 3;
-    g.seg[0] = SegA{du, nullptr, H, H, 0};
-    g.seg[1] = SegA{du, w.csr.sp, H, H, H};
-    g.seg[2] = SegA{du, w.csr.sm, H, H, 2 * H};
-    g.ileave_n = 3;
+    if (c->nb) {
+      g.nseg = 1;
+      g.seg[0] = SegA{du, nullptr, H, H, 0};
+      g.ldb = H;
+      g.perm = w.csr.perm;
+      g.brow = w.csr.brow;
+      g.nb = c->nb;
+      g.bstride = (long long)4 * H * H;
+    } else {
+      g.nseg = 3;
+      g.seg[0] = SegA{du, nullptr, H, H, 0};
+      g.seg[1] = SegA{du, w.csr.sp, H, H, H};
+      g.seg[2] = SegA{du, w.csr.sm, H, H, 2 * H};
+      g.ileave_n = 3;
+      g.ldb = 3 * H;
+    }
     g.B = c->WpTA[l];
     g.B_lo = c->prec ? c->WpTA_lo[l] : nullptr;
-    g.ldb = 3 * H;
     g.Ncols = 4 * H;
     g.C = w.dA;
     g.ldc = 4 * H;
@@ -1161,6 +1227,8 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
       c->ld.push_back(d);
     }
   }
+  c->nb = (pna && c->maxd + 1 <= kMaxBuckets) ? c->maxd + 1 : 0;
+  int zmax = 0; // chunks of the bucketed update weight gradient
   for (int l = 0; pna && l < c->L; ++l) {
     LayerDesc d;
     d.F = l == 0 ? c->F0 : H;
@@ -1175,9 +1243,13 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
     d.obp = off;
     off += H;
     d.size = off - d.off;
-    d.split_p = tn_splits(H, d.Fp + 12 * H + 4, cfg->precision);
+    // the update weight gradient's columns: [h | A | s+ A | s- A | sum] or,
+    // with degree buckets, [h | A | sum] over nb more (bucket-pure) chunks
+    const int wcols = d.Fp + (c->nb ? 4 : 12) * H + 4;
+    d.split_p = tn_splits(H, wcols, cfg->precision);
     d.split_m = tn_splits((2 + c->Fe) * H, d.Fp + 4, cfg->precision);
-    const size_t a = (size_t)d.split_p * H * (d.Fp + 12 * H + 4);
+    zmax = std::max(zmax, d.split_p + c->nb);
+    const size_t a = (size_t)(d.split_p + c->nb) * H * wcols;
     const size_t b = (size_t)d.split_m * (2 + c->Fe) * H * (d.Fp + 4);
     part_max = std::max(part_max, std::max(a, b));
     c->ld.push_back(d);
@@ -1256,6 +1328,7 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
   HGNN_CALLOC(c->ex.dims, 1);
   HGNN_CALLOC(c->ex.w.csr.err, 1);
   HGNN_CALLOC(c->part, part_max);
+  if (c->nb) HGNN_CALLOC(c->zscale, 2 * (size_t)zmax);
   HGNN_CALLOC(c->gw_dev, Tg);
   if (Tn > 0) {
     HGNN_CALLOC(c->nw_dev, Tn);
@@ -1315,8 +1388,12 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
   }
   for (int l = 0; pna && l < c->L; ++l) {
     const LayerDesc &d = c->ld[l];
-    const size_t n[4] = {(size_t)2 * H * d.Fp, (size_t)H * (d.Fp + 12 * H), (size_t)12 * H * H,
-                         (size_t)3 * H * d.Fp};
+    // bucketed: the update copies hold one [W_h | W_eff(q)] and one
+    // W_eff(q)^T per degree bucket q
+    const size_t nbk = c->nb ? (size_t)c->nb : 1;
+    const size_t n[4] = {(size_t)2 * H * d.Fp,
+                         c->nb ? nbk * H * (d.Fp + 4 * H) : (size_t)H * (d.Fp + 12 * H),
+                         c->nb ? nbk * 4 * H * H : (size_t)12 * H * H, (size_t)3 * H * d.Fp};
     std::vector<void *> *hi[4] = {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT};
     std::vector<void *> *lo[4] = {&c->Wds_lo, &c->Wpp_lo, &c->WpTA_lo, &c->WhdsT_lo};
     for (int k = 0; k < 4; ++k) {
@@ -1401,7 +1478,7 @@ void hgnn_destroy(hgnn_ctx *c) {
                    (void **)&c->gw_dev, (void **)&c->nw_dev, (void **)&c->W1n,
                    (void **)&c->W1nT, (void **)&c->nh_part,
                    (void **)&c->table, (void **)&c->ex.dims, (void **)&c->ex.w.csr.err,
-                   (void **)&c->part};
+                   (void **)&c->part, (void **)&c->zscale};
   for (void **p : ptrs) dfree(*p);
   for (auto *v : {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT, &c->Wds_lo, &c->Wpp_lo, &c->WpTA_lo,
                   &c->WhdsT_lo, &c->WeT, &c->Wg1, &c->Wg1_lo, &c->Wg2, &c->Wg2_lo})

@@ -98,6 +98,9 @@ struct hgnn_ctx {
   int dev = 0;
   int kind = HGNN_GC_PNA; // GC layer kind
   int L = 0, H = 0, F0 = 0, F0p = 0, Fe = 0, maxd = 0, prec = 0, recompute = 0;
+  // degree buckets of the update linear: max_degree + 1 when that is at most
+  // kMaxBuckets (PNA), else 0 (the concatenated form)
+  int nb = 0;
   int64_t P = 0, off_head = 0;
   std::vector<hgnn::LayerDesc> ld;
   std::vector<hgnn::InitTensor> init_tab; // packing order
@@ -129,6 +132,7 @@ struct hgnn_ctx {
   long long gc_max_elems = 0;
   bool staged_from_params = false;
   float *part = nullptr;
+  float *zscale = nullptr; // per-chunk scalers of the bucketed update weight gradient
   hgnn::Exec ex; // the training path's batch state
   // batch state of hgnn_forward_noalloc: its buffers are carved from the
   // device's scratch array (noalloc.hip) and never freed
