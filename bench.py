@@ -35,6 +35,17 @@ def _log(msg):
 # kernel and is not used.
 UPDATE_GEMM_TRAFFIC = ("update_gemm_c1_fp32_traffic.txt",
                        ["csrc/gemm_nt.hip", "csrc/mfma_tile.hpp"])
+# per launch site of the C1 FP32 step (the headline's dominant site is
+# looked up here)
+SITE_TRAFFIC = {
+    "update_gemm": UPDATE_GEMM_TRAFFIC,
+    "update_wgrad": ("update_wgrad_c1_fp32_traffic.txt",
+                     ["csrc/gemm_tn.hip", "csrc/mfma_tile.hpp"]),
+    "message_wgrad": ("message_wgrad_c1_fp32_traffic.txt",
+                      ["csrc/gemm_tn.hip", "csrc/mfma_tile.hpp"]),
+    "agg_input_gemm": ("agg_input_gemm_c1_fp32_traffic.txt",
+                       ["csrc/gemm_nt.hip", "csrc/mfma_tile.hpp"]),
+}
 AGGREGATE_TRAFFIC = {
     "aggregate": ("aggregate_c3_traffic.txt", ["csrc/aggregate.hip"]),
     "aggregate_bwd": ("aggregate_bwd_c3_traffic.txt", ["csrc/aggregate.hip"]),
@@ -57,7 +68,116 @@ def measured_traffic(name, sources):
         return None
 
 
-def train_rate(workload, steps, warmup, roofline_site=None):
+# Launch sites of the PNA training step timed by the library's event pairs
+# (kernel alone for the GEMM and aggregation sites), the kernel each one
+# runs (as named in the rocprofv3 summaries) and what bounds it.
+SITES = {
+    "message_gemm": ("S1 message linear", "k_gemm_nt<P, 64, 128, *, 2, 4, *>", "mfma"),
+    "aggregate": ("S2 aggregation", "k_aggregate<1>", "hbm"),
+    "update_gemm": ("S3 update linear", "k_gemm_nt<P, 64, 128, *, 1, 4, *>", "mfma"),
+    "update_wgrad": ("S6 update weight gradient", "k_gemm_tn<P, 64, 64, 1>", "mfma"),
+    "agg_input_gemm": ("S6 aggregate-input gradient", "k_gemm_nt<P, 64, 128, *, 3, 4, *>", "mfma"),
+    "aggregate_bwd": ("S7 aggregation adjoint", "k_aggregate_bwd<1>", "hbm"),
+    "input_gemm": ("S6+S8 layer-input gradient", "k_gemm_nt<P, 64, 128, *, 4, 4, *>", "mfma"),
+    "message_wgrad": ("S8 message weight gradient", "k_gemm_tn<P, 64, 64, 2>", "mfma"),
+}
+
+
+def site_work(site, w, N, E):
+    """Algorithmic work of one launch of a site (FLOPs for the linears, bytes
+    for the aggregations), averaged over the launches of one step, and the
+    launches per step.  The linears count the least work the method needs:
+    the decomposed message linear [N, F] x [F, 2H], and the update linear by
+    degree bucket, [N, F + 4H] x [F + 4H, H] (the degree scalers fold into one
+    weight per degree), F = 9 real input features in layer 0 and H after."""
+    H, L, Fe = w.hidden, w.num_layers, w.edge_feat
+    Fs = [9] + [H] * (L - 1)
+    rec = 2 if w.recompute else 1
+    if site == "message_gemm":
+        return sum(2.0 * N * F * 2 * H for F in Fs) / L, rec * L
+    if site == "update_gemm":
+        return sum(2.0 * N * (F + 4 * H) * H for F in Fs) / L, L
+    if site == "update_wgrad":
+        return sum(2.0 * N * H * (F + 4 * H) for F in Fs) / L, L
+    if site == "agg_input_gemm":
+        return 2.0 * N * H * 4 * H, L
+    if site == "input_gemm":
+        return 2.0 * N * 3 * H * H, L - 1
+    if site == "message_wgrad":
+        return sum(2.0 * N * 2 * H * F for F in Fs) / L, L
+    if site == "aggregate":
+        return float(aggregate_bytes(N, E, H, Fe)), rec * L
+    if site == "aggregate_bwd":
+        return float(aggregate_bwd_bytes(N, E, H, Fe)), L
+    raise KeyError(site)
+
+
+def time_sites(m, step, steps, w, N, E, sites=tuple(SITES)):
+    """Per launch site: average kernel duration over `steps` further steps and
+    the roofline figures."""
+    import torch
+    bf16 = w.precision == 1
+    out = {}
+    for site in sites:
+        m.timer_start(site, steps * 2 * w.num_layers + 16)
+        torch.cuda.synchronize()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms, n = m.timer_read()
+        if n == 0:
+            continue
+        work, per_step = site_work(site, w, N, E)
+        avg = ms / 1e3 / n
+        what, kern, bound = SITES[site]
+        if bound == "hbm":
+            ach, peak, unit = work / avg / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            peak = BF16_PEAK_TFLOPS if bf16 else FP32_PEAK_TFLOPS
+            ach, unit = work / avg / 1e12, "TFLOP/s"
+        out[site] = {"step": what, "kernel": kern.replace("P", str(w.precision), 1),
+                     "bound": bound, "avg_us": avg * 1e6, "launches": n,
+                     "launches_per_step": per_step, "us_per_step": avg * 1e6 * per_step,
+                     ("bytes_per_launch" if bound == "hbm" else "flops_per_launch"): work,
+                     "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak}
+    return out
+
+
+def dominant_roofline(sites):
+    """The roofline object of the site with the most kernel time per step."""
+    name = max(sites, key=lambda k: sites[k]["us_per_step"])
+    r = dict(sites[name])
+    r["site"] = name
+    r["traffic"] = measured_traffic(*SITE_TRAFFIC[name]) if name in SITE_TRAFFIC else None
+    return r
+
+
+def phase_split(m, step_parts, steps):
+    """Mean time per step of the CSR build (S0, its own event pair), the rest
+    of the forward pass, the backward pass and the AdamW step (event pairs on
+    the caller's stream between the calls)."""
+    import torch
+    fwd, bwd, opt = step_parts
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    m.timer_start("csr", steps + 4)
+    torch.cuda.synchronize()
+    for e in evs:
+        e[0].record()
+        fwd()
+        e[1].record()
+        bwd()
+        e[2].record()
+        opt()
+        e[3].record()
+    torch.cuda.synchronize()
+    s0_ms, n = m.timer_read()
+    s0 = s0_ms / max(1, n)
+    mean = lambda a, b: sum(e[a].elapsed_time(e[b]) for e in evs) / steps
+    return {"s0_csr_ms": s0, "forward_ms": mean(0, 1) - s0, "backward_ms": mean(1, 2),
+            "adamw_ms": mean(2, 3)}
+
+
+def train_rate(workload, steps, warmup, sites=False, phases=False):
     import torch
     from paper_2207_11333_amd import hgnn
     b = workload.batch()
@@ -85,14 +205,14 @@ def train_rate(workload, steps, warmup, roofline_site=None):
     out = {"graphs_per_s": b.num_graphs * steps / dt, "ms_per_step": 1e3 * dt / steps,
            "B": b.num_graphs, "N": b.num_nodes, "E": b.num_edges,
            "loss": float(loss.item())}
-    if roofline_site:
-        m.timer_start(roofline_site, steps * workload.num_layers + 16)
-        torch.cuda.synchronize()
-        for _ in range(steps):
-            step()
-        torch.cuda.synchronize()
-        ms, n = m.timer_read()
-        out["site_ms_total"], out["site_launches"] = ms, n
+    # the further passes below are timed separately and leave the figures
+    # above untouched
+    if sites:
+        out["sites"] = time_sites(m, step, max(4, min(steps, 20)), workload, b.num_nodes,
+                                  b.num_edges)
+    if phases:
+        out["phases"] = phase_split(m, (lambda: m.forward(db, pred, loss), m.backward,
+                                        lambda: m.adam_step(lr=1e-3)), max(4, min(steps, 50)))
     m.close()
     return out
 
@@ -266,7 +386,7 @@ def gc_measure(workload, steps, warmup):
     return out
 
 
-def serve_bench(qps=500.0, warm_s=2.0, measure_s=10.0, pool=48):
+def serve_bench(qps=500.0, warm_s=2.0, measure_s=20.0, pool=48):
     """Open-loop Poisson arrivals at a fixed rate; latency is measured from the
     scheduled arrival time to the poll that observes completion."""
     import numpy as np
@@ -316,7 +436,7 @@ def serve_bench(qps=500.0, warm_s=2.0, measure_s=10.0, pool=48):
     lat = np.sort(np.asarray(lat)) * 1e3
     return {"workload": "serving: 6-layer PNA, hidden 128, BF16; requests of 1-256 molecules "
                         "of 5-70 atoms (pool of %d synthetic requests), Poisson arrivals" % pool,
-            "qps": qps, "requests_measured": int(lat.size),
+            "qps": qps, "window_s": measure_s, "requests_measured": int(lat.size),
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "graphs_per_s": graphs_done / measure_s, "batches": stats["batches"],
@@ -443,32 +563,89 @@ def aggregate_bwd_bytes(N, E, H, Fe):
 
 def c3_measure(steps=8, warmup=2):
     """One GPU's share of the large data-parallel step: 8 layers, hidden 256,
-    1024 molecules, BF16 linears, recomputation on.  Times the step and the two
-    aggregation kernels against the HBM roofline."""
+    1024 molecules, BF16 linears, recomputation on.  Times the step, every
+    launch site (the two aggregation kernels against the HBM roofline), the
+    phases, and the device memory with recomputation on and off."""
     from paper_2207_11333_amd import synth
     w = synth.WORKLOADS["c3_large_bf16"]
-    out = {}
+    r = train_rate(w, steps, warmup, sites=True, phases=True)
+    out = {"graphs_per_s": r["graphs_per_s"], "ms_per_step": r["ms_per_step"],
+           "nodes": r["N"], "edges": r["E"]}
     for site in ("aggregate", "aggregate_bwd"):
-        r = train_rate(w, steps, warmup, roofline_site=site)
-        out.setdefault("graphs_per_s", r["graphs_per_s"])
-        out.setdefault("ms_per_step", r["ms_per_step"])
-        out.setdefault("nodes", r["N"])
-        out.setdefault("edges", r["E"])
-        fn = aggregate_bytes if site == "aggregate" else aggregate_bwd_bytes
-        nbytes = fn(r["N"], r["E"], w.hidden, w.edge_feat)
-        avg = r["site_ms_total"] / 1e3 / max(1, r["site_launches"])
-        gbs = nbytes / avg / 1e9
-        out[site] = {"avg_us": avg * 1e6, "bytes_per_launch": nbytes, "achieved": gbs,
-                     "unit": "GB/s", "peak": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
-                     "launches": r["site_launches"],
+        st = r["sites"][site]
+        out[site] = {"avg_us": st["avg_us"], "bytes_per_launch": st["bytes_per_launch"],
+                     "achieved": st["achieved"], "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                     "frac": st["frac"], "launches": st["launches"],
                      "traffic": measured_traffic(*AGGREGATE_TRAFFIC[site])}
     out["workload"] = ("c3_large_bf16: 8-layer PNA, hidden 256, 1024 molecules of 10-70 atoms, "
                        "BF16 linears, FP32 aggregation, recomputation on")
+    out["sites"] = r["sites"]
+    out["phases"] = r["phases"]
+    out["memory"] = {"recompute_on_bytes": step_memory(w, 1),
+                     "recompute_off_bytes": step_memory(w, 0),
+                     "note": "device memory taken by the context and one training step: the "
+                             "drop in free device memory from before the model is created to "
+                             "after its first step (parameters, moments, staged weights, "
+                             "workspace, the batch)"}
     copy = copy_bandwidth()
     out["copy_gbs"] = copy
     for site in ("aggregate", "aggregate_bwd"):
         out[site]["frac_of_copy"] = out[site]["achieved"] / copy
     return out
+
+
+def step_memory(w, recompute):
+    """Free device memory before creating the model minus after one step."""
+    import dataclasses
+    import gc
+    import torch
+    from paper_2207_11333_amd import hgnn
+    w = dataclasses.replace(w, recompute=recompute)
+    b = w.batch()
+    torch.cuda.synchronize()
+    gc.collect()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    m = hgnn.Model(w.num_layers, w.hidden, 9, w.edge_feat, 4, w.precision, recompute, w.delta)
+    m.set_params(w.params())
+    db = hgnn.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    m.forward(db, pred, loss)
+    m.backward()
+    m.adam_step(lr=1e-3)
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    m.close()
+    del db, pred, loss
+    return int(used)
+
+
+def accuracy_sample(w, ngraphs=32):
+    """Prediction and loss of the first `ngraphs` graphs of the workload's
+    batch on the GPU against the FP64 oracle: L2 ratio and max|a-r|/max|r|."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2207_11333_amd import hgnn, synth
+    b = synth.select_graphs(w.batch(), range(ngraphs))
+    params = w.params()
+    m = hgnn.Model(w.num_layers, w.hidden, 9, w.edge_feat, 4, w.precision, w.recompute,
+                   w.delta)
+    m.set_params(params)
+    db = hgnn.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    m.forward(db, pred, loss, validate=True)
+    torch.cuda.synchronize()
+    a = pred.cpu().numpy().astype(np.float64)
+    m.close()
+    rec = oracle.forward(params.astype(np.float64), b, w.num_layers, w.hidden, w.delta)
+    r = np.asarray(rec.y, np.float64)
+    return {"graphs": ngraphs, "atoms": b.num_nodes,
+            "pred_rel_l2": float(np.linalg.norm(a - r) / np.linalg.norm(r)),
+            "pred_rel_max": float(np.abs(a - r).max() / np.abs(r).max()),
+            "loss_rel": float(abs(loss.item() - rec.loss) / abs(rec.loss))}
 
 
 def copy_bandwidth(mib=1024, reps=20):
@@ -490,32 +667,13 @@ def copy_bandwidth(mib=1024, reps=20):
     return 2 * n * 4 / sec / 1e9
 
 
-def update_gemm_bytes(w, N):
-    """Algorithmic HBM bytes of one launch of the update linear, averaged over
-    layers: read h [N, F], A [N, 4H], the two scalers [N, 2] and the weight
-    [F + 12H, H]; write h' [N, H] once (FP32 throughout)."""
-    H, L = w.hidden, w.num_layers
-    tot = 0.0
-    for l in range(L):
-        F = 9 if l == 0 else H
-        tot += 4.0 * (N * (F + 4 * H + 2) + (F + 12 * H) * H + N * H)
-    return tot / L
-
-
-def update_gemm_flops(w, N):
-    """Algorithmic FLOPs of one launch of the update linear, averaged over layers:
-    [N, F + 12H] x [F + 12H, H] with F = 9 for the first layer, H after."""
-    H, L = w.hidden, w.num_layers
-    tot = sum(2.0 * N * (9 if l == 0 else H) * H + 2.0 * N * 12 * H * H for l in range(L))
-    return tot / L
-
-
-def cpu_baseline(workload, budget_s=12.0):
+def _oracle_steps(workload, ngraphs, budget_s):
+    """FP64 oracle train steps (forward, backward, AdamW) on the first
+    `ngraphs` graphs of the workload's batch for about budget_s seconds."""
     import numpy as np
     import oracle
     from paper_2207_11333_amd import synth
-    b = workload.batch()
-    sample = synth.select_graphs(b, range(16))
+    sample = synth.select_graphs(workload.batch(), range(ngraphs))
     params = workload.params().astype(np.float64)
     m = np.zeros_like(params)
     v = np.zeros_like(params)
@@ -528,17 +686,49 @@ def cpu_baseline(workload, budget_s=12.0):
         params, m, v = oracle.adamw(params, g, m, v, t)
         n_graphs += sample.num_graphs
     dt = time.perf_counter() - t0
-    threads = 1
+    return n_graphs / dt, t, sample.num_nodes, dt
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(workload, budget_s=7.0):
+    """The FP64 oracle on the host: the headline workload's first 16 graphs with
+    every BLAS thread (the reported value) and pinned to one thread, and the
+    small workload's first 16 graphs."""
+    from paper_2207_11333_amd import synth
     try:
         import threadpoolctl
+    except ImportError:
+        threadpoolctl = None
+    threads = None
+    if threadpoolctl is not None:
         info = threadpoolctl.threadpool_info()
         threads = max([i.get("num_threads", 1) for i in info] + [1])
-    except Exception:
-        pass
-    return {"value": n_graphs / dt, "unit": "graphs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{t} FP64 oracle train steps (forward + backward + AdamW) on the first "
-                      f"16 graphs ({sample.num_nodes} atoms) of the same batch, {dt:.1f} s",
-            "host_cores": len(os.sched_getaffinity(0))}
+    v_all, t_all, atoms, dt_all = _oracle_steps(workload, 16, budget_s)
+    if threadpoolctl is not None:
+        with threadpoolctl.threadpool_limits(limits=1):
+            v_one, t_one, _, dt_one = _oracle_steps(workload, 16, budget_s * 0.7)
+    else:
+        v_one = t_one = dt_one = None
+    w0 = synth.WORKLOADS["c0_small_fp32"]
+    v_c0, t_c0, atoms0, dt_c0 = _oracle_steps(w0, 16, budget_s * 0.5)
+    return {"value": v_all, "unit": "graphs/s", "cores": threads or 1, "kind": "oracle",
+            "sample": f"{t_all} FP64 oracle train steps (forward + backward + AdamW) on the "
+                      f"first 16 graphs ({atoms} atoms) of the same batch, {dt_all:.1f} s, "
+                      "all BLAS threads",
+            "one_thread": {"value": v_one, "steps": t_one, "seconds": dt_one},
+            "c0_small": {"value": v_c0, "steps": t_c0, "atoms": atoms0, "seconds": dt_c0},
+            "blas_threads": threads, "host_cores": len(os.sched_getaffinity(0)),
+            "cpu_model": _cpu_model()}
 
 
 def main():
@@ -591,22 +781,12 @@ def main():
         print(json.dumps({"c3": c3_measure()}), flush=True)
         return
     _log(f"bench: {w.name} steps={args.steps} warmup={args.warmup}")
-    r = train_rate(w, args.steps, args.warmup, roofline_site="update_gemm")
+    r = train_rate(w, args.steps, args.warmup, sites=True, phases=True)
     _log(f"bench: {'bf16' if bf16 else 'fp32'} {r['graphs_per_s']:.1f} graphs/s, "
          f"{r['ms_per_step']:.3f} ms/step")
-    flops = update_gemm_flops(w, r["N"])
-    avg_s = r["site_ms_total"] / 1e3 / max(1, r["site_launches"])
-    achieved = flops / avg_s / 1e12
-    peak = BF16_PEAK_TFLOPS if bf16 else FP32_PEAK_TFLOPS
-    # the launch rule of the NT GEMM (64 x 128 tiles, K tiles of 64): the K
-    # split, then the double-buffered form for grids of at most 256 workgroups
-    # whose splits run at least four K tiles (hidden layers' K: H + 3 x 4H)
-    tiles = -(-r["N"] // 64) * -(-w.hidden // 128)
-    kt = -(-w.hidden // 64) + 3 * -(-4 * w.hidden // 64)
-    splits = max(1, min(256 // tiles, kt // 2, 8))
-    db = tiles * splits <= 256 and kt >= 4 * splits
-    kname = (f"update GEMM (S3) k_gemm_nt<{w.precision}, 64, 128, {'true' if bf16 else 'false'}, "
-             f"1, 4, {'true' if db else 'false'}>")
+    roof = dominant_roofline(r["sites"])
+    _log(f"bench: dominant site {roof['site']} {roof['us_per_step']:.1f} us/step, "
+         f"{roof['achieved']:.1f} {roof['unit']} ({100 * roof['frac']:.1f}% of peak)")
     wdesc = (f"{w.name}: {w.num_layers}-layer PNA GCNN, hidden {w.hidden}, {w.num_graphs} "
              f"synthetic molecules of {w.n_lo}-{w.n_hi} atoms, {w.edge_feat} edge feature, "
              f"{'BF16 linears, FP32 aggregation' if bf16 else 'FP32'}, "
@@ -621,26 +801,27 @@ def main():
                    "graphs_per_step": r["B"], "nodes": r["N"], "edges": r["E"],
                    "layers": w.num_layers, "hidden": w.hidden,
                    "precision": "bf16" if bf16 else "fp32"},
-        "roofline": {"kernel": kname, "bound": "mfma",
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": None if bf16 else measured_traffic(*UPDATE_GEMM_TRAFFIC),
-                     "launches": r["site_launches"], "avg_us": avg_s * 1e6,
-                     "flops_per_launch": flops,
-                     "algorithmic_bytes_per_launch": update_gemm_bytes(w, r["N"])},
+        "roofline": roof,
+        "sites": r["sites"],
+        "phases": r["phases"],
     }
+    if not args.no_extras:
+        _log("bench: prediction and loss against the FP64 oracle")
+        line["error_vs_fp64"] = {w.name: accuracy_sample(w)}
     if not args.no_extras and not bf16:
         rg = train_rate_graph(w, args.steps, args.warmup)
         _log(f"bench: fp32 graph-replayed {rg['graphs_per_s']:.1f} graphs/s")
         line["fp32_graph_replay"] = {"value": rg["graphs_per_s"], "unit": "graphs/s",
                                      "ms_per_step": rg["ms_per_step"]}
         wb = synth.WORKLOADS["c2_train_bf16"]
-        rb = train_rate(wb, args.steps, args.warmup)
+        rb = train_rate(wb, args.steps, args.warmup, sites=True, phases=True)
         rbg = train_rate_graph(wb, args.steps, args.warmup)
         _log(f"bench: bf16 {rb['graphs_per_s']:.1f} graphs/s, graph-replayed "
              f"{rbg['graphs_per_s']:.1f}")
+        line["error_vs_fp64"][wb.name] = accuracy_sample(wb)
         line["bf16"] = {"workload": wb.name, "value": rb["graphs_per_s"], "unit": "graphs/s",
-                        "ms_per_step": rb["ms_per_step"],
+                        "ms_per_step": rb["ms_per_step"], "sites": rb["sites"],
+                        "phases": rb["phases"],
                         "ratio_vs_fp32": rb["graphs_per_s"] / r["graphs_per_s"],
                         "graph_replay_value": rbg["graphs_per_s"],
                         "graph_replay_ratio_vs_fp32": rbg["graphs_per_s"] / rg["graphs_per_s"]}

@@ -311,7 +311,9 @@ int hgnn_op_fetch(hgnn_ctx *ctx, int32_t which, int32_t layer, void *dst_dev,
  * HIP events recorded on that launch's stream, for up to max_launches
  * launches.  Sites: 1 message GEMM, 2 aggregation, 3 update GEMM, 4 update
  * weight-gradient GEMM, 5 aggregate-gradient GEMM, 6 aggregation adjoint,
- * 7 input-gradient GEMM.  For GraphSAGE models site 3 is the layer GEMM and
+ * 7 input-gradient GEMM, 8 message weight-gradient GEMM (these time the
+ * kernel alone, not a split-K reduction after it), 9 the CSR build of a
+ * training-path forward (all of its launches).  For GraphSAGE models site 3 is the layer GEMM and
  * 4 its weight gradient; for CGCNN models 2 is the gated aggregation, 4 the
  * layer weight gradient, 6 the aggregation adjoint and 7 the input-gradient
  * GEMM.  Synchronises the device. */

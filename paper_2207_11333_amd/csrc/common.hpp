@@ -204,8 +204,9 @@ hipError_t launch_pad_copy(const Dims *dims, int capN, const float *x, int F,
 // gemm.hip
 // Picks the tile shape and the split count from the capacity capM and the
 // shape; g.splits/g.P are set here (P must hold nt_partial_floats()).
-// tag 1 names the update-linear instantiation; ev0/ev1 (optional) bracket
-// the GEMM kernel alone (not the split-K reduction).
+// tag names the launch site's instantiation (1 update, 2 message, 3
+// aggregate-input gradient, 4 layer-input gradient); ev0/ev1 (optional)
+// bracket the GEMM kernel alone (not the split-K reduction).
 hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
                           float *partials, hipStream_t s, int tag = 0,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
@@ -215,8 +216,10 @@ hipError_t launch_calib_copy(const float *src, float *dst, long long n, hipStrea
 int nt_splits(int capM, int Ncols, int Ktot, int precision);
 size_t nt_partial_floats(int capM, int Ncols, int Ktot, int precision);
 // Grid capacity: g.splits chunks, plus g.nb when bucketed.
+// tag names the launch site in profiles (1 update, 2 message weight gradient)
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
-                          hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                          hipStream_t s, int tag = 0, hipEvent_t ev0 = nullptr,
+                          hipEvent_t ev1 = nullptr);
 // reduce.hip
 hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s);
 hipError_t launch_reduce_upd(const ReduceUpd &r, hipStream_t s);

@@ -10,7 +10,9 @@ namespace {
 // --------------------------------------------------------------------------
 // NT form
 // --------------------------------------------------------------------------
-// TAG only distinguishes launch sites in profiles (1: the update linear).
+// TAG only distinguishes launch sites in profiles: 1 the update linear (S3),
+// 2 the message linear (S1), 3 the aggregate-input gradient (S6), 4 the
+// layer-input gradient (S6 + S8), 0 the others.
 // Waves form a 2 x WGN grid over the BM x BN tile (NTH = 128 WGN threads).
 // DB doubles the LDS tiles: tile t+1 is staged while tile t computes, with one
 // barrier per K step.  It needs 102 KB of LDS (FP32), so it is taken only
@@ -23,7 +25,7 @@ template <int PREC, int BM, int BN, bool SPLIT, int TAG, int WGN, bool DB>
 // the weight-gradient GEMM that runs beside this kernel on the second stream
 // then slows by 40% on the 8-layer hidden-256 workload (measured 63k vs 75k
 // graphs/s end to end).  DB: two, all that its LDS allows.
-__global__ void __launch_bounds__(128 * WGN, DB ? 2 : (PREC == 0 ? 4 : 5))
+__global__ void __launch_bounds__(128 * WGN, DB ? 2 : 4)
 k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   using P = Prec<PREC>;
   using T = typename P::T;
@@ -105,11 +107,11 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   const T *Bg = reinterpret_cast<const T *>(g.B) + (size_t)bq * g.bstride;
   const T *Blg = g.B_lo ? reinterpret_cast<const T *>(g.B_lo) + (size_t)bq * g.bstride : nullptr;
   // two register stages: tiles t and t+1 are in flight while t-1 computes.
-  // Loads are unconditional from clamped (in-bounds) addresses.  With DB the
-  // stages keep the raw values and the row/column masks are applied only
-  // when a stage is written to LDS (a select right after the load makes the
-  // compiler wait for that load at once); the single-buffer form masks at
-  // the load, which needs fewer registers.
+  // Loads are unconditional from clamped (in-bounds) addresses.  The stages
+  // keep the raw values and the row/column masks are applied only when a
+  // stage is written to LDS: a select right after the load makes the
+  // compiler wait for that load at once, so no load would overlap the
+  // products of the step that issued it.
   f4 ra[2][NA], rb[2][NB], rl[2][SPLIT ? NB : 1];
   float rs[2][NA];
   unsigned am[2], bm[2]; // bit j: element vector j is inside the matrix
@@ -156,9 +158,9 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
       q = il_first + (int)(r - 3u * (unsigned)kt);
     }
   };
-  // DB: loads of tile t into stage S; the stage keeps the raw values, the
-  // bits of the K-tail and edge masks and whether the segment has a row
-  // scale, all applied when it is stashed.
+  // Loads of tile t into stage S; the stage keeps the raw values, the bits of
+  // the K-tail and edge masks and whether the segment has a row scale, all
+  // applied when it is stashed.
   auto dload = [&](auto st, int t) {
     constexpr int S = decltype(st)::value;
     int q, kt;
@@ -188,43 +190,6 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
       mk |= (b_ok[j] && k < ks) ? 1u << j : 0u;
     }
     bm[S] = mk;
-  };
-  // single buffer: segment lookup and loads together, masks applied at once
-  auto load = [&](auto st, int t) {
-    constexpr int S = decltype(st)::value;
-    int q, kt;
-    locate(t, q, kt);
-    const float *aptr = g.seg[q].ptr;
-    const float *scale = g.seg[q].scale;
-    const int lda = g.seg[q].ld, ks = g.seg[q].k, boff = g.seg[q].boff;
-    const int k0 = kt * BK;
-    const float *sbase = scale ? scale : aptr;
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int k = k0 + a_col[j];
-      const f4 val = *reinterpret_cast<const f4 *>(aptr + (size_t)a_row[j] * lda + min(k, ks - 4));
-      ra[S][j] = (a_ok[j] && k < ks) ? val : f4{0.f, 0.f, 0.f, 0.f};
-      rs[S][j] = sbase[a_row[j]];
-    }
-    if (!scale) {
-#pragma unroll
-      for (int j = 0; j < NA; ++j) rs[S][j] = 1.0f;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int k = k0 + b_col[j];
-      const size_t off = (size_t)b_row[j] * g.ldb + boff + min(k, ks - BVEC);
-      const bool ok = b_ok[j] && k < ks;
-      const f4 val = *reinterpret_cast<const f4 *>(Bg + off);
-      rb[S][j] = ok ? val : f4{0.f, 0.f, 0.f, 0.f};
-      if constexpr (SPLIT) {
-        const f4 vlo = *reinterpret_cast<const f4 *>(Blg + off);
-        rl[S][j] = ok ? vlo : f4{0.f, 0.f, 0.f, 0.f};
-      }
-    }
-    am[S] = ~0u;
-    bm[S] = ~0u;
-    hs[S] = true; // rs already holds 1 where there is no scale
   };
   // register stage S goes to LDS buffer b (b = S when DB, else 0)
   auto stash_a = [&](auto st, auto buf) {
@@ -271,7 +236,7 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     __syncthreads();
     stash(st, IC<0>{});
     __syncthreads();
-    if (PREC == 1 || t + 2 < KT) load(st, t + 2);
+    if (PREC == 1 || t + 2 < KT) dload(st, t + 2);
     mma(IC<0>{});
   };
   // double buffer, on entry: LDS buffer S holds tile t, register stage 1-S
@@ -327,8 +292,8 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     }
     if (t < KT) dstep(IC<0>{}, t);
   } else {
-    if (KT > 0) load(IC<0>{}, 0);
-    if (KT > 1) load(IC<1>{}, 1);
+    if (KT > 0) dload(IC<0>{}, 0);
+    if (KT > 1) dload(IC<1>{}, 1);
     for (int t = 0; t < KT; t += 2) {
       step(IC<0>{}, t);
       if (t + 1 >= KT) break;
@@ -336,8 +301,22 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     }
   }
 
+  // Epilogue.  The rows of this lane's outputs (and, bucketed, their nodes)
+  // are fetched once, from clamped indices and without a branch, so their
+  // loads are in flight together; only the stores are predicated.
   const int lane = tid & 63;
   const int cr = 4 * (lane >> 4), cc = lane & 15;
+  int node[TM][4];
+  bool rok[TM][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = m0 + wm0 + i * 16 + cr + v;
+      rok[i][v] = r < m_hi;
+      const int rr = min(r, m_hi - 1);
+      node[i][v] = g.perm ? g.perm[rr] : rr;
+    }
   if (g.splits > 1) {
     float *Pz = g.P + (size_t)z * M * g.Ncols;
 #pragma unroll
@@ -347,36 +326,46 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = m0 + wm0 + i * 16 + cr + v;
-          if (r < m_hi) {
-            const int m = g.perm ? g.perm[r] : r;
-            Pz[(size_t)m * g.Ncols + n] = acc[i][j][v];
-          }
-        }
+        for (int v = 0; v < 4; ++v)
+          if (rok[i][v]) Pz[(size_t)node[i][v] * g.Ncols + n] = acc[i][j][v];
     }
     return;
   }
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int n = n0 + wn0 + j * 16 + cc;
-    if (n >= g.Ncols) continue;
-    const float bias = g.bias ? g.bias[n] : 0.f;
+    const bool nok = n < g.Ncols;
+    const int nc = min(n, g.Ncols - 1);
+    const float bias = g.bias ? g.bias[nc] : 0.f;
+    float o[TM][4];
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = m0 + wm0 + i * 16 + cr + v;
-        if (r < m_hi) {
-          const int m = g.perm ? g.perm[r] : r;
-          float o = acc[i][j][v] + bias;
-          if (g.addend) o += g.addend[(size_t)m * g.ld_add + n];
-          if (g.relu) o = o > 0.f ? o : 0.f;
-          if (g.mask && !(g.mask[(size_t)m * g.ldc + n] > 0.f)) o = 0.f;
-          g.C[(size_t)m * g.ldc + n] = o;
-        }
-      }
+      for (int v = 0; v < 4; ++v) o[i][v] = acc[i][j][v] + bias;
+    if (g.addend) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[i][v] += g.addend[(size_t)node[i][v] * g.ld_add + nc];
     }
+    if (g.relu) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[i][v] = o[i][v] > 0.f ? o[i][v] : 0.f;
+    }
+    if (g.mask) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (!(g.mask[(size_t)node[i][v] * g.ldc + nc] > 0.f)) o[i][v] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (nok && rok[i][v]) g.C[(size_t)node[i][v] * g.ldc + n] = o[i][v];
   }
 }
 
@@ -474,12 +463,21 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
   const long long grid =
       (long long)(cdiv(capM, kNtBM) + (g.perm ? g.nb : 0)) * cdiv(g.Ncols, kNtBN) * g.splits;
   const bool db = grid <= kNtDbMaxGrid && kt >= kNtDbMinKt * g.splits;
-  if (tag == 1) {
-    if (precision == 0) return run_nt<0, kNtBM, kNtBN, 1>(dims, capM, g, db, s, ev0, ev1);
-    return run_nt<1, kNtBM, kNtBN, 1>(dims, capM, g, db, s, ev0, ev1);
+  // one instantiation per launch site, so that profiles name the site
+  switch (tag) {
+#define HGNN_NT_TAG(T)                                                                    \
+  case T:                                                                                 \
+    if (precision == 0) return run_nt<0, kNtBM, kNtBN, T>(dims, capM, g, db, s, ev0, ev1); \
+    return run_nt<1, kNtBM, kNtBN, T>(dims, capM, g, db, s, ev0, ev1);
+    HGNN_NT_TAG(1)
+    HGNN_NT_TAG(2)
+    HGNN_NT_TAG(3)
+    HGNN_NT_TAG(4)
+#undef HGNN_NT_TAG
+  default:
+    if (precision == 0) return run_nt<0, kNtBM, kNtBN, 0>(dims, capM, g, db, s, ev0, ev1);
+    return run_nt<1, kNtBM, kNtBN, 0>(dims, capM, g, db, s, ev0, ev1);
   }
-  if (precision == 0) return run_nt<0, kNtBM, kNtBN, 0>(dims, capM, g, db, s, ev0, ev1);
-  return run_nt<1, kNtBM, kNtBN, 0>(dims, capM, g, db, s, ev0, ev1);
 }
 
 } // namespace hgnn

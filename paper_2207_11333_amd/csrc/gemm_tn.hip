@@ -10,7 +10,11 @@ namespace {
 // --------------------------------------------------------------------------
 // TN form (split-K weight gradients)
 // --------------------------------------------------------------------------
-template <int PREC, int BM, int BN>
+// TAG only distinguishes launch sites in profiles: 1 the update weight
+// gradient (S6), 2 the message weight gradient (S8), 0 the others.  PERM:
+// bucketed chunks (g.perm non-null), a template parameter so that the row
+// lookups add no branch to the loop.
+template <int PREC, int BM, int BN, int TAG, bool PERM>
 __global__ void __launch_bounds__(256)
 k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   using P = Prec<PREC>;
@@ -19,6 +23,8 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
   constexpr int NA = BM * BK / 4 / 256;
   constexpr int NB = BN * BK / 4 / 256;
+  // the A and B vectors of a thread lie in the same rows (a_il == b_il)
+  static_assert(BM == BN && NA == NB, "square tiles");
   // FP32 keeps the tiles in LDS as they lie in memory, k-major ([k][m] and
   // [k][n], rows padded by 4 floats), written with 16-byte stores; the MFMA
   // operands are read one k-slot at a time.  With a 68-float row pitch the
@@ -40,7 +46,7 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   chunk = (chunk + BK - 1) / BK * BK;
   int i_lo = z * chunk;
   int i_hi = min(rows, i_lo + chunk);
-  if (g.perm) {
+  if constexpr (PERM) {
     // bucket-pure chunks over the permuted rows: bucket q holds
     // ceil(n_q / chunk) chunks, in bucket order; the chunks past the last
     // are empty and write zero partials
@@ -73,9 +79,14 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   // Per-thread column pointers are fixed over the K loop (only the row i
-  // moves); loads are unconditional from clamped rows and masked by select.
+  // moves); loads are unconditional from clamped rows.  A stage keeps the
+  // raw values and one bit per vector of whether its row is inside the
+  // chunk; masks, constant columns and row scales are applied when the stage
+  // is written to LDS, so the loads stay in flight over the step's products
+  // (a select right after a load would make the compiler wait for it there).
   f4 ra[2][NA], rb[2][NB];
   float rsc[2][NB];
+  unsigned amk[2], bmk[2];
   int a_il[NA], a_m[NA];
   bool a_ok[NA];
 #pragma unroll
@@ -109,48 +120,66 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     if (b_ones[j]) b_ok[j] = b_ok[j] && n == 0;
   }
   const int i_last = max(i_hi - 1, 0);
-  auto load = [&](auto st, int t) {
-    constexpr int S = decltype(st)::value;
+  // Row ids (nodes) of tile t's rows into slot Q.  With bucketed chunks
+  // each is a load of the permutation: they are fetched one step before the
+  // data loads that use them and issued ahead of that step's data loads, so
+  // waiting for them never waits for data still in flight.
+  int prow[2][NA];
+  auto fetch_rows = [&](auto slot, int t) {
+    constexpr int Q = decltype(slot)::value;
     const int i0 = i_lo + t * BK;
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-      const int i = i0 + a_il[j];
-      int ic = min(i, i_last);
-      if (g.perm) ic = g.perm[ic];
-      const f4 val = *reinterpret_cast<const f4 *>(g.X + (size_t)ic * g.ldx + a_m[j]);
-      ra[S][j] = (a_ok[j] && i < i_hi) ? val : f4{0.f, 0.f, 0.f, 0.f};
+      const int ic = min(i0 + a_il[j], i_last);
+      if constexpr (PERM) prow[Q][j] = g.perm[ic];
+      else prow[Q][j] = ic;
     }
+  };
+  // data loads of tile t into stage S, from the row ids in slot S
+  auto load = [&](auto st, int t) {
+    constexpr int S = decltype(st)::value;
+    const int i0 = i_lo + t * BK;
+    unsigned mk = 0;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int i = i0 + a_il[j];
+      ra[S][j] = *reinterpret_cast<const f4 *>(g.X + (size_t)prow[S][j] * g.ldx + a_m[j]);
+      mk |= (a_ok[j] && i < i_hi) ? 1u << j : 0u;
+    }
+    amk[S] = mk;
+    mk = 0;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int i = i0 + b_il[j];
-      int ic = min(i, i_last);
-      if (g.perm) ic = g.perm[ic];
-      f4 val = *reinterpret_cast<const f4 *>(b_ptr[j] + (size_t)ic * b_ld[j]);
-      const float sv = b_sptr[j][(size_t)ic * b_sstride[j]];
-      const float sc = b_has_scale[j] ? sv : 1.0f;
-      if (b_ones[j]) val = f4{1.f, 0.f, 0.f, 0.f};
-      rb[S][j] = (b_ok[j] && i < i_hi) ? val : f4{0.f, 0.f, 0.f, 0.f};
-      rsc[S][j] = sc;
+      const int ic = prow[S][j];
+      rb[S][j] = *reinterpret_cast<const f4 *>(b_ptr[j] + (size_t)ic * b_ld[j]);
+      rsc[S][j] = b_sptr[j][(size_t)ic * b_sstride[j]];
+      mk |= (b_ok[j] && i < i_hi) ? 1u << j : 0u;
     }
+    bmk[S] = mk;
   };
   auto stash = [&](auto st) {
     constexpr int S = decltype(st)::value;
+    const f4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       const int v = tid + j * 256;
       const int il = v / (BM / 4), mc = (v % (BM / 4)) * 4;
+      const f4 av = (amk[S] >> j & 1u) ? ra[S][j] : zero;
       if constexpr (KMAJ) {
-        store4(As + il * LDKA + mc, ra[S][j]);
+        store4(As + il * LDKA + mc, av);
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) store1(As + (mc + e) * LDA + il, ra[S][j][e]);
+        for (int e = 0; e < 4; ++e) store1(As + (mc + e) * LDA + il, av[e]);
       }
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int v = tid + j * 256;
       const int il = v / (BN / 4), nc = (v % (BN / 4)) * 4;
-      const f4 val = rb[S][j] * rsc[S][j];
+      const f4 raw = b_ones[j] ? f4{1.f, 0.f, 0.f, 0.f} : rb[S][j];
+      const float sc = b_has_scale[j] ? rsc[S][j] : 1.0f;
+      const f4 val = (bmk[S] >> j & 1u) ? raw * sc : zero;
       if constexpr (KMAJ) {
         store4(Bs + il * LDKB + nc, val);
       } else {
@@ -182,17 +211,26 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
       }
     }
   };
+  // step t (stage S = t % 2): slot S holds tile t+2's rows (fetched in step
+  // t-1), slot 1-S is free (tile t+1's loads used it) and takes tile t+3's
   auto step = [&](auto st, int t) {
+    constexpr int S = decltype(st)::value;
     __syncthreads();
     stash(st);
     __syncthreads();
+    fetch_rows(IC<1 - S>{}, min(t + 3, KT - 1));
     load(st, min(t + 2, KT - 1));
     if constexpr (KMAJ) mma_kmajor();
     else mma_tile<PREC, TM, TN, LDA, BK>(As, Bs, wm0, wn0, acc);
   };
 
-  if (KT > 0) load(IC<0>{}, 0);
-  if (KT > 1) load(IC<1>{}, 1);
+  if (KT > 0) {
+    fetch_rows(IC<0>{}, 0);
+    load(IC<0>{}, 0);
+    fetch_rows(IC<1>{}, min(1, KT - 1));
+    if (KT > 1) load(IC<1>{}, 1);
+    fetch_rows(IC<0>{}, min(2, KT - 1));
+  }
   for (int t = 0; t < KT; t += 2) {
     step(IC<0>{}, t);
     if (t + 1 >= KT) break;
@@ -218,18 +256,27 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
 
 } // namespace
 
+template <int TAG, bool PERM>
+static void run_tn(const Dims *dims, const GemmTN &g, int precision, hipStream_t s,
+                   hipEvent_t ev0, hipEvent_t ev1, int grid, int nt) {
+  // a non-null event pair is stamped with the kernel's own start and end
+  if (precision == 0)
+    hipExtLaunchKernelGGL(k_gemm_tn<0, 64, 64, TAG, PERM>, dim3(grid), dim3(256), 0, s, ev0,
+                          ev1, 0, dims, g, nt);
+  else
+    hipExtLaunchKernelGGL(k_gemm_tn<1, 64, 64, TAG, PERM>, dim3(grid), dim3(256), 0, s, ev0,
+                          ev1, 0, dims, g, nt);
+}
+
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
-                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                          hipStream_t s, int tag, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.M <= 0 || g.Ncols <= 0) return hipSuccess;
   const int nt = cdiv(g.Ncols, 64);
   const int grid = cdiv(g.M, 64) * nt * (g.splits + (g.perm ? g.nb : 0));
-  // a non-null event pair is stamped with the kernel's own start and end
-  if (precision == 0)
-    hipExtLaunchKernelGGL(k_gemm_tn<0, 64, 64>, dim3(grid), dim3(256), 0, s, ev0, ev1, 0, dims,
-                          g, nt);
-  else
-    hipExtLaunchKernelGGL(k_gemm_tn<1, 64, 64>, dim3(grid), dim3(256), 0, s, ev0, ev1, 0, dims,
-                          g, nt);
+  if (tag == 1 && g.perm) run_tn<1, true>(dims, g, precision, s, ev0, ev1, grid, nt);
+  else if (tag == 1) run_tn<1, false>(dims, g, precision, s, ev0, ev1, grid, nt);
+  else if (tag == 2) run_tn<2, false>(dims, g, precision, s, ev0, ev1, grid, nt);
+  else run_tn<0, false>(dims, g, precision, s, ev0, ev1, grid, nt);
   return hipGetLastError();
 }
 

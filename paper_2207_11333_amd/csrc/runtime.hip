@@ -298,12 +298,15 @@ int prepare(hgnn_ctx *c, Exec &ex, const hgnn_batch *b, int flags, hipStream_t s
   Work &w = ex.w;
   // the first layer's padded input is written once here, while the CSR is
   // built; the batch's arrays are read at prepare time only
-  hipError_t e = launch_set_dims(ex.dims, b->num_graphs, b->num_nodes, b->num_edges,
-                                 w.csr.err, s);
-  if (e == hipSuccess)
-    e = launch_csr_build(ex.dims, b->num_graphs, b->num_nodes, b->num_edges, b->graph_ptr,
-                         b->edge_index, b->edge_attr, c->Fe, c->maxd, c->table, w.csr,
-                         /*clear_err=*/false, b->x, c->F0, w.xpad, c->F0p, s);
+  hipError_t e;
+  {
+    TimedLaunch tl(c, ex, SITE_CSR, s);
+    e = launch_set_dims(ex.dims, b->num_graphs, b->num_nodes, b->num_edges, w.csr.err, s);
+    if (e == hipSuccess)
+      e = launch_csr_build(ex.dims, b->num_graphs, b->num_nodes, b->num_edges, b->graph_ptr,
+                           b->edge_index, b->edge_attr, c->Fe, c->maxd, c->table, w.csr,
+                           /*clear_err=*/false, b->x, c->F0, w.xpad, c->F0p, s);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "csr build");
   ex.x_padded = true;
   ex.B = b->num_graphs;
@@ -344,8 +347,8 @@ static int message_and_aggregate(hgnn_ctx *c, Exec &ex, int l, const float *wl, 
   g.M_fixed = -1;
   hipError_t e;
   {
-    TimedLaunch tl(c, ex, SITE_MESSAGE_GEMM, s);
-    e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
+    TimedLaunch tl(c, ex, SITE_MESSAGE_GEMM, s, /*manual=*/true);
+    e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s, /*tag=*/2, tl.start(), tl.stop());
   }
   if (e != hipSuccess) return hip_fail(c, e, "message GEMM");
   const float *bm = wl + (d.obm - d.off);
@@ -490,7 +493,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     t.zscale = c->zscale;
     {
       TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, a, /*manual=*/true);
-      e = launch_gemm_tn(ex.dims, t, c->prec, a, tl.start(), tl.stop());
+      e = launch_gemm_tn(ex.dims, t, c->prec, a, /*tag=*/1, tl.start(), tl.stop());
     }
     if (e == hipSuccess) {
       ReduceUpd r{};
@@ -524,7 +527,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     t.splits = d.split_p;
     {
       TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, a, /*manual=*/true);
-      e = launch_gemm_tn(ex.dims, t, c->prec, a, tl.start(), tl.stop());
+      e = launch_gemm_tn(ex.dims, t, c->prec, a, /*tag=*/1, tl.start(), tl.stop());
     }
     if (e == hipSuccess) {
       ReduceMap r{};
@@ -568,8 +571,9 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     g.ldc = 4 * H;
     g.M_fixed = -1;
     {
-      TimedLaunch tl(c, ex, SITE_AGG_INPUT_GEMM, s);
-      e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
+      TimedLaunch tl(c, ex, SITE_AGG_INPUT_GEMM, s, /*manual=*/true);
+      e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s, /*tag=*/3, tl.start(),
+                         tl.stop());
     }
     if (e != hipSuccess) return hip_fail(c, e, "aggregate-input gradient GEMM");
   }
@@ -605,7 +609,10 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     t.Ncols = d.Fp + 4;
     t.P = c->part;
     t.splits = d.split_m;
-    e = launch_gemm_tn(ex.dims, t, c->prec, a);
+    {
+      TimedLaunch tl(c, ex, SITE_MESSAGE_WGRAD, a, /*manual=*/true);
+      e = launch_gemm_tn(ex.dims, t, c->prec, a, /*tag=*/2, tl.start(), tl.stop());
+    }
     if (e == hipSuccess) {
       const int ldm = 2 * d.F + Fe;
       ReduceMap r{};
@@ -645,8 +652,9 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     // C1 131k -> 126k)
     g.max_splits = c->prec ? 1 : 0;
     {
-      TimedLaunch tl(c, ex, SITE_INPUT_GEMM, s);
-      e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s);
+      TimedLaunch tl(c, ex, SITE_INPUT_GEMM, s, /*manual=*/true);
+      e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s, /*tag=*/4, tl.start(),
+                         tl.stop());
     }
     if (e != hipSuccess) return hip_fail(c, e, "input gradient GEMM");
   }

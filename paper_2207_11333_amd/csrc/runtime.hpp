@@ -82,7 +82,9 @@ enum Site : int {
   SITE_AGG_INPUT_GEMM = 5, // S6 gradient of the aggregates
   SITE_AGGREGATE_BWD = 6,  // S7 per-edge adjoint
   SITE_INPUT_GEMM = 7,     // S6+S8 input gradient
-  SITE_COUNT = 8
+  SITE_MESSAGE_WGRAD = 8,  // S8 weight gradient (split-K GEMM)
+  SITE_CSR = 9,            // S0 CSR build (all of its launches)
+  SITE_COUNT = 10
 };
 
 struct SiteTimer {

@@ -452,7 +452,8 @@ class Model:
 
     # -- measurement --
     SITES = {"message_gemm": 1, "aggregate": 2, "update_gemm": 3, "update_wgrad": 4,
-             "agg_input_gemm": 5, "aggregate_bwd": 6, "input_gemm": 7}
+             "agg_input_gemm": 5, "aggregate_bwd": 6, "input_gemm": 7, "message_wgrad": 8,
+             "csr": 9}
 
     def timer_start(self, site: str, max_launches: int = 4096):
         _check(lib().hgnn_timer_start(self.handle, self.SITES[site], max_launches))
