@@ -25,7 +25,7 @@ template <int PREC, int BM, int BN, bool SPLIT, int TAG, int WGN, bool DB>
 // the weight-gradient GEMM that runs beside this kernel on the second stream
 // then slows by 40% on the 8-layer hidden-256 workload (measured 63k vs 75k
 // graphs/s end to end).  DB: two, all that its LDS allows.
-__global__ void __launch_bounds__(128 * WGN, DB ? 2 : 4)
+__global__ void __launch_bounds__(128 * WGN, (DB || BM * BN > 8192) ? 2 : 4)
 k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   using P = Prec<PREC>;
   using T = typename P::T;

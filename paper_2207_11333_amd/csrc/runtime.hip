@@ -59,16 +59,24 @@ template <typename T> static hipError_t dalloc(T *&p, size_t count) {
   return e;
 }
 
-// Split count of a weight-gradient GEMM: at least 1024 workgroups in all for
-// FP32 operands, 512 for BF16, whose tiles finish sooner so that the partial
-// traffic weighs more (measured on the hidden-128 step: FP32 +2.4% at 1024,
-// BF16 -1.4%; 256 is slower in both even though the partial traffic halves).
+// Split count of a weight-gradient GEMM.  FP32 (64 x 64 tiles): at least
+// 1024 workgroups in all (measured on the hidden-128 step: +2.4% against
+// 512; 256 is slower even though the partial traffic halves).  BF16
+// (128 x 128 tiles, gemm_tn.hip): about 384 workgroups, at most 32 splits
+// (measured at 40k and 4.5k nodes: 16-32 splits are fastest).
+// Batches of at least this many nodes take the De rows of the message
+// weight gradient apart (two more launches save a third of its products;
+// measured: a gain at 40k nodes, a loss at 4.5k, where the launches lie on
+// the critical path of the backward pass).
+constexpr int kSplitDeRows = 16384;
+
 int tn_splits(int M, int Ncols, int precision) {
-  const int tiles = ((M + 63) / 64) * ((Ncols + 63) / 64);
-  const int target = precision ? 512 : 1024;
+  const int T = precision ? 128 : 64;
+  const int tiles = ((M + T - 1) / T) * ((Ncols + T - 1) / T);
+  const int target = precision ? 384 : 1024;
   int s = (target + tiles - 1) / tiles;
   if (s < 1) s = 1;
-  if (s > 64) s = 64;
+  if (s > (precision ? 32 : 64)) s = precision ? 32 : 64;
   return s;
 }
 
@@ -597,18 +605,22 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   e = hipEventRecord(c->fork_ev[1], s);
   if (e == hipSuccess) e = hipStreamWaitEvent(a, c->fork_ev[1], 0);
   if (e != hipSuccess) return hip_fail(c, e, "fork");
-  // S8: [dW_dst | dW_src] = [D_in | D_out]^T h
+  // S8: [dW_dst | dW_src] = [D_in | D_out]^T h, db^m = sum_i D_in, and the
+  // edge-feature columns sum_i De_i = sum_k dm_k e_k (the sum column of the
+  // De rows, whose product with h is not needed: for large batches those
+  // rows get a GEMM of their own with the sum column alone)
+  const bool split_de = Fe > 0 && ex.N >= kSplitDeRows;
   {
     GemmTN t{};
     t.X = w.D;
     t.ldx = ldD;
-    t.M = ldD;
+    t.M = split_de ? 2 * H : ldD;
     t.nseg = 2;
     t.seg[0] = SegY{hin, nullptr, ldh, d.Fp};
     t.seg[1] = SegY{nullptr, nullptr, 0, 4}; // sum column: db^m and the e_k weights
     t.Ncols = d.Fp + 4;
     t.P = c->part;
-    t.splits = d.split_m;
+    t.splits = split_de ? d.split_m2 : d.split_m;
     {
       TimedLaunch tl(c, ex, SITE_MESSAGE_WGRAD, a, /*manual=*/true);
       e = launch_gemm_tn(ex.dims, t, c->prec, a, /*tag=*/2, tl.start(), tl.stop());
@@ -617,8 +629,8 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       const int ldm = 2 * d.F + Fe;
       ReduceMap r{};
       r.P = c->part;
-      r.splits = d.split_m;
-      r.M = ldD;
+      r.splits = t.splits;
+      r.M = t.M;
       r.Ncols = d.Fp + 4;
       r.main_cols = d.Fp;
       r.F = d.F;
@@ -626,8 +638,35 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       r.route[0] = ReduceRoute{0, H, dWm, ldm, 0, dbm, 1, H};               // D_in
       r.route[1] = ReduceRoute{H, 2 * H, dWm, ldm, d.F, nullptr, 0, 1};      // D_out
       r.route[2] = ReduceRoute{2 * H, ldD, nullptr, 0, 0, dWm + 2 * d.F, ldm, H}; // De
-      r.nroute = Fe > 0 ? 3 : 2;
+      r.nroute = (Fe > 0 && !split_de) ? 3 : 2;
       e = launch_reduce_map(r, a);
+    }
+    if (e == hipSuccess && split_de) {
+      // column sums of De: a product with the constant-one column only
+      GemmTN te{};
+      te.X = w.D + 2 * H;
+      te.ldx = ldD;
+      te.M = Fe * H;
+      te.seg[0] = SegY{nullptr, nullptr, 0, 4};
+      te.nseg = 1;
+      te.Ncols = 4;
+      te.P = c->part;
+      te.splits = d.split_e;
+      e = launch_gemm_tn(ex.dims, te, c->prec, a);
+      if (e == hipSuccess) {
+        const int ldm = 2 * d.F + Fe;
+        ReduceMap r{};
+        r.P = c->part;
+        r.splits = d.split_e;
+        r.M = Fe * H;
+        r.Ncols = 4;
+        r.main_cols = 0;
+        r.F = 0;
+        r.Fp = 0;
+        r.route[0] = ReduceRoute{0, Fe * H, nullptr, 0, 0, dWm + 2 * d.F, ldm, H}; // De
+        r.nroute = 1;
+        e = launch_reduce_map(r, a);
+      }
     }
     if (e != hipSuccess) return hip_fail(c, e, "message weight gradient");
   }
@@ -1255,11 +1294,18 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
     // with degree buckets, [h | A | sum] over nb more (bucket-pure) chunks
     const int wcols = d.Fp + (c->nb ? 4 : 12) * H + 4;
     d.split_p = tn_splits(H, wcols, cfg->precision);
+    // message weight gradient: [D_in | D_out | De]^T [h | 1] in one GEMM, or
+    // for large batches [D_in | D_out]^T [h | 1] and the column sums of De
+    // apart (the De^T h block is not needed; see kSplitDeRows)
     d.split_m = tn_splits((2 + c->Fe) * H, d.Fp + 4, cfg->precision);
+    d.split_m2 = tn_splits(2 * H, d.Fp + 4, cfg->precision);
+    d.split_e = c->Fe ? tn_splits(c->Fe * H, 4, cfg->precision) : 0;
     zmax = std::max(zmax, d.split_p + c->nb);
     const size_t a = (size_t)(d.split_p + c->nb) * H * wcols;
-    const size_t b = (size_t)d.split_m * (2 + c->Fe) * H * (d.Fp + 4);
-    part_max = std::max(part_max, std::max(a, b));
+    const size_t b = std::max((size_t)d.split_m * (2 + c->Fe) * H * (d.Fp + 4),
+                              (size_t)d.split_m2 * 2 * H * (d.Fp + 4));
+    const size_t e = (size_t)d.split_e * c->Fe * H * 4;
+    part_max = std::max(part_max, std::max(a, std::max(b, e)));
     c->ld.push_back(d);
   }
   c->Tg = Tg;

@@ -212,6 +212,42 @@ def test_fp32_forward_backward_parity(name):
     m.close()
 
 
+@pytest.mark.parametrize("Fe", [1, 2])
+def test_large_batch_fp32_parity(Fe):
+    """A batch above 16,384 atoms, where the message weight gradient takes the
+    De rows apart (their column sums in a GEMM of their own): FP32 parity of
+    predictions, loss and every gradient tensor (decision replay), with a
+    2-layer hidden-32 model so that the FP64 oracle stays quick."""
+    b = synth.make_batch(777 + Fe, 500, 20, 50, Fe)
+    assert b.num_nodes >= 16384
+    L, H, delta = 2, 32, 1.3
+    shape = synth.ModelShape(L, H, 9, Fe)
+    params = synth.init_params(shape, 99 + Fe)
+    say(f"large fp32 Fe={Fe}: N={b.num_nodes} E={b.num_edges}")
+    m = make_model(L, H, Fe, 0, 0, delta)
+    out = run_train_step(m, b, params)
+    rec = oracle.forward(params, b, L, H, delta)
+    pred = out["pred"].cpu().numpy()
+    r_pred, e_pred = rel(pred, rec.y), maxrel(pred, rec.y)
+    r_loss = rel([out["loss"].item()], [rec.loss])
+    dec = gpu_decisions(m, L, H, b.num_nodes, b.num_graphs)
+    g_ref, _, stats = oracle.backward(rec, hint=dec, tau=TAU_FP32)
+    g = out["grads"].cpu().numpy()
+    rep = grad_report(m, g, g_ref, shape)
+    erep = grad_report(m, g, g_ref, shape, elementwise=True)
+    worst = max(rep, key=rep.get)
+    eworst = max(erep, key=erep.get)
+    say(f"  pred rel {r_pred:.2e} (element-wise {e_pred:.2e}) loss rel {r_loss:.2e}; "
+        f"worst grad {worst} {rep[worst]:.2e}; element-wise {eworst} {erep[eworst]:.2e}; "
+        f"adopted {stats}")
+    assert r_pred <= 1e-5 and r_loss <= 1e-5 and e_pred <= ELEM_FP32
+    for k, v in rep.items():
+        assert v <= 1e-5, (k, v)
+    for k, v in erep.items():
+        assert v <= ELEM_FP32, (k, v)
+    m.close()
+
+
 def test_recompute_matches_stored_activations():
     w = synth.WORKLOADS["c0_small_fp32"]
     b, params = w.batch(), w.params()
