@@ -79,8 +79,7 @@ __device__ __forceinline__ void stage_elem(const float *__restrict__ Wm,
   const int wu = nb ? Fp + 4 * H : Fp + 12 * H; // row width of the update copy
   const long long n1 = 2LL * H * Fp;
   const long long n2 = (long long)(nb ? nb : 1) * H * wu;
-  const long long n3 = nb ? 4LL * nb * H * H : 12LL * H * H;
-  const long long n4 = 3LL * Fp * H, n5 = (long long)Fe * H;
+  const long long n5 = (long long)Fe * H;
   if (t < n1) {
     const int r = (int)(t / Fp), c = (int)(t % Fp);
     float v = 0.f;
@@ -96,33 +95,110 @@ __device__ __forceinline__ void stage_elem(const float *__restrict__ Wm,
     else if (nb) v = w_eff(Wp, ldp, F, H, table, q, r, c - Fp);
     else v = Wp[(size_t)r * ldp + F + (c - Fp)];
     put<T>(o.hi[1], o.lo[1], u, v);
-  } else if (t < n1 + n2 + n3) {
+  } else if (t < n1 + n2 + n5) {
     const long long u = t - n1 - n2;
-    if (nb) {
-      const int q = (int)(u / (4LL * H * H));
-      const int r = (int)((u / H) % (4 * H)), m = (int)(u % H);
-      put<T>(o.hi[2], o.lo[2], u, w_eff(Wp, ldp, F, H, table, q, m, r));
-    } else {
-      const int r = (int)(u / (3 * H)), c = (int)(u % (3 * H));
-      const int j = c / H, m = c % H;
-      put<T>(o.hi[2], o.lo[2], u, Wp[(size_t)m * ldp + F + 4 * H * j + r]);
-    }
-  } else if (t < n1 + n2 + n3 + n4) {
-    const long long u = t - n1 - n2 - n3;
-    const int r = (int)(u / (3 * H)), c = (int)(u % (3 * H));
-    const int j = c / H, m = c % H;
-    float v = 0.f;
-    if (r < F) {
-      if (j == 0) v = Wp[(size_t)m * ldp + r];
-      else if (j == 1) v = Wm[(size_t)m * ldm + r];
-      else v = Wm[(size_t)m * ldm + F + r];
-    }
-    put<T>(o.hi[3], o.lo[3], u, v);
-  } else if (t < n1 + n2 + n3 + n4 + n5) {
-    const long long u = t - n1 - n2 - n3 - n4;
     const int f = (int)(u / H), c = (int)(u % H);
     o.weT[u] = Wm[(size_t)c * ldm + 2 * F + f];
   }
+}
+
+// The transposed copies (WpTA and WhdsT of the layout above), through LDS in
+// 32 x 32 tiles so that both the reads of W^p / W^m rows and the writes are
+// coalesced: dst[c, col0 + m] = sum_s coef_s src_s[m, c] for m < H, c < C
+// (zero for c >= cvalid).  Tile jobs per layer:
+//  bucketed: nb jobs, job q: C = 4H, dst = WpTA + q 4H H (ld H), sources
+//            the W_0, W_+, W_- blocks with 1, s+(q), s-(q);
+//  else:     3 jobs, job j: C = 4H, dst = WpTA (ld 3H) at column j H, source
+//            the block j of W^p's 12H aggregate columns;
+//  then 3 WhdsT jobs, job j: C = Fp (F valid), dst = WhdsT (ld 3H) at column
+//  j H, source W^p[:, 0:F], W^m[:, 0:F] or W^m[:, F:2F].
+template <typename T>
+__device__ void stage_transposed(const float *__restrict__ Wm, const float *__restrict__ Wp,
+                                 int F, int Fp, int H, int Fe, int nb,
+                                 const float *__restrict__ table, const StageOut &o,
+                                 int tile) {
+  __shared__ float tl[32][33];
+  const int ldm = 2 * F + Fe, ldp = F + 12 * H;
+  const int mt = (H + 31) / 32;
+  const int ta = ((4 * H + 31) / 32) * mt; // tiles of one WpTA job
+  const int tw = ((Fp + 31) / 32) * mt;    // tiles of one WhdsT job
+  const int na = nb ? nb : 3;
+  int job, jt, C, cvalid, ld_dst, col0, nsrc = 1;
+  const float *src[3] = {nullptr, nullptr, nullptr};
+  float coef[3] = {1.f, 0.f, 0.f};
+  int ld_src;
+  void *dhi, *dlo;
+  size_t dbase = 0;
+  if (tile < na * ta) {
+    job = tile / ta;
+    jt = tile % ta;
+    C = cvalid = 4 * H;
+    ld_src = ldp;
+    dhi = o.hi[2];
+    dlo = o.lo[2];
+    if (nb) {
+      dbase = (size_t)job * 4 * H * H;
+      ld_dst = H;
+      col0 = 0;
+      src[0] = Wp + F;
+      src[1] = Wp + F + 4 * H;
+      src[2] = Wp + F + 8 * H;
+      coef[1] = table[2 * job];
+      coef[2] = table[2 * job + 1];
+      nsrc = 3;
+    } else {
+      ld_dst = 3 * H;
+      col0 = job * H;
+      src[0] = Wp + F + 4 * H * job;
+    }
+  } else {
+    tile -= na * ta;
+    if (tile >= 3 * tw) return;
+    job = tile / tw;
+    jt = tile % tw;
+    C = Fp;
+    cvalid = F;
+    ld_dst = 3 * H;
+    col0 = job * H;
+    dhi = o.hi[3];
+    dlo = o.lo[3];
+    src[0] = job == 0 ? Wp : (job == 1 ? Wm : Wm + F);
+    ld_src = job == 0 ? ldp : ldm;
+  }
+  const int c0 = (jt / mt) * 32, m0 = (jt % mt) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5; // 32 x 8 threads
+  // read rows m (coalesced along c) into the tile
+  for (int r = ty; r < 32; r += 8) {
+    const int m = m0 + r, c = c0 + tx;
+    float v = 0.f;
+    if (m < H && c < cvalid) {
+      const size_t off = (size_t)m * ld_src + c;
+      v = src[0][off];
+      if (nsrc == 3) v = fmaf(coef[2], src[2][off], fmaf(coef[1], src[1][off], v));
+    }
+    tl[r][tx] = v;
+  }
+  __syncthreads();
+  // write rows c (coalesced along m)
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r, m = m0 + tx;
+    if (c < C && m < H) put<T>(dhi, dlo, dbase + (size_t)c * ld_dst + col0 + m, tl[tx][r]);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_stage_t_all(const StageDesc *__restrict__ tab, int H, int Fe, int nb,
+              const float *__restrict__ table) {
+  const StageDesc &d = tab[blockIdx.y];
+  stage_transposed<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, nb, table, d.o, blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_stage_t_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F, int Fp,
+                int H, int Fe, int nb, const float *__restrict__ table, StageOut o) {
+  stage_transposed<T>(Wm, Wp, F, Fp, H, Fe, nb, table, o, blockIdx.x);
 }
 
 template <typename T>
@@ -169,19 +245,29 @@ hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_
   return hipGetLastError();
 }
 
+// elements of the untransposed copies (Wds, Wpp, weT) of one layer
 static long long stage_total(int Fp, int H, int Fe, int nb) {
   const long long nbk = nb ? nb : 1;
-  return 2LL * H * Fp + nbk * H * (Fp + (nb ? 4 : 12) * H) + (nb ? 4 * nbk : 12LL) * H * H +
-         3LL * Fp * H + (long long)Fe * H;
+  return 2LL * H * Fp + nbk * H * (Fp + (nb ? 4 : 12) * H) + (long long)Fe * H;
+}
+
+// 32 x 32 tiles of the transposed copies of one layer
+static int stage_t_tiles(int Fp, int H, int nb) {
+  const int mt = (H + 31) / 32;
+  return (nb ? nb : 3) * ((4 * H + 31) / 32) * mt + 3 * ((Fp + 31) / 32) * mt;
 }
 
 hipError_t launch_stage_all(const StageDesc *tab, int L, int maxFp, int H, int Fe, int nb,
                             const float *table, int to_bf16, long long *bump, hipStream_t s) {
   const dim3 grid(cdiv(stage_total(maxFp, H, Fe, nb), 256), L);
-  if (to_bf16)
+  const dim3 grid_t(stage_t_tiles(maxFp, H, nb), L);
+  if (to_bf16) {
     k_stage_all<__bf16><<<grid, 256, 0, s>>>(tab, H, Fe, nb, table, bump);
-  else
+    k_stage_t_all<__bf16><<<grid_t, 256, 0, s>>>(tab, H, Fe, nb, table);
+  } else {
     k_stage_all<float><<<grid, 256, 0, s>>>(tab, H, Fe, nb, table, bump);
+    k_stage_t_all<float><<<grid_t, 256, 0, s>>>(tab, H, Fe, nb, table);
+  }
   return hipGetLastError();
 }
 
@@ -189,10 +275,14 @@ hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp, i
                               int Fe, int nb, const float *table, const StageOut &o,
                               int to_bf16, hipStream_t s) {
   const long long total = stage_total(Fp, H, Fe, nb);
-  if (to_bf16)
+  const int tiles = stage_t_tiles(Fp, H, nb);
+  if (to_bf16) {
     k_stage_layer<__bf16><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
-  else
+    k_stage_t_layer<__bf16><<<tiles, 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
+  } else {
     k_stage_layer<float><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
+    k_stage_t_layer<float><<<tiles, 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
+  }
   return hipGetLastError();
 }
 
