@@ -59,21 +59,22 @@ template <typename T> static hipError_t dalloc(T *&p, size_t count) {
   return e;
 }
 
-// Split count of a weight-gradient GEMM.  FP32 (64 x 64 tiles): at least
-// 1024 workgroups in all (measured on the hidden-128 step: +2.4% against
-// 512; 256 is slower even though the partial traffic halves).  BF16
-// (128 x 128 tiles, gemm_tn.hip): about 384 workgroups, at most 32 splits
-// (measured at 40k and 4.5k nodes: 16-32 splits are fastest).
 // Batches of at least this many nodes take the De rows of the message
 // weight gradient apart (two more launches save a third of its products;
 // measured: a gain at 40k nodes, a loss at 4.5k, where the launches lie on
 // the critical path of the backward pass).
 constexpr int kSplitDeRows = 16384;
 
+// Split count of a weight-gradient GEMM (GEMM and ordered reduction timed
+// together at 4.5k and 40k nodes).  FP32 (64 x 64 tiles): about 512
+// workgroups (the update and message weight gradients at 4.5k nodes: 26
+// and 19 us, against 28 and 21 us at 1024).  BF16 (128 x 128 tiles,
+// gemm_tn.hip): about 384 workgroups, at most 32 splits (16-32 splits are
+// fastest at both sizes).
 int tn_splits(int M, int Ncols, int precision) {
   const int T = precision ? 128 : 64;
   const int tiles = ((M + T - 1) / T) * ((Ncols + T - 1) / T);
-  const int target = precision ? 384 : 1024;
+  const int target = precision ? 384 : 512;
   int s = (target + tiles - 1) / tiles;
   if (s < 1) s = 1;
   if (s > (precision ? 32 : 64)) s = precision ? 32 : 64;
@@ -685,11 +686,6 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     g.ldc = d.F;
     g.M_fixed = -1;
     g.mask = (mask_dh_in && l > 0) ? h_in : nullptr;
-    // BF16: unsplit, so the CUs a K split would take are left to the message
-    // weight-gradient GEMM running beside this one and no reduction follows
-    // (C2 169k -> 172k graphs/s; FP32, whose unsplit GEMM is slower, loses:
-    // C1 131k -> 126k)
-    g.max_splits = c->prec ? 1 : 0;
     {
       TimedLaunch tl(c, ex, SITE_INPUT_GEMM, s, /*manual=*/true);
       e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s, /*tag=*/4, tl.start(),
