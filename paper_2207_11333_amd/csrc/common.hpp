@@ -223,6 +223,11 @@ hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
 // reduce.hip
 hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s);
 hipError_t launch_reduce_upd(const ReduceUpd &r, hipStream_t s);
+// Column sums of X [dims->N, C] (leading dimension ldx) over Z fixed row
+// chunks into P [Z][C][4] (sum in element 0, zeros after): partials in the
+// layout of a weight-gradient GEMM's sum column, for launch_reduce_map.
+hipError_t launch_colsum(const Dims *dims, const float *X, int ldx, int C, int Z, float *P,
+                         hipStream_t s);
 hipError_t launch_reduce_nt(const Dims *dims, int capM, const GemmNT &g, hipStream_t s);
 
 // aggregate.hip

@@ -170,7 +170,38 @@ __global__ void __launch_bounds__(256) k_reduce_upd(const ReduceUpd r) {
   }
 }
 
+// Column sums of X [N rows, C columns] over fixed row chunks: chunk z of
+// Z covers rows [z R, (z + 1) R), R = ceil(N / Z); each thread owns one
+// column and adds the chunk's rows in order with four interleaved partial
+// sums (rows r mod 4) combined at the end in a fixed order.  The partials are
+// written as P[z][c][0..3] = {sum, 0, 0, 0}: the layout of a weight-gradient
+// GEMM's sum column, so that launch_reduce_map adds them.
+__global__ void __launch_bounds__(256)
+k_colsum(const Dims *__restrict__ dims, const float *__restrict__ X, int ldx, int C, int Z,
+         float *__restrict__ P) {
+  const int c = blockIdx.y * 256 + threadIdx.x, z = blockIdx.x;
+  if (c >= C) return;
+  const int N = dims->N;
+  const int R = (N + Z - 1) / Z;
+  const int lo = min(z * R, N), hi = min(lo + R, N);
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  int i = lo;
+  for (; i + 4 <= hi; i += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] += X[(size_t)(i + u) * ldx + c];
+  }
+  for (int u = 0; i < hi; ++i, ++u) s[u] += X[(size_t)i * ldx + c];
+  *reinterpret_cast<f4 *>(P + ((size_t)z * C + c) * 4) = f4{(s[0] + s[1]) + (s[2] + s[3]), 0.f, 0.f, 0.f};
+}
+
 } // namespace
+
+hipError_t launch_colsum(const Dims *dims, const float *X, int ldx, int C, int Z, float *P,
+                         hipStream_t s) {
+  if (C <= 0 || Z <= 0) return hipSuccess;
+  k_colsum<<<dim3(Z, cdiv(C, 256)), 256, 0, s>>>(dims, X, ldx, C, Z, P);
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce_upd(const ReduceUpd &r, hipStream_t s) {
   const long long total = (long long)r.M * r.Ncols;

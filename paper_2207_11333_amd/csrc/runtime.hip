@@ -64,6 +64,9 @@ template <typename T> static hipError_t dalloc(T *&p, size_t count) {
 // measured: a gain at 40k nodes, a loss at 4.5k, where the launches lie on
 // the critical path of the backward pass).
 constexpr int kSplitDeRows = 16384;
+// Row chunks of the De column sums (at 40k rows: about 320 rows per chunk;
+// the sums then cost about as much as reading De once)
+constexpr int kColsumChunks = 128;
 
 // Split count of a weight-gradient GEMM (GEMM and ordered reduction timed
 // together at 4.5k and 40k nodes).  FP32 (64 x 64 tiles): about 512
@@ -643,22 +646,13 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       e = launch_reduce_map(r, a);
     }
     if (e == hipSuccess && split_de) {
-      // column sums of De: a product with the constant-one column only
-      GemmTN te{};
-      te.X = w.D + 2 * H;
-      te.ldx = ldD;
-      te.M = Fe * H;
-      te.seg[0] = SegY{nullptr, nullptr, 0, 4};
-      te.nseg = 1;
-      te.Ncols = 4;
-      te.P = c->part;
-      te.splits = d.split_e;
-      e = launch_gemm_tn(ex.dims, te, c->prec, a);
+      // column sums of De over kColsumChunks row chunks
+      e = launch_colsum(ex.dims, w.D + 2 * H, ldD, Fe * H, kColsumChunks, c->part, a);
       if (e == hipSuccess) {
         const int ldm = 2 * d.F + Fe;
         ReduceMap r{};
         r.P = c->part;
-        r.splits = d.split_e;
+        r.splits = kColsumChunks;
         r.M = Fe * H;
         r.Ncols = 4;
         r.main_cols = 0;
@@ -1295,12 +1289,12 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
     // apart (the De^T h block is not needed; see kSplitDeRows)
     d.split_m = tn_splits((2 + c->Fe) * H, d.Fp + 4, cfg->precision);
     d.split_m2 = tn_splits(2 * H, d.Fp + 4, cfg->precision);
-    d.split_e = c->Fe ? tn_splits(c->Fe * H, 4, cfg->precision) : 0;
+
     zmax = std::max(zmax, d.split_p + c->nb);
     const size_t a = (size_t)(d.split_p + c->nb) * H * wcols;
     const size_t b = std::max((size_t)d.split_m * (2 + c->Fe) * H * (d.Fp + 4),
                               (size_t)d.split_m2 * 2 * H * (d.Fp + 4));
-    const size_t e = (size_t)d.split_e * c->Fe * H * 4;
+    const size_t e = (size_t)kColsumChunks * c->Fe * H * 4;
     part_max = std::max(part_max, std::max(a, std::max(b, e)));
     c->ld.push_back(d);
   }

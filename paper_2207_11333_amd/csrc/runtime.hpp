@@ -15,8 +15,7 @@ struct LayerDesc {
   int64_t off, oWm, obm, oWp, obp; // offsets into the packed vector
   int64_t size;
   int split_p, split_m;            // split-K counts of the two weight gradients
-  int split_m2, split_e;           // message weight gradient without the De
-                                   // rows, and the De column sums
+  int split_m2;                    // message weight gradient without the De rows
 };
 
 // Capacity-sized device buffers of one batch.

@@ -5,6 +5,8 @@
     python -m paper_2207_11333_amd.profile_summary traffic \\
         --fetch FETCH_CSV --write WRITE_CSV --kernel NAME --calib-bytes B \\
         --sources FILE ... --title TEXT --command CMD ... -o OUT.txt
+    python -m paper_2207_11333_amd.profile_summary counters COUNTER_CSV \\
+        --kernel NAME ... [--flops F ...] --title TEXT --command CMD -o OUT.txt
 
 The traffic summary reads two counter-collection runs (one ``--pmc FETCH_SIZE``,
 one ``--pmc WRITE_SIZE``), in each of which the first dispatch of the plain copy
@@ -121,6 +123,59 @@ def traffic(fetch_csv, write_csv, kernel, calib_bytes, sources, title, commands,
         f.write("\n".join(lines) + "\n")
 
 
+def counters(csv_path, kernels, simds, title, commands, out, flops=None, xcds=8):
+    """Per kernel family (a name substring): the per-dispatch mean of every
+    counter in one counter-collection CSV, with the derived MFMA and LDS
+    figures of the counter definitions: MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES
+    / (GRBM_GUI_ACTIVE per XCD x SIMDs) (the CSV sums GRBM_GUI_ACTIVE over
+    the XCDs; a counter run serialises the dispatches, so this active time is
+    longer than the kernel's traced duration), executed MFMA FLOPs = MOPS x
+    512, LDS bank conflicts per conflict-free LDS cycle = SQ_LDS_BANK_CONFLICT
+    / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT).  flops: optional algorithmic
+    FLOPs per dispatch of each family, to compare with the executed count."""
+    rows = list(csv.DictReader(open(csv_path)))
+    names = sorted({r["Counter_Name"] for r in rows})
+    lines = [f"# {title}"]
+    lines += [f"# command: {c}" for c in commands]
+    lines += ["# per-dispatch means of rocprofv3 --pmc counters; derived figures as in",
+              "# the counter definitions (SIMDs = %d, GRBM_GUI_ACTIVE / %d XCDs)" % (simds, xcds),
+              ""]
+    for i, k in enumerate(kernels):
+        sel = [r for r in rows if k in r["Kernel_Name"]]
+        if not sel:
+            raise SystemExit(f"no dispatch of {k!r}")
+        nd = len({r["Dispatch_Id"] for r in sel})
+        mean = {}
+        for n in names:
+            v = [float(r["Counter_Value"]) for r in sel if r["Counter_Name"] == n]
+            if v:
+                mean[n] = sum(v) / len(v)
+        lines.append(f"kernel: {k}")
+        lines.append(f"  dispatches: {nd}")
+        for n in names:
+            if n in mean:
+                lines.append(f"  {n}: {mean[n]:.1f}")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in mean and mean.get("GRBM_GUI_ACTIVE"):
+            gui = mean["GRBM_GUI_ACTIVE"] / xcds
+            lines.append(f"  mfma_busy_cycles_per_simd: {mean['SQ_VALU_MFMA_BUSY_CYCLES'] / simds:.0f}")
+            lines.append(f"  mfma_busy: {mean['SQ_VALU_MFMA_BUSY_CYCLES'] / (gui * simds):.4f}")
+        mops = sum(mean.get(n, 0.0) for n in ("SQ_INSTS_VALU_MFMA_MOPS_F32",
+                                                "SQ_INSTS_VALU_MFMA_MOPS_BF16",
+                                                "SQ_INSTS_VALU_MFMA_MOPS_F16"))
+        if mops:
+            lines.append(f"  mfma_flops_executed: {mops * 512:.4g}")
+            if flops and i < len(flops) and flops[i]:
+                lines.append(f"  mfma_flops_algorithmic: {flops[i]:.4g}")
+                lines.append(f"  executed_over_algorithmic: {mops * 512 / flops[i]:.3f}")
+        if "SQ_LDS_BANK_CONFLICT" in mean and "SQ_LDS_IDX_ACTIVE" in mean:
+            free = mean["SQ_LDS_IDX_ACTIVE"] - mean["SQ_LDS_BANK_CONFLICT"]
+            if free > 0:
+                lines.append(f"  lds_bank_conflict_ratio: {mean['SQ_LDS_BANK_CONFLICT'] / free:.3f}")
+        lines.append("")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -141,9 +196,20 @@ def main():
     t.add_argument("--title", required=True)
     t.add_argument("--command", action="append", default=[])
     t.add_argument("-o", "--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--kernel", action="append", required=True)
+    c.add_argument("--flops", type=float, action="append", default=None)
+    c.add_argument("--simds", type=int, default=1024)
+    c.add_argument("--xcds", type=int, default=8)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", action="append", default=[])
+    c.add_argument("-o", "--out", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         kernel_stats(a.csv, a.steps, a.title, a.command, a.out)
+    elif a.cmd == "counters":
+        counters(a.csv, a.kernel, a.simds, a.title, a.command, a.out, a.flops, a.xcds)
     else:
         traffic(a.fetch, a.write, a.kernel, a.calib_bytes, a.sources, a.title, a.command,
                 a.out, a.algorithmic)
