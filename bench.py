@@ -581,6 +581,12 @@ def c3_measure(steps=8, warmup=2):
                        "BF16 linears, FP32 aggregation, recomputation on")
     out["sites"] = r["sites"]
     out["phases"] = r["phases"]
+    # the same step with FP32 linears: the BF16 / FP32 ratio where the
+    # linears dominate the step
+    import dataclasses
+    r32 = train_rate(dataclasses.replace(w, precision=0), 4, 1)
+    out["fp32_graphs_per_s"] = r32["graphs_per_s"]
+    out["bf16_ratio_vs_fp32"] = r["graphs_per_s"] / r32["graphs_per_s"]
     out["memory"] = {"recompute_on_bytes": step_memory(w, 1),
                      "recompute_off_bytes": step_memory(w, 0),
                      "note": "device memory taken by the context and one training step: the "

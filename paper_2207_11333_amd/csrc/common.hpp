@@ -256,10 +256,12 @@ hipError_t launch_transpose_sum(const Dims *dims, int capN, int H,
 // Graph heads (Tg, packed head after head: W1 [H,H], b1, w2, b2): pooled
 // embedding g [B, H], q [Tg][B][H], predictions pred (and pred2 if non-null)
 // [B, Tg].
+// W1T (nullable): the staged transposes of the heads' W1 (launch_stage_head_t)
 hipError_t launch_head_forward(const Dims *dims, int capB, int H, int Tg,
                                const int *graph_ptr, const float *h, const float *wh,
-                               float *g, float *q, float *pred, float *pred2,
+                               const float *W1T, float *g, float *q, float *pred, float *pred2,
                                hipStream_t s);
+hipError_t launch_stage_head_t(const float *wh, int H, int Tg, float *W1T, hipStream_t s);
 // loss = sum_t gw_t mean_b (pred - t)^2 + sum_s nw_s mean_i (z - zt)^2
 // (gw, nw nullable: weight 1).
 hipError_t launch_loss(const Dims *dims, int Tg, const float *pred, const float *t,

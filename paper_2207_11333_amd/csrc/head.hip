@@ -38,12 +38,14 @@ __device__ float block_sum(float v, float *red) {
 
 // Graph head t of Tg (blockIdx.y): head weights at wh + t (H^2 + 2H + 1) as
 // W1 [H, H], b1 [H], w2 [H], b2 [1]; q of head t at q + (t B + b) H; the
-// prediction goes to pred[b Tg + t].
+// prediction goes to pred[b Tg + t].  W1T (nullable): the staged transposes
+// [Tg][H][H] of the W1s, read along the threads' outputs (coalesced); the
+// sums run over k in the same order either way.
 __global__ void __launch_bounds__(kHeadThreads)
 k_head_forward(const Dims *__restrict__ dims, int H, int Tg, const int *__restrict__ gptr,
                const float *__restrict__ h, const float *__restrict__ wh,
-               float *__restrict__ g, float *__restrict__ q, float *__restrict__ pred,
-               float *__restrict__ pred2) {
+               const float *__restrict__ W1T, float *__restrict__ g, float *__restrict__ q,
+               float *__restrict__ pred, float *__restrict__ pred2) {
   __shared__ float gs[512];
   __shared__ float red[kHeadThreads];
   const int b = blockIdx.x, t = blockIdx.y;
@@ -65,11 +67,17 @@ k_head_forward(const Dims *__restrict__ dims, int H, int Tg, const int *__restri
   __syncthreads();
   float *qt = q + ((size_t)t * B + b) * H;
   float part = 0.f;
+  const float *W1Tt = W1T ? W1T + (size_t)t * H * H : nullptr;
   for (int c = threadIdx.x; c < H; c += kHeadThreads) {
     float s = b1[c];
-    const float *row = W1 + (size_t)c * H;
+    if (W1Tt) {
 #pragma unroll 8
-    for (int k = 0; k < H; ++k) s += row[k] * gs[k];
+      for (int k = 0; k < H; ++k) s += W1Tt[(size_t)k * H + c] * gs[k];
+    } else {
+      const float *row = W1 + (size_t)c * H;
+#pragma unroll 8
+      for (int k = 0; k < H; ++k) s += row[k] * gs[k];
+    }
     const float qv = s > 0.f ? s : 0.f;
     qt[c] = qv;
     part += w2[c] * qv;
@@ -368,11 +376,37 @@ hipError_t launch_node_head_small(const Dims *dims, int capN, int H, int Tn, con
 }
 
 hipError_t launch_head_forward(const Dims *dims, int capB, int H, int Tg, const int *graph_ptr,
-                               const float *h, const float *wh, float *g, float *q,
-                               float *pred, float *pred2, hipStream_t s) {
+                               const float *h, const float *wh, const float *W1T, float *g,
+                               float *q, float *pred, float *pred2, hipStream_t s) {
   if (capB <= 0) return hipSuccess;
-  k_head_forward<<<dim3(capB, Tg), kHeadThreads, 0, s>>>(dims, H, Tg, graph_ptr, h, wh, g, q,
-                                                         pred, pred2);
+  k_head_forward<<<dim3(capB, Tg), kHeadThreads, 0, s>>>(dims, H, Tg, graph_ptr, h, wh, W1T, g,
+                                                         q, pred, pred2);
+  return hipGetLastError();
+}
+
+// W1T[t][k][c] = W1_t[c][k] for the Tg graph heads, through 32 x 32 LDS tiles.
+__global__ void __launch_bounds__(256)
+k_stage_head_t(const float *__restrict__ wh, int H, float *__restrict__ W1T) {
+  __shared__ float tl[32][33];
+  const int t = blockIdx.z;
+  const float *W1 = wh + (size_t)t * (H * H + 2 * H + 1);
+  float *out = W1T + (size_t)t * H * H;
+  const int c0 = blockIdx.y * 32, k0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r, k = k0 + tx;
+    tl[r][tx] = (c < H && k < H) ? W1[(size_t)c * H + k] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int k = k0 + r, c = c0 + tx;
+    if (k < H && c < H) out[(size_t)k * H + c] = tl[tx][r];
+  }
+}
+
+hipError_t launch_stage_head_t(const float *wh, int H, int Tg, float *W1T, hipStream_t s) {
+  const dim3 grid(cdiv(H, 32), cdiv(H, 32), Tg);
+  k_stage_head_t<<<grid, 256, 0, s>>>(wh, H, W1T);
   return hipGetLastError();
 }
 

@@ -252,16 +252,18 @@ static StageOut stage_out(hgnn_ctx *c, int l) {
 }
 
 int stage_all(hgnn_ctx *c, hipStream_t s, long long *bump_step) {
+  hipError_t e = launch_stage_head_t(c->params + c->off_head, c->H, c->Tg, c->W1T, s);
+  if (e != hipSuccess) return hip_fail(c, e, "stage head weights");
   if (c->kind != HGNN_GC_PNA) {
-    hipError_t e = launch_gc_stage(c->gc_jobs, c->gc_njobs, c->gc_max_elems, bump_step, s);
+    e = launch_gc_stage(c->gc_jobs, c->gc_njobs, c->gc_max_elems, bump_step, s);
     if (e != hipSuccess) return hip_fail(c, e, "stage weights");
     c->staged_from_params = true;
     return HGNN_OK;
   }
   int maxFp = 0;
   for (const LayerDesc &d : c->ld) maxFp = std::max(maxFp, d.Fp);
-  hipError_t e = launch_stage_all(c->stage_tab, c->L, maxFp, c->H, c->Fe, c->nb, c->table,
-                                  c->prec, bump_step, s);
+  e = launch_stage_all(c->stage_tab, c->L, maxFp, c->H, c->Fe, c->nb, c->table, c->prec,
+                       bump_step, s);
   if (e != hipSuccess) return hip_fail(c, e, "stage weights");
   c->staged_from_params = true;
   return HGNN_OK;
@@ -701,8 +703,10 @@ int head_forward(hgnn_ctx *c, Exec &ex, const float *wh, const float *h, const f
                  const float *ynode) {
   const int H = c->H, Tn = c->Tn;
   Work &w = ex.w;
-  hipError_t e = launch_head_forward(ex.dims, ex.B, H, c->Tg, ex.graph_ptr, h, wh, w.g, w.q,
-                                     w.ypred, pred, s);
+  // the staged W1 transposes describe the context's own head weights
+  const float *W1T = (wh == c->params + c->off_head && c->staged_from_params) ? c->W1T : nullptr;
+  hipError_t e = launch_head_forward(ex.dims, ex.B, H, c->Tg, ex.graph_ptr, h, wh, W1T, w.g,
+                                     w.q, w.ypred, pred, s);
   if (e == hipSuccess && Tn > 0) {
     const float *wn = c->params + c->off_node;
     e = launch_stage_node_heads(H, Tn, wn, c->W1n, c->W1nT, s);
@@ -1374,6 +1378,7 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
   HGNN_CALLOC(c->part, part_max);
   if (c->nb) HGNN_CALLOC(c->zscale, 2 * (size_t)zmax);
   HGNN_CALLOC(c->gw_dev, Tg);
+  HGNN_CALLOC(c->W1T, (size_t)Tg * H * H);
   if (Tn > 0) {
     HGNN_CALLOC(c->nw_dev, Tn);
     HGNN_CALLOC(c->W1n, (size_t)Tn * H * H);
@@ -1522,7 +1527,7 @@ void hgnn_destroy(hgnn_ctx *c) {
                    (void **)&c->gw_dev, (void **)&c->nw_dev, (void **)&c->W1n,
                    (void **)&c->W1nT, (void **)&c->nh_part,
                    (void **)&c->table, (void **)&c->ex.dims, (void **)&c->ex.w.csr.err,
-                   (void **)&c->part, (void **)&c->zscale};
+                   (void **)&c->part, (void **)&c->zscale, (void **)&c->W1T};
   for (void **p : ptrs) dfree(*p);
   for (auto *v : {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT, &c->Wds_lo, &c->Wpp_lo, &c->WpTA_lo,
                   &c->WhdsT_lo, &c->WeT, &c->Wg1, &c->Wg1_lo, &c->Wg2, &c->Wg2_lo})

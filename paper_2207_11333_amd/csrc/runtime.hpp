@@ -136,6 +136,7 @@ struct hgnn_ctx {
   bool staged_from_params = false;
   float *part = nullptr;
   float *zscale = nullptr; // per-chunk scalers of the bucketed update weight gradient
+  float *W1T = nullptr;    // graph heads' W1 transposed [Tg][H][H] (staged with the layers)
   hgnn::Exec ex; // the training path's batch state
   // batch state of hgnn_forward_noalloc: its buffers are carved from the
   // device's scratch array (noalloc.hip) and never freed
