@@ -210,7 +210,9 @@ int hgnn_forward_multitask(hgnn_ctx *ctx, const hgnn_batch *batch,
 int hgnn_backward(hgnn_ctx *ctx, const float *dpred_dev, void *stream);
 /* One AdamW step (decoupled decay, bias-corrected, step count kept by the
  * context starting at 1) on the packed parameters with the current
- * gradients; refreshes the internal GEMM copies. */
+ * gradients (Section 5.1 trains with AdamW).  The internal GEMM copies of the
+ * weights are refreshed by the next call that needs them (the next forward
+ * does it on a second stream, beside its CSR build). */
 int hgnn_adam_step(hgnn_ctx *ctx, float lr, float beta1, float beta2,
                    float eps, float weight_decay, void *stream);
 

@@ -51,7 +51,7 @@ constexpr int kMaxBuckets = 16;
 // ints per block record of the multi-block CSR scan: the in- and out-degree
 // sums and one count per bucket
 constexpr int kScanRec = 2 + kMaxBuckets;
-constexpr int kScanNodes = 1024; // nodes per block of that scan
+constexpr int kScanNodes = 256; // nodes per block of that scan
 
 struct SegA {
   const float *ptr;   // [rows, ld] row-major, k-contiguous

@@ -26,40 +26,53 @@ __global__ void k_set_dims(Dims *d, int B, int N, int E, int *err) {
   }
 }
 
-// node -> graph id by binary search over graph_ptr; zero the counters;
+// node -> graph id by binary search over graph_ptr (staged in LDS when it
+// fits, so the search costs no dependent global loads); zero the counters;
 // check graph_ptr.
-__global__ void k_csr_init(const Dims *__restrict__ dims,
-                           const int *__restrict__ graph_ptr,
-                           int *__restrict__ node_graph, int *__restrict__ cnt_in,
-                           int *__restrict__ cnt_out, int *__restrict__ err,
-                           const float *__restrict__ x, int F, float *__restrict__ xpad,
-                           int Fp) {
+constexpr int kInitThreads = 256;
+constexpr int kGraphPtrLds = 4096;
+
+__global__ void __launch_bounds__(kInitThreads)
+k_csr_init(const Dims *__restrict__ dims, const int *__restrict__ graph_ptr,
+           int *__restrict__ node_graph, int *__restrict__ cnt_in, int *__restrict__ cnt_out,
+           int *__restrict__ err, const float *__restrict__ x, int F,
+           float *__restrict__ xpad, int Fp) {
+  __shared__ int s_gp[kGraphPtrLds];
   const int B = dims->B, N = dims->N;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool staged = B + 1 <= kGraphPtrLds;
+  if (staged)
+    for (int k = threadIdx.x; k <= B; k += kInitThreads) s_gp[k] = graph_ptr[k];
+  __syncthreads();
+  const int *gp = staged ? s_gp : graph_ptr;
+  const int i = blockIdx.x * kInitThreads + threadIdx.x;
   if (i < B) {
-    if (graph_ptr[i + 1] <= graph_ptr[i]) atomicOr(err, ERR_GRAPH_PTR);
+    if (gp[i + 1] <= gp[i]) atomicOr(err, ERR_GRAPH_PTR);
   }
   if (i == 0) {
-    if (graph_ptr[0] != 0 || graph_ptr[B] != N) atomicOr(err, ERR_GRAPH_PTR);
+    if (gp[0] != 0 || gp[B] != N) atomicOr(err, ERR_GRAPH_PTR);
   }
   if (i < N) {
     int lo = 0, hi = B; // find last b with graph_ptr[b] <= i
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (graph_ptr[mid] <= i) lo = mid; else hi = mid;
+      if (gp[mid] <= i) lo = mid; else hi = mid;
     }
     node_graph[i] = lo;
     cnt_in[i] = 0;
     cnt_out[i] = 0;
-    if (x) { // the first layer's input, zero-padded from F to Fp columns
-      bool finite = true;
-      for (int c = 0; c < Fp; ++c) {
-        const float v = c < F ? x[(size_t)i * F + c] : 0.f;
-        finite = finite && isfinite(v);
-        xpad[(size_t)i * Fp + c] = v;
-      }
-      if (!finite) atomicOr(err, ERR_NONFINITE);
+  }
+  if (x) {
+    // the first layer's input, zero-padded from F to Fp columns: the block's
+    // kInitThreads rows, element by element so that stores are coalesced
+    const int r0 = blockIdx.x * kInitThreads, nr = min(kInitThreads, N - r0);
+    bool finite = true;
+    for (int e = threadIdx.x; e < nr * Fp; e += kInitThreads) {
+      const int r = r0 + e / Fp, c = e % Fp;
+      const float v = c < F ? x[(size_t)r * F + c] : 0.f;
+      finite = finite && isfinite(v);
+      xpad[(size_t)r * Fp + c] = v;
     }
+    if (!finite) atomicOr(err, ERR_NONFINITE);
   }
 }
 
@@ -91,12 +104,14 @@ __global__ void k_csr_count(const Dims *__restrict__ dims,
 
 // Exclusive scans of both degree counters (rowptr, srcptr) over all nodes in
 // three passes, no workgroup waiting on another: per block of kScanNodes
-// nodes the counter sums and the node count of every degree bucket
-// (k_scan_count); one workgroup turns those into block offsets and bucket
-// offsets (k_scan_top); every block then scans its own nodes again, adds its
-// offsets and writes rowptr, srcptr, degrees, scalers and, with degree
-// buckets, each node's place in the (degree, node id) order (k_scan_apply).
+// nodes (one per thread) the counter sums and the node count of every degree
+// bucket (k_scan_count); one workgroup, a wave per column, turns those into
+// block offsets and bucket offsets (k_scan_top); every block then scans its
+// own nodes again, adds its offsets and writes rowptr, srcptr, degrees,
+// scalers and, with degree buckets, each node's place in the (degree, node
+// id) order (k_scan_apply).
 constexpr int kScanTop = 1024;
+static_assert(kScanNodes == 256, "one node per thread of a 256-thread block");
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -112,180 +127,125 @@ __device__ __forceinline__ int bucket_of(int d, int max_degree) {
   return d < max_degree ? d : max_degree; // clamped: a bad degree is flagged elsewhere
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kScanNodes)
 k_scan_count(const Dims *__restrict__ dims, const int *__restrict__ cnt_in,
              const int *__restrict__ cnt_out, int max_degree, int nb,
              int *__restrict__ scan) {
-  __shared__ int s_b[kMaxBuckets];
-  __shared__ int s_w[2][4];
+  __shared__ int s_w[2 + kMaxBuckets][kScanNodes / 64];
   const int N = dims->N;
   const int base = blockIdx.x * kScanNodes;
   if (base >= N) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid < kMaxBuckets) s_b[tid] = 0;
-  __syncthreads();
-  int si = 0, so = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int i = base + 4 * tid + j;
-    if (i < N) {
-      const int vi = cnt_in[i];
-      si += vi;
-      so += cnt_out[i];
-      if (nb) atomicAdd(&s_b[bucket_of(vi, max_degree)], 1); // an order-free count
-    }
-  }
-  si = wave_incl_scan(si);
-  so = wave_incl_scan(so);
+  const int i = base + tid;
+  const int vi = i < N ? cnt_in[i] : 0, vo = i < N ? cnt_out[i] : 0;
+  const int bq = i < N ? bucket_of(vi, max_degree) : -1;
+  const int si = wave_incl_scan(vi), so = wave_incl_scan(vo);
   if (lane == 63) {
     s_w[0][wid] = si;
     s_w[1][wid] = so;
   }
+  for (int q = 0; q < nb; ++q) {
+    const unsigned long long m = __ballot(bq == q);
+    if (lane == 0) s_w[2 + q][wid] = __popcll(m);
+  }
   __syncthreads();
   int *rec = scan + (size_t)blockIdx.x * kScanRec;
-  if (tid == 0) {
-    rec[0] = s_w[0][0] + s_w[0][1] + s_w[0][2] + s_w[0][3];
-    rec[1] = s_w[1][0] + s_w[1][1] + s_w[1][2] + s_w[1][3];
-  }
-  if (tid < nb) rec[2 + tid] = s_b[tid];
+  if (tid < 2 + nb) rec[tid] = s_w[tid][0] + s_w[tid][1] + s_w[tid][2] + s_w[tid][3];
 }
 
-// One workgroup: each column of the block records becomes its exclusive
-// prefix over the blocks; the bucket columns then get their bucket's first
-// row added (brow[q] = nodes of lower degree).
+// One workgroup; wave c scans column c of the block records (c < 2 + nb)
+// over the blocks, 64 at a time with a carry.  The column totals give
+// rowptr[N], srcptr[N] and the first row of every degree bucket (brow[q] =
+// nodes of lower degree), which k_scan_apply adds to the bucket columns.
 __global__ void __launch_bounds__(kScanTop)
 k_scan_top(const Dims *__restrict__ dims, int nb, int *__restrict__ scan,
            int *__restrict__ brow, int *__restrict__ rowptr, int *__restrict__ srcptr) {
-  __shared__ int wsum[kScanTop / 64];
-  __shared__ int carry;
   __shared__ int tot[kScanRec];
-  __shared__ int s_brow[kMaxBuckets + 1];
   const int N = dims->N;
   const int nblk = (N + kScanNodes - 1) / kScanNodes;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  constexpr int nw = kScanTop / 64;
-  for (int c = 0; c < 2 + nb; ++c) {
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int b0 = 0; b0 < nblk; b0 += kScanTop) {
-      const int k = b0 + tid;
-      const int v = k < nblk ? scan[(size_t)k * kScanRec + c] : 0;
+  const int ncol = 2 + nb;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c = wid; c < ncol; c += kScanTop / 64) {
+    int carry = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 64) {
+      const int k = b0 + lane;
+      int *cell = scan + (size_t)k * kScanRec + c;
+      const int v = k < nblk ? *cell : 0;
       const int inc = wave_incl_scan(v);
-      if (lane == 63) wsum[wid] = inc;
-      __syncthreads();
-      if (wid == 0) {
-        int a = lane < nw ? wsum[lane] : 0;
-        a = wave_incl_scan(a);
-        if (lane < nw) wsum[lane] = a;
-      }
-      __syncthreads();
-      const int excl = carry + (wid ? wsum[wid - 1] : 0) + inc - v;
-      if (k < nblk) scan[(size_t)k * kScanRec + c] = excl;
-      __syncthreads();
-      if (tid == kScanTop - 1) carry = excl + v;
-      __syncthreads();
+      if (k < nblk) *cell = carry + inc - v;
+      carry += __shfl(inc, 63, 64);
     }
-    if (tid == 0) tot[c] = carry;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    rowptr[N] = tot[0];
-    srcptr[N] = tot[1];
-    int a = 0;
-    for (int q = 0; q < nb; ++q) {
-      s_brow[q] = a;
-      a += tot[2 + q];
-    }
-    s_brow[nb] = a;
+    if (lane == 0) tot[c] = carry;
   }
   __syncthreads();
-  if (nb == 0) return;
-  if (tid <= nb) brow[tid] = s_brow[tid];
-  for (int k = tid; k < nblk; k += kScanTop)
-    for (int q = 0; q < nb; ++q) scan[(size_t)k * kScanRec + 2 + q] += s_brow[q];
+  if (threadIdx.x == 0) {
+    rowptr[N] = tot[0];
+    srcptr[N] = tot[1];
+    if (nb) {
+      int a = 0;
+      for (int q = 0; q < nb; ++q) {
+        brow[q] = a;
+        a += tot[2 + q];
+      }
+      brow[nb] = a;
+    }
+  }
 }
 
 // Per block: its own exclusive scans plus the block offsets.  A node's place
 // among the nodes of its degree bucket counts the block's earlier nodes of
-// that bucket (earlier waves, earlier lanes, then the lane's own earlier
-// nodes), so the permutation is stable in node id.
-__global__ void __launch_bounds__(256)
+// that bucket (earlier waves, then earlier lanes of its wave), so the
+// permutation is stable in node id.
+__global__ void __launch_bounds__(kScanNodes)
 k_scan_apply(const Dims *__restrict__ dims, int *__restrict__ cnt_in,
              int *__restrict__ cnt_out, const int *__restrict__ scan,
              const float *__restrict__ table, int max_degree, int nb,
              int *__restrict__ rowptr, int *__restrict__ srcptr, int *__restrict__ deg,
              float *__restrict__ sp, float *__restrict__ sm, int *__restrict__ perm,
-             int *__restrict__ err) {
-  __shared__ int s_w[2][4];
-  __shared__ int s_bw[4][kMaxBuckets];
+             const int *__restrict__ brow, int *__restrict__ err) {
+  __shared__ int s_w[2][kScanNodes / 64];
+  __shared__ int s_bw[kScanNodes / 64][kMaxBuckets];
   const int N = dims->N;
   const int base = blockIdx.x * kScanNodes;
   if (base >= N) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int *rec = scan + (size_t)blockIdx.x * kScanRec;
-  int vi[4], vo[4], bq[4];
-  int si = 0, so = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int i = base + 4 * tid + j;
-    vi[j] = i < N ? cnt_in[i] : 0;
-    vo[j] = i < N ? cnt_out[i] : 0;
-    bq[j] = i < N ? bucket_of(vi[j], max_degree) : -1;
-    si += vi[j];
-    so += vo[j];
-  }
-  const int ii = wave_incl_scan(si), io = wave_incl_scan(so);
+  const int i = base + tid;
+  const int vi = i < N ? cnt_in[i] : 0, vo = i < N ? cnt_out[i] : 0;
+  const int bq = i < N ? bucket_of(vi, max_degree) : -1;
+  const int ii = wave_incl_scan(vi), io = wave_incl_scan(vo);
   if (lane == 63) {
     s_w[0][wid] = ii;
     s_w[1][wid] = io;
   }
-  // bucket ranks inside the wave: per bucket, the lane's count and the
-  // exclusive sum over lower lanes
-  int pos[4] = {0, 0, 0, 0};
+  // rank among the wave's earlier lanes of the same bucket
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int pos = 0;
   for (int q = 0; q < nb; ++q) {
-    int cq = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) cq += bq[j] == q ? 1 : 0;
-    const int inc = wave_incl_scan(cq);
-    if (lane == 63) s_bw[wid][q] = inc;
-    int run = inc - cq;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (bq[j] == q) pos[j] = run++;
+    const unsigned long long m = __ballot(bq == q);
+    if (lane == 0) s_bw[wid][q] = __popcll(m);
+    if (bq == q) pos = __popcll(m & below);
   }
   __syncthreads();
-  int ei_ = rec[0], eo_ = rec[1];
+  if (i >= N) return;
+  int ei_ = rec[0] + ii - vi, eo_ = rec[1] + io - vo;
   for (int w = 0; w < wid; ++w) {
     ei_ += s_w[0][w];
     eo_ += s_w[1][w];
   }
-  ei_ += ii - si;
-  eo_ += io - so;
-  int bad = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int i = base + 4 * tid + j;
-    if (i < N) {
-      rowptr[i] = ei_;
-      srcptr[i] = eo_;
-      deg[i] = vi[j];
-      const int dc = bucket_of(vi[j], max_degree);
-      sp[i] = table[2 * dc];
-      sm[i] = table[2 * dc + 1];
-      if (vi[j] > max_degree || vo[j] > max_degree) bad = 1;
-      cnt_in[i] = 0;
-      cnt_out[i] = 0;
-      if (nb) {
-        const int q = bq[j];
-        int p = rec[2 + q] + pos[j];
-        for (int w = 0; w < wid; ++w) p += s_bw[w][q];
-        perm[p] = i;
-      }
-    }
-    ei_ += vi[j];
-    eo_ += vo[j];
+  rowptr[i] = ei_;
+  srcptr[i] = eo_;
+  deg[i] = vi;
+  sp[i] = table[2 * bq];
+  sm[i] = table[2 * bq + 1];
+  cnt_in[i] = 0;
+  cnt_out[i] = 0;
+  if (nb) {
+    int p = brow[bq] + rec[2 + bq] + pos;
+    for (int w = 0; w < wid; ++w) p += s_bw[w][bq];
+    perm[p] = i;
   }
-  if (bad) atomicOr(err, ERR_DEGREE);
+  if (vi > max_degree || vo > max_degree) atomicOr(err, ERR_DEGREE);
 }
 
 __global__ void k_csr_fill(const Dims *__restrict__ dims,
@@ -304,6 +264,26 @@ __global__ void k_csr_fill(const Dims *__restrict__ dims,
   tmp_out[srcptr[s] + atomicAdd(&cnt_out[s], 1)] = k;
 }
 
+// Segments of at most kRegSort entries (every molecular graph's) are
+// sorted in registers: their entries are loaded at once and put in order by
+// a fixed network of compare-exchanges, so a segment costs a few rounds of
+// independent loads.  Longer segments take an insertion sort in place.
+constexpr int kRegSort = 8;
+
+template <typename K> __device__ __forceinline__ void cswap(K &a, K &b) {
+  const K lo = a < b ? a : b, hi = a < b ? b : a;
+  a = lo;
+  b = hi;
+}
+
+// odd-even transposition sort of kRegSort keys (ascending)
+template <typename K> __device__ __forceinline__ void sort_regs(K (&v)[kRegSort]) {
+#pragma unroll
+  for (int pass = 0; pass < kRegSort; ++pass)
+#pragma unroll
+    for (int a = pass & 1; a + 1 < kRegSort; a += 2) cswap(v[a], v[a + 1]);
+}
+
 // Per destination: order the segment by (source, edge id); write csr_src,
 // the inverse map and the edge attributes in CSR order.
 __global__ void k_csr_sort_in(const Dims *__restrict__ dims,
@@ -317,8 +297,37 @@ __global__ void k_csr_sort_in(const Dims *__restrict__ dims,
   const int N = dims->N;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const int lo = rowptr[i], hi = rowptr[i + 1];
-  if (hi - lo <= max_degree) {
+  const int lo = rowptr[i], hi = rowptr[i + 1], n = hi - lo;
+  if (n <= kRegSort) {
+    // key = source << 32 | edge id; empty slots sort last
+    unsigned long long key[kRegSort];
+    int k[kRegSort];
+#pragma unroll
+    for (int a = 0; a < kRegSort; ++a) k[a] = a < n ? csr_eid[lo + a] : 0;
+#pragma unroll
+    for (int a = 0; a < kRegSort; ++a)
+      key[a] = a < n ? ((unsigned long long)(unsigned)ei[k[a]] << 32) | (unsigned)k[a]
+                     : ~0ull;
+    sort_regs(key);
+    bool finite = true;
+#pragma unroll
+    for (int a = 0; a < kRegSort; ++a)
+      if (a < n) {
+        const int ka = (int)(unsigned)(key[a] & 0xffffffffu);
+        csr_eid[lo + a] = ka;
+        csr_src[lo + a] = (int)(key[a] >> 32);
+        csr_dst[lo + a] = i;
+        csr_pos[ka] = lo + a;
+        for (int f = 0; f < Fe; ++f) {
+          const float v = edge_attr[(size_t)ka * Fe + f];
+          finite = finite && isfinite(v);
+          csr_e[(size_t)(lo + a) * Fe + f] = v;
+        }
+      }
+    if (!finite) atomicOr(err, ERR_NONFINITE);
+    return;
+  }
+  if (n <= max_degree) {
     for (int a = lo + 1; a < hi; ++a) { // insertion sort by (src, eid)
       const int ka = csr_eid[a];
       const int sa = ei[ka];
@@ -333,12 +342,15 @@ __global__ void k_csr_sort_in(const Dims *__restrict__ dims,
       csr_eid[b + 1] = ka;
     }
   }
-  bool finite = true;
   for (int q = lo; q < hi; ++q) {
     const int k = csr_eid[q];
     csr_src[q] = ei[k];
     csr_dst[q] = i;
     csr_pos[k] = q;
+  }
+  bool finite = true;
+  for (int q = lo; q < hi; ++q) {
+    const int k = csr_eid[q];
     for (int f = 0; f < Fe; ++f) {
       const float v = edge_attr[(size_t)k * Fe + f];
       finite = finite && isfinite(v);
@@ -357,9 +369,22 @@ __global__ void k_csr_sort_out(const Dims *__restrict__ dims,
   const int N = dims->N;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
-  const int lo = srcptr[j], hi = srcptr[j + 1];
+  const int lo = srcptr[j], hi = srcptr[j + 1], n = hi - lo;
+  if (n <= kRegSort) {
+    int k[kRegSort];
+    unsigned v[kRegSort];
+#pragma unroll
+    for (int a = 0; a < kRegSort; ++a) k[a] = a < n ? tmp_out[lo + a] : 0;
+#pragma unroll
+    for (int a = 0; a < kRegSort; ++a) v[a] = a < n ? (unsigned)csr_pos[k[a]] : ~0u;
+    sort_regs(v);
+#pragma unroll
+    for (int a = 0; a < kRegSort; ++a)
+      if (a < n) t2csr[lo + a] = (int)v[a];
+    return;
+  }
   for (int p = lo; p < hi; ++p) t2csr[p] = csr_pos[tmp_out[p]];
-  if (hi - lo > max_degree) return;
+  if (n > max_degree) return;
   for (int a = lo + 1; a < hi; ++a) {
     const int va = t2csr[a];
     int b = a - 1;
@@ -396,9 +421,8 @@ hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
                             const float *x, int F, float *xpad, int Fp, hipStream_t s) {
   if (clear_err) k_set_dims<<<1, 64, 0, s>>>(nullptr, 0, 0, 0, c.err);
   const int nb = capN > capB ? capN : capB;
-  k_csr_init<<<cdiv(nb > 0 ? nb : 1, 256), 256, 0, s>>>(dims, graph_ptr, c.node_graph,
-                                                        c.cnt_in, c.cnt_out, c.err, x, F,
-                                                        xpad, Fp);
+  k_csr_init<<<cdiv(nb > 0 ? nb : 1, kInitThreads), kInitThreads, 0, s>>>(
+      dims, graph_ptr, c.node_graph, c.cnt_in, c.cnt_out, c.err, x, F, xpad, Fp);
   if (capE > 0)
     k_csr_count<<<cdiv(capE, 256), 256, 0, s>>>(dims, edge_index, c.node_graph,
                                                 c.cnt_in, c.cnt_out, c.err);
@@ -408,7 +432,7 @@ hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
     k_scan_top<<<1, kScanTop, 0, s>>>(dims, c.nb, c.scan, c.brow, c.rowptr, c.srcptr);
     k_scan_apply<<<nsb, 256, 0, s>>>(dims, c.cnt_in, c.cnt_out, c.scan, table, max_degree,
                                      c.nb, c.rowptr, c.srcptr, c.deg, c.sp, c.sm, c.perm,
-                                     c.err);
+                                     c.brow, c.err);
   }
   if (capE > 0)
     k_csr_fill<<<cdiv(capE, 256), 256, 0, s>>>(dims, edge_index, c.node_graph, c.rowptr,

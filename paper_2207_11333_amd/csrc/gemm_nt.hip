@@ -52,28 +52,22 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   // bucket's last tile may be partial).  The tile covers rows [m0, m_hi) of
   // the (permuted) row order and multiplies with bucket q's weights.
   int mtiles = (M + BM - 1) / BM;
-  if (g.perm) {
-    mtiles = 0;
-    for (int q = 0; q < g.nb; ++q) mtiles += (g.brow[q + 1] - g.brow[q] + BM - 1) / BM;
-  }
   const int z = blockIdx.y;
-  if ((int)blockIdx.x >= mtiles * ntiles_n) return;
-  const int tile = xcd_tile(blockIdx.x, mtiles * ntiles_n);
-  const int mt = tile / ntiles_n, n0 = (tile % ntiles_n) * BN;
-  int m0 = mt * BM, m_hi = M, bq = 0;
+  int mt, n0, m0, m_hi = M, bq = 0;
   if (g.perm) {
-    int first = 0;
-    for (int q = 0; q < g.nb; ++q) {
-      const int r0 = g.brow[q], r1 = g.brow[q + 1];
-      const int nt_q = (r1 - r0 + BM - 1) / BM;
-      if (mt < first + nt_q) {
-        bq = q;
-        m0 = r0 + (mt - first) * BM;
-        m_hi = r1;
-        break;
-      }
-      first += nt_q;
-    }
+    const BucketWalk bw(g.brow, g.nb, BM);
+    mtiles = bw.total();
+    if ((int)blockIdx.x >= mtiles * ntiles_n) return;
+    const int tile = xcd_tile(blockIdx.x, mtiles * ntiles_n);
+    mt = tile / ntiles_n;
+    n0 = (tile % ntiles_n) * BN;
+    bw.find(mt, bq, m0, m_hi);
+  } else {
+    if ((int)blockIdx.x >= mtiles * ntiles_n) return;
+    const int tile = xcd_tile(blockIdx.x, mtiles * ntiles_n);
+    mt = tile / ntiles_n;
+    n0 = (tile % ntiles_n) * BN;
+    m0 = mt * BM;
   }
   const int tid = threadIdx.x, wid = tid >> 6;
   const int wm0 = (wid / WGN) * WM, wn0 = (wid % WGN) * WN;

@@ -50,19 +50,10 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     // bucket-pure chunks over the permuted rows: bucket q holds
     // ceil(n_q / chunk) chunks, in bucket order; the chunks past the last
     // are empty and write zero partials
-    int first = 0, bq = -1;
-    i_lo = i_hi = 0;
-    for (int q = 0; q < g.nb; ++q) {
-      const int r0 = g.brow[q], r1 = g.brow[q + 1];
-      const int nc = (r1 - r0 + chunk - 1) / chunk;
-      if (z < first + nc) {
-        bq = q;
-        i_lo = r0 + (z - first) * chunk;
-        i_hi = min(r1, i_lo + chunk);
-        break;
-      }
-      first += nc;
-    }
+    int bq, r0, r1;
+    BucketWalk(g.brow, g.nb, chunk).find(z, bq, r0, r1);
+    i_lo = bq >= 0 ? r0 : 0;
+    i_hi = bq >= 0 ? min(r1, r0 + chunk) : 0;
     if (blockIdx.x % T2 == 0 && threadIdx.x == 0) {
       g.zscale[2 * z] = bq >= 0 ? g.table[2 * bq] : 0.f;
       g.zscale[2 * z + 1] = bq >= 0 ? g.table[2 * bq + 1] : 0.f;
@@ -295,19 +286,10 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   int i_lo = z * chunk;
   int i_hi = min(rows, i_lo + chunk);
   if constexpr (PERM) {
-    int first = 0, bq = -1;
-    i_lo = i_hi = 0;
-    for (int q = 0; q < g.nb; ++q) {
-      const int r0 = g.brow[q], r1 = g.brow[q + 1];
-      const int nc = (r1 - r0 + chunk - 1) / chunk;
-      if (z < first + nc) {
-        bq = q;
-        i_lo = r0 + (z - first) * chunk;
-        i_hi = min(r1, i_lo + chunk);
-        break;
-      }
-      first += nc;
-    }
+    int bq, r0, r1;
+    BucketWalk(g.brow, g.nb, chunk).find(z, bq, r0, r1);
+    i_lo = bq >= 0 ? r0 : 0;
+    i_hi = bq >= 0 ? min(r1, r0 + chunk) : 0;
     if (blockIdx.x % T2 == 0 && threadIdx.x == 0) {
       g.zscale[2 * z] = bq >= 0 ? g.table[2 * bq] : 0.f;
       g.zscale[2 * z + 1] = bq >= 0 ? g.table[2 * bq + 1] : 0.f;

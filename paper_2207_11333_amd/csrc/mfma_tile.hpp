@@ -68,6 +68,43 @@ __device__ __forceinline__ int xcd_tile(int bid, int T) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// Bucketed tiles: bucket q's rows [brow[q], brow[q + 1]) of the
+// (degree, id)-ordered rows are cut into ceil(n_q / T) tiles of T rows,
+// bucket after bucket.  Lane q of the wave takes bucket q (lanes past nb see
+// empty buckets), so the walk costs one round of loads and a wave scan rather
+// than a dependent load per bucket.  total() is the tile count; find() gives,
+// for tile `want`, the bucket bq (-1 past the last tile), the tile's first
+// row r0 and the bucket's end r1, the same in every lane.
+struct BucketWalk {
+  int lo, hi, nt, incl, T;
+  __device__ __forceinline__ BucketWalk(const int *__restrict__ brow, int nb, int T_) : T(T_) {
+    const int lane = threadIdx.x & 63;
+    const int q = min(lane, kMaxBuckets - 1);
+    lo = brow[min(q, nb)];
+    hi = brow[min(q + 1, nb)];
+    nt = lane < kMaxBuckets ? (hi - lo + T - 1) / T : 0;
+    incl = nt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+  }
+  __device__ __forceinline__ void find(int want, int &bq, int &r0, int &r1) const {
+    const int first = incl - nt;
+    const unsigned long long hit = __ballot(nt > 0 && want >= first && want < incl);
+    bq = hit ? __ffsll((long long)hit) - 1 : -1;
+    const int src = bq < 0 ? 0 : bq;
+    // wave-uniform results: keep them in scalar registers
+    r0 = __builtin_amdgcn_readfirstlane(__shfl(lo, src, 64) + (want - __shfl(first, src, 64)) * T);
+    r1 = __builtin_amdgcn_readfirstlane(__shfl(hi, src, 64));
+    bq = __builtin_amdgcn_readfirstlane(bq);
+  }
+  __device__ __forceinline__ int total() const {
+    return __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+  }
+};
+
 __device__ __forceinline__ void store4(float *dst, f4 v) {
   *reinterpret_cast<f4 *>(dst) = v;
 }

@@ -251,7 +251,9 @@ static StageOut stage_out(hgnn_ctx *c, int l) {
   return o;
 }
 
-int stage_all(hgnn_ctx *c, hipStream_t s, long long *bump_step) {
+int stage_all(hgnn_ctx *c, hipStream_t s) {
+  long long *bump_step = c->bump_pending ? c->step_dev : nullptr;
+  c->bump_pending = false;
   hipError_t e = launch_stage_head_t(c->params + c->off_head, c->H, c->Tg, c->W1T, s);
   if (e != hipSuccess) return hip_fail(c, e, "stage head weights");
   if (c->kind != HGNN_GC_PNA) {
@@ -1495,7 +1497,8 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
   if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->fork_ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->fork_ev[1], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming) != hipSuccess) {
     hgnn_destroy(c);
     return fail(HGNN_EDEVICE, "stream/event creation failed");
   }
@@ -1519,7 +1522,7 @@ void hgnn_destroy(hgnn_ctx *c) {
   free_work(c->ex);
   for (hipEvent_t ev : c->timer.ev) (void)hipEventDestroy(ev);
   c->timer.ev.clear();
-  for (hipEvent_t ev : {c->fork_ev[0], c->fork_ev[1], c->join_ev})
+  for (hipEvent_t ev : {c->fork_ev[0], c->fork_ev[1], c->join_ev, c->stage_ev})
     if (ev) (void)hipEventDestroy(ev);
   if (c->aux) (void)hipStreamDestroy(c->aux);
   void **ptrs[] = {(void **)&c->params, (void **)&c->grads, (void **)&c->adam_m,
@@ -1628,10 +1631,25 @@ int hgnn_forward_multitask(hgnn_ctx *c, const hgnn_batch *b, const float *y_node
     return fail(HGNN_EINVAL, "loss requested without targets");
   hipStream_t s = (hipStream_t)stream;
   Exec &ex = c->ex;
-  int rc = prepare(c, ex, b, flags, s);
+  // Weights changed since they were last staged (an AdamW step): refresh the
+  // copies on the aux stream while this batch's CSR is built on s.
+  int rc = HGNN_OK;
+  const bool fork = !c->staged_from_params;
+  if (fork) {
+    hipError_t e = hipEventRecord(c->fork_ev[0], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->fork_ev[0], 0);
+    if (e != hipSuccess) return hip_fail(c, e, "fork");
+    if ((rc = stage_all(c, c->aux))) return rc;
+    if (hipError_t e = hipEventRecord(c->stage_ev, c->aux); e != hipSuccess)
+      return hip_fail(c, e, "fork");
+  }
+  rc = prepare(c, ex, b, flags, s);
+  if (fork) { // joined whether or not the batch was accepted
+    if (hipError_t e = hipStreamWaitEvent(s, c->stage_ev, 0); e != hipSuccess)
+      return hip_fail(c, e, "join");
+  }
   if (rc) return rc;
   ex.ynode = y_node;
-  if (!c->staged_from_params && (rc = stage_all(c, s))) return rc;
   const float *h = b->x;
   if (c->kind != HGNN_GC_PNA) {
     rc = gc_forward(c, ex, s, &h);
@@ -1689,10 +1707,18 @@ int hgnn_adam_step(hgnn_ctx *c, float lr, float beta1, float beta2, float eps, f
       !(eps > 0.f) || !(wd >= 0.f))
     return fail(HGNN_EINVAL, "bad AdamW hyperparameters");
   hipStream_t s = (hipStream_t)stream;
+  // a previous step's counter advance has not run yet (no forward since):
+  // run it before this step reads the counter
+  if (c->bump_pending)
+    if (int rc = stage_all(c, s)) return rc;
   hipError_t e = launch_adamw(c->params, c->grads, c->adam_m, c->adam_v, c->P, lr,
                               (double)beta1, (double)beta2, eps, wd, c->step_dev, s);
   if (e != hipSuccess) return hip_fail(c, e, "adamw");
-  return stage_all(c, s, c->step_dev); // also advances the step counter
+  // the weight copies are refreshed, and the counter advanced, by the next
+  // forward (on the aux stream, beside its CSR build) or staging call
+  c->staged_from_params = false;
+  c->bump_pending = true;
+  return HGNN_OK;
 }
 
 // ---- checkpoint -----------------------------------------------------------
@@ -1721,7 +1747,7 @@ int hgnn_get_state(hgnn_ctx *c, void *buf, size_t *bytes) {
   long long step = 0;
   hipError_t e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(&step, c->step_dev, sizeof(step), hipMemcpyDeviceToHost);
-  h.step = step;
+  h.step = step + (c->bump_pending ? 1 : 0); // an AdamW step's advance not yet run
   char *p = reinterpret_cast<char *>(buf);
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
@@ -1758,6 +1784,7 @@ int hgnn_set_state(hgnn_ctx *c, const void *buf, size_t bytes) {
   if (e == hipSuccess) e = hipMemcpy(c->step_dev, &step, sizeof(step), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(c, e, "set_state");
   c->sticky = 0;
+  c->bump_pending = false; // the stored counter already counts every step
   int rc = stage_all(c, nullptr);
   if (rc) return rc;
   e = hipDeviceSynchronize();

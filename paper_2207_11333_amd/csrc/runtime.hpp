@@ -151,6 +151,11 @@ struct hgnn_ctx {
   hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev = nullptr;
   // the main stream has not yet waited for join_ev (a deferred layer join)
   bool join_pending = false;
+  // The weight copies are refreshed on the aux stream while the next batch's
+  // CSR is built (stage_ev marks the end); AdamW's step counter is advanced
+  // by that refresh, which is pending after an AdamW step until it runs.
+  hipEvent_t stage_ev = nullptr;
+  bool bump_pending = false;
 };
 
 namespace hgnn {
@@ -179,8 +184,9 @@ int head_forward(hgnn_ctx *c, Exec &ex, const float *wh, const float *h,
                  const float *target, float *pred, float *loss, hipStream_t s,
                  float *pred_node = nullptr, const float *ynode = nullptr);
 // Refresh every layer's GEMM-layout weight copies from the parameters in one
-// launch; bump_step (AdamW's step counter) is advanced when non-null.
-int stage_all(hgnn_ctx *c, hipStream_t s, long long *bump_step = nullptr);
+// launch; AdamW's step counter is advanced by it when an AdamW step left that
+// pending (bump_pending).
+int stage_all(hgnn_ctx *c, hipStream_t s);
 
 // Records an event pair around one launch when the timer watches `site`.
 // Only the training path's launches are timed (serving lanes never are).

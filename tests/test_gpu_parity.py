@@ -383,6 +383,39 @@ def test_adamw_step_isolated():
     m.close()
 
 
+def test_adam_steps_without_a_forward_between_them():
+    """The weight copies and AdamW's step counter are refreshed by the next
+    forward after a step; two steps in a row (no forward between them) must
+    still count t = 1, 2, and a checkpoint taken before the refresh must hold
+    the advanced count."""
+    w = synth.WORKLOADS["c0_small_fp32"]
+    b, params = w.batch(), w.params()
+    m = make_model(w.num_layers, w.hidden, w.edge_feat, 0, 0, w.delta)
+    m.set_params(params)
+    hg = _hgnn()
+    db = hg.DeviceBatch.from_host(b)
+    pred = torch.empty(b.num_graphs, device="cuda")
+    m.forward(db, pred)
+    m.backward()
+    g = m.grads().cpu().numpy().astype(np.float64)
+    theta = m.params().cpu().numpy().astype(np.float64)
+    mm, vv = np.zeros_like(theta), np.zeros_like(theta)
+    for t in (1, 2):
+        m.adam_step(lr=1e-3, weight_decay=0.01)
+        theta, mm, vv = oracle.adamw(theta, g, mm, vv, t, lr=1e-3, weight_decay=0.01)
+        r = rel(m.params().cpu().numpy().astype(np.float64), theta)
+        say(f"  step {t} without a forward: rel {r:.2e}")
+        assert r <= 1e-6
+    state = m.get_state()
+    # the header ends with the step count (int64), then params, m, v follow
+    hdr = state[:len(state) - 12 * m.num_params]
+    assert int.from_bytes(hdr[-8:], "little", signed=True) == 2
+    # a forward (which runs the refresh) leaves the count where it was
+    m.forward(db, pred)
+    assert m.get_state() == state
+    m.close()
+
+
 def test_checkpoint_resume_bitwise():
     hg = _hgnn()
     w = synth.WORKLOADS["c0_small_fp32"]
