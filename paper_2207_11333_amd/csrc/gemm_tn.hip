@@ -13,8 +13,9 @@ namespace {
 // TAG only distinguishes launch sites in profiles: 1 the update weight
 // gradient (S6), 2 the message weight gradient (S8), 0 the others.  PERM:
 // bucketed chunks (g.perm non-null), a template parameter so that the row
-// lookups add no branch to the loop.
-template <int PREC, int BM, int BN, int TAG, bool PERM>
+// lookups add no branch to the loop.  SCALE: some segment has row scales
+// (the concatenated update input); without it no scale is loaded at all.
+template <int PREC, int BM, int BN, int TAG, bool PERM, bool SCALE>
 __global__ void __launch_bounds__(256)
 k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   using P = Prec<PREC>;
@@ -144,7 +145,7 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
       const int i = i0 + b_il[j];
       const int ic = prow[S][j];
       rb[S][j] = *reinterpret_cast<const f4 *>(b_ptr[j] + (size_t)ic * b_ld[j]);
-      rsc[S][j] = b_sptr[j][(size_t)ic * b_sstride[j]];
+      if constexpr (SCALE) rsc[S][j] = b_sptr[j][(size_t)ic * b_sstride[j]];
       mk |= (b_ok[j] && i < i_hi) ? 1u << j : 0u;
     }
     bmk[S] = mk;
@@ -169,7 +170,8 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
       const int v = tid + j * 256;
       const int il = v / (BN / 4), nc = (v % (BN / 4)) * 4;
       const f4 raw = b_ones[j] ? f4{1.f, 0.f, 0.f, 0.f} : rb[S][j];
-      const float sc = b_has_scale[j] ? rsc[S][j] : 1.0f;
+      float sc = 1.0f;
+      if constexpr (SCALE) sc = b_has_scale[j] ? rsc[S][j] : 1.0f;
       const f4 val = (bmk[S] >> j & 1u) ? raw * sc : zero;
       if constexpr (KMAJ) {
         store4(Bs + il * LDKB + nc, val);
@@ -204,12 +206,19 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   };
   // step t (stage S = t % 2): slot S holds tile t+2's rows (fetched in step
   // t-1), slot 1-S is free (tile t+1's loads used it) and takes tile t+3's
+  // The scheduling barrier keeps the compiler from hoisting the other
+  // stage's masking selects into this step: they would make it wait for the
+  // loads still in flight.
   auto step = [&](auto st, int t) {
     constexpr int S = decltype(st)::value;
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
     stash(st);
     __syncthreads();
     fetch_rows(IC<1 - S>{}, min(t + 3, KT - 1));
+    // the row ids are issued before the data loads: the next step waits for
+    // them, and a wait for the youngest loads would wait for all
+    __builtin_amdgcn_sched_barrier(0);
     load(st, min(t + 2, KT - 1));
     if constexpr (KMAJ) mma_kmajor();
     else mma_tile<PREC, TM, TN, LDA, BK>(As, Bs, wm0, wn0, acc);
@@ -219,14 +228,21 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     fetch_rows(IC<0>{}, 0);
     load(IC<0>{}, 0);
     fetch_rows(IC<1>{}, min(1, KT - 1));
-    if (KT > 1) load(IC<1>{}, 1);
+    load(IC<1>{}, min(1, KT - 1)); // KT = 1: tile 0 again, never stashed
     fetch_rows(IC<0>{}, min(2, KT - 1));
   }
-  for (int t = 0; t < KT; t += 2) {
+  // drain the prologue's loads once here: otherwise the compiler carries
+  // their pending register writes into the loop head and waits for every
+  // load in flight there, each step
+  __builtin_amdgcn_s_waitcnt(0x0f70); // vmcnt(0)
+  // pairs of steps, then an odd last tile: no branch inside the loop body,
+  // so the waits for a stage's loads leave the other stage's loads in flight
+  int t = 0;
+  for (; t + 1 < KT; t += 2) {
     step(IC<0>{}, t);
-    if (t + 1 >= KT) break;
     step(IC<1>{}, t + 1);
   }
+  if (t < KT) step(IC<0>{}, t);
 
   const int lane = tid & 63;
   const int cr = 4 * (lane >> 4), cc = lane & 15;
@@ -263,7 +279,7 @@ typedef short v4s_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) v4s_t lds_v4s_t;
 typedef __attribute__((address_space(3))) __bf16 lds_bf16_t;
 
-template <int TAG, bool PERM>
+template <int TAG, bool PERM, bool SCALE>
 __global__ void __launch_bounds__(256, 2)
 k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   constexpr int BM = 128, BN = 128, BK = 32;
@@ -347,7 +363,7 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
       const int r = prow[S][j];
       ra[S][j] = *reinterpret_cast<const f4 *>(g.X + (size_t)r * g.ldx + a_m);
       rb[S][j] = *reinterpret_cast<const f4 *>(b_ptr + (size_t)r * b_ld);
-      rsc[S][j] = b_sptr[(size_t)r * b_sstride];
+      if constexpr (SCALE) rsc[S][j] = b_sptr[(size_t)r * b_sstride];
       mk |= (i0 + RSTEP * j < i_hi) ? 1u << j : 0u;
     }
     rmk[S] = mk;
@@ -360,7 +376,8 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
       const bool in = rmk[S] >> j & 1u;
       const f4 av = (a_ok && in) ? ra[S][j] : zero;
       const f4 raw = b_ones ? f4{1.f, 0.f, 0.f, 0.f} : rb[S][j];
-      const float sc = b_has_scale ? rsc[S][j] : 1.0f;
+      float sc = 1.0f;
+      if constexpr (SCALE) sc = b_has_scale ? rsc[S][j] : 1.0f;
       const f4 bv = (b_ok && in) ? raw * sc : zero;
       store4(As + (il0 + RSTEP * j) * LDK + c, av);
       store4(Bs + (il0 + RSTEP * j) * LDK + c, bv);
@@ -392,12 +409,17 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
       for (int j = 0; j < TN; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   };
+  // scheduling barrier: as in k_gemm_tn
   auto step = [&](auto st, int t) {
     constexpr int S = decltype(st)::value;
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
     stash(st);
     __syncthreads();
     fetch_rows(IC<1 - S>{}, min(t + 3, KT - 1));
+    // the row ids are issued before the data loads: the next step waits for
+    // them, and a wait for the youngest loads would wait for all
+    __builtin_amdgcn_sched_barrier(0);
     load(st, min(t + 2, KT - 1));
     mma();
   };
@@ -405,14 +427,21 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     fetch_rows(IC<0>{}, 0);
     load(IC<0>{}, 0);
     fetch_rows(IC<1>{}, min(1, KT - 1));
-    if (KT > 1) load(IC<1>{}, 1);
+    load(IC<1>{}, min(1, KT - 1)); // KT = 1: tile 0 again, never stashed
     fetch_rows(IC<0>{}, min(2, KT - 1));
   }
-  for (int t = 0; t < KT; t += 2) {
+  // drain the prologue's loads once here: otherwise the compiler carries
+  // their pending register writes into the loop head and waits for every
+  // load in flight there, each step
+  __builtin_amdgcn_s_waitcnt(0x0f70); // vmcnt(0)
+  // pairs of steps, then an odd last tile: no branch inside the loop body,
+  // so the waits for a stage's loads leave the other stage's loads in flight
+  int t = 0;
+  for (; t + 1 < KT; t += 2) {
     step(IC<0>{}, t);
-    if (t + 1 >= KT) break;
     step(IC<1>{}, t + 1);
   }
+  if (t < KT) step(IC<0>{}, t);
 
   const int cr = 4 * (lane >> 4), cc = lane & 15;
   float *Pz = g.P + (size_t)z * g.M * g.Ncols;
@@ -432,42 +461,49 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
 
 } // namespace
 
-template <int TAG, bool PERM>
-static void run_tn(const Dims *dims, const GemmTN &g, int precision, hipStream_t s,
-                   hipEvent_t ev0, hipEvent_t ev1, int grid, int nt) {
-  (void)precision; // FP32 only: BF16 takes k_gemm_tn_tr
+template <int TAG, bool PERM, bool SCALE>
+static void run_tn(const Dims *dims, const GemmTN &g, hipStream_t s, hipEvent_t ev0,
+                   hipEvent_t ev1, int grid, int nt) {
   // a non-null event pair is stamped with the kernel's own start and end
-  hipExtLaunchKernelGGL(k_gemm_tn<0, 64, 64, TAG, PERM>, dim3(grid), dim3(256), 0, s, ev0, ev1,
-                        0, dims, g, nt);
+  hipExtLaunchKernelGGL(k_gemm_tn<0, 64, 64, TAG, PERM, SCALE>, dim3(grid), dim3(256), 0, s,
+                        ev0, ev1, 0, dims, g, nt);
 }
 
-template <int TAG, bool PERM>
+template <int TAG, bool PERM, bool SCALE>
 static void run_tn_tr(const Dims *dims, const GemmTN &g, hipStream_t s, hipEvent_t ev0,
                       hipEvent_t ev1, int grid, int nt) {
-  hipExtLaunchKernelGGL(k_gemm_tn_tr<TAG, PERM>, dim3(grid), dim3(256), 0, s, ev0, ev1, 0,
-                        dims, g, nt);
+  hipExtLaunchKernelGGL(k_gemm_tn_tr<TAG, PERM, SCALE>, dim3(grid), dim3(256), 0, s, ev0, ev1,
+                        0, dims, g, nt);
 }
 
 // FP32: 64 x 64 tiles (k_gemm_tn); BF16: 128 x 128 tiles read through the
 // transposing LDS loads (k_gemm_tn_tr).  Measured at 40k nodes: the BF16
 // update weight gradient 257 -> 139 us and the message weight gradient
 // 115 -> 70 us at their best split counts, with bitwise equal partials.
+// Instances: the bucketed update weight gradient (no row scales), the
+// concatenated one (scaled segments), the message weight gradient (no
+// scales) and a general one for the other sites.
 hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
                           hipStream_t s, int tag, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.M <= 0 || g.Ncols <= 0) return hipSuccess;
+  bool scaled = false;
+  for (int q = 0; q < g.nseg; ++q) scaled = scaled || g.seg[q].scale != nullptr;
+  if (tag == 1 && g.perm && scaled) return hipErrorInvalidValue;
+  if (tag == 2 && (scaled || g.perm)) tag = 0;
+  if (tag == 0 && g.perm) return hipErrorInvalidValue;
   const int T = precision ? 128 : 64;
   const int nt = cdiv(g.Ncols, T);
   const int grid = cdiv(g.M, T) * nt * (g.splits + (g.perm ? g.nb : 0));
   if (precision) {
-    if (tag == 1 && g.perm) run_tn_tr<1, true>(dims, g, s, ev0, ev1, grid, nt);
-    else if (tag == 1) run_tn_tr<1, false>(dims, g, s, ev0, ev1, grid, nt);
-    else if (tag == 2) run_tn_tr<2, false>(dims, g, s, ev0, ev1, grid, nt);
-    else run_tn_tr<0, false>(dims, g, s, ev0, ev1, grid, nt);
+    if (tag == 1 && g.perm) run_tn_tr<1, true, false>(dims, g, s, ev0, ev1, grid, nt);
+    else if (tag == 1) run_tn_tr<1, false, true>(dims, g, s, ev0, ev1, grid, nt);
+    else if (tag == 2) run_tn_tr<2, false, false>(dims, g, s, ev0, ev1, grid, nt);
+    else run_tn_tr<0, false, true>(dims, g, s, ev0, ev1, grid, nt);
   } else {
-    if (tag == 1 && g.perm) run_tn<1, true>(dims, g, 0, s, ev0, ev1, grid, nt);
-    else if (tag == 1) run_tn<1, false>(dims, g, 0, s, ev0, ev1, grid, nt);
-    else if (tag == 2) run_tn<2, false>(dims, g, 0, s, ev0, ev1, grid, nt);
-    else run_tn<0, false>(dims, g, 0, s, ev0, ev1, grid, nt);
+    if (tag == 1 && g.perm) run_tn<1, true, false>(dims, g, s, ev0, ev1, grid, nt);
+    else if (tag == 1) run_tn<1, false, true>(dims, g, s, ev0, ev1, grid, nt);
+    else if (tag == 2) run_tn<2, false, false>(dims, g, s, ev0, ev1, grid, nt);
+    else run_tn<0, false, true>(dims, g, s, ev0, ev1, grid, nt);
   }
   return hipGetLastError();
 }
