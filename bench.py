@@ -47,8 +47,9 @@ SITE_TRAFFIC = {
                        ["csrc/gemm_nt.hip", "csrc/mfma_tile.hpp"]),
 }
 AGGREGATE_TRAFFIC = {
-    "aggregate": ("aggregate_c3_traffic.txt", ["csrc/aggregate.hip"]),
-    "aggregate_bwd": ("aggregate_bwd_c3_traffic.txt", ["csrc/aggregate.hip"]),
+    "aggregate": ("aggregate_c3_traffic.txt", ["csrc/aggregate.hip", "csrc/agg_msg.hpp"]),
+    "aggregate_bwd": ("aggregate_bwd_c3_traffic.txt",
+                      ["csrc/agg_fused.hip", "csrc/agg_msg.hpp", "csrc/mfma_tile.hpp"]),
 }
 
 
@@ -77,7 +78,9 @@ SITES = {
     "update_gemm": ("S3 update linear", "k_gemm_nt<P, 64, 128, *, 1, 4, *>", "mfma"),
     "update_wgrad": ("S6 update weight gradient", "k_gemm_tn<P, 64, 64, 1>", "mfma"),
     "agg_input_gemm": ("S6 aggregate-input gradient", "k_gemm_nt<P, 64, 128, *, 3, 4, *>", "mfma"),
-    "aggregate_bwd": ("S7 aggregation adjoint", "k_aggregate_bwd<1>", "hbm"),
+    # by degree bucket dA is formed inside the adjoint (one fused kernel, dA
+    # not stored) and the S6 aggregate-input GEMM site has no launches
+    "aggregate_bwd": ("S6 dA + S7 aggregation adjoint, fused", "k_agg_bwd_fused<P, 1, *>", "hbm"),
     "input_gemm": ("S6+S8 layer-input gradient", "k_gemm_nt<P, 64, 128, *, 4, 4, *>", "mfma"),
     "message_wgrad": ("S8 message weight gradient", "k_gemm_tn<P, 64, 64, 2>", "mfma"),
 }
@@ -108,7 +111,7 @@ def site_work(site, w, N, E):
     if site == "aggregate":
         return float(aggregate_bytes(N, E, H, Fe)), rec * L
     if site == "aggregate_bwd":
-        return float(aggregate_bwd_bytes(N, E, H, Fe)), L
+        return float(aggregate_bwd_bytes(N, E, H, Fe, fused=True)), L
     raise KeyError(site)
 
 
@@ -551,11 +554,13 @@ def aggregate_bytes(N, E, H, Fe):
     return 4 * H * E + 4 * H * N + 4 * (N + 1) + 4 * E + 4 * E * Fe + 16 * H * N + 2 * H * N
 
 
-def aggregate_bwd_bytes(N, E, H, Fe):
+def aggregate_bwd_bytes(N, E, H, Fe, fused=False):
     """Algorithmic bytes of one aggregation-adjoint launch (S7): dA (4H), mean
     and std (2H), arg bytes (2H) and P (H) per node, gathered Q (H) per edge and
-    the CSR read; per-edge dm (E x H), D_in (N x H) and De (N x H Fe) written."""
-    reads = 16 * H * N + 8 * H * N + 2 * H * N + 4 * H * N + 4 * H * E
+    the CSR read; per-edge dm (E x H), D_in (N x H) and De (N x H Fe) written.
+    Fused with the aggregate-input gradient, du (H per node) is read instead
+    of dA (the weights, a few MB, are left out)."""
+    reads = (4 if fused else 16) * H * N + 8 * H * N + 2 * H * N + 4 * H * N + 4 * H * E
     reads += 4 * (N + 1) + 4 * E + 4 * E * Fe
     writes = 4 * H * E + 4 * H * N + 4 * H * N * Fe
     return reads + writes

@@ -15,58 +15,13 @@
 // per-edge dm is stored in CSR order; D_in[i] = sum over in-edges (same
 // pass) and D_out[j] = sum over the out-edges of j through the by-source
 // transpose (second kernel): fixed summation orders, no atomics.
-#include "common.hpp"
+#include "agg_msg.hpp"
 
 namespace hgnn {
 
 namespace {
 
 inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
-
-constexpr int kCache = 4; // messages kept in registers per thread
-
-template <int FE>
-__device__ __forceinline__ f4 message(const float *__restrict__ PQ, int H, int s,
-                                      int c, f4 p, f4 bm, const f4 (&we)[4],
-                                      const float *__restrict__ csr_e, int q) {
-  f4 m = p + *reinterpret_cast<const f4 *>(PQ + (size_t)s * 2 * H + H + c);
-#pragma unroll
-  for (int f = 0; f < FE; ++f) m += csr_e[(size_t)q * FE + f] * we[f];
-  return m + bm;
-}
-
-// Up to kCache in-edges of a node are fetched together: all source ids,
-// then all gathered Q rows, so a node costs three dependent memory latencies
-// (rowptr, ids, rows) whatever its degree up to kCache; the loads are from
-// clamped indices and masked, so no branch serialises them.
-template <int FE>
-__device__ __forceinline__ int gather_messages(const float *__restrict__ PQ, int H, int c,
-                                               f4 p, f4 bm, const f4 (&we)[4],
-                                               const int *__restrict__ csr_src,
-                                               const float *__restrict__ csr_e, int lo,
-                                               int d, f4 (&m)[kCache], float (&ev)[kCache][4]) {
-  int src[kCache];
-#pragma unroll
-  for (int o = 0; o < kCache; ++o) src[o] = csr_src[lo + min(o, d - 1)];
-#pragma unroll
-  for (int o = 0; o < kCache; ++o) {
-    const int q = lo + min(o, d - 1);
-#pragma unroll
-    for (int f = 0; f < FE; ++f) ev[o][f] = csr_e[(size_t)q * FE + f];
-  }
-  f4 qr[kCache];
-#pragma unroll
-  for (int o = 0; o < kCache; ++o)
-    qr[o] = *reinterpret_cast<const f4 *>(PQ + (size_t)src[o] * 2 * H + H + c);
-#pragma unroll
-  for (int o = 0; o < kCache; ++o) {
-    f4 v = p + qr[o];
-#pragma unroll
-    for (int f = 0; f < FE; ++f) v += ev[o][f] * we[f];
-    m[o] = v + bm;
-  }
-  return min(d, kCache);
-}
 
 template <int FE>
 __global__ void __launch_bounds__(256)
@@ -154,59 +109,13 @@ k_aggregate_bwd(const Dims *__restrict__ dims, int H, const float *__restrict__ 
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)(t / tpn), c = (int)(t % tpn) * 4;
   if (i >= dims->N) return;
-  const int lo = rowptr[i], hi = rowptr[i + 1], d = hi - lo;
-  f4 din = {0.f, 0.f, 0.f, 0.f};
-  f4 de[4] = {din, din, din, din};
-  if (d > 0) {
-    f4 we[4];
-#pragma unroll
-    for (int f = 0; f < FE; ++f)
-      we[f] = *reinterpret_cast<const f4 *>(WeT + (size_t)f * H + c);
-    const f4 bm = *reinterpret_cast<const f4 *>(bmv + c);
-    const f4 p = *reinterpret_cast<const f4 *>(PQ + (size_t)i * 2 * H + c);
-    const float *Ai = A + (size_t)i * 4 * H;
-    const float *dAi = dA + (size_t)i * 4 * H;
-    const f4 mu = *reinterpret_cast<const f4 *>(Ai + c);
-    const f4 sd = *reinterpret_cast<const f4 *>(Ai + 3 * H + c);
-    const f4 dmu = *reinterpret_cast<const f4 *>(dAi + c);
-    const f4 dmn = *reinterpret_cast<const f4 *>(dAi + H + c);
-    const f4 dmx = *reinterpret_cast<const f4 *>(dAi + 2 * H + c);
-    const f4 dsd = *reinterpret_cast<const f4 *>(dAi + 3 * H + c);
-    const uint32_t amin = *reinterpret_cast<const uint32_t *>(args + (size_t)i * 2 * H + c);
-    const uint32_t amax = *reinterpret_cast<const uint32_t *>(args + (size_t)i * 2 * H + H + c);
-    f4 cache[kCache];
-    float ev[kCache][4];
-    const int dc = gather_messages<FE>(PQ, H, c, p, bm, we, csr_src, csr_e, lo, d, cache, ev);
-    const float fd = (float)d;
-    const f4 base = dmu / fd;
-    const f4 coef = dsd / (fd * sd);
-    auto emit = [&](const f4 &m, int o, const float *e) {
-      f4 g = base + coef * (m - mu);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if ((int)((amin >> (8 * k)) & 0xff) == o) g[k] += dmn[k];
-        if ((int)((amax >> (8 * k)) & 0xff) == o) g[k] += dmx[k];
-      }
-      *reinterpret_cast<f4 *>(dm + (size_t)(lo + o) * H + c) = g;
-      din += g;
-#pragma unroll
-      for (int f = 0; f < FE; ++f) de[f] += g * e[f];
-    };
-#pragma unroll
-    for (int o = 0; o < kCache; ++o)
-      if (o < dc) emit(cache[o], o, ev[o]);
-    for (int o = kCache; o < d; ++o) {
-      const int q = lo + o;
-      float e[4];
-#pragma unroll
-      for (int f = 0; f < FE; ++f) e[f] = csr_e[(size_t)q * FE + f];
-      emit(message<FE>(PQ, H, csr_src[q], c, p, bm, we, csr_e, q), o, e);
-    }
-  }
-  float *Di = D + (size_t)i * ldD;
-  *reinterpret_cast<f4 *>(Di + c) = din;
-#pragma unroll
-  for (int f = 0; f < FE; ++f) *reinterpret_cast<f4 *>(Di + (2 + f) * H + c) = de[f];
+  const float *dAi = dA + (size_t)i * 4 * H;
+  const f4 dmu = *reinterpret_cast<const f4 *>(dAi + c);
+  const f4 dmn = *reinterpret_cast<const f4 *>(dAi + H + c);
+  const f4 dmx = *reinterpret_cast<const f4 *>(dAi + 2 * H + c);
+  const f4 dsd = *reinterpret_cast<const f4 *>(dAi + 3 * H + c);
+  node_adjoint<FE>(i, c, H, PQ, rowptr, csr_src, csr_e, WeT, bmv, A, args, dmu, dmn, dmx, dsd,
+                   dm, D, ldD);
 }
 
 __global__ void __launch_bounds__(256)

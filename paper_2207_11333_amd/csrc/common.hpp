@@ -249,6 +249,26 @@ hipError_t launch_aggregate_bwd(const Dims *dims, int capN, int H, int Fe,
                                 const float *dA, float *dm, float *D, int ldD,
                                 hipStream_t s, hipEvent_t ev0 = nullptr,
                                 hipEvent_t ev1 = nullptr);
+// The aggregate-input gradient dA = du W_eff(d) fused into the aggregation
+// adjoint (agg_fused.hip), for degree-bucketed models with H a multiple of
+// 32: dA is formed per 64-row, 32-feature block in LDS and never stored.
+struct AggBwdFused {
+  int H, nb;
+  const float *du;         // [N, H]
+  const void *B, *B_lo;    // per bucket [4H, H] (FP32, or BF16 hi and lo), bstride apart
+  long long bstride;
+  const int *perm, *brow;  // the (degree, id) row order and its bucket bounds
+  const float *PQ;         // [N, 2H] message halves
+  const int *rowptr, *csr_src;
+  const float *csr_e, *WeT, *bm, *A;
+  const uint8_t *args;
+  float *dm, *D;           // per-edge dm [E, H]; D rows [N, ldD] (D_in and De written)
+  int ldD;
+};
+bool agg_bwd_fused_ok(int H, int nb);
+hipError_t launch_agg_bwd_fused(int capN, const AggBwdFused &a, int precision, int Fe,
+                                hipStream_t s, hipEvent_t ev0 = nullptr,
+                                hipEvent_t ev1 = nullptr);
 hipError_t launch_transpose_sum(const Dims *dims, int capN, int H,
                                 const int *srcptr, const int *t2csr,
                                 const float *dm, float *D, int ldD, hipStream_t s);

@@ -93,7 +93,7 @@ void free_work(Exec &ex) {
                    (void **)&w.csr.csr_pos, (void **)&w.csr.csr_e, (void **)&w.csr.sp,
                    (void **)&w.csr.sm, (void **)&w.xpad, (void **)&w.g, (void **)&w.q,
                    (void **)&w.ypred, (void **)&w.dy, (void **)&w.dq, (void **)&w.du,
-                   (void **)&w.dA, (void **)&w.dm, (void **)&w.D, (void **)&w.dh0,
+                   (void **)&w.dA, (void **)&w.dm, (void **)&w.D, (void **)&w.D2, (void **)&w.dh0,
                    (void **)&w.dh1, (void **)&w.ntpart, (void **)&w.zn, (void **)&w.Qn,
                    (void **)&w.dQn, (void **)&w.en, (void **)&w.dhn,
                    (void **)&w.csr.csr_dst, (void **)&w.csr.perm, (void **)&w.csr.brow,
@@ -170,9 +170,12 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
            f(w.dhn, (size_t)capN * H);
     ok = ok && f(w.du, (size_t)capN * H) && f(w.dh0, (size_t)capN * H) &&
          f(w.dh1, (size_t)capN * H);
-    if (pna)
-      ok = ok && f(w.dA, (size_t)capN * 4 * H) && f(w.dm, (size_t)capE * H) &&
-           f(w.D, (size_t)capN * (2 + c->Fe) * H);
+    if (pna) {
+      // dA is stored only when the adjoint does not form it itself
+      if (!agg_bwd_fused_ok(H, c->nb)) ok = ok && f(w.dA, (size_t)capN * 4 * H);
+      ok = ok && f(w.dm, (size_t)capE * H) && f(w.D, (size_t)capN * (2 + c->Fe) * H);
+      if (!c->recompute) ok = ok && f(w.D2, (size_t)capN * (2 + c->Fe) * H);
+    }
     else if (c->kind == HGNN_GC_SAGE)
       ok = ok && f(w.gcG, (size_t)capN * 2 * H);
     else
@@ -449,11 +452,12 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
 // dh_out_masked: dh_out already carries this layer's ReLU adjoint (it is du).
 // mask_dh_in: fold the previous layer's ReLU adjoint (h_in > 0) into dh_in.
 // defer_join: leave the main stream's wait for this layer's weight-gradient
-// work to the next layer_backward call, which takes it just before its
-// aggregation adjoint, the first of its launches that overwrites a buffer the
-// weight gradients read (D; the next input gradient GEMM then overwrites this
-// layer's du).  Not with recomputation, which rewrites the stored A and PQ at
-// the start of the next layer.
+// work to the later layer_backward calls, which take it just before the
+// first launch that overwrites a buffer it reads: the next layer's input
+// gradient GEMM (this layer's du) and, with the second D buffer, the
+// aggregation adjoint two layers on (with one D buffer, the next one's).
+// Not with recomputation, which rewrites the stored A and PQ at the start of
+// the next layer.
 int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_in,
                    const float *h_out, const float *dh_out, float *dh_in, float *dwl,
                    hipStream_t s, bool dh_out_masked = false, bool mask_dh_in = false,
@@ -473,6 +477,10 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   }
   float *PQ = w.PQ[slot], *A = w.A[slot];
   const uint8_t *args = w.args[slot];
+  // D of this layer: odd layers use the second buffer when it exists (no
+  // recomputation), so that writing it need not wait for the previous
+  // layer's weight gradients, which read the other one
+  float *Dl = (l & 1) && w.D2 ? w.D2 : w.D;
   const float *bm = wl + (d.obm - d.off);
   float *dWm = dwl + (d.oWm - d.off), *dbm = dwl + (d.obm - d.off);
   float *dWp = dwl + (d.oWp - d.off), *dbp = dwl + (d.obp - d.off);
@@ -560,9 +568,12 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     }
     if (e != hipSuccess) return hip_fail(c, e, "update weight gradient");
   }
-  // S6: dA = [du || s+ du || s- du] [W0; W+; W-], with degree buckets
-  // du W_eff(d) per bucket of rows
-  {
+  // S6 + S7.  With degree buckets: dA = du W_eff(d) formed per row and
+  // feature block inside the aggregation adjoint (one launch, dA not
+  // stored).  Otherwise dA = [du || s+ du || s- du] [W0; W+; W-] by the NT
+  // GEMM, then the adjoint.
+  const bool fused = c->nb && agg_bwd_fused_ok(H, c->nb);
+  if (!fused) {
     GemmNT g{};
     if (c->nb) {
       g.nseg = 1;
@@ -593,21 +604,49 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     }
     if (e != hipSuccess) return hip_fail(c, e, "aggregate-input gradient GEMM");
   }
-  // the previous layer's weight gradients read D: wait for them now
-  if (c->join_pending) {
-    c->join_pending = false;
-    e = hipStreamWaitEvent(s, c->join_ev, 0);
-    if (e != hipSuccess) return hip_fail(c, e, "join");
+  // the weight gradients of the last layer that read this D (l + 2, or l + 1
+  // with a single D) must be done before it is rewritten
+  {
+    const int k = w.D2 ? (l & 1) : -1;
+    for (int q = 0; q < 2; ++q)
+      if ((k < 0 || q == k) && c->pjoin_pending[q]) {
+        c->pjoin_pending[q] = false;
+        e = hipStreamWaitEvent(s, c->pjoin_ev[q], 0);
+        if (e != hipSuccess) return hip_fail(c, e, "join");
+      }
   }
   // S7: per-edge dm, D_in, De; then D_out through the transpose
-  {
+  if (fused) {
+    AggBwdFused f{};
+    f.H = H;
+    f.nb = c->nb;
+    f.du = du;
+    f.B = c->WpTA[l];
+    f.B_lo = c->prec ? c->WpTA_lo[l] : nullptr;
+    f.bstride = (long long)4 * H * H;
+    f.perm = w.csr.perm;
+    f.brow = w.csr.brow;
+    f.PQ = PQ;
+    f.rowptr = w.csr.rowptr;
+    f.csr_src = w.csr.csr_src;
+    f.csr_e = w.csr.csr_e;
+    f.WeT = static_cast<const float *>(c->WeT[l]);
+    f.bm = bm;
+    f.A = A;
+    f.args = args;
+    f.dm = w.dm;
+    f.D = Dl;
+    f.ldD = ldD;
+    TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s, /*manual=*/true);
+    e = launch_agg_bwd_fused(ex.N, f, c->prec, Fe, s, tl.start(), tl.stop());
+  } else {
     TimedLaunch tl(c, ex, SITE_AGGREGATE_BWD, s, /*manual=*/true);
     e = launch_aggregate_bwd(ex.dims, ex.N, H, Fe, PQ, w.csr.rowptr, w.csr.csr_src,
                              w.csr.csr_e, static_cast<const float *>(c->WeT[l]), bm, A, args, w.dA,
-                             w.dm, w.D, ldD, s, tl.start(), tl.stop());
+                             w.dm, Dl, ldD, s, tl.start(), tl.stop());
   }
   if (e == hipSuccess)
-    e = launch_transpose_sum(ex.dims, ex.N, H, w.csr.srcptr, w.csr.t2csr, w.dm, w.D, ldD, s);
+    e = launch_transpose_sum(ex.dims, ex.N, H, w.csr.srcptr, w.csr.t2csr, w.dm, Dl, ldD, s);
   if (e != hipSuccess) return hip_fail(c, e, "aggregation adjoint");
   // second fork: D = [D_in | D_out | De] is ready
   e = hipEventRecord(c->fork_ev[1], s);
@@ -620,7 +659,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   const bool split_de = Fe > 0 && ex.N >= kSplitDeRows;
   {
     GemmTN t{};
-    t.X = w.D;
+    t.X = Dl;
     t.ldx = ldD;
     t.M = split_de ? 2 * H : ldD;
     t.nseg = 2;
@@ -651,7 +690,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     }
     if (e == hipSuccess && split_de) {
       // column sums of De over kColsumChunks row chunks
-      e = launch_colsum(ex.dims, w.D + 2 * H, ldD, Fe * H, kColsumChunks, c->part, a);
+      e = launch_colsum(ex.dims, Dl + 2 * H, ldD, Fe * H, kColsumChunks, c->part, a);
       if (e == hipSuccess) {
         const int ldm = 2 * d.F + Fe;
         ReduceMap r{};
@@ -671,11 +710,18 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   }
   // S6 + S8 input gradient: dh = [du || D_in || D_out] [W_h; W_dst; W_src]
   if (dh_in) {
+    // it rewrites the du that the previous layer's weight gradients read
+    const int k = (l + 1) & 1;
+    if (c->pjoin_pending[k]) {
+      c->pjoin_pending[k] = false;
+      e = hipStreamWaitEvent(s, c->pjoin_ev[k], 0);
+      if (e != hipSuccess) return hip_fail(c, e, "join");
+    }
     GemmNT g{};
     g.nseg = 3;
     g.seg[0] = SegA{du, nullptr, H, H, 0};
-    g.seg[1] = SegA{w.D, nullptr, ldD, H, H};
-    g.seg[2] = SegA{w.D + H, nullptr, ldD, H, 2 * H};
+    g.seg[1] = SegA{Dl, nullptr, ldD, H, H};
+    g.seg[2] = SegA{Dl + H, nullptr, ldD, H, 2 * H};
     g.B = c->WhdsT[l];
     g.B_lo = c->prec ? c->WhdsT_lo[l] : nullptr;
     g.ldb = 3 * H;
@@ -691,11 +737,13 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     }
     if (e != hipSuccess) return hip_fail(c, e, "input gradient GEMM");
   }
-  // join (now, or deferred to the next layer's aggregation adjoint)
-  e = hipEventRecord(c->join_ev, a);
-  if (e == hipSuccess && !defer_join) e = hipStreamWaitEvent(s, c->join_ev, 0);
+  // join now, or leave it to the launches above of the next layers
+  e = hipEventRecord(c->pjoin_ev[l & 1], a);
+  if (e == hipSuccess && !defer_join) e = hipStreamWaitEvent(s, c->pjoin_ev[l & 1], 0);
   if (e != hipSuccess) return hip_fail(c, e, "join");
-  c->join_pending = defer_join;
+  // a join covers every earlier record (the aux stream runs in order)
+  if (!defer_join) c->pjoin_pending[0] = c->pjoin_pending[1] = false;
+  else c->pjoin_pending[l & 1] = true;
   return HGNN_OK;
 }
 
@@ -1498,7 +1546,9 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
       hipEventCreateWithFlags(&c->fork_ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->fork_ev[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->pjoin_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->pjoin_ev[1], hipEventDisableTiming) != hipSuccess) {
     hgnn_destroy(c);
     return fail(HGNN_EDEVICE, "stream/event creation failed");
   }
@@ -1522,7 +1572,8 @@ void hgnn_destroy(hgnn_ctx *c) {
   free_work(c->ex);
   for (hipEvent_t ev : c->timer.ev) (void)hipEventDestroy(ev);
   c->timer.ev.clear();
-  for (hipEvent_t ev : {c->fork_ev[0], c->fork_ev[1], c->join_ev, c->stage_ev})
+  for (hipEvent_t ev : {c->fork_ev[0], c->fork_ev[1], c->join_ev, c->stage_ev, c->pjoin_ev[0],
+                        c->pjoin_ev[1]})
     if (ev) (void)hipEventDestroy(ev);
   if (c->aux) (void)hipStreamDestroy(c->aux);
   void **ptrs[] = {(void **)&c->params, (void **)&c->grads, (void **)&c->adam_m,
@@ -1687,6 +1738,12 @@ int hgnn_backward(hgnn_ctx *c, const float *dpred, void *stream) {
     if (hipError_t e = hipStreamWaitEvent(s, c->join_ev, 0); e != hipSuccess)
       return hip_fail(c, e, "join");
   }
+  for (int q = 0; q < 2; ++q)
+    if (c->pjoin_pending[q]) {
+      c->pjoin_pending[q] = false;
+      if (hipError_t e = hipStreamWaitEvent(s, c->pjoin_ev[q], 0); e != hipSuccess)
+        return hip_fail(c, e, "join");
+    }
   for (int l = c->L - 1; l >= 0; --l) {
     const float *h_in = l ? w.hbuf[l - 1] : c->ex.xin;
     // the last call (l = 0) joins, which orders all weight-gradient work
@@ -1775,6 +1832,7 @@ int hgnn_set_state(hgnn_ctx *c, const void *buf, size_t bytes) {
   (void)hipSetDevice(c->dev);
   hipError_t e = hipDeviceSynchronize();
   c->join_pending = false; // the synchronisation retired any deferred join
+  c->pjoin_pending[0] = c->pjoin_pending[1] = false;
   if (e != hipSuccess) (void)hipGetLastError(); // clear a sticky launch error if possible
   const char *p = reinterpret_cast<const char *>(buf) + sizeof(h);
   long long step = h.step;

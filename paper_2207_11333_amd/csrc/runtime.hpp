@@ -30,6 +30,7 @@ struct Work {
   float *g = nullptr, *q = nullptr, *ypred = nullptr, *dy = nullptr, *dq = nullptr;
   float *du = nullptr, *dA = nullptr, *dm = nullptr;
   float *D = nullptr;                    // [N, (2 + Fe) H] = [D_in | D_out | De]
+  float *D2 = nullptr;                   // odd layers' D (deferred joins, no recompute)
   float *dh0 = nullptr, *dh1 = nullptr;
   float *ntpart = nullptr;               // split-K partials of the NT GEMMs
   // node heads: outputs [N, Tn], hidden [Tn][N][H], its adjoint, errors
@@ -156,6 +157,13 @@ struct hgnn_ctx {
   // by that refresh, which is pending after an AdamW step until it runs.
   hipEvent_t stage_ev = nullptr;
   bool bump_pending = false;
+  // PNA backward: the end of layer l's weight-gradient work (aux) is marked
+  // by pjoin_ev[l & 1]; the main stream waits for it before the first of its
+  // launches that overwrites what that work reads (layer l - 2's aggregation
+  // adjoint rewrites D of the same parity, layer l - 1's input gradient GEMM
+  // rewrites layer l's du)
+  hipEvent_t pjoin_ev[2] = {nullptr, nullptr};
+  bool pjoin_pending[2] = {false, false};
 };
 
 namespace hgnn {
