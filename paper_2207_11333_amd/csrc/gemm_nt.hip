@@ -18,7 +18,9 @@ namespace {
 // barrier per K step.  It needs 102 KB of LDS (FP32), so it is taken only
 // where the grid holds at most one workgroup per CU anyway and each K split
 // runs at least four K tiles (launch_gemm_nt).
-template <int PREC, int BM, int BN, bool SPLIT, int TAG, int WGN, bool DB>
+// SCALE: some segment has per-row scales (the concatenated update and
+// aggregate-input forms); without it no scale is loaded or applied.
+template <int PREC, int BM, int BN, bool SPLIT, int TAG, int WGN, bool DB, bool SCALE>
 // FP32: four waves per SIMD (the compiler fits the kernel in 128 registers;
 // measured 1.7% faster end to end).  BF16: five, which holds the kernel to
 // 96 registers (one spilled).  Left to itself the compiler takes 125, and
@@ -106,28 +108,28 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
   // stage is written to LDS: a select right after the load makes the
   // compiler wait for that load at once, so no load would overlap the
   // products of the step that issued it.
+  // Rows and columns past the matrix read clamped (valid) rows: their
+  // products land only in outputs that are never stored, so they need no
+  // mask.  Only the K tail of a segment's last tile is zeroed, from klim (the
+  // segment's k left at the tile's start, uniform), when it is below BK.
   f4 ra[2][NA], rb[2][NB], rl[2][SPLIT ? NB : 1];
-  float rs[2][NA];
-  unsigned am[2], bm[2]; // bit j: element vector j is inside the matrix
-  bool hs[2];            // the stage's segment has a row scale
+  float rs[2][SCALE ? NA : 1];
+  int klim[2];
+  bool hs[2]; // the stage's segment has a row scale (SCALE only)
   int a_row[NA], a_col[NA];
-  bool a_ok[NA];
 #pragma unroll
   for (int j = 0; j < NA; ++j) {
     const int v = tid + j * NTH;
     const int m = m0 + v / (BK / 4);
-    a_ok[j] = m < m_hi;
     a_row[j] = min(m, m_hi - 1);
     if (g.perm) a_row[j] = g.perm[a_row[j]];
     a_col[j] = (v % (BK / 4)) * 4;
   }
   int b_row[NB], b_col[NB];
-  bool b_ok[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int v = tid + j * NTH;
     const int n = n0 + v / (BK / BVEC);
-    b_ok[j] = n < g.Ncols;
     b_row[j] = min(n, g.Ncols - 1);
     b_col[j] = (v % (BK / BVEC)) * BVEC;
   }
@@ -164,51 +166,69 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     const int lda = g.seg[q].ld, ks = g.seg[q].k, boff = g.seg[q].boff;
     const int k0 = kt * BK;
     const float *sbase = scale ? scale : aptr; // a readable word either way
-    unsigned mk = 0;
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       const int k = k0 + a_col[j];
       ra[S][j] = *reinterpret_cast<const f4 *>(aptr + (size_t)a_row[j] * lda + min(k, ks - 4));
-      rs[S][j] = sbase[a_row[j]];
-      mk |= (a_ok[j] && k < ks) ? 1u << j : 0u;
+      if constexpr (SCALE) rs[S][j] = sbase[a_row[j]];
     }
-    am[S] = mk;
+    klim[S] = ks - k0;
     hs[S] = scale != nullptr;
-    mk = 0;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int k = k0 + b_col[j];
       const size_t off = (size_t)b_row[j] * g.ldb + boff + min(k, ks - BVEC);
       rb[S][j] = *reinterpret_cast<const f4 *>(Bg + off);
       if constexpr (SPLIT) rl[S][j] = *reinterpret_cast<const f4 *>(Blg + off);
-      mk |= (b_ok[j] && k < ks) ? 1u << j : 0u;
     }
-    bm[S] = mk;
   };
   // register stage S goes to LDS buffer b (b = S when DB, else 0)
   auto stash_a = [&](auto st, auto buf) {
     constexpr int S = decltype(st)::value;
     T *Ad = decltype(buf)::value ? As1 : As;
     const f4 zero = {0.f, 0.f, 0.f, 0.f};
+    // a uniform branch: only a segment's last, partial K tile pays for masks
+    if (klim[S] >= BK) {
 #pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int v = tid + j * NTH;
-      const int r = v / (BK / 4), c = (v % (BK / 4)) * 4;
-      const float sc = hs[S] ? rs[S][j] : 1.0f;
-      store4(Ad + r * LDA + c, (am[S] >> j & 1u) ? ra[S][j] * sc : zero);
+      for (int j = 0; j < NA; ++j) {
+        const int v = tid + j * NTH;
+        const int r = v / (BK / 4), c = (v % (BK / 4)) * 4;
+        f4 x = ra[S][j];
+        if constexpr (SCALE) x = x * (hs[S] ? rs[S][j] : 1.0f);
+        store4(Ad + r * LDA + c, x);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        const int v = tid + j * NTH;
+        const int r = v / (BK / 4), c = (v % (BK / 4)) * 4;
+        f4 x = ra[S][j];
+        if constexpr (SCALE) x = x * (hs[S] ? rs[S][j] : 1.0f);
+        store4(Ad + r * LDA + c, c < klim[S] ? x : zero);
+      }
     }
   };
   auto stash_b = [&](auto st, auto buf) {
     constexpr int S = decltype(st)::value;
     T *Bd = decltype(buf)::value ? Bs1 : Bs, *Ld = decltype(buf)::value ? Bl1 : Bl;
     const f4 zero = {0.f, 0.f, 0.f, 0.f};
+    if (klim[S] >= BK) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int v = tid + j * NTH;
-      const int r = v / (BK / BVEC), c = (v % (BK / BVEC)) * BVEC;
-      const bool ok = bm[S] >> j & 1u;
-      *reinterpret_cast<f4 *>(Bd + r * LDA + c) = ok ? rb[S][j] : zero; // 16 raw bytes
-      if constexpr (SPLIT) *reinterpret_cast<f4 *>(Ld + r * LDA + c) = ok ? rl[S][j] : zero;
+      for (int j = 0; j < NB; ++j) {
+        const int v = tid + j * NTH;
+        const int r = v / (BK / BVEC), c = (v % (BK / BVEC)) * BVEC;
+        *reinterpret_cast<f4 *>(Bd + r * LDA + c) = rb[S][j]; // 16 raw bytes
+        if constexpr (SPLIT) *reinterpret_cast<f4 *>(Ld + r * LDA + c) = rl[S][j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int v = tid + j * NTH;
+        const int r = v / (BK / BVEC), c = (v % (BK / BVEC)) * BVEC;
+        const bool ok = c < klim[S];
+        *reinterpret_cast<f4 *>(Bd + r * LDA + c) = ok ? rb[S][j] : zero;
+        if constexpr (SPLIT) *reinterpret_cast<f4 *>(Ld + r * LDA + c) = ok ? rl[S][j] : zero;
+      }
     }
   };
   auto stash = [&](auto st, auto buf) {
@@ -371,7 +391,7 @@ constexpr int kNtWGN = 4; // 8 waves per workgroup
 constexpr long long kNtDbMaxGrid = 256;
 constexpr int kNtDbMinKt = 4;
 
-template <int PREC, int BM, int BN, int TAG>
+template <int PREC, int BM, int BN, int TAG, bool SCALE>
 hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, bool db, hipStream_t s,
                   hipEvent_t ev0, hipEvent_t ev1) {
   const int nt = cdiv(g.Ncols, BN);
@@ -386,18 +406,18 @@ hipError_t run_nt(const Dims *dims, int capM, const GemmNT &g, bool db, hipStrea
   if (split_weights) {
     if constexpr (PREC == 1) {
       if (db)
-        hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, true, TAG, kNtWGN, true>, grid, block, 0,
-                              s, ev0, ev1, 0, dims, ga, nt);
+        hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, true, TAG, kNtWGN, true, SCALE>, grid,
+                              block, 0, s, ev0, ev1, 0, dims, ga, nt);
       else
-        hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, true, TAG, kNtWGN, false>, grid, block, 0,
-                              s, ev0, ev1, 0, dims, ga, nt);
+        hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, true, TAG, kNtWGN, false, SCALE>, grid,
+                              block, 0, s, ev0, ev1, 0, dims, ga, nt);
     }
   } else if (db) {
-    hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN, true>, grid, block, 0, s,
-                          ev0, ev1, 0, dims, ga, nt);
+    hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN, true, SCALE>, grid,
+                          block, 0, s, ev0, ev1, 0, dims, ga, nt);
   } else {
-    hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN, false>, grid, block, 0, s,
-                          ev0, ev1, 0, dims, ga, nt);
+    hipExtLaunchKernelGGL(k_gemm_nt<PREC, BM, BN, false, TAG, kNtWGN, false, SCALE>, grid,
+                          block, 0, s, ev0, ev1, 0, dims, ga, nt);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && g.splits > 1) e = launch_reduce_nt(dims, capM, g, s);
@@ -462,20 +482,21 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
   const long long grid =
       (long long)(cdiv(capM, kNtBM) + (g.perm ? g.nb : 0)) * cdiv(g.Ncols, kNtBN) * g.splits;
   const bool db = grid <= kNtDbMaxGrid && kt >= kNtDbMinKt * g.splits;
-  // one instantiation per launch site, so that profiles name the site
+  // one instantiation per launch site, so that profiles name the site; row
+  // scales occur only in the concatenated update and aggregate-input forms
+  bool scaled = false;
+  for (int q = 0; q < g.nseg; ++q) scaled = scaled || g.seg[q].scale != nullptr;
+  if (scaled && tag != 1 && tag != 3) return hipErrorInvalidValue;
   switch (tag) {
-#define HGNN_NT_TAG(T)                                                                    \
-  case T:                                                                                 \
-    if (precision == 0) return run_nt<0, kNtBM, kNtBN, T>(dims, capM, g, db, s, ev0, ev1); \
-    return run_nt<1, kNtBM, kNtBN, T>(dims, capM, g, db, s, ev0, ev1);
-    HGNN_NT_TAG(1)
-    HGNN_NT_TAG(2)
-    HGNN_NT_TAG(3)
-    HGNN_NT_TAG(4)
-#undef HGNN_NT_TAG
-  default:
-    if (precision == 0) return run_nt<0, kNtBM, kNtBN, 0>(dims, capM, g, db, s, ev0, ev1);
-    return run_nt<1, kNtBM, kNtBN, 0>(dims, capM, g, db, s, ev0, ev1);
+#define HGNN_NT_RUN(T, SC)                                                                     \
+  (precision == 0 ? run_nt<0, kNtBM, kNtBN, T, SC>(dims, capM, g, db, s, ev0, ev1)              \
+                  : run_nt<1, kNtBM, kNtBN, T, SC>(dims, capM, g, db, s, ev0, ev1))
+  case 1: return scaled ? HGNN_NT_RUN(1, true) : HGNN_NT_RUN(1, false);
+  case 2: return HGNN_NT_RUN(2, false);
+  case 3: return scaled ? HGNN_NT_RUN(3, true) : HGNN_NT_RUN(3, false);
+  case 4: return HGNN_NT_RUN(4, false);
+  default: return HGNN_NT_RUN(0, false);
+#undef HGNN_NT_RUN
   }
 }
 

@@ -76,29 +76,30 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   // chunk; masks, constant columns and row scales are applied when the stage
   // is written to LDS, so the loads stay in flight over the step's products
   // (a select right after a load would make the compiler wait for it there).
+  // Columns past the matrix read clamped (valid) columns: their products
+  // land only in outputs that are never stored, so they need no mask.  Rows
+  // past the chunk (its last step) are zeroed, from rlim (rows of the chunk
+  // left at the step's first row, uniform) when it is below BK.
   f4 ra[2][NA], rb[2][NB];
   float rsc[2][NB];
-  unsigned amk[2], bmk[2];
+  int rlim[2];
   int a_il[NA], a_m[NA];
-  bool a_ok[NA];
 #pragma unroll
   for (int j = 0; j < NA; ++j) {
     const int v = tid + j * 256;
     a_il[j] = v / (BM / 4);
     const int m = m0 + (v % (BM / 4)) * 4;
-    a_ok[j] = m < g.M;
     a_m[j] = min(m, g.M - 4);
   }
   const float *b_ptr[NB];
   const float *b_sptr[NB]; // row scales, or the operand itself when unscaled
   int b_ld[NB], b_il[NB], b_sstride[NB];
-  bool b_ok[NB], b_has_scale[NB], b_ones[NB];
+  bool b_has_scale[NB], b_ones[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int v = tid + j * 256;
     b_il[j] = v / (BN / 4);
     int n = n0 + (v % (BN / 4)) * 4;
-    b_ok[j] = n < g.Ncols;
     n = min(n, g.Ncols - 4);
     int q = 0;
     while (q + 1 < g.nseg && n >= g.seg[q].ncols) { n -= g.seg[q].ncols; ++q; }
@@ -109,7 +110,6 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     b_has_scale[j] = g.seg[q].scale != nullptr;
     b_sptr[j] = b_has_scale[j] ? g.seg[q].scale : b_ptr[j];
     b_sstride[j] = b_has_scale[j] ? 1 : b_ld[j];
-    if (b_ones[j]) b_ok[j] = b_ok[j] && n == 0;
   }
   const int i_last = max(i_hi - 1, 0);
   // Row ids (nodes) of tile t's rows into slot Q.  With bucketed chunks
@@ -130,34 +130,27 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   // data loads of tile t into stage S, from the row ids in slot S
   auto load = [&](auto st, int t) {
     constexpr int S = decltype(st)::value;
-    const int i0 = i_lo + t * BK;
-    unsigned mk = 0;
+    rlim[S] = i_hi - (i_lo + t * BK);
 #pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int i = i0 + a_il[j];
+    for (int j = 0; j < NA; ++j)
       ra[S][j] = *reinterpret_cast<const f4 *>(g.X + (size_t)prow[S][j] * g.ldx + a_m[j]);
-      mk |= (a_ok[j] && i < i_hi) ? 1u << j : 0u;
-    }
-    amk[S] = mk;
-    mk = 0;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int i = i0 + b_il[j];
       const int ic = prow[S][j];
       rb[S][j] = *reinterpret_cast<const f4 *>(b_ptr[j] + (size_t)ic * b_ld[j]);
       if constexpr (SCALE) rsc[S][j] = b_sptr[j][(size_t)ic * b_sstride[j]];
-      mk |= (b_ok[j] && i < i_hi) ? 1u << j : 0u;
     }
-    bmk[S] = mk;
   };
-  auto stash = [&](auto st) {
+  // (a uniform branch: only a chunk's last, partial step pays for masks)
+  auto stash_rows = [&](auto st, auto masked) {
     constexpr int S = decltype(st)::value;
+    constexpr bool MASK = decltype(masked)::value;
     const f4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       const int v = tid + j * 256;
       const int il = v / (BM / 4), mc = (v % (BM / 4)) * 4;
-      const f4 av = (amk[S] >> j & 1u) ? ra[S][j] : zero;
+      const f4 av = (!MASK || a_il[j] < rlim[S]) ? ra[S][j] : zero;
       if constexpr (KMAJ) {
         store4(As + il * LDKA + mc, av);
       } else {
@@ -169,10 +162,9 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     for (int j = 0; j < NB; ++j) {
       const int v = tid + j * 256;
       const int il = v / (BN / 4), nc = (v % (BN / 4)) * 4;
-      const f4 raw = b_ones[j] ? f4{1.f, 0.f, 0.f, 0.f} : rb[S][j];
-      float sc = 1.0f;
-      if constexpr (SCALE) sc = b_has_scale[j] ? rsc[S][j] : 1.0f;
-      const f4 val = (bmk[S] >> j & 1u) ? raw * sc : zero;
+      f4 val = b_ones[j] ? f4{1.f, 0.f, 0.f, 0.f} : rb[S][j];
+      if constexpr (SCALE) val = val * (b_has_scale[j] ? rsc[S][j] : 1.0f);
+      if constexpr (MASK) val = b_il[j] < rlim[S] ? val : zero;
       if constexpr (KMAJ) {
         store4(Bs + il * LDKB + nc, val);
       } else {
@@ -180,6 +172,11 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
         for (int e = 0; e < 4; ++e) store1(Bs + (nc + e) * LDA + il, val[e]);
       }
     }
+  };
+  auto stash = [&](auto st) {
+    constexpr int S = decltype(st)::value;
+    if (rlim[S] >= BK) stash_rows(st, std::false_type{});
+    else stash_rows(st, std::true_type{});
   };
   // k-major multiply: lane group g supplies k = kc + 4 g + s in instruction
   // s, the assignment mma_tile uses, so the sum runs in the same order.
@@ -326,9 +323,8 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   // thread has the same columns and one set of column pointers serves all)
   const int c = (tid % (BM / 4)) * 4, il0 = tid / (BM / 4);
   constexpr int RSTEP = 256 / (BM / 4);
-  const bool a_ok = m0 + c < g.M;
+  // columns past the matrix and rows past the chunk: as in k_gemm_tn
   const int a_m = min(m0 + c, g.M - 4);
-  bool b_ok = n0 + c < g.Ncols;
   int n = min(n0 + c, g.Ncols - 4);
   int q = 0;
   while (q + 1 < g.nseg && n >= g.seg[q].ncols) { n -= g.seg[q].ncols; ++q; }
@@ -338,11 +334,10 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   const bool b_has_scale = g.seg[q].scale != nullptr;
   const float *b_sptr = b_has_scale ? g.seg[q].scale : b_ptr;
   const int b_sstride = b_has_scale ? 1 : b_ld;
-  if (b_ones) b_ok = b_ok && n == 0;
   const int i_last = max(i_hi - 1, 0);
   f4 ra[2][NV], rb[2][NV];
   float rsc[2][NV];
-  unsigned rmk[2];
+  int rlim[2];
   int prow[2][NV];
   auto fetch_rows = [&](auto slot, int t) {
     constexpr int Q = decltype(slot)::value;
@@ -356,32 +351,32 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
   };
   auto load = [&](auto st, int t) {
     constexpr int S = decltype(st)::value;
-    const int i0 = i_lo + t * BK + il0;
-    unsigned mk = 0;
+    rlim[S] = i_hi - (i_lo + t * BK);
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const int r = prow[S][j];
       ra[S][j] = *reinterpret_cast<const f4 *>(g.X + (size_t)r * g.ldx + a_m);
       rb[S][j] = *reinterpret_cast<const f4 *>(b_ptr + (size_t)r * b_ld);
       if constexpr (SCALE) rsc[S][j] = b_sptr[(size_t)r * b_sstride];
-      mk |= (i0 + RSTEP * j < i_hi) ? 1u << j : 0u;
     }
-    rmk[S] = mk;
   };
-  auto stash = [&](auto st) {
+  auto stash_rows = [&](auto st, auto masked) {
     constexpr int S = decltype(st)::value;
+    constexpr bool MASK = decltype(masked)::value;
     const f4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-      const bool in = rmk[S] >> j & 1u;
-      const f4 av = (a_ok && in) ? ra[S][j] : zero;
-      const f4 raw = b_ones ? f4{1.f, 0.f, 0.f, 0.f} : rb[S][j];
-      float sc = 1.0f;
-      if constexpr (SCALE) sc = b_has_scale ? rsc[S][j] : 1.0f;
-      const f4 bv = (b_ok && in) ? raw * sc : zero;
-      store4(As + (il0 + RSTEP * j) * LDK + c, av);
-      store4(Bs + (il0 + RSTEP * j) * LDK + c, bv);
+      const bool in = !MASK || il0 + RSTEP * j < rlim[S];
+      f4 bv = b_ones ? f4{1.f, 0.f, 0.f, 0.f} : rb[S][j];
+      if constexpr (SCALE) bv = bv * (b_has_scale ? rsc[S][j] : 1.0f);
+      store4(As + (il0 + RSTEP * j) * LDK + c, in ? ra[S][j] : zero);
+      store4(Bs + (il0 + RSTEP * j) * LDK + c, in ? bv : zero);
     }
+  };
+  auto stash = [&](auto st) {
+    constexpr int S = decltype(st)::value;
+    if (rlim[S] >= BK) stash_rows(st, std::false_type{});
+    else stash_rows(st, std::true_type{});
   };
   // lane part of a transposing read: row 8 g + 4 p + (li / 4), column
   // 4 (li % 4) of the 16-wide block
