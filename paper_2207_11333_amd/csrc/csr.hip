@@ -43,19 +43,27 @@ k_csr_init(const Dims *__restrict__ dims, const int *__restrict__ graph_ptr,
   if (staged)
     for (int k = threadIdx.x; k <= B; k += kInitThreads) s_gp[k] = graph_ptr[k];
   __syncthreads();
-  const int *gp = staged ? s_gp : graph_ptr;
   const int i = blockIdx.x * kInitThreads + threadIdx.x;
   if (i < B) {
-    if (gp[i + 1] <= gp[i]) atomicOr(err, ERR_GRAPH_PTR);
+    if (graph_ptr[i + 1] <= graph_ptr[i]) atomicOr(err, ERR_GRAPH_PTR);
   }
   if (i == 0) {
-    if (gp[0] != 0 || gp[B] != N) atomicOr(err, ERR_GRAPH_PTR);
+    if (graph_ptr[0] != 0 || graph_ptr[B] != N) atomicOr(err, ERR_GRAPH_PTR);
   }
   if (i < N) {
-    int lo = 0, hi = B; // find last b with graph_ptr[b] <= i
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (gp[mid] <= i) lo = mid; else hi = mid;
+    // last b with graph_ptr[b] <= i (two loops, so that each reads its own
+    // address space: LDS reads rather than generic ones)
+    int lo = 0, hi = B;
+    if (staged) {
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_gp[mid] <= i) lo = mid; else hi = mid;
+      }
+    } else {
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (graph_ptr[mid] <= i) lo = mid; else hi = mid;
+      }
     }
     node_graph[i] = lo;
     cnt_in[i] = 0;
@@ -64,8 +72,10 @@ k_csr_init(const Dims *__restrict__ dims, const int *__restrict__ graph_ptr,
   if (x) {
     // the first layer's input, zero-padded from F to Fp columns: the block's
     // kInitThreads rows, element by element so that stores are coalesced
+    // (unrolled so that the loads of several elements are in flight together)
     const int r0 = blockIdx.x * kInitThreads, nr = min(kInitThreads, N - r0);
     bool finite = true;
+#pragma unroll 8
     for (int e = threadIdx.x; e < nr * Fp; e += kInitThreads) {
       const int r = r0 + e / Fp, c = e % Fp;
       const float v = c < F ? x[(size_t)r * F + c] : 0.f;

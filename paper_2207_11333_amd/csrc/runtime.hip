@@ -72,15 +72,16 @@ constexpr int kColsumChunks = 128;
 // together at 4.5k and 40k nodes).  FP32 (64 x 64 tiles): about 512
 // workgroups (the update and message weight gradients at 4.5k nodes: 26
 // and 19 us, against 28 and 21 us at 1024).  BF16 (128 x 128 tiles,
-// gemm_tn.hip): about 384 workgroups, at most 32 splits (16-32 splits are
-// fastest at both sizes).
+// gemm_tn.hip): about 384 workgroups, at most 24 splits (swept again after
+// the loads were kept in flight: the update weight gradient at 4.5k nodes
+// 17.4 us at 24 splits, 19.5 us at 32; the message weight gradient equal).
 int tn_splits(int M, int Ncols, int precision) {
   const int T = precision ? 128 : 64;
   const int tiles = ((M + T - 1) / T) * ((Ncols + T - 1) / T);
   const int target = precision ? 384 : 512;
   int s = (target + tiles - 1) / tiles;
   if (s < 1) s = 1;
-  if (s > (precision ? 32 : 64)) s = precision ? 32 : 64;
+  if (s > (precision ? 24 : 64)) s = precision ? 24 : 64;
   return s;
 }
 
