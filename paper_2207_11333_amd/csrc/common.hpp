@@ -223,6 +223,17 @@ hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
 // reduce.hip
 hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s);
 hipError_t launch_reduce_upd(const ReduceUpd &r, hipStream_t s);
+// Up to three reductions in one launch (a layer's weight gradients): job k
+// is the ReduceUpd u when upd[k], else m[k]; the launcher fills G and grid.
+// At most one job is a ReduceUpd.
+struct ReduceJobs {
+  int njobs;
+  bool upd[3];
+  ReduceUpd u;
+  ReduceMap m[3];
+  int G[3], grid[3];
+};
+hipError_t launch_reduce_jobs(ReduceJobs j, hipStream_t s);
 // Column sums of X [dims->N, C] (leading dimension ldx) over Z fixed row
 // chunks into P [Z][C][4] (sum in element 0, zeros after): partials in the
 // layout of a weight-gradient GEMM's sum column, for launch_reduce_map.

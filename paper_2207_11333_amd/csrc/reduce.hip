@@ -194,6 +194,129 @@ k_colsum(const Dims *__restrict__ dims, const float *__restrict__ X, int ldx, in
   *reinterpret_cast<f4 *>(P + ((size_t)z * C + c) * 4) = f4{(s[0] + s[1]) + (s[2] + s[3]), 0.f, 0.f, 0.f};
 }
 
+// Several reductions in one launch (the weight gradients of one layer): job
+// j takes grid[j] workgroups; each job's lane groups are G[j] lanes wide (a
+// runtime width: the shuffle tree reads lanes up to G - 1 above, and only a
+// group's first lane, which sums its own group, writes).  The bodies are
+// k_reduce_upd's and k_reduce_map's, so each output is the same sum in the
+// same order as in those kernels.
+__device__ __forceinline__ float tree_sum(float v, int G) {
+  for (int off = 1; off < G; off <<= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ void job_upd(const ReduceUpd &r, long long gt, int G) {
+  const long long t = gt / G;
+  const long long total = (long long)r.M * r.Ncols;
+  const bool live = 4 * t < total;
+  const float *src = r.P + (live ? 4 * t : 0);
+  const int g = (int)(gt % G);
+  const int per = (r.Z + G - 1) / G;
+  const int z_lo = g * per, z_hi = min(r.Z, z_lo + per);
+  f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0, s2 = s0;
+  for (int z0 = z_lo; z0 < z_hi; z0 += kPerLane) {
+    f4 v[kPerLane];
+    float a[kPerLane], b[kPerLane];
+#pragma unroll
+    for (int u = 0; u < kPerLane; ++u) {
+      const int z = min(z0 + u, r.Z - 1);
+      v[u] = *reinterpret_cast<const f4 *>(src + z * total);
+      a[u] = r.zscale[2 * z];
+      b[u] = r.zscale[2 * z + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kPerLane; ++u)
+      if (z0 + u < z_hi) {
+        s0 += v[u];
+        s1 += a[u] * v[u];
+        s2 += b[u] * v[u];
+      }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    s0[e] = tree_sum(s0[e], G);
+    s1[e] = tree_sum(s1[e], G);
+    s2[e] = tree_sum(s2[e], G);
+  }
+  if (!live || g != 0) return;
+  const int m = (int)(4 * t / r.Ncols), c0 = (int)(4 * t % r.Ncols);
+  const int H = r.H, ldp = r.F + 12 * H;
+  float *row = r.dWp + (size_t)m * ldp;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c = c0 + e;
+    if (c < r.Fp) {
+      if (c < r.F) row[c] = s0[e];
+    } else if (c < r.Fp + 4 * H) {
+      const int cc = c - r.Fp;
+      row[r.F + cc] = s0[e];
+      row[r.F + 4 * H + cc] = s1[e];
+      row[r.F + 8 * H + cc] = s2[e];
+    } else if (c == r.Fp + 4 * H) {
+      r.dbp[m] = s0[e];
+    }
+  }
+}
+
+__device__ __forceinline__ void job_map(const ReduceMap &r, long long gt, int G) {
+  const long long t = gt / G;
+  const long long total = (long long)r.M * r.Ncols;
+  const bool live = 4 * t < total;
+  const float *src = r.P + (live ? 4 * t : 0);
+  const int g = (int)(gt % G);
+  const int per = (r.splits + G - 1) / G;
+  const int z_lo = g * per, z_hi = min(r.splits, z_lo + per);
+  f4 sum = f4{0.f, 0.f, 0.f, 0.f};
+  for (int z0 = z_lo; z0 < z_hi; z0 += kPerLane) {
+    f4 v[kPerLane];
+#pragma unroll
+    for (int u = 0; u < kPerLane; ++u) {
+      const int z = min(z0 + u, r.splits - 1);
+      v[u] = *reinterpret_cast<const f4 *>(src + z * total);
+    }
+#pragma unroll
+    for (int u = 0; u < kPerLane; ++u)
+      if (z0 + u < z_hi) sum += v[u];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) sum[e] = tree_sum(sum[e], G);
+  if (!live || g != 0) return;
+  const int m = (int)(4 * t / r.Ncols), c0 = (int)(4 * t % r.Ncols);
+  for (int k = 0; k < r.nroute; ++k) {
+    const ReduceRoute &ro = r.route[k];
+    if (m < ro.r0 || m >= ro.r1) continue;
+    const int u = m - ro.r0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = c0 + e;
+      if (c < r.main_cols) {
+        if (!ro.main) continue;
+        const int nb = r.npad > 1 ? r.npad : 1;
+        int oc;
+        if (c < nb * r.Fp) {
+          const int blk = c / r.Fp, w = c - blk * r.Fp;
+          if (w >= r.F) continue;
+          oc = blk * r.F + w;
+        } else {
+          oc = c - nb * (r.Fp - r.F);
+        }
+        ro.main[(size_t)u * ro.main_ld + ro.main_coloff + oc] = sum[e];
+      } else if (c == r.main_cols && ro.ones) {
+        ro.ones[(size_t)(u % ro.ones_split) * ro.ones_stride + u / ro.ones_split] = sum[e];
+      }
+    }
+    return;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_reduce_jobs(const ReduceJobs j) {
+  int b = blockIdx.x, k = 0;
+  while (k + 1 < j.njobs && b >= j.grid[k]) b -= j.grid[k++];
+  const long long gt = (long long)b * blockDim.x + threadIdx.x;
+  if (j.upd[k]) job_upd(j.u, gt, j.G[k]);
+  else job_map(j.m[k], gt, j.G[k]);
+}
+
 } // namespace
 
 hipError_t launch_colsum(const Dims *dims, const float *X, int ldx, int C, int Z, float *P,
@@ -245,6 +368,19 @@ hipError_t launch_reduce_map(const ReduceMap &r, hipStream_t s) {
   case 8: k_reduce_map<8><<<grid, 256, 0, s>>>(r); break;
   default: k_reduce_map<16><<<grid, 256, 0, s>>>(r); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_jobs(ReduceJobs j, hipStream_t s) {
+  int total = 0;
+  for (int k = 0; k < j.njobs; ++k) {
+    const long long n = j.upd[k] ? (long long)j.u.M * j.u.Ncols : (long long)j.m[k].M * j.m[k].Ncols;
+    j.G[k] = pick_group(j.upd[k] ? j.u.Z : j.m[k].splits);
+    j.grid[k] = n > 0 ? cdiv(n / 4 * j.G[k], 256) : 0;
+    total += j.grid[k];
+  }
+  if (total <= 0) return hipSuccess;
+  k_reduce_jobs<<<total, 256, 0, s>>>(j);
   return hipGetLastError();
 }
 

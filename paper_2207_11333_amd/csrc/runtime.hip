@@ -498,7 +498,10 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   if (e == hipSuccess) e = hipStreamWaitEvent(a, c->fork_ev[0], 0);
   if (e != hipSuccess) return hip_fail(c, e, "fork");
   // S6: dW^p = du^T [h || A || s+ A || s- A]; with degree buckets
-  // du^T [h || A] per bucket-pure chunk, the scalers applied by the reduction
+  // du^T [h || A] per bucket-pure chunk, the scalers applied by the
+  // reduction.  Its partial sums stay in part_u until the message weight
+  // gradient's are in part too: one launch reduces both.
+  ReduceJobs red{};
   if (c->nb) {
     GemmTN t{};
     t.X = du;
@@ -509,7 +512,7 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     t.seg[2] = SegY{nullptr, nullptr, 0, 4}; // sum column: db^p
     t.nseg = 3;
     t.Ncols = d.Fp + 4 * H + 4;
-    t.P = c->part;
+    t.P = c->part_u;
     t.splits = d.split_p;
     t.perm = w.csr.perm;
     t.brow = w.csr.brow;
@@ -520,21 +523,19 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, a, /*manual=*/true);
       e = launch_gemm_tn(ex.dims, t, c->prec, a, /*tag=*/1, tl.start(), tl.stop());
     }
-    if (e == hipSuccess) {
-      ReduceUpd r{};
-      r.P = c->part;
-      r.zscale = c->zscale;
-      r.Z = d.split_p + c->nb;
-      r.M = H;
-      r.Ncols = t.Ncols;
-      r.F = d.F;
-      r.Fp = d.Fp;
-      r.H = H;
-      r.dWp = dWp;
-      r.dbp = dbp;
-      e = launch_reduce_upd(r, a);
-    }
     if (e != hipSuccess) return hip_fail(c, e, "update weight gradient");
+    red.upd[0] = true;
+    ReduceUpd &r = red.u;
+    r.P = c->part_u;
+    r.zscale = c->zscale;
+    r.Z = d.split_p + c->nb;
+    r.M = H;
+    r.Ncols = t.Ncols;
+    r.F = d.F;
+    r.Fp = d.Fp;
+    r.H = H;
+    r.dWp = dWp;
+    r.dbp = dbp;
   } else {
     GemmTN t{};
     t.X = du;
@@ -548,27 +549,25 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
     t.seg[4] = SegY{nullptr, nullptr, 0, 4}; // sum column: db^p
     t.nseg = 5;
     t.Ncols = d.Fp + 12 * H + 4;
-    t.P = c->part;
+    t.P = c->part_u;
     t.splits = d.split_p;
     {
       TimedLaunch tl(c, ex, SITE_UPDATE_WGRAD, a, /*manual=*/true);
       e = launch_gemm_tn(ex.dims, t, c->prec, a, /*tag=*/1, tl.start(), tl.stop());
     }
-    if (e == hipSuccess) {
-      ReduceMap r{};
-      r.P = c->part;
-      r.splits = d.split_p;
-      r.M = H;
-      r.Ncols = d.Fp + 12 * H + 4;
-      r.main_cols = d.Fp + 12 * H;
-      r.F = d.F;
-      r.Fp = d.Fp;
-      r.route[0] = ReduceRoute{0, H, dWp, d.F + 12 * H, 0, dbp, 1, H};
-      r.nroute = 1;
-      e = launch_reduce_map(r, a);
-    }
     if (e != hipSuccess) return hip_fail(c, e, "update weight gradient");
+    ReduceMap &r = red.m[0];
+    r.P = c->part_u;
+    r.splits = d.split_p;
+    r.M = H;
+    r.Ncols = d.Fp + 12 * H + 4;
+    r.main_cols = d.Fp + 12 * H;
+    r.F = d.F;
+    r.Fp = d.Fp;
+    r.route[0] = ReduceRoute{0, H, dWp, d.F + 12 * H, 0, dbp, 1, H};
+    r.nroute = 1;
   }
+  red.njobs = 1;
   // S6 + S7.  With degree buckets: dA = du W_eff(d) formed per row and
   // feature block inside the aggregation adjoint (one launch, dA not
   // stored).  Otherwise dA = [du || s+ du || s- du] [W0; W+; W-] by the NT
@@ -673,9 +672,9 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       TimedLaunch tl(c, ex, SITE_MESSAGE_WGRAD, a, /*manual=*/true);
       e = launch_gemm_tn(ex.dims, t, c->prec, a, /*tag=*/2, tl.start(), tl.stop());
     }
-    if (e == hipSuccess) {
-      const int ldm = 2 * d.F + Fe;
-      ReduceMap r{};
+    const int ldm = 2 * d.F + Fe;
+    {
+      ReduceMap &r = red.m[red.njobs++];
       r.P = c->part;
       r.splits = t.splits;
       r.M = t.M;
@@ -687,27 +686,25 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       r.route[1] = ReduceRoute{H, 2 * H, dWm, ldm, d.F, nullptr, 0, 1};      // D_out
       r.route[2] = ReduceRoute{2 * H, ldD, nullptr, 0, 0, dWm + 2 * d.F, ldm, H}; // De
       r.nroute = (Fe > 0 && !split_de) ? 3 : 2;
-      e = launch_reduce_map(r, a);
     }
+    // column sums of De over kColsumChunks row chunks, after the GEMM's
+    // partials in the same buffer
+    float *pcol = c->part + (size_t)t.splits * t.M * t.Ncols;
     if (e == hipSuccess && split_de) {
-      // column sums of De over kColsumChunks row chunks
-      e = launch_colsum(ex.dims, Dl + 2 * H, ldD, Fe * H, kColsumChunks, c->part, a);
-      if (e == hipSuccess) {
-        const int ldm = 2 * d.F + Fe;
-        ReduceMap r{};
-        r.P = c->part;
-        r.splits = kColsumChunks;
-        r.M = Fe * H;
-        r.Ncols = 4;
-        r.main_cols = 0;
-        r.F = 0;
-        r.Fp = 0;
-        r.route[0] = ReduceRoute{0, Fe * H, nullptr, 0, 0, dWm + 2 * d.F, ldm, H}; // De
-        r.nroute = 1;
-        e = launch_reduce_map(r, a);
-      }
+      e = launch_colsum(ex.dims, Dl + 2 * H, ldD, Fe * H, kColsumChunks, pcol, a);
+      ReduceMap &r = red.m[red.njobs++];
+      r.P = pcol;
+      r.splits = kColsumChunks;
+      r.M = Fe * H;
+      r.Ncols = 4;
+      r.main_cols = 0;
+      r.F = 0;
+      r.Fp = 0;
+      r.route[0] = ReduceRoute{0, Fe * H, nullptr, 0, 0, dWm + 2 * d.F, ldm, H}; // De
+      r.nroute = 1;
     }
-    if (e != hipSuccess) return hip_fail(c, e, "message weight gradient");
+    if (e == hipSuccess) e = launch_reduce_jobs(red, a);
+    if (e != hipSuccess) return hip_fail(c, e, "weight gradients");
   }
   // S6 + S8 input gradient: dh = [du || D_in || D_out] [W_h; W_dst; W_src]
   if (dh_in) {
@@ -1285,7 +1282,7 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
   c->kind = kind;
   const int H = c->H;
   int64_t off = 0;
-  size_t part_max = 0;
+  size_t part_max = 0, part_u_max = 0;
   if (kind == HGNN_GC_SAGE) {
     for (int l = 0; l < c->L; ++l) {
       LayerDesc d{};
@@ -1346,11 +1343,13 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
     d.split_m2 = tn_splits(2 * H, d.Fp + 4, cfg->precision);
 
     zmax = std::max(zmax, d.split_p + c->nb);
-    const size_t a = (size_t)(d.split_p + c->nb) * H * wcols;
+    // the update weight gradient's partials have a buffer of their own: they
+    // are reduced together with the message weight gradient's
+    part_u_max = std::max(part_u_max, (size_t)(d.split_p + c->nb) * H * wcols);
     const size_t b = std::max((size_t)d.split_m * (2 + c->Fe) * H * (d.Fp + 4),
-                              (size_t)d.split_m2 * 2 * H * (d.Fp + 4));
-    const size_t e = (size_t)kColsumChunks * c->Fe * H * 4;
-    part_max = std::max(part_max, std::max(a, std::max(b, e)));
+                              (size_t)d.split_m2 * 2 * H * (d.Fp + 4) +
+                                  (size_t)kColsumChunks * c->Fe * H * 4);
+    part_max = std::max(part_max, b);
     c->ld.push_back(d);
   }
   c->Tg = Tg;
@@ -1427,6 +1426,7 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
   HGNN_CALLOC(c->ex.dims, 1);
   HGNN_CALLOC(c->ex.w.csr.err, 1);
   HGNN_CALLOC(c->part, part_max);
+  if (part_u_max) HGNN_CALLOC(c->part_u, part_u_max);
   if (c->nb) HGNN_CALLOC(c->zscale, 2 * (size_t)zmax);
   HGNN_CALLOC(c->gw_dev, Tg);
   HGNN_CALLOC(c->W1T, (size_t)Tg * H * H);
@@ -1582,7 +1582,7 @@ void hgnn_destroy(hgnn_ctx *c) {
                    (void **)&c->gw_dev, (void **)&c->nw_dev, (void **)&c->W1n,
                    (void **)&c->W1nT, (void **)&c->nh_part,
                    (void **)&c->table, (void **)&c->ex.dims, (void **)&c->ex.w.csr.err,
-                   (void **)&c->part, (void **)&c->zscale, (void **)&c->W1T};
+                   (void **)&c->part, (void **)&c->part_u, (void **)&c->zscale, (void **)&c->W1T};
   for (void **p : ptrs) dfree(*p);
   for (auto *v : {&c->Wds, &c->Wpp, &c->WpTA, &c->WhdsT, &c->Wds_lo, &c->Wpp_lo, &c->WpTA_lo,
                   &c->WhdsT_lo, &c->WeT, &c->Wg1, &c->Wg1_lo, &c->Wg2, &c->Wg2_lo})

@@ -136,6 +136,7 @@ struct hgnn_ctx {
   long long gc_max_elems = 0;
   bool staged_from_params = false;
   float *part = nullptr;
+  float *part_u = nullptr; // the update weight gradient's split-K partials
   float *zscale = nullptr; // per-chunk scalers of the bucketed update weight gradient
   float *W1T = nullptr;    // graph heads' W1 transposed [Tg][H][H] (staged with the layers)
   hgnn::Exec ex; // the training path's batch state
