@@ -13,8 +13,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libhgnn.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["csr.hip", "gemm_nt.hip", "gemm_tn.hip", "reduce.hip", "aggregate.hip", "agg_fused.hip", "head.hip", "adam.hip",
-           "gc.hip", "runtime.hip", "serve.hip", "store.hip", "noalloc.hip"]
+SOURCES = ["csr.hip", "gemm_nt.hip", "gemm_ntb.hip", "gemm_tn.hip", "reduce.hip", "aggregate.hip",
+           "agg_fused.hip", "head.hip", "adam.hip", "gc.hip", "runtime.hip", "serve.hip",
+           "store.hip", "noalloc.hip"]
 ARCH = os.environ.get("HGNN_OFFLOAD_ARCH", "gfx950")
 
 

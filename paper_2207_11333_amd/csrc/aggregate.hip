@@ -29,7 +29,7 @@ k_aggregate(const Dims *__restrict__ dims, int H, const float *__restrict__ PQ,
             const int *__restrict__ rowptr, const int *__restrict__ csr_src,
             const float *__restrict__ csr_e, const float *__restrict__ WeT,
             const float *__restrict__ bmv, float *__restrict__ A,
-            uint8_t *__restrict__ args, float eps) {
+            uint8_t *__restrict__ args, float eps, __bf16 *__restrict__ Ab) {
   const int tpn = H >> 2;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)(t / tpn), c = (int)(t % tpn) * 4;
@@ -90,6 +90,17 @@ k_aggregate(const Dims *__restrict__ dims, int H, const float *__restrict__ PQ,
   *reinterpret_cast<f4 *>(Ai + H + c) = mn;
   *reinterpret_cast<f4 *>(Ai + 2 * H + c) = mx;
   *reinterpret_cast<f4 *>(Ai + 3 * H + c) = sd;
+  if (Ab) { // the BF16 copy read by the BF16 update linear (RNE, as its staging rounds)
+    __bf16 *Bi = Ab + (size_t)i * 4 * H;
+    const f4 v[4] = {mu, mn, mx, sd};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf16x4 b;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[e] = (__bf16)v[j][e];
+      *reinterpret_cast<bf16x4 *>(Bi + j * H + c) = b;
+    }
+  }
   if (args) {
     uint8_t *ai = args + (size_t)i * 2 * H;
     *reinterpret_cast<uint32_t *>(ai + c) = amin;
@@ -166,12 +177,12 @@ hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
                             const float *PQ, const int *rowptr, const int *csr_src,
                             const float *csr_e, const float *WeT,
                             const float *bm, float *A, uint8_t *args, float eps,
-                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, __bf16 *Ab) {
   if (capN <= 0) return hipSuccess;
   const dim3 grid(cdiv((long long)capN * (H / 4), 256));
 #define HGNN_AGG(FE)                                                                      \
   hipExtLaunchKernelGGL(k_aggregate<FE>, grid, dim3(256), 0, s, ev0, ev1, 0, dims, H, PQ,  \
-                        rowptr, csr_src, csr_e, WeT, bm, A, args, eps)
+                        rowptr, csr_src, csr_e, WeT, bm, A, args, eps, Ab)
   switch (Fe) {
   case 0: HGNN_AGG(0); break;
   case 1: HGNN_AGG(1); break;

@@ -100,7 +100,45 @@ struct GemmNT {
   const int *brow;
   int nb;
   long long bstride;
+  // optional: a BF16 copy of C (the stored values rounded, RNE) for the
+  // consumers that read it in BF16; the product is then not split
+  __bf16 *Cb;
+  int ldcb;
 };
+
+// BF16-operand NT form (gemm_ntb.hip): C = act(sum_seg A_seg B_seg^T + bias)
+// with every A segment already in BF16 (written by its producer) and every
+// segment length a multiple of 64, so that whole K tiles are copied from
+// HBM to LDS without passing through registers.  Same products, in the same
+// order, as GemmNT's BF16 hi + lo form on the same values: the outputs are
+// bitwise equal.  No split-K, row scales, interleave or addend.
+struct SegB {
+  const __bf16 *ptr; // [rows, ld] row-major, k-contiguous, 16-byte aligned rows
+  int ld;            // leading dimension (elements, multiple of 8)
+  int k;             // segment length (multiple of 64)
+  int boff;          // column offset of this segment inside the B rows (multiple of 8)
+};
+struct GemmNTB {
+  SegB seg[kMaxSeg];
+  int nseg;
+  const __bf16 *B, *B_lo; // [Ncols, ldb] hi and lo halves of the weights
+  int ldb;
+  long long bstride;      // per-bucket weight stride (bucketed rows)
+  const int *perm, *brow; // degree-bucketed rows as in GemmNT, or nullptr
+  int nb;
+  int Ncols;
+  const float *bias;
+  int relu;
+  const float *mask; // as in GemmNT
+  float *C;
+  int ldc;
+  __bf16 *Cb; // optional BF16 copy of C (the same values rounded), or nullptr
+  int ldcb;
+  int M_fixed;
+};
+bool gemm_ntb_ok(const GemmNTB &g);
+hipError_t launch_gemm_ntb(const Dims *dims, int capM, const GemmNTB &g, hipStream_t s, int tag,
+                           hipEvent_t ev0, hipEvent_t ev1);
 
 // Weight-gradient form, reduction over rows i (nodes):
 // P[z][m, n] = sum_{i in chunk z} X[i, m] * Yv[i, n]
@@ -247,7 +285,8 @@ hipError_t launch_aggregate(const Dims *dims, int capN, int H, int Fe,
                             const int *csr_src, const float *csr_e,
                             const float *WeT, const float *bm,
                             float *A, uint8_t *args, float eps, hipStream_t s,
-                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                            __bf16 *Ab = nullptr); // optional BF16 copy of A
 hipError_t launch_relu_mask(const Dims *dims, int capN, int H,
                             const float *dh, const float *hout, float *du,
                             hipStream_t s);

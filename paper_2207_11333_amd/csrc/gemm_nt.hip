@@ -379,7 +379,10 @@ k_gemm_nt(const Dims *__restrict__ dims, const GemmNT g, int ntiles_n) {
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        if (nok && rok[i][v]) g.C[(size_t)node[i][v] * g.ldc + n] = o[i][v];
+        if (nok && rok[i][v]) {
+          g.C[(size_t)node[i][v] * g.ldc + n] = o[i][v];
+          if (g.Cb) g.Cb[(size_t)node[i][v] * g.ldcb + n] = (__bf16)o[i][v];
+        }
   }
 }
 
@@ -475,6 +478,7 @@ hipError_t launch_gemm_nt(const Dims *dims, int capM, GemmNT g, int precision,
   // layer-input gradient 12.1 -> 10.8 us)
   if (precision == 1) g.splits = 1;
   if (g.max_splits > 0 && g.splits > g.max_splits) g.splits = g.max_splits;
+  if (g.Cb) g.splits = 1; // the split reduction writes no BF16 copy
   g.P = partials;
   if (g.splits > 1 && !partials) g.splits = 1;
   while (g.splits > 1 && (size_t)g.splits * capM * g.Ncols > nt_partial_floats(0, 0, 0, 0))

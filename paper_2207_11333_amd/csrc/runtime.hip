@@ -104,6 +104,9 @@ void free_work(Exec &ex) {
   for (auto &p : w.gcA) dfree(reinterpret_cast<void *&>(p));
   w.gcA.clear();
   for (auto &p : w.hbuf) dfree(reinterpret_cast<void *&>(p));
+  for (auto &p : w.hbuf_b) dfree(reinterpret_cast<void *&>(p));
+  w.hbuf_b.clear();
+  dfree(reinterpret_cast<void *&>(w.Ab));
   for (auto &p : w.PQ) dfree(reinterpret_cast<void *&>(p));
   for (auto &p : w.A) dfree(reinterpret_cast<void *&>(p));
   for (auto &p : w.args) dfree(reinterpret_cast<void *&>(p));
@@ -112,6 +115,14 @@ void free_work(Exec &ex) {
   w.A.clear();
   w.args.clear();
   w.capB = w.capN = w.capE = 0;
+}
+
+// The BF16 linears of layers 1.. read BF16 copies of their inputs, written by
+// the producers (update linear, aggregation), so that whole K tiles go from
+// HBM to LDS untouched (gemm_ntb.hip): BF16 PNA models with degree buckets
+// and a hidden width that whole 64-deep K tiles cover.
+static bool bf16_copies(const hgnn_ctx *c) {
+  return c->kind == HGNN_GC_PNA && c->prec == 1 && c->nb > 0 && c->H % 64 == 0;
 }
 
 // Every capacity-sized buffer of an Exec, with its element count: the one
@@ -137,6 +148,10 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
   if (w.csr.nb) ok = ok && f(w.csr.perm, (size_t)capN) && f(w.csr.brow, (size_t)kMaxBuckets + 1);
   if (w.hbuf.size() != (size_t)nh) w.hbuf.assign(nh, nullptr);
   for (int l = 0; l < nh && ok; ++l) ok = f(w.hbuf[l], (size_t)capN * H);
+  const bool shadows = !inference && bf16_copies(c);
+  if (w.hbuf_b.size() != (size_t)(shadows ? nh : 0)) w.hbuf_b.assign(shadows ? nh : 0, nullptr);
+  for (int l = 0; l < (int)w.hbuf_b.size() && ok; ++l) ok = f(w.hbuf_b[l], (size_t)capN * H);
+  if (shadows) ok = ok && f(w.Ab, (size_t)capN * 4 * H);
   const bool pna = c->kind == HGNN_GC_PNA;
   if (pna) {
     if (w.PQ.size() != (size_t)nstore) {
@@ -348,13 +363,59 @@ int prepare(hgnn_ctx *c, Exec &ex, const hgnn_batch *b, int flags, hipStream_t s
   return HGNN_OK;
 }
 
+// Layer l's S2 (aggregation) from its messages' P|Q.
+static int aggregate_into(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *PQ,
+                          float *A, uint8_t *args, __bf16 *Ab, hipStream_t s) {
+  const LayerDesc &d = c->ld[l];
+  Work &w = ex.w;
+  const float *bm = wl + (d.obm - d.off);
+  hipError_t e;
+  {
+    TimedLaunch tl(c, ex, SITE_AGGREGATE, s, /*manual=*/true);
+    e = launch_aggregate(ex.dims, ex.N, c->H, c->Fe, PQ, w.csr.rowptr, w.csr.csr_src,
+                         w.csr.csr_e, static_cast<const float *>(c->WeT[l]), bm, A, args,
+                         (float)c->cfg.std_eps, s, tl.start(), tl.stop(), Ab);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "aggregate");
+  return HGNN_OK;
+}
+
+// The BF16 copy of layer l's input when the context holds one: the input is
+// the previous layer's output buffer, written together with its copy.
+static const __bf16 *input_copy(const Exec &ex, int l, const float *h_in) {
+  const Work &w = ex.w;
+  return (l > 0 && (size_t)l <= w.hbuf_b.size() && h_in == w.hbuf[l - 1]) ? w.hbuf_b[l - 1]
+                                                                           : nullptr;
+}
+
 // Layer l: S1 (P|Q GEMM), S2 (aggregation) into the given buffers.
+// hb: BF16 copy of hin (or null); Ab: where to write the BF16 copy of A (or null).
 static int message_and_aggregate(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *hin,
                                  int ldh, float *PQ, float *A, uint8_t *args,
-                                 hipStream_t s) {
+                                 hipStream_t s, const __bf16 *hb = nullptr,
+                                 __bf16 *Ab = nullptr) {
   const LayerDesc &d = c->ld[l];
   const int H = c->H;
   Work &w = ex.w;
+  if (hb) {
+    GemmNTB q{};
+    q.nseg = 1;
+    q.seg[0] = SegB{hb, H, d.Fp, 0};
+    q.B = static_cast<const __bf16 *>(c->Wds[l]);
+    q.B_lo = static_cast<const __bf16 *>(c->Wds_lo[l]);
+    q.ldb = d.Fp;
+    q.Ncols = 2 * H;
+    q.C = PQ;
+    q.ldc = 2 * H;
+    q.M_fixed = -1;
+    hipError_t e;
+    {
+      TimedLaunch tl(c, ex, SITE_MESSAGE_GEMM, s, /*manual=*/true);
+      e = launch_gemm_ntb(ex.dims, ex.N, q, s, /*tag=*/2, tl.start(), tl.stop());
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "message GEMM");
+    return aggregate_into(c, ex, l, wl, PQ, A, args, Ab, s);
+  }
   GemmNT g{};
   g.nseg = 1;
   g.seg[0] = SegA{hin, nullptr, ldh, d.Fp, 0};
@@ -371,15 +432,7 @@ static int message_and_aggregate(hgnn_ctx *c, Exec &ex, int l, const float *wl, 
     e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s, /*tag=*/2, tl.start(), tl.stop());
   }
   if (e != hipSuccess) return hip_fail(c, e, "message GEMM");
-  const float *bm = wl + (d.obm - d.off);
-  {
-    TimedLaunch tl(c, ex, SITE_AGGREGATE, s, /*manual=*/true);
-    e = launch_aggregate(ex.dims, ex.N, H, c->Fe, PQ, w.csr.rowptr, w.csr.csr_src,
-                         w.csr.csr_e, static_cast<const float *>(c->WeT[l]), bm, A, args,
-                         (float)c->cfg.std_eps, s, tl.start(), tl.stop());
-  }
-  if (e != hipSuccess) return hip_fail(c, e, "aggregate");
-  return HGNN_OK;
+  return aggregate_into(c, ex, l, wl, PQ, A, args, Ab, s);
 }
 
 static const float *layer_input(hgnn_ctx *c, Exec &ex, int l, const float *h_in, int *ldh,
@@ -407,12 +460,48 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
   const float *hin = layer_input(c, ex, l, h_in, &ldh, s, &rc);
   if (rc) return rc;
   const int slot = (c->recompute || ex.inference_only) ? 0 : l;
+  // BF16 copies: of this layer's input (layers 1..), of its aggregates (for
+  // the update linear) and of its output (for the next layer)
+  const __bf16 *hb = input_copy(ex, l, h_in);
+  __bf16 *hb_out = ((size_t)l < w.hbuf_b.size() && h_out == w.hbuf[l]) ? w.hbuf_b[l] : nullptr;
   rc = message_and_aggregate(c, ex, l, wl, hin, ldh, w.PQ[slot], w.A[slot],
-                             ex.inference_only ? nullptr : w.args[slot], s);
+                             ex.inference_only ? nullptr : w.args[slot], s, hb,
+                             hb ? w.Ab : nullptr);
   if (rc) return rc;
   w.stored_layer = l;
   float *A = w.A[slot];
+  if (hb && c->nb) {
+    // u = [h || A] [W_h | W_eff(d)]^T per bucket, on the BF16 copies
+    GemmNTB q{};
+    q.nseg = 2;
+    q.seg[0] = SegB{hb, H, d.Fp, 0};
+    q.seg[1] = SegB{w.Ab, 4 * H, 4 * H, d.Fp};
+    q.B = static_cast<const __bf16 *>(c->Wpp[l]);
+    q.B_lo = static_cast<const __bf16 *>(c->Wpp_lo[l]);
+    q.ldb = d.Fp + 4 * H;
+    q.bstride = (long long)H * q.ldb;
+    q.perm = w.csr.perm;
+    q.brow = w.csr.brow;
+    q.nb = c->nb;
+    q.Ncols = H;
+    q.bias = wl + (d.obp - d.off);
+    q.relu = 1;
+    q.C = h_out;
+    q.ldc = H;
+    q.Cb = hb_out;
+    q.ldcb = H;
+    q.M_fixed = -1;
+    hipError_t e;
+    {
+      TimedLaunch tl(c, ex, SITE_UPDATE_GEMM, s, /*manual=*/true);
+      e = launch_gemm_ntb(ex.dims, ex.N, q, s, /*tag=*/1, tl.start(), tl.stop());
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "update GEMM");
+    return HGNN_OK;
+  }
   GemmNT g{};
+  g.Cb = hb_out;
+  g.ldcb = H;
   if (c->nb) {
     // degree buckets: u = [h || A] [W_h | W_eff(d)]^T per bucket of rows
     g.nseg = 2;
@@ -472,7 +561,8 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
   if (rc) return rc;
   const int slot = c->recompute ? 0 : l;
   if (c->recompute && w.stored_layer != l) { // S10: re-run S1/S2 for this layer
-    rc = message_and_aggregate(c, ex, l, wl, hin, ldh, w.PQ[0], w.A[0], w.args[0], s);
+    rc = message_and_aggregate(c, ex, l, wl, hin, ldh, w.PQ[0], w.A[0], w.args[0], s,
+                               input_copy(ex, l, h_in));
     if (rc) return rc;
     w.stored_layer = l;
   }

@@ -24,6 +24,11 @@ struct Work {
   CsrBufs csr{};
   float *xpad = nullptr;                 // [N, F0p] padded layer-0 input
   std::vector<float *> hbuf;             // [L] layer outputs [N, H]
+  // BF16 copies of the layer outputs [L][N, H] and of one layer's aggregates
+  // [N, 4H], read by the BF16 linears (gemm_ntb.hip); training batches of
+  // bucketed BF16 PNA models only (empty / null otherwise)
+  std::vector<__bf16 *> hbuf_b;
+  __bf16 *Ab = nullptr;
   std::vector<float *> PQ, A;            // [L] (or 1 with recompute)
   std::vector<uint8_t *> args;
   int stored_layer = -1;                 // layer held by the shared slot
