@@ -4,18 +4,21 @@
 // Every A segment is already BF16 in HBM (its producer wrote the RNE-rounded
 // copy), so a K tile needs no conversion: it is copied from HBM to LDS by
 // the LDS-DMA loads of gfx950 (global_load_lds_dwordx4: 16 bytes per lane,
-// written to LDS in lane order), never passing through registers.  That
-// leaves the registers to the products: 128 x 128 tiles, four waves in a
-// 2 x 2 grid, each wave 64 x 64 of output (4 x 4 MFMA blocks), a third of
-// the LDS fragment reads per MFMA of the 32 x 32-per-wave register-staged
-// kernel (gemm_nt.hip).
+// written to LDS in lane order), never passing through registers, which are
+// left to the products: 128 x 128 tiles, eight waves in a 2 x 4 grid, each
+// wave 64 x 32 of output (4 x 2 MFMA blocks).  Measured: a wave's LDS-DMA
+// loads are served about one at a time, so the copy rate grows with the
+// waves that issue them (four waves per CU reach about 8 TB/s from L2,
+// sixteen about 25); eight waves of 64 x 32 beat four of 64 x 64 (update
+// linear at 40k rows: 80 against 96 us, the register-staged kernel 105).
 //
 // Pipeline: three LDS stages of one 64-deep K tile each (A, weight hi, weight
 // lo: 48 KB); tiles t + 1 and t + 2 are in flight while tile t computes.
 // Each wave counts its own DMA loads (vmcnt) and one barrier per tile makes
-// every wave's loads visible and frees the stage read by the previous tile.
-// The barrier sits before the tile's last quarter of MFMAs, which covers
-// the next tile's fragment reads.
+// every wave's loads visible and frees the stage read by the previous tile
+// (a plain s_barrier: the fence of __syncthreads would wait for every load
+// in flight).  The barrier sits before the tile's last quarter of MFMAs,
+// which covers the next tile's fragment reads.
 //
 // LDS rows are 128 bytes (64 BF16 of k): chunk c (8 k) of row r is stored at
 // 16 (c ^ (r & 7)), so the eight rows read by eight adjacent lanes of a
