@@ -68,6 +68,22 @@ __device__ __forceinline__ int xcd_tile(int bid, int T) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// Split-K grids of the weight-gradient GEMMs: a group is the column tiles of
+// one (chunk, row tile), which read the same rows and columns of X.  Groups
+// are dealt to the 8 XCDs in turn, each group whole on one XCD, so its
+// X block is fetched from HBM once and then served by that XCD's L2 (spread
+// over the XCDs, every column tile fetched it again).  bid -> (group grp,
+// column tile j); grp = -1 for the padding blocks of the last round.
+__device__ __forceinline__ void xcd_group(int bid, int ngroups, int gsize, int &grp, int &j) {
+  constexpr int X = 8;
+  const int x = bid % X, l = bid / X;
+  const int gi = l / gsize;
+  j = l - gi * gsize;
+  grp = gi * X + x;
+  if (grp >= ngroups) grp = -1;
+}
+inline int xcd_group_grid(int ngroups, int gsize) { return 8 * ((ngroups + 7) / 8) * gsize; }
+
 // Bucketed tiles: bucket q's rows [brow[q], brow[q + 1]) of the
 // (degree, id)-ordered rows are cut into ceil(n_q / T) tiles of T rows,
 // bucket after bucket.  Lane q of the wave takes bucket q (lanes past nb see
