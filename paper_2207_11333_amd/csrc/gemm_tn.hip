@@ -39,11 +39,12 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
 
   const int rows = dims->N;
   const int mtiles = (g.M + BM - 1) / BM;
-  int grp, jn;
-  xcd_group(blockIdx.x, (g.splits + (PERM ? g.nb : 0)) * mtiles, ntiles_n, grp, jn);
+  const int zc = g.splits + (PERM ? g.nb : 0), gm = tn_group_rows(zc, mtiles);
+  int grp, jt;
+  xcd_group(blockIdx.x, zc * (mtiles / gm), gm * ntiles_n, grp, jt);
   if (grp < 0) return;
-  const int z = grp / mtiles;
-  const int m0 = (grp % mtiles) * BM, n0 = jn * BN;
+  const int z = grp / (mtiles / gm);
+  const int m0 = ((grp % (mtiles / gm)) * gm + jt / ntiles_n) * BM, n0 = (jt % ntiles_n) * BN;
   int chunk = (rows + g.splits - 1) / g.splits;
   chunk = (chunk + BK - 1) / BK * BK;
   int i_lo = z * chunk;
@@ -56,7 +57,7 @@ k_gemm_tn(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     BucketWalk(g.brow, g.nb, chunk).find(z, bq, r0, r1);
     i_lo = bq >= 0 ? r0 : 0;
     i_hi = bq >= 0 ? min(r1, r0 + chunk) : 0;
-    if (grp % mtiles == 0 && jn == 0 && threadIdx.x == 0) {
+    if (m0 == 0 && n0 == 0 && threadIdx.x == 0) {
       g.zscale[2 * z] = bq >= 0 ? g.table[2 * bq] : 0.f;
       g.zscale[2 * z + 1] = bq >= 0 ? g.table[2 * bq + 1] : 0.f;
     }
@@ -291,11 +292,12 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
 
   const int rows = dims->N;
   const int mtiles = (g.M + BM - 1) / BM;
-  int grp, jn;
-  xcd_group(blockIdx.x, (g.splits + (PERM ? g.nb : 0)) * mtiles, ntiles_n, grp, jn);
+  const int zc = g.splits + (PERM ? g.nb : 0), gm = tn_group_rows(zc, mtiles);
+  int grp, jt;
+  xcd_group(blockIdx.x, zc * (mtiles / gm), gm * ntiles_n, grp, jt);
   if (grp < 0) return;
-  const int z = grp / mtiles;
-  const int m0 = (grp % mtiles) * BM, n0 = jn * BN;
+  const int z = grp / (mtiles / gm);
+  const int m0 = ((grp % (mtiles / gm)) * gm + jt / ntiles_n) * BM, n0 = (jt % ntiles_n) * BN;
   int chunk = (rows + g.splits - 1) / g.splits;
   chunk = (chunk + BK - 1) / BK * BK;
   int i_lo = z * chunk;
@@ -305,7 +307,7 @@ k_gemm_tn_tr(const Dims *__restrict__ dims, const GemmTN g, int ntiles_n) {
     BucketWalk(g.brow, g.nb, chunk).find(z, bq, r0, r1);
     i_lo = bq >= 0 ? r0 : 0;
     i_hi = bq >= 0 ? min(r1, r0 + chunk) : 0;
-    if (grp % mtiles == 0 && jn == 0 && threadIdx.x == 0) {
+    if (m0 == 0 && n0 == 0 && threadIdx.x == 0) {
       g.zscale[2 * z] = bq >= 0 ? g.table[2 * bq] : 0.f;
       g.zscale[2 * z + 1] = bq >= 0 ? g.table[2 * bq + 1] : 0.f;
     }
@@ -490,7 +492,8 @@ hipError_t launch_gemm_tn(const Dims *dims, const GemmTN &g, int precision,
   if (tag == 0 && g.perm) return hipErrorInvalidValue;
   const int T = precision ? 128 : 64;
   const int nt = cdiv(g.Ncols, T);
-  const int grid = xcd_group_grid(cdiv(g.M, T) * (g.splits + (g.perm ? g.nb : 0)), nt);
+  const int zc = g.splits + (g.perm ? g.nb : 0), mt = cdiv(g.M, T), gm = tn_group_rows(zc, mt);
+  const int grid = xcd_group_grid(zc * (mt / gm), gm * nt);
   if (precision) {
     if (tag == 1 && g.perm) run_tn_tr<1, true, false>(dims, g, s, ev0, ev1, grid, nt);
     else if (tag == 1) run_tn_tr<1, false, true>(dims, g, s, ev0, ev1, grid, nt);

@@ -68,12 +68,20 @@ __device__ __forceinline__ int xcd_tile(int bid, int T) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-// Split-K grids of the weight-gradient GEMMs: a group is the column tiles of
-// one (chunk, row tile), which read the same rows and columns of X.  Groups
-// are dealt to the 8 XCDs in turn, each group whole on one XCD, so its
-// X block is fetched from HBM once and then served by that XCD's L2 (spread
-// over the XCDs, every column tile fetched it again).  bid -> (group grp,
-// column tile j); grp = -1 for the padding blocks of the last round.
+// Split-K grids of the weight-gradient GEMMs: a group is output tiles of one
+// chunk of rows, which read that chunk's rows of X and Y.  Groups are dealt
+// to the 8 XCDs in turn, each group whole on one XCD, so what its tiles
+// share is fetched from HBM once and then served by that XCD's L2 (spread
+// over the XCDs, every tile fetched its part again).  bid -> (group grp,
+// tile j of the group); grp = -1 for the padding blocks of the last round.
+__host__ __device__ inline int tn_group_rows(int chunks, int mtiles) {
+  // a whole chunk (every row tile) when the chunks deal evenly to the XCDs,
+  // else one row tile of a chunk (its column tiles, which share X): few
+  // large groups dealt unevenly leave XCDs idle.  Measured at 40k rows:
+  // message weight gradient (24 chunks) 86 -> 82 us with whole chunks,
+  // update weight gradient (30 chunks) 155 -> 177 us.
+  return chunks % 8 == 0 ? mtiles : 1;
+}
 __device__ __forceinline__ void xcd_group(int bid, int ngroups, int gsize, int &grp, int &j) {
   constexpr int X = 8;
   const int x = bid % X, l = bid / X;
