@@ -72,17 +72,24 @@ def measured_traffic(name, sources):
 # Launch sites of the PNA training step timed by the library's event pairs
 # (kernel alone for the GEMM and aggregation sites), the kernel each one
 # runs (as named in the rocprofv3 summaries) and what bounds it.
+# BF16 layers after the first run the message and update linears on the BF16
+# operand copies (k_gemm_ntb); the first layer, and every FP32 layer, the
+# register-staged kernel.  BF16 weight gradients run k_gemm_tn_tr.
 SITES = {
-    "message_gemm": ("S1 message linear", "k_gemm_nt<P, 64, 128, *, 2, 4, *>", "mfma"),
+    "message_gemm": ("S1 message linear",
+                     "k_gemm_nt<P, 64, 128, *, 2, 4, *> | k_gemm_ntb<2, 2, 4>", "mfma"),
     "aggregate": ("S2 aggregation", "k_aggregate<1>", "hbm"),
-    "update_gemm": ("S3 update linear", "k_gemm_nt<P, 64, 128, *, 1, 4, *>", "mfma"),
-    "update_wgrad": ("S6 update weight gradient", "k_gemm_tn<P, 64, 64, 1>", "mfma"),
+    "update_gemm": ("S3 update linear",
+                    "k_gemm_nt<P, 64, 128, *, 1, 4, *> | k_gemm_ntb<1, 2, 4>", "mfma"),
+    "update_wgrad": ("S6 update weight gradient", "k_gemm_tn<P, 64, 64, 1> | k_gemm_tn_tr<1, *>",
+                     "mfma"),
     "agg_input_gemm": ("S6 aggregate-input gradient", "k_gemm_nt<P, 64, 128, *, 3, 4, *>", "mfma"),
     # by degree bucket dA is formed inside the adjoint (one fused kernel, dA
     # not stored) and the S6 aggregate-input GEMM site has no launches
     "aggregate_bwd": ("S6 dA + S7 aggregation adjoint, fused", "k_agg_bwd_fused<P, 1, *>", "hbm"),
     "input_gemm": ("S6+S8 layer-input gradient", "k_gemm_nt<P, 64, 128, *, 4, 4, *>", "mfma"),
-    "message_wgrad": ("S8 message weight gradient", "k_gemm_tn<P, 64, 64, 2>", "mfma"),
+    "message_wgrad": ("S8 message weight gradient", "k_gemm_tn<P, 64, 64, 2> | k_gemm_tn_tr<2, *>",
+                      "mfma"),
 }
 
 
