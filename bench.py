@@ -41,6 +41,8 @@ SITE_TRAFFIC = {
     "update_gemm": UPDATE_GEMM_TRAFFIC,
     "update_wgrad": ("update_wgrad_c1_fp32_traffic.txt",
                      ["csrc/gemm_tn.hip", "csrc/mfma_tile.hpp"]),
+    "aggregate_bwd": ("aggregate_bwd_c1_fp32_traffic.txt",
+                      ["csrc/agg_fused.hip", "csrc/agg_msg.hpp", "csrc/mfma_tile.hpp"]),
     "message_wgrad": ("message_wgrad_c1_fp32_traffic.txt",
                       ["csrc/gemm_tn.hip", "csrc/mfma_tile.hpp"]),
     "agg_input_gemm": ("agg_input_gemm_c1_fp32_traffic.txt",
