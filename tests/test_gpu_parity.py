@@ -474,7 +474,8 @@ C3_SAMPLE = list(range(0, 1024, 16))   # 64 graphs spread over the batch
 
 def test_large_config_sampled_graphs():
     """8 layers, H=256, 1024 graphs, BF16 + recompute, the whole batch on the
-    GPU: graphs are independent, so the oracle checks 64 of them."""
+    GPU: graphs are independent, so the oracle checks 64 of them; the
+    per-operation path gives bitwise the same predictions."""
     w = synth.WORKLOADS["c3_large_bf16"]
     b, params = w.batch(), w.params()
     L, H = w.num_layers, w.hidden
@@ -482,6 +483,16 @@ def test_large_config_sampled_graphs():
     m = make_model(L, H, w.edge_feat, 1, 1, w.delta)
     out = run_train_step(m, b, params)
     assert torch.isfinite(out["grads"]).all()
+    # At this size the training path runs the message and update linears of
+    # layers 1.. on BF16 copies of their inputs (the LDS-DMA kernel); the
+    # per-operation path runs the register-staged kernel on the FP32 inputs.
+    # Same roundings, same products in the same order: bitwise equal.
+    net = _hgnn().PNANet(m, params)
+    with torch.no_grad():
+        p_ops = net(_hgnn().DeviceBatch.from_host(b))
+    torch.cuda.synchronize()
+    assert torch.equal(p_ops, out["pred"])
+    say("  per-operation path (register-staged linears): predictions bitwise equal")
     pred = out["pred"].cpu().numpy()
     sub = synth.select_graphs(b, C3_SAMPLE)
     rec = oracle.forward(params, sub, L, H, w.delta)
