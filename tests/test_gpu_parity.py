@@ -503,6 +503,34 @@ def test_large_config_sampled_graphs():
     m.close()
 
 
+@pytest.mark.parametrize("H,recompute", [(64, 0), (192, 1)])
+def test_bf16_copies_at_other_widths(H, recompute):
+    """Batches of at least 16k nodes run the BF16 linears of layers 1.. on BF16
+    copies of their inputs (LDS-DMA kernel, 128 x 128 tiles).  At H = 64 and
+    192 the column tiles are partial (Ncols 64, 192, 384): the predictions
+    equal the per-operation path's (register-staged kernel) bitwise, and
+    sampled graphs match the FP64 oracle within the BF16 bound."""
+    L = 3
+    b = synth.make_batch(1009, 520, 10, 60, 1)
+    assert b.num_nodes >= 16384
+    params = synth.init_params(synth.ModelShape(L, H, 9, 1), 2009)
+    say(f"H={H} recompute={recompute}: N={b.num_nodes} E={b.num_edges}")
+    m = make_model(L, H, 1, 1, recompute, synth.DELTA_C1)
+    out = run_train_step(m, b, params)
+    assert torch.isfinite(out["grads"]).all()
+    net = _hgnn().PNANet(m, params)
+    with torch.no_grad():
+        p_ops = net(_hgnn().DeviceBatch.from_host(b))
+    torch.cuda.synchronize()
+    assert torch.equal(p_ops, out["pred"])
+    sample = [0, 1, 137, 260, 399, 519]
+    rec = oracle.forward(params, synth.select_graphs(b, sample), L, H, synth.DELTA_C1)
+    r = rel(out["pred"].cpu().numpy()[sample], rec.y)
+    say(f"  bitwise equal to the per-operation path; sampled pred rel {r:.2e}")
+    assert r <= 2e-2
+    m.close()
+
+
 def test_large_config_subbatch_loss_and_gradients():
     """The C3 model (8 layers, H=256, BF16 linears, recompute) on a 64-graph
     sub-batch of the C3 batch: predictions and loss within 2e-2 of the FP64
