@@ -106,22 +106,23 @@ struct GemmNT {
   int ldcb;
 };
 
-// BF16-operand NT form (gemm_ntb.hip): C = act(sum_seg A_seg B_seg^T + bias)
-// with every A segment already in BF16 (written by its producer) and every
-// segment length a multiple of 64, so that whole K tiles are copied from
-// HBM to LDS without passing through registers.  Same products, in the same
-// order, as GemmNT's BF16 hi + lo form on the same values: the outputs are
-// bitwise equal.  No split-K, row scales, interleave or addend.
+// LDS-DMA NT form (gemm_ntb.hip): C = act(sum_seg A_seg B_seg^T + bias) with
+// every A segment in the product's precision in HBM (FP32 as it lies, BF16 as
+// a copy written by its producer) and every segment length a multiple of the
+// K tile (32 FP32 or 64 BF16), so that whole K tiles are copied from HBM to
+// LDS without passing through registers.  Same products, in the same order,
+// as GemmNT's unsplit form on the same values: the outputs are bitwise equal.
+// No split-K, row scales, interleave or addend.
 struct SegB {
-  const __bf16 *ptr; // [rows, ld] row-major, k-contiguous, 16-byte aligned rows
-  int ld;            // leading dimension (elements, multiple of 8)
-  int k;             // segment length (multiple of 64)
-  int boff;          // column offset of this segment inside the B rows (multiple of 8)
+  const void *ptr; // [rows, ld] row-major, k-contiguous, 16-byte aligned rows
+  int ld;          // leading dimension (elements; rows 16-byte multiples)
+  int k;           // segment length (multiple of the K tile)
+  int boff;        // column offset of this segment inside the B rows
 };
 struct GemmNTB {
   SegB seg[kMaxSeg];
   int nseg;
-  const __bf16 *B, *B_lo; // [Ncols, ldb] hi and lo halves of the weights
+  const void *B, *B_lo;   // [Ncols, ldb] weights (FP32, or BF16 hi and lo halves)
   int ldb;
   long long bstride;      // per-bucket weight stride (bucketed rows)
   const int *perm, *brow; // degree-bucketed rows as in GemmNT, or nullptr
@@ -132,13 +133,13 @@ struct GemmNTB {
   const float *mask; // as in GemmNT
   float *C;
   int ldc;
-  __bf16 *Cb; // optional BF16 copy of C (the same values rounded), or nullptr
+  __bf16 *Cb; // BF16 only: optional BF16 copy of C (the same values rounded), or nullptr
   int ldcb;
   int M_fixed;
 };
-bool gemm_ntb_ok(const GemmNTB &g);
-hipError_t launch_gemm_ntb(const Dims *dims, int capM, const GemmNTB &g, hipStream_t s, int tag,
-                           hipEvent_t ev0, hipEvent_t ev1);
+bool gemm_ntb_ok(const GemmNTB &g, int precision);
+hipError_t launch_gemm_ntb(const Dims *dims, int capM, const GemmNTB &g, int precision,
+                           hipStream_t s, int tag, hipEvent_t ev0, hipEvent_t ev1);
 
 // Weight-gradient form, reduction over rows i (nodes):
 // P[z][m, n] = sum_{i in chunk z} X[i, m] * Yv[i, n]

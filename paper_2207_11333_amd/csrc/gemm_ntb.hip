@@ -1,35 +1,41 @@
-// NT-form MFMA GEMM on BF16 operands (steps S1, S3 and the layer-input
-// gradient of S6 + S8 in BF16 mode, when their inputs have BF16 copies).
+// NT-form MFMA GEMM with its operand tiles copied from HBM straight into LDS
+// (steps S1, S3 and the layer-input gradient of S6 + S8).
 //
-// Every A segment is already BF16 in HBM (its producer wrote the RNE-rounded
-// copy), so a K tile needs no conversion: it is copied from HBM to LDS by
-// the LDS-DMA loads of gfx950 (global_load_lds_dwordx4: 16 bytes per lane,
-// written to LDS in lane order), never passing through registers, which are
-// left to the products: 128 x 128 tiles, eight waves in a 2 x 4 grid, each
-// wave 64 x 32 of output (4 x 2 MFMA blocks).  Measured: a wave's LDS-DMA
-// loads are served about one at a time, so the copy rate grows with the
-// waves that issue them (four waves per CU reach about 8 TB/s from L2,
-// sixteen about 25); eight waves of 64 x 32 beat four of 64 x 64 (update
-// linear at 40k rows: 80 against 96 us, the register-staged kernel 105).
+// Every A segment is in the product's own precision in HBM: FP32 as it lies,
+// or for BF16 a copy its producer wrote (RNE-rounded, the rounding the
+// register-staged kernel applies while staging).  A K tile then needs no
+// conversion and goes from HBM to LDS by gfx950's LDS-DMA loads
+// (global_load_lds_dwordx4: 16 bytes per lane, written to LDS in lane order),
+// never through registers, which are left to the products.
 //
-// Pipeline: three LDS stages of one 64-deep K tile each (A, weight hi, weight
-// lo: 48 KB); tiles t + 1 and t + 2 are in flight while tile t computes.
-// Each wave counts its own DMA loads (vmcnt) and one barrier per tile makes
-// every wave's loads visible and frees the stage read by the previous tile
-// (a plain s_barrier: the fence of __syncthreads would wait for every load
-// in flight).  The barrier sits before the tile's last quarter of MFMAs,
-// which covers the next tile's fragment reads.
+// LDS rows are 128 bytes: one K tile holds 32 FP32 or 64 BF16 of k.  Chunk c
+// (16 bytes) of row r is stored at 16 (c ^ (r & 7)), so the eight rows read by
+// eight adjacent lanes of a fragment load fall in distinct banks (the LDS
+// bank-conflict counter reads 0).  A DMA instruction fills 8 rows: lane L
+// writes row L / 8, position L % 8, so it loads logical chunk (L % 8) ^ (L / 8)
+// of that row.  The loads of a tile (A rows, weight rows, BF16 weight low
+// halves) are dealt to the waves in turn, the same number to each.
 //
-// LDS rows are 128 bytes (64 BF16 of k): chunk c (8 k) of row r is stored at
-// 16 (c ^ (r & 7)), so the eight rows read by eight adjacent lanes of a
-// fragment load fall in distinct banks.  A DMA instruction fills 8 rows:
-// lane L writes row L / 8, position L % 8, so it loads logical chunk
-// (L % 8) ^ (L / 8) of that row.
+// Pipeline: three LDS stages; tiles t + 1 and t + 2 are in flight while tile t
+// computes.  Each wave counts its own DMA loads (vmcnt) and one plain
+// s_barrier per tile (the fence of __syncthreads would wait for every load in
+// flight) makes every wave's loads visible and frees the stage read by the
+// previous tile.  The barrier sits before the tile's last products, which
+// cover the next tile's fragment reads.
 //
-// Products and their order are those of the register-staged kernel's BF16
-// hi + lo form on the same operand values (per 64-deep K tile: weight hi over
-// k 0-31, hi over 32-63, lo over 0-31, lo over 32-63), so the outputs are
-// bitwise equal to it.
+// Measured: a wave's LDS-DMA loads are served about one at a time, so the copy
+// rate grows with the waves that issue them (a streaming test: four waves per
+// CU about 8 TB/s from L2, sixteen about 25, whatever the number of loads each
+// keeps in flight); every configuration runs eight waves.  Two tile shapes:
+// 128 x 128 (waves of 64 x 32) for grids that fill the GPU, 64 x 64 (waves of
+// 32 x 16) for smaller ones, whose time is set by how many tiles run at once
+// (update linear, BF16, alone: 80 against 105 us for the register-staged
+// kernel at 40k rows; 9.7 against 14.3 us at 4.5k rows with 64 x 64 tiles).
+//
+// Products and their order per output are those of the register-staged
+// kernel when it runs unsplit (FP32: per 16 k, four k-slots of
+// v_mfma_f32_16x16x4_f32; BF16: per 64 k, weight hi over k 0-31 and 32-63,
+// then lo over the same), so outputs are bitwise equal to its unsplit form.
 #include "mfma_tile.hpp"
 
 namespace hgnn {
@@ -38,12 +44,9 @@ namespace {
 
 typedef __attribute__((address_space(3))) void lds_t;
 
-constexpr int kQBM = 128, kQBN = 128, kQBK = 64;
-constexpr int kQRow = kQBK * 2;              // bytes per LDS row
-constexpr int kQA = kQBM * kQRow;            // A tile bytes
-constexpr int kQB = kQBN * kQRow;            // one weight half's tile bytes
-constexpr int kQStage = kQA + 2 * kQB;       // 48 KB
+constexpr int kQRow = 128; // bytes per LDS row (one K tile)
 constexpr int kQStages = 3;
+constexpr int kQWGM = 2, kQWGN = 4; // waves of a workgroup
 
 // s_waitcnt immediate for vmcnt(n) with lgkmcnt(0) (expcnt left alone)
 template <int N> struct WaitVm {
@@ -51,34 +54,39 @@ template <int N> struct WaitVm {
   static constexpr int value = 0x0070 | (N & 15) | ((N >> 4) << 14);
 };
 
-// WGM x WGN waves, each (128 / WGM) x (128 / WGN) of output.
-template <int TAG, int WGM, int WGN>
+// PREC 0: FP32 operands and weights; 1: BF16 operands, weights as hi + lo.
+// BM x BN tile, WGM x WGN waves.
+template <int PREC, int BM, int BN, int WGM, int WGN, int TAG>
 __global__ void __launch_bounds__(64 * WGM * WGN, 1)
 k_gemm_ntb(const Dims *__restrict__ dims, const GemmNTB g, int ntiles_n) {
-  constexpr int NW = WGM * WGN, WM = kQBM / WGM, WN = kQBN / WGN, TM = WM / 16, TN = WN / 16;
-  constexpr int RPW = kQBM / NW;   // rows of each operand tile one wave loads
-  constexpr int JD = RPW / 8;      // DMA loads per wave per operand tile
-  constexpr int DMA = 3 * JD;      // per wave per K tile
-  static_assert(kQBM == kQBN && RPW % 8 == 0 && TM >= 1 && TN >= 1, "tile shape");
-  __shared__ __attribute__((aligned(1024))) char smem[kQStages * kQStage];
+  using T = typename Prec<PREC>::T;
+  constexpr bool SPLIT = PREC == 1;
+  constexpr int EPC = 16 / (int)sizeof(T);   // elements per 16-byte chunk
+  constexpr int BKE = kQRow / (int)sizeof(T); // k per K tile
+  constexpr int NW = WGM * WGN, WM = BM / WGM, WN = BN / WGN, TM = WM / 16, TN = WN / 16;
+  constexpr int IA = BM / 8, IB = BN / 8, IT = IA + IB * (SPLIT ? 2 : 1);
+  static_assert(IT % NW == 0 && TM >= 1 && TN >= 1, "tile shape");
+  constexpr int DMA = IT / NW; // DMA loads per wave per K tile
+  constexpr int SA = BM * kQRow, SB = BN * kQRow, STAGE = SA + SB * (SPLIT ? 2 : 1);
+  __shared__ __attribute__((aligned(1024))) char smem[kQStages * STAGE];
 
   const int M = g.M_fixed >= 0 ? g.M_fixed : dims->N;
-  int mtiles = (M + kQBM - 1) / kQBM;
+  int mtiles = (M + BM - 1) / BM;
   int mt, n0, m0, m_hi = M, bq = 0;
   if (g.perm) {
-    const BucketWalk bw(g.brow, g.nb, kQBM);
+    const BucketWalk bw(g.brow, g.nb, BM);
     mtiles = bw.total();
     if ((int)blockIdx.x >= mtiles * ntiles_n) return;
     const int tile = xcd_tile(blockIdx.x, mtiles * ntiles_n);
     mt = tile / ntiles_n;
-    n0 = (tile % ntiles_n) * kQBN;
+    n0 = (tile % ntiles_n) * BN;
     bw.find(mt, bq, m0, m_hi);
   } else {
     if ((int)blockIdx.x >= mtiles * ntiles_n) return;
     const int tile = xcd_tile(blockIdx.x, mtiles * ntiles_n);
     mt = tile / ntiles_n;
-    n0 = (tile % ntiles_n) * kQBN;
-    m0 = mt * kQBM;
+    n0 = (tile % ntiles_n) * BN;
+    m0 = mt * BM;
   }
   const int tid = threadIdx.x, w = tid >> 6, L = tid & 63;
   const int wm0 = (w / WGN) * WM, wn0 = (w % WGN) * WN;
@@ -87,73 +95,83 @@ k_gemm_ntb(const Dims *__restrict__ dims, const GemmNTB g, int ntiles_n) {
   int cum[kMaxSeg + 1];
   cum[0] = 0;
 #pragma unroll
-  for (int q = 0; q < kMaxSeg; ++q) cum[q + 1] = cum[q] + (q < g.nseg ? g.seg[q].k / kQBK : 0);
+  for (int q = 0; q < kMaxSeg; ++q) cum[q + 1] = cum[q] + (q < g.nseg ? g.seg[q].k / BKE : 0);
   const int KT = cum[kMaxSeg];
 
-  // DMA roles: wave w fills rows RPW w .. RPW (w + 1) - 1 of each tile, 8 per load;
-  // rows and columns past the matrix read clamped (valid) rows, whose
-  // products land only in outputs that are never stored
+  // DMA load u of this wave is load w + NW u of the tile: A rows, then weight
+  // rows, then (BF16) weight low halves, 8 rows each.  Rows and columns past
+  // the matrix read clamped (valid) rows, whose products land only in
+  // outputs that are never stored.
   const int dr = L >> 3;
-  const int dk = 8 * ((L & 7) ^ dr); // first k of the chunk this lane loads
-  int anode[JD], bcol[JD];
+  const int dk = EPC * ((L & 7) ^ dr); // first k of the chunk this lane loads
+  int rowi[DMA], kind[DMA], ldsoff[DMA];
 #pragma unroll
-  for (int j = 0; j < JD; ++j) {
-    const int m = min(m0 + RPW * w + 8 * j + dr, m_hi - 1);
-    anode[j] = g.perm ? g.perm[m] : m;
-    bcol[j] = min(n0 + RPW * w + 8 * j + dr, g.Ncols - 1);
+  for (int u = 0; u < DMA; ++u) {
+    const int gi = w + NW * u;
+    if (gi < IA) {
+      kind[u] = 0;
+      const int m = min(m0 + 8 * gi + dr, m_hi - 1);
+      rowi[u] = g.perm ? g.perm[m] : m;
+      ldsoff[u] = 8 * gi * kQRow;
+    } else {
+      const int bi = gi - IA, half = bi / IB, bb = bi - half * IB;
+      kind[u] = 1 + half;
+      rowi[u] = min(n0 + 8 * bb + dr, g.Ncols - 1);
+      ldsoff[u] = SA + half * SB + 8 * bb * kQRow;
+    }
   }
-  const __bf16 *Bq = g.B + (size_t)bq * g.bstride;
-  const __bf16 *Lq = g.B_lo + (size_t)bq * g.bstride;
-  char *const wa = smem + RPW * w * kQRow; // this wave's rows of stage 0
+  const T *Bq = static_cast<const T *>(g.B) + (size_t)bq * g.bstride;
+  const T *Lq = SPLIT ? static_cast<const T *>(g.B_lo) + (size_t)bq * g.bstride : Bq;
 
   // the loads of K tile t into the stage at byte offset st
   auto issue = [&](int t, int st) {
     int q = 0;
 #pragma unroll
     for (int u = 1; u < kMaxSeg; ++u) q += (t >= cum[u]) ? 1 : 0;
-    const int k0 = (t - cum[q]) * kQBK;
-    const __bf16 *ap = g.seg[q].ptr + k0 + dk;
+    const int k0 = (t - cum[q]) * BKE;
+    const T *ap = static_cast<const T *>(g.seg[q].ptr) + k0 + dk;
     const int lda = g.seg[q].ld;
     const size_t bo = (size_t)g.seg[q].boff + k0 + dk;
 #pragma unroll
-    for (int j = 0; j < JD; ++j)
-      __builtin_amdgcn_global_load_lds(ap + (size_t)anode[j] * lda,
-                                       (lds_t *)(wa + st + 8 * j * kQRow), 16, 0, 0);
-#pragma unroll
-    for (int j = 0; j < JD; ++j)
-      __builtin_amdgcn_global_load_lds(Bq + (size_t)bcol[j] * g.ldb + bo,
-                                       (lds_t *)(wa + st + kQA + 8 * j * kQRow), 16, 0, 0);
-#pragma unroll
-    for (int j = 0; j < JD; ++j)
-      __builtin_amdgcn_global_load_lds(Lq + (size_t)bcol[j] * g.ldb + bo,
-                                       (lds_t *)(wa + st + kQA + kQB + 8 * j * kQRow), 16, 0, 0);
+    for (int u = 0; u < DMA; ++u) {
+      const T *src = kind[u] == 0 ? ap + (size_t)rowi[u] * lda
+                                  : (kind[u] == 1 ? Bq : Lq) + (size_t)rowi[u] * g.ldb + bo;
+      // the builtin takes a non-const pointer: without the cast the host pass
+      // drops the kernel templates (their launch handles stay undefined)
+      __builtin_amdgcn_global_load_lds((void *)src, (lds_t *)(smem + st + ldsoff[u]), 16, 0, 0);
+    }
   };
 
   // fragment reads: lane (r = L % 16, group L / 16) takes row r of each
-  // 16-row block, logical chunk 4 c + L / 16 (k 32 c + 8 (L / 16) ..)
+  // 16-row block and logical chunk 4 c + L / 16 of the tile's two halves c
+  // (BF16: 8 k per lane of a 32-deep MFMA; FP32: 4 k, the k-slots of four
+  // 4-deep MFMAs)
+  using V = typename Frag<PREC>::V;
   const int fr = L & 15;
   const int p0 = (L >> 4) ^ (fr & 7);
   const int offA0 = (wm0 + fr) * kQRow + 16 * p0, offA1 = (wm0 + fr) * kQRow + 16 * (p0 ^ 4);
-  const int offB0 = kQA + (wn0 + fr) * kQRow + 16 * p0;
-  const int offB1 = kQA + (wn0 + fr) * kQRow + 16 * (p0 ^ 4);
-  bf16x8 fa[2][2][TM], fb[2][2][TN], fl[2][2][TN]; // [register set][k chunk][block]
+  const int offB0 = SA + (wn0 + fr) * kQRow + 16 * p0;
+  const int offB1 = SA + (wn0 + fr) * kQRow + 16 * (p0 ^ 4);
+  V fa[2][2][TM], fb[2][2][TN], fl[2][2][SPLIT ? TN : 1]; // [set][half][block]
   auto read = [&](auto set, int st) {
     constexpr int S = decltype(set)::value;
     const char *base = smem + st;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
-      fa[S][0][i] = *reinterpret_cast<const bf16x8 *>(base + offA0 + 16 * i * kQRow);
-      fa[S][1][i] = *reinterpret_cast<const bf16x8 *>(base + offA1 + 16 * i * kQRow);
+      fa[S][0][i] = *reinterpret_cast<const V *>(base + offA0 + 16 * i * kQRow);
+      fa[S][1][i] = *reinterpret_cast<const V *>(base + offA1 + 16 * i * kQRow);
     }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      fb[S][0][j] = *reinterpret_cast<const bf16x8 *>(base + offB0 + 16 * j * kQRow);
-      fb[S][1][j] = *reinterpret_cast<const bf16x8 *>(base + offB1 + 16 * j * kQRow);
+      fb[S][0][j] = *reinterpret_cast<const V *>(base + offB0 + 16 * j * kQRow);
+      fb[S][1][j] = *reinterpret_cast<const V *>(base + offB1 + 16 * j * kQRow);
     }
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      fl[S][0][j] = *reinterpret_cast<const bf16x8 *>(base + kQB + offB0 + 16 * j * kQRow);
-      fl[S][1][j] = *reinterpret_cast<const bf16x8 *>(base + kQB + offB1 + 16 * j * kQRow);
+      for (int j = 0; j < TN; ++j) {
+        fl[S][0][j] = *reinterpret_cast<const V *>(base + SB + offB0 + 16 * j * kQRow);
+        fl[S][1][j] = *reinterpret_cast<const V *>(base + SB + offB1 + 16 * j * kQRow);
+      }
     }
   };
 
@@ -162,23 +180,19 @@ k_gemm_ntb(const Dims *__restrict__ dims, const GemmNTB g, int ntiles_n) {
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  auto mm = [&](const bf16x8 (&a)[TM], const bf16x8 (&b)[TN]) {
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-  };
-  auto next = [](int st) { return st == (kQStages - 1) * kQStage ? 0 : st + kQStage; };
+  auto mm = [&](const V (&a)[TM], const V (&b)[TN]) { mma_frags<PREC, TM, TN>(a, b, acc); };
+  auto next = [](int st) { return st == (kQStages - 1) * STAGE ? 0 : st + STAGE; };
 
-  // tile t (register set S, LDS stage st): three quarters of its products;
-  // then, if a tile follows, wait for it, refill this stage with tile t + 3
-  // and read tile t + 1's fragments; then the last quarter
+  // tile t (register set S, LDS stage st): its first products; then, if a
+  // tile follows, wait for it, refill this stage with tile t + 3 and read
+  // tile t + 1's fragments; then the last products
   auto step = [&](auto set, int t, int st) {
     constexpr int S = decltype(set)::value;
     mm(fa[S][0], fb[S][0]);
-    mm(fa[S][1], fb[S][1]);
-    mm(fa[S][0], fl[S][0]);
+    if constexpr (SPLIT) {
+      mm(fa[S][1], fb[S][1]);
+      mm(fa[S][0], fl[S][0]);
+    }
     __builtin_amdgcn_sched_barrier(0);
     if (t + 1 < KT) {
       if (t + 2 < KT) __builtin_amdgcn_s_waitcnt(WaitVm<DMA>::value);
@@ -189,12 +203,13 @@ k_gemm_ntb(const Dims *__restrict__ dims, const GemmNTB g, int ntiles_n) {
       read(IC<1 - S>{}, next(st));
     }
     __builtin_amdgcn_sched_barrier(0);
-    mm(fa[S][1], fl[S][1]);
+    if constexpr (SPLIT) mm(fa[S][1], fl[S][1]);
+    else mm(fa[S][1], fb[S][1]);
   };
 
   issue(0, 0);
-  if (KT > 1) issue(1, kQStage);
-  if (KT > 2) issue(2, 2 * kQStage);
+  if (KT > 1) issue(1, STAGE);
+  if (KT > 2) issue(2, 2 * STAGE);
   if (KT > 2) __builtin_amdgcn_s_waitcnt(WaitVm<2 * DMA>::value);
   else if (KT > 1) __builtin_amdgcn_s_waitcnt(WaitVm<DMA>::value);
   else __builtin_amdgcn_s_waitcnt(WaitVm<0>::value);
@@ -211,7 +226,8 @@ k_gemm_ntb(const Dims *__restrict__ dims, const GemmNTB g, int ntiles_n) {
   }
 
   // Epilogue (as the register-staged kernel's): lane (cr = 4 (L / 16),
-  // cc = L % 16) holds rows wm0 + 16 i + cr + v, columns wn0 + 16 j + cc.
+  // cc = L % 16) holds rows wm0 + 16 i + cr + v, columns wn0 + 16 j + cc; the
+  // rows' nodes are fetched once, from clamped indices, without a branch.
   const int cr = 4 * (L >> 4), cc = L & 15;
   int node[TM][4];
   bool rok[TM][4];
@@ -259,40 +275,54 @@ k_gemm_ntb(const Dims *__restrict__ dims, const GemmNTB g, int ntiles_n) {
   }
 }
 
-constexpr int kQWGM = 2, kQWGN = 4; // waves of a workgroup
-
 inline bool al16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// the large tile when its grid fills every CU at least once
+bool large_tiles(int capM, const GemmNTB &g) {
+  return (long long)(cdiv(capM, 128) + (g.perm ? g.nb : 0)) * cdiv(g.Ncols, 128) >= 256;
+}
 
 } // namespace
 
-bool gemm_ntb_ok(const GemmNTB &g) {
-  if (g.nseg < 1 || g.nseg > kMaxSeg || !g.B || !g.B_lo || !g.C || g.Ncols <= 0) return false;
-  if (g.ldb % 8 || !al16(g.B) || !al16(g.B_lo) || (g.perm && (!g.brow || g.nb < 1))) return false;
-  if (g.perm && g.bstride % 8) return false;
+bool gemm_ntb_ok(const GemmNTB &g, int precision) {
+  const int bke = precision ? 64 : 32, esz = precision ? 2 : 4;
+  if (g.nseg < 1 || g.nseg > kMaxSeg || !g.B || !g.C || g.Ncols <= 0) return false;
+  if ((precision == 1) != (g.B_lo != nullptr) || (precision == 0 && g.Cb)) return false;
+  if ((g.ldb * esz) % 16 || !al16(g.B) || (g.B_lo && !al16(g.B_lo))) return false;
+  if (g.perm && (!g.brow || g.nb < 1 || (g.bstride * esz) % 16)) return false;
   for (int q = 0; q < g.nseg; ++q) {
     const SegB &s = g.seg[q];
-    if (!s.ptr || !al16(s.ptr) || s.k <= 0 || s.k % kQBK || s.ld % 8 || s.boff % 8) return false;
+    if (!s.ptr || !al16(s.ptr) || s.k <= 0 || s.k % bke || (s.ld * esz) % 16 ||
+        (s.boff * esz) % 16)
+      return false;
   }
   return true;
 }
 
-hipError_t launch_gemm_ntb(const Dims *dims, int capM, const GemmNTB &g, hipStream_t s, int tag,
-                           hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_gemm_ntb(const Dims *dims, int capM, const GemmNTB &g, int precision,
+                           hipStream_t s, int tag, hipEvent_t ev0, hipEvent_t ev1) {
   if (capM <= 0) return hipSuccess;
-  if (!gemm_ntb_ok(g)) return hipErrorInvalidValue;
-  const int nt = cdiv(g.Ncols, kQBN);
+  if (!gemm_ntb_ok(g, precision)) return hipErrorInvalidValue;
+  const int B = large_tiles(capM, g) ? 128 : 64;
+  const int nt = cdiv(g.Ncols, B);
   // bucketed rows: each bucket's last tile may be partial
-  const dim3 grid((cdiv(capM, kQBM) + (g.perm ? g.nb : 0)) * nt);
-  switch (tag) {
-#define HGNN_NTB(T)                                                                              \
-  hipExtLaunchKernelGGL(k_gemm_ntb<T, kQWGM, kQWGN>, grid, dim3(64 * kQWGM * kQWGN), 0, s, ev0,   \
-                        ev1, 0, dims, g, nt);                                                    \
-  break
-  case 1: HGNN_NTB(1);
-  case 2: HGNN_NTB(2);
-  case 4: HGNN_NTB(4);
-  default: HGNN_NTB(0);
+  const dim3 grid((cdiv(capM, B) + (g.perm ? g.nb : 0)) * nt), block(64 * kQWGM * kQWGN);
+  const int key = precision * 1000 + B * 10 + tag;
+  switch (key) {
+#define HGNN_NTB(P, BB, T)                                                                     \
+  case P * 1000 + BB * 10 + T:                                                                 \
+    hipExtLaunchKernelGGL(k_gemm_ntb<P, BB, BB, kQWGM, kQWGN, T>, grid, block, 0, s, ev0, ev1,  \
+                          0, dims, g, nt);                                                     \
+    break;
+#define HGNN_NTB_TAGS(P, BB) HGNN_NTB(P, BB, 0) HGNN_NTB(P, BB, 1) HGNN_NTB(P, BB, 2) HGNN_NTB(P, BB, 4)
+    HGNN_NTB_TAGS(0, 64)
+    HGNN_NTB_TAGS(0, 128)
+    HGNN_NTB_TAGS(1, 64)
+    HGNN_NTB_TAGS(1, 128)
+#undef HGNN_NTB_TAGS
 #undef HGNN_NTB
+  default:
+    return hipErrorInvalidValue; // a tag without an instance
   }
   return hipGetLastError();
 }

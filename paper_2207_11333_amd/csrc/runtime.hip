@@ -121,12 +121,6 @@ void free_work(Exec &ex) {
 // the producers (update linear, aggregation), so that whole K tiles go from
 // HBM to LDS untouched (gemm_ntb.hip): BF16 PNA models with degree buckets
 // and a hidden width that whole 64-deep K tiles cover.
-// The copies are written and read for batches of at least kCopyRows nodes
-// only (and allocated for workspaces that large): below that the LDS-DMA
-// kernel's grid covers few CUs and the register-staged kernel is as fast or
-// faster (measured alone at 4.5k rows: update linear 15.3 against 14.2 us; at
-// 40k rows 80 against 105 us; the whole C2 step the same either way).
-constexpr int kCopyRows = 16384;
 static bool bf16_copies(const hgnn_ctx *c) {
   return c->kind == HGNN_GC_PNA && c->prec == 1 && c->nb > 0 && c->H % 64 == 0;
 }
@@ -154,7 +148,7 @@ static bool for_each_buffer(const hgnn_ctx *c, Work &w, int capB, int capN, int 
   if (w.csr.nb) ok = ok && f(w.csr.perm, (size_t)capN) && f(w.csr.brow, (size_t)kMaxBuckets + 1);
   if (w.hbuf.size() != (size_t)nh) w.hbuf.assign(nh, nullptr);
   for (int l = 0; l < nh && ok; ++l) ok = f(w.hbuf[l], (size_t)capN * H);
-  const bool shadows = !inference && bf16_copies(c) && capN >= kCopyRows;
+  const bool shadows = !inference && bf16_copies(c);
   if (w.hbuf_b.size() != (size_t)(shadows ? nh : 0)) w.hbuf_b.assign(shadows ? nh : 0, nullptr);
   for (int l = 0; l < (int)w.hbuf_b.size() && ok; ++l) ok = f(w.hbuf_b[l], (size_t)capN * H);
   if (shadows) ok = ok && f(w.Ab, (size_t)capN * 4 * H);
@@ -388,7 +382,7 @@ static int aggregate_into(hgnn_ctx *c, Exec &ex, int l, const float *wl, const f
 
 // The BF16 copy of layer l's input when the context holds one: the input is
 // the previous layer's output buffer, written together with its copy.
-static bool copies_on(const Exec &ex) { return !ex.w.hbuf_b.empty() && ex.N >= kCopyRows; }
+static bool copies_on(const Exec &ex) { return !ex.w.hbuf_b.empty(); }
 static const __bf16 *input_copy(const Exec &ex, int l, const float *h_in) {
   const Work &w = ex.w;
   return (copies_on(ex) && l > 0 && (size_t)l <= w.hbuf_b.size() && h_in == w.hbuf[l - 1])
@@ -405,21 +399,23 @@ static int message_and_aggregate(hgnn_ctx *c, Exec &ex, int l, const float *wl, 
   const LayerDesc &d = c->ld[l];
   const int H = c->H;
   Work &w = ex.w;
-  if (hb) {
-    GemmNTB q{};
-    q.nseg = 1;
-    q.seg[0] = SegB{hb, H, d.Fp, 0};
-    q.B = static_cast<const __bf16 *>(c->Wds[l]);
-    q.B_lo = static_cast<const __bf16 *>(c->Wds_lo[l]);
-    q.ldb = d.Fp;
-    q.Ncols = 2 * H;
-    q.C = PQ;
-    q.ldc = 2 * H;
-    q.M_fixed = -1;
+  // the LDS-DMA form where it applies: FP32 on the input as it lies, BF16 on
+  // its copy
+  GemmNTB q{};
+  q.nseg = 1;
+  q.seg[0] = c->prec ? SegB{hb, H, d.Fp, 0} : SegB{hin, ldh, d.Fp, 0};
+  q.B = c->Wds[l];
+  q.B_lo = c->prec ? c->Wds_lo[l] : nullptr;
+  q.ldb = d.Fp;
+  q.Ncols = 2 * H;
+  q.C = PQ;
+  q.ldc = 2 * H;
+  q.M_fixed = -1;
+  if (q.seg[0].ptr && gemm_ntb_ok(q, c->prec)) {
     hipError_t e;
     {
       TimedLaunch tl(c, ex, SITE_MESSAGE_GEMM, s, /*manual=*/true);
-      e = launch_gemm_ntb(ex.dims, ex.N, q, s, /*tag=*/2, tl.start(), tl.stop());
+      e = launch_gemm_ntb(ex.dims, ex.N, q, c->prec, s, /*tag=*/2, tl.start(), tl.stop());
     }
     if (e != hipSuccess) return hip_fail(c, e, "message GEMM");
     return aggregate_into(c, ex, l, wl, PQ, A, args, Ab, s);
@@ -479,14 +475,20 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
   if (rc) return rc;
   w.stored_layer = l;
   float *A = w.A[slot];
-  if (hb && c->nb) {
-    // u = [h || A] [W_h | W_eff(d)]^T per bucket, on the BF16 copies
-    GemmNTB q{};
+  // u = [h || A] [W_h | W_eff(d)]^T per bucket in the LDS-DMA form where it
+  // applies: FP32 on the inputs as they lie, BF16 on their copies
+  GemmNTB q{};
+  if (c->nb) {
     q.nseg = 2;
-    q.seg[0] = SegB{hb, H, d.Fp, 0};
-    q.seg[1] = SegB{w.Ab, 4 * H, 4 * H, d.Fp};
-    q.B = static_cast<const __bf16 *>(c->Wpp[l]);
-    q.B_lo = static_cast<const __bf16 *>(c->Wpp_lo[l]);
+    if (c->prec) {
+      q.seg[0] = SegB{hb, H, d.Fp, 0};
+      q.seg[1] = SegB{hb ? w.Ab : nullptr, 4 * H, 4 * H, d.Fp};
+    } else {
+      q.seg[0] = SegB{hin, ldh, d.Fp, 0};
+      q.seg[1] = SegB{A, 4 * H, 4 * H, d.Fp};
+    }
+    q.B = c->Wpp[l];
+    q.B_lo = c->prec ? c->Wpp_lo[l] : nullptr;
     q.ldb = d.Fp + 4 * H;
     q.bstride = (long long)H * q.ldb;
     q.perm = w.csr.perm;
@@ -500,10 +502,12 @@ int layer_forward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h_
     q.Cb = hb_out;
     q.ldcb = H;
     q.M_fixed = -1;
+  }
+  if (c->nb && q.seg[0].ptr && q.seg[1].ptr && gemm_ntb_ok(q, c->prec)) {
     hipError_t e;
     {
       TimedLaunch tl(c, ex, SITE_UPDATE_GEMM, s, /*manual=*/true);
-      e = launch_gemm_ntb(ex.dims, ex.N, q, s, /*tag=*/1, tl.start(), tl.stop());
+      e = launch_gemm_ntb(ex.dims, ex.N, q, c->prec, s, /*tag=*/1, tl.start(), tl.stop());
     }
     if (e != hipSuccess) return hip_fail(c, e, "update GEMM");
     return HGNN_OK;
@@ -814,20 +818,37 @@ int layer_backward(hgnn_ctx *c, Exec &ex, int l, const float *wl, const float *h
       e = hipStreamWaitEvent(s, c->pjoin_ev[k], 0);
       if (e != hipSuccess) return hip_fail(c, e, "join");
     }
-    GemmNT g{};
-    g.nseg = 3;
-    g.seg[0] = SegA{du, nullptr, H, H, 0};
-    g.seg[1] = SegA{Dl, nullptr, ldD, H, H};
-    g.seg[2] = SegA{Dl + H, nullptr, ldD, H, 2 * H};
-    g.B = c->WhdsT[l];
-    g.B_lo = c->prec ? c->WhdsT_lo[l] : nullptr;
-    g.ldb = 3 * H;
-    g.Ncols = d.F;
-    g.C = dh_in;
-    g.ldc = d.F;
-    g.M_fixed = -1;
-    g.mask = (mask_dh_in && l > 0) ? h_in : nullptr;
-    {
+    const float *mask = (mask_dh_in && l > 0) ? h_in : nullptr;
+    // the LDS-DMA form where it applies (FP32: on the inputs as they lie)
+    GemmNTB q{};
+    q.nseg = 3;
+    q.seg[0] = SegB{du, H, H, 0};
+    q.seg[1] = SegB{Dl, ldD, H, H};
+    q.seg[2] = SegB{Dl + H, ldD, H, 2 * H};
+    q.B = c->WhdsT[l];
+    q.ldb = 3 * H;
+    q.Ncols = d.F;
+    q.C = dh_in;
+    q.ldc = d.F;
+    q.M_fixed = -1;
+    q.mask = mask;
+    if (c->prec == 0 && gemm_ntb_ok(q, 0)) {
+      TimedLaunch tl(c, ex, SITE_INPUT_GEMM, s, /*manual=*/true);
+      e = launch_gemm_ntb(ex.dims, ex.N, q, 0, s, /*tag=*/4, tl.start(), tl.stop());
+    } else {
+      GemmNT g{};
+      g.nseg = 3;
+      g.seg[0] = SegA{du, nullptr, H, H, 0};
+      g.seg[1] = SegA{Dl, nullptr, ldD, H, H};
+      g.seg[2] = SegA{Dl + H, nullptr, ldD, H, 2 * H};
+      g.B = c->WhdsT[l];
+      g.B_lo = c->prec ? c->WhdsT_lo[l] : nullptr;
+      g.ldb = 3 * H;
+      g.Ncols = d.F;
+      g.C = dh_in;
+      g.ldc = d.F;
+      g.M_fixed = -1;
+      g.mask = mask;
       TimedLaunch tl(c, ex, SITE_INPUT_GEMM, s, /*manual=*/true);
       e = launch_gemm_nt(ex.dims, ex.N, g, c->prec, w.ntpart, s, /*tag=*/4, tl.start(),
                          tl.stop());
