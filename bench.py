@@ -34,7 +34,7 @@ def _log(msg):
 # header); a summary taken before that source changed no longer describes the
 # kernel and is not used.
 UPDATE_GEMM_TRAFFIC = ("update_gemm_c1_fp32_traffic.txt",
-                       ["csrc/gemm_nt.hip", "csrc/mfma_tile.hpp"])
+                       ["csrc/gemm_ntb.hip", "csrc/mfma_tile.hpp"])
 # per launch site of the C1 FP32 step (the headline's dominant site is
 # looked up here)
 SITE_TRAFFIC = {
@@ -74,22 +74,24 @@ def measured_traffic(name, sources):
 # Launch sites of the PNA training step timed by the library's event pairs
 # (kernel alone for the GEMM and aggregation sites), the kernel each one
 # runs (as named in the rocprofv3 summaries) and what bounds it.
-# BF16 layers after the first run the message and update linears on the BF16
-# operand copies (k_gemm_ntb); the first layer, and every FP32 layer, the
+# Layers after the first run the message and update linears in the LDS-DMA
+# form (k_gemm_ntb: FP32 on the inputs, BF16 on operand copies), FP32 also the
+# layer-input gradient; the first layer and the other BF16 sites the
 # register-staged kernel.  BF16 weight gradients run k_gemm_tn_tr.
 SITES = {
     "message_gemm": ("S1 message linear",
-                     "k_gemm_nt<P, 64, 128, *, 2, 4, *> | k_gemm_ntb<2, 2, 4>", "mfma"),
+                     "k_gemm_nt<P, 64, 128, *, 2, 4, *> | k_gemm_ntb<P, *, *, 2, 4, 2>", "mfma"),
     "aggregate": ("S2 aggregation", "k_aggregate<1>", "hbm"),
     "update_gemm": ("S3 update linear",
-                    "k_gemm_nt<P, 64, 128, *, 1, 4, *> | k_gemm_ntb<1, 2, 4>", "mfma"),
+                    "k_gemm_nt<P, 64, 128, *, 1, 4, *> | k_gemm_ntb<P, *, *, 2, 4, 1>", "mfma"),
     "update_wgrad": ("S6 update weight gradient", "k_gemm_tn<P, 64, 64, 1> | k_gemm_tn_tr<1, *>",
                      "mfma"),
     "agg_input_gemm": ("S6 aggregate-input gradient", "k_gemm_nt<P, 64, 128, *, 3, 4, *>", "mfma"),
     # by degree bucket dA is formed inside the adjoint (one fused kernel, dA
     # not stored) and the S6 aggregate-input GEMM site has no launches
     "aggregate_bwd": ("S6 dA + S7 aggregation adjoint, fused", "k_agg_bwd_fused<P, 1, *>", "hbm"),
-    "input_gemm": ("S6+S8 layer-input gradient", "k_gemm_nt<P, 64, 128, *, 4, 4, *>", "mfma"),
+    "input_gemm": ("S6+S8 layer-input gradient",
+                   "k_gemm_nt<P, 64, 128, *, 4, 4, *> | k_gemm_ntb<0, 64, 64, 2, 4, 4>", "mfma"),
     "message_wgrad": ("S8 message weight gradient", "k_gemm_tn<P, 64, 64, 2> | k_gemm_tn_tr<2, *>",
                       "mfma"),
 }
@@ -147,7 +149,7 @@ def time_sites(m, step, steps, w, N, E, sites=tuple(SITES)):
         else:
             peak = BF16_PEAK_TFLOPS if bf16 else FP32_PEAK_TFLOPS
             ach, unit = work / avg / 1e12, "TFLOP/s"
-        out[site] = {"step": what, "kernel": kern.replace("P", str(w.precision), 1),
+        out[site] = {"step": what, "kernel": kern.replace("<P,", f"<{w.precision},"),
                      "bound": bound, "avg_us": avg * 1e6, "launches": n,
                      "launches_per_step": per_step, "us_per_step": avg * 1e6 * per_step,
                      ("bytes_per_launch" if bound == "hbm" else "flops_per_launch"): work,
