@@ -15,7 +15,11 @@
 // waves in a 2 x 4 grid, 64-deep K steps, the same staging and the same
 // MFMA order over K, so dA is bitwise the NT GEMM's.  Tile column
 // j * 32 + f is dA column j H + c0 + f (wave column j holds aggregator j).
-// The adjoint is node_adjoint (agg_msg.hpp), as in k_aggregate_bwd.
+// The adjoint is node_adjoint's (agg_msg.hpp), as in k_aggregate_bwd, with
+// its loads split off: the node's index chain (id, CSR bounds, source ids) is
+// fetched with the product's first operand tiles, and the rows it gathers
+// are in flight while the dA block goes through LDS, so after the product a
+// node waits on no dependent load.
 #include "mfma_tile.hpp"
 #include "agg_msg.hpp"
 
@@ -60,6 +64,11 @@ k_agg_bwd_fused(const AggBwdFused a) {
   bw.find(mt, bq, m0, m_hi);
   const int tid = threadIdx.x, wid = tid >> 6;
   const int wm0 = (wid / WGN) * WM, wn0 = (wid % WGN) * WN;
+  // this thread's node in the adjoint (rows past the bucket's end repeat its
+  // last node and write nothing); its index chain is fetched beside the
+  // product's operands
+  const int r = tid >> 3, q4 = 4 * (tid & 7);
+  const int node = a.perm[min(m0 + r, m_hi - 1)];
 
   f4 acc[TM][TN];
 #pragma unroll
@@ -138,12 +147,12 @@ k_agg_bwd_fused(const AggBwdFused a) {
     __syncthreads();
     stash(st);
     __syncthreads();
-    dload(st, t + 2);
+    if (t + 2 < KT) dload(st, t + 2);
     mma_tile<PREC, TM, TN, LDA, BK>(As, Bs, wm0, wn0, acc);
     if constexpr (SPLIT) mma_tile<PREC, TM, TN, LDA, BK>(As, Bl, wm0, wn0, acc);
   };
   dload(IC<0>{}, 0);
-  dload(IC<1>{}, 1); // K = 64: tile 0 again, never stashed
+  if (KT > 1) dload(IC<1>{}, 1);
   __builtin_amdgcn_s_waitcnt(0x0f70); // vmcnt(0): see the TN GEMMs
   int t = 0;
   for (; t + 1 < KT; t += 2) {
@@ -151,6 +160,13 @@ k_agg_bwd_fused(const AggBwdFused a) {
     step(IC<1>{}, t + 1);
   }
   if (t < KT) step(IC<0>{}, t);
+  // the adjoint's operands that do not depend on dA are in flight while the
+  // block goes through LDS
+  const int lo = a.rowptr[node], deg = a.rowptr[node + 1] - lo;
+  int src[kCache];
+  if (deg > 0) fetch_sources(a.csr_src, lo, deg, src);
+  AdjIn in;
+  adj_load<FE>(in, node, lo, deg, src, c0 + q4, H, a.PQ, a.csr_e, a.WeT, a.bm, a.A, a.args);
 
   // the dA block into LDS, over the operand tiles once every wave is done
   __syncthreads();
@@ -168,14 +184,12 @@ k_agg_bwd_fused(const AggBwdFused a) {
   __syncthreads();
 
   // adjoint: thread (row r, features c0 + 4 q .. + 3)
-  const int r = tid >> 3, q4 = 4 * (tid & 7);
   if (m0 + r >= m_hi) return;
-  const int i = a.perm[m0 + r];
   const float *d = sD + r * LDD + q4;
-  node_adjoint<FE>(i, c0 + q4, H, a.PQ, a.rowptr, a.csr_src, a.csr_e, a.WeT, a.bm, a.A, a.args,
-                   *reinterpret_cast<const f4 *>(d), *reinterpret_cast<const f4 *>(d + kFusedFC),
-                   *reinterpret_cast<const f4 *>(d + 2 * kFusedFC),
-                   *reinterpret_cast<const f4 *>(d + 3 * kFusedFC), a.dm, a.D, a.ldD);
+  adj_finish<FE>(in, node, c0 + q4, H, a.PQ, a.csr_src, a.csr_e,
+                 *reinterpret_cast<const f4 *>(d), *reinterpret_cast<const f4 *>(d + kFusedFC),
+                 *reinterpret_cast<const f4 *>(d + 2 * kFusedFC),
+                 *reinterpret_cast<const f4 *>(d + 3 * kFusedFC), a.dm, a.D, a.ldD);
 }
 
 template <int PREC, bool SPLIT>
