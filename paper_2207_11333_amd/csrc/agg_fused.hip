@@ -16,10 +16,12 @@
 // MFMA order over K, so dA is bitwise the NT GEMM's.  Tile column
 // j * 32 + f is dA column j H + c0 + f (wave column j holds aggregator j).
 // The adjoint is node_adjoint's (agg_msg.hpp), as in k_aggregate_bwd, with
-// its loads split off: the node's index chain (id, CSR bounds, source ids) is
-// fetched with the product's first operand tiles, and the rows it gathers
-// are in flight while the dA block goes through LDS, so after the product a
-// node waits on no dependent load.
+// its loads split off: the node id is fetched with the product's first
+// operand tiles, and after the product the CSR bounds, source ids and the
+// rows they gather are loaded before the dA block goes through LDS, so they
+// are in flight meanwhile.  The CSR bounds and source ids are not fetched
+// earlier: held over the K loop they raise the register count past what two
+// workgroups per CU allow, which costs more than they save.
 #include "mfma_tile.hpp"
 #include "agg_msg.hpp"
 
@@ -65,8 +67,7 @@ k_agg_bwd_fused(const AggBwdFused a) {
   const int tid = threadIdx.x, wid = tid >> 6;
   const int wm0 = (wid / WGN) * WM, wn0 = (wid % WGN) * WN;
   // this thread's node in the adjoint (rows past the bucket's end repeat its
-  // last node and write nothing); its index chain is fetched beside the
-  // product's operands
+  // last node and write nothing), fetched beside the product's operands
   const int r = tid >> 3, q4 = 4 * (tid & 7);
   const int node = a.perm[min(m0 + r, m_hi - 1)];
 
