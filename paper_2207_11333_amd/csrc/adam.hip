@@ -91,36 +91,37 @@ __device__ __forceinline__ float w_eff(const float *__restrict__ Wp, int ldp, in
   return fmaf(table[2 * q + 1], row[8 * H], fmaf(table[2 * q], row[4 * H], row[0]));
 }
 
+// One row of the untransposed copies: rows 0 .. 2H - 1 are Wds's, the next
+// nb H (or H) the update copy's, the last Fe weT's; the workgroup's threads
+// stride over the row's columns (one division per row, coalesced loads and
+// stores along it).
 template <typename T>
-__device__ __forceinline__ void stage_elem(const float *__restrict__ Wm,
-                                           const float *__restrict__ Wp, int F, int Fp,
-                                           int H, int Fe, int nb,
-                                           const float *__restrict__ table,
-                                           const StageOut &o, long long t) {
+__device__ __forceinline__ void stage_row(const float *__restrict__ Wm,
+                                          const float *__restrict__ Wp, int F, int Fp,
+                                          int H, int Fe, int nb,
+                                          const float *__restrict__ table,
+                                          const StageOut &o, int row) {
   const int ldm = 2 * F + Fe, ldp = F + 12 * H;
   const int wu = nb ? Fp + 4 * H : Fp + 12 * H; // row width of the update copy
-  const long long n1 = 2LL * H * Fp;
-  const long long n2 = (long long)(nb ? nb : 1) * H * wu;
-  const long long n5 = (long long)Fe * H;
-  if (t < n1) {
-    const int r = (int)(t / Fp), c = (int)(t % Fp);
-    float v = 0.f;
-    if (c < F) v = r < H ? Wm[(size_t)r * ldm + c] : Wm[(size_t)(r - H) * ldm + F + c];
-    put<T>(o.hi[0], o.lo[0], t, v);
-  } else if (t < n1 + n2) {
-    const long long u = t - n1;
-    const long long rr = u / wu;
-    const int c = (int)(u % wu);
-    const int q = (int)(rr / H), r = (int)(rr % H);
-    float v = 0.f;
-    if (c < Fp) { if (c < F) v = Wp[(size_t)r * ldp + c]; }
-    else if (nb) v = w_eff(Wp, ldp, F, H, table, q, r, c - Fp);
-    else v = Wp[(size_t)r * ldp + F + (c - Fp)];
-    put<T>(o.hi[1], o.lo[1], u, v);
-  } else if (t < n1 + n2 + n5) {
-    const long long u = t - n1 - n2;
-    const int f = (int)(u / H), c = (int)(u % H);
-    o.weT[u] = Wm[(size_t)c * ldm + 2 * F + f];
+  const int r1 = 2 * H, r2 = r1 + (nb ? nb : 1) * H;
+  if (row < r1) {
+    const float *src = row < H ? Wm + (size_t)row * ldm : Wm + (size_t)(row - H) * ldm + F;
+    for (int c = threadIdx.x; c < Fp; c += blockDim.x)
+      put<T>(o.hi[0], o.lo[0], (size_t)row * Fp + c, c < F ? src[c] : 0.f);
+  } else if (row < r2) {
+    const int rr = row - r1, q = rr / H, m = rr - q * H;
+    const float *src = Wp + (size_t)m * ldp;
+    for (int c = threadIdx.x; c < wu; c += blockDim.x) {
+      float v = 0.f;
+      if (c < Fp) { if (c < F) v = src[c]; }
+      else if (nb) v = w_eff(Wp, ldp, F, H, table, q, m, c - Fp);
+      else v = src[F + (c - Fp)];
+      put<T>(o.hi[1], o.lo[1], (size_t)rr * wu + c, v);
+    }
+  } else if (row < r2 + Fe) {
+    const int f = row - r2;
+    for (int c = threadIdx.x; c < H; c += blockDim.x)
+      o.weT[(size_t)f * H + c] = Wm[(size_t)c * ldm + 2 * F + f];
   }
 }
 
@@ -227,8 +228,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F, int Fp,
               int H, int Fe, int nb, const float *__restrict__ table, StageOut o) {
-  stage_elem<T>(Wm, Wp, F, Fp, H, Fe, nb, table, o,
-                (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  stage_row<T>(Wm, Wp, F, Fp, H, Fe, nb, table, o, blockIdx.x);
 }
 
 // Every layer in one launch (blockIdx.y = layer); optionally advances the
@@ -238,8 +238,7 @@ __global__ void __launch_bounds__(256)
 k_stage_all(const StageDesc *__restrict__ tab, int H, int Fe, int nb,
             const float *__restrict__ table, long long *bump) {
   const StageDesc &d = tab[blockIdx.y];
-  stage_elem<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, nb, table, d.o,
-                (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  stage_row<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, nb, table, d.o, blockIdx.x);
   if (bump && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *bump += 1;
 }
 
@@ -267,11 +266,8 @@ hipError_t launch_adamw(float *theta, const float *g, float *m, float *v, int64_
   return hipGetLastError();
 }
 
-// elements of the untransposed copies (Wds, Wpp, weT) of one layer
-static long long stage_total(int Fp, int H, int Fe, int nb) {
-  const long long nbk = nb ? nb : 1;
-  return 2LL * H * Fp + nbk * H * (Fp + (nb ? 4 : 12) * H) + (long long)Fe * H;
-}
+// rows of the untransposed copies (Wds, Wpp, weT) of one layer
+static int stage_rows(int H, int Fe, int nb) { return (2 + (nb ? nb : 1)) * H + Fe; }
 
 // 32 x 32 tiles of the transposed copies of one layer
 static int stage_t_tiles(int Fp, int H, int nb) {
@@ -281,7 +277,7 @@ static int stage_t_tiles(int Fp, int H, int nb) {
 
 hipError_t launch_stage_all(const StageDesc *tab, int L, int maxFp, int H, int Fe, int nb,
                             const float *table, int to_bf16, long long *bump, hipStream_t s) {
-  const dim3 grid(cdiv(stage_total(maxFp, H, Fe, nb), 256), L);
+  const dim3 grid(stage_rows(H, Fe, nb), L);
   const dim3 grid_t(stage_t_tiles(maxFp, H, nb), L);
   if (to_bf16) {
     k_stage_all<__bf16><<<grid, 256, 0, s>>>(tab, H, Fe, nb, table, bump);
@@ -296,13 +292,13 @@ hipError_t launch_stage_all(const StageDesc *tab, int L, int maxFp, int H, int F
 hipError_t launch_stage_layer(const float *Wm, const float *Wp, int F, int Fp, int H,
                               int Fe, int nb, const float *table, const StageOut &o,
                               int to_bf16, hipStream_t s) {
-  const long long total = stage_total(Fp, H, Fe, nb);
+  const int rows = stage_rows(H, Fe, nb);
   const int tiles = stage_t_tiles(Fp, H, nb);
   if (to_bf16) {
-    k_stage_layer<__bf16><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
+    k_stage_layer<__bf16><<<rows, 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
     k_stage_t_layer<__bf16><<<tiles, 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
   } else {
-    k_stage_layer<float><<<cdiv(total, 256), 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
+    k_stage_layer<float><<<rows, 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
     k_stage_t_layer<float><<<tiles, 256, 0, s>>>(Wm, Wp, F, Fp, H, Fe, nb, table, o);
   }
   return hipGetLastError();

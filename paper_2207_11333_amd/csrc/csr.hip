@@ -28,7 +28,9 @@ __global__ void k_set_dims(Dims *d, int B, int N, int E, int *err) {
 
 // node -> graph id by binary search over graph_ptr (staged in LDS when it
 // fits, so the search costs no dependent global loads); zero the counters;
-// check graph_ptr.
+// check graph_ptr; the first layer's input zero-padded from F to Fp columns.
+// Thread t covers node t and the four padded-input columns 4 (t % (Fp/4)) ..
+// of row t / (Fp/4), so the grid spreads the copy over many CUs.
 constexpr int kInitThreads = 256;
 constexpr int kGraphPtrLds = 4096;
 
@@ -39,11 +41,12 @@ k_csr_init(const Dims *__restrict__ dims, const int *__restrict__ graph_ptr,
            float *__restrict__ xpad, int Fp) {
   __shared__ int s_gp[kGraphPtrLds];
   const int B = dims->B, N = dims->N;
-  const bool staged = B + 1 <= kGraphPtrLds;
+  const int i = blockIdx.x * kInitThreads + threadIdx.x;
+  // only workgroups holding nodes search (the condition is uniform per block)
+  const bool staged = B + 1 <= kGraphPtrLds && (int)blockIdx.x * kInitThreads < N;
   if (staged)
     for (int k = threadIdx.x; k <= B; k += kInitThreads) s_gp[k] = graph_ptr[k];
   __syncthreads();
-  const int i = blockIdx.x * kInitThreads + threadIdx.x;
   if (i < B) {
     if (graph_ptr[i + 1] <= graph_ptr[i]) atomicOr(err, ERR_GRAPH_PTR);
   }
@@ -69,20 +72,16 @@ k_csr_init(const Dims *__restrict__ dims, const int *__restrict__ graph_ptr,
     cnt_in[i] = 0;
     cnt_out[i] = 0;
   }
-  if (x) {
-    // the first layer's input, zero-padded from F to Fp columns: the block's
-    // kInitThreads rows, element by element so that stores are coalesced
-    // (unrolled so that the loads of several elements are in flight together)
-    const int r0 = blockIdx.x * kInitThreads, nr = min(kInitThreads, N - r0);
-    bool finite = true;
-#pragma unroll 8
-    for (int e = threadIdx.x; e < nr * Fp; e += kInitThreads) {
-      const int r = r0 + e / Fp, c = e % Fp;
-      const float v = c < F ? x[(size_t)r * F + c] : 0.f;
-      finite = finite && isfinite(v);
-      xpad[(size_t)r * Fp + c] = v;
-    }
-    if (!finite) atomicOr(err, ERR_NONFINITE);
+  const int q = Fp >> 2; // 16-byte groups per padded row
+  if (x && i < N * q) {
+    const int r = i / q, c0 = (i - r * q) * 4;
+    const float *xr = x + (size_t)r * F;
+    f4 v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = c0 + k < F ? xr[c0 + k] : 0.f;
+    if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3])))
+      atomicOr(err, ERR_NONFINITE);
+    *reinterpret_cast<f4 *>(xpad + (size_t)r * Fp + c0) = v;
   }
 }
 
@@ -430,8 +429,11 @@ hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
                             const float *table, const CsrBufs &c, bool clear_err,
                             const float *x, int F, float *xpad, int Fp, hipStream_t s) {
   if (clear_err) k_set_dims<<<1, 64, 0, s>>>(nullptr, 0, 0, 0, c.err);
-  const int nb = capN > capB ? capN : capB;
-  k_csr_init<<<cdiv(nb > 0 ? nb : 1, kInitThreads), kInitThreads, 0, s>>>(
+  // Fp is a multiple of 16 (whole 16-byte groups per padded row)
+  if (x && Fp % 16) return hipErrorInvalidValue;
+  long long nt = capN > capB ? capN : capB;
+  if (x && (long long)capN * (Fp / 4) > nt) nt = (long long)capN * (Fp / 4);
+  k_csr_init<<<cdiv(nt > 0 ? nt : 1, kInitThreads), kInitThreads, 0, s>>>(
       dims, graph_ptr, c.node_graph, c.cnt_in, c.cnt_out, c.err, x, F, xpad, Fp);
   if (capE > 0)
     k_csr_count<<<cdiv(capE, 256), 256, 0, s>>>(dims, edge_index, c.node_graph,
