@@ -171,27 +171,48 @@ __global__ void __launch_bounds__(256) k_reduce_upd(const ReduceUpd r) {
 }
 
 // Column sums of X [N rows, C columns] over fixed row chunks: chunk z of
-// Z covers rows [z R, (z + 1) R), R = ceil(N / Z); each thread owns one
-// column and adds the chunk's rows in order with four interleaved partial
-// sums (rows r mod 4) combined at the end in a fixed order.  The partials are
-// written as P[z][c][0..3] = {sum, 0, 0, 0}: the layout of a weight-gradient
-// GEMM's sum column, so that launch_reduce_map adds them.
-__global__ void __launch_bounds__(256)
+// Z covers rows [z R, (z + 1) R), R = ceil(N / Z), and is one workgroup.
+// Its threads split into RP row lanes of one 16-byte column group each: lane
+// rl adds rows lo + rl, lo + rl + RP, ... in order, and the lanes' sums are
+// added in lane order through LDS (a fixed order, so the result does not
+// depend on timing).  The partials are written as P[z][c][0..3] =
+// {sum, 0, 0, 0}: the layout of a weight-gradient GEMM's sum column, so that
+// launch_reduce_map adds them.
+constexpr int kColsumThreads = 1024;
+
+__global__ void __launch_bounds__(kColsumThreads)
 k_colsum(const Dims *__restrict__ dims, const float *__restrict__ X, int ldx, int C, int Z,
          float *__restrict__ P) {
-  const int c = blockIdx.y * 256 + threadIdx.x, z = blockIdx.x;
-  if (c >= C) return;
-  const int N = dims->N;
+  __shared__ f4 part[kColsumThreads];
+  // thread (row lane rl, 16-byte column group cg): the workgroup reads RP
+  // rows of up to 256 column groups at a time, four such passes in flight
+  const int CG = C >> 2, g0 = blockIdx.y * 256;
+  const int cgb = min(CG - g0, 256), RP = kColsumThreads / cgb;
+  const int t = threadIdx.x, rl = t / cgb, cg = g0 + t % cgb;
+  const int N = dims->N, z = blockIdx.x;
   const int R = (N + Z - 1) / Z;
   const int lo = min(z * R, N), hi = min(lo + R, N);
-  float s[4] = {0.f, 0.f, 0.f, 0.f};
-  int i = lo;
-  for (; i + 4 <= hi; i += 4) {
+  f4 sum = {0.f, 0.f, 0.f, 0.f};
+  if (rl < RP) {
+    const float *base = X + 4 * cg;
+    int i = lo + rl;
+    for (; i + 3 * RP < hi; i += 4 * RP) {
+      f4 v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s[u] += X[(size_t)(i + u) * ldx + c];
+      for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const f4 *>(base + (size_t)(i + u * RP) * ldx);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sum += v[u];
+    }
+    for (; i < hi; i += RP) sum += *reinterpret_cast<const f4 *>(base + (size_t)i * ldx);
   }
-  for (int u = 0; i < hi; ++i, ++u) s[u] += X[(size_t)i * ldx + c];
-  *reinterpret_cast<f4 *>(P + ((size_t)z * C + c) * 4) = f4{(s[0] + s[1]) + (s[2] + s[3]), 0.f, 0.f, 0.f};
+  part[t] = sum;
+  __syncthreads();
+  if (rl != 0) return;
+  // the row lanes' sums in lane order
+  for (int k = 1; k < RP; ++k) sum += part[t + k * cgb];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    *reinterpret_cast<f4 *>(P + ((size_t)z * C + 4 * cg + e) * 4) = f4{sum[e], 0.f, 0.f, 0.f};
 }
 
 // Several reductions in one launch (the weight gradients of one layer): job
@@ -322,7 +343,9 @@ __global__ void __launch_bounds__(256) k_reduce_jobs(const ReduceJobs j) {
 hipError_t launch_colsum(const Dims *dims, const float *X, int ldx, int C, int Z, float *P,
                          hipStream_t s) {
   if (C <= 0 || Z <= 0) return hipSuccess;
-  k_colsum<<<dim3(Z, cdiv(C, 256)), 256, 0, s>>>(dims, X, ldx, C, Z, P);
+  // whole 16-byte column groups
+  if (C % 4 || ldx % 4 || reinterpret_cast<uintptr_t>(X) % 16) return hipErrorInvalidValue;
+  k_colsum<<<dim3(Z, cdiv(C / 4, 256)), kColsumThreads, 0, s>>>(dims, X, ldx, C, Z, P);
   return hipGetLastError();
 }
 
