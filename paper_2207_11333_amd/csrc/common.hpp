@@ -346,7 +346,10 @@ hipError_t launch_head_backward(const Dims *dims, int capB, int H, int Tg,
                                 const float *q, const float *pred, const float *target,
                                 const float *dpred, const float *gw, float *dy, float *dq,
                                 float *dh, float *dw_head, const float *relu_of,
-                                const float *add, hipStream_t s);
+                                const float *add, float *part, hipStream_t s);
+// part (nullable): scratch of head_partial_floats(H, Tg) floats; with it,
+// batches of 512 graphs or more take the head weight gradients in chunks.
+size_t head_partial_floats(int H, int Tg);
 // Node heads (Tn): aligned weight copies, outputs, errors and small gradients.
 hipError_t launch_stage_node_heads(int H, int Tn, const float *wn, float *W1n, float *W1nT,
                                    hipStream_t s);

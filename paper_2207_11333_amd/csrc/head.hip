@@ -249,6 +249,81 @@ k_head_bwd_weights(const Dims *__restrict__ dims, int H, int Tg, const float *__
   }
 }
 
+// The same gradients for large batches, in two launches.  The graphs are
+// split into Z chunks of R = ceil(B / Z); k_head_w_part writes every
+// output's sum over each chunk (P [Tg][Z][n], n = H^2 + 2H + 1) and
+// k_head_w_sum adds the chunks in order.  dW1: a workgroup takes a 16 x 64
+// block of (c, k) and walks its chunk 64 graphs at a time, the rows of dq
+// and g staged in LDS (thread: one c, four k); db1, dw2 and db2 take one more
+// workgroup per chunk (thread: one c, the chunk's graphs in order).  The
+// one-pass kernel above reads each g and dq value once per output.
+constexpr int kHeadChunks = 16, kHeadTC = 16, kHeadTK = 64, kHeadRows = 64;
+constexpr int kHeadChunkedMinB = 512;
+
+__global__ void __launch_bounds__(256)
+k_head_w_part(const Dims *__restrict__ dims, int H, int Tg, int Z, const float *__restrict__ g,
+              const float *__restrict__ qall, const float *__restrict__ dyall,
+              const float *__restrict__ dqall, float *__restrict__ Pall) {
+  __shared__ float sdq[kHeadRows][kHeadTC];
+  __shared__ f4 sg[kHeadRows][kHeadTK / 4];
+  const int B = dims->B, n1 = H * H, n = n1 + 2 * H + 1;
+  const int hd = blockIdx.z, z = blockIdx.y;
+  const float *q = qall + (size_t)hd * B * H, *dq = dqall + (size_t)hd * B * H;
+  float *P = Pall + ((size_t)hd * Z + z) * n;
+  const int R = (B + Z - 1) / Z, b_lo = min(z * R, B), b_hi = min(b_lo + R, B);
+  const int ntk = (H + kHeadTK - 1) / kHeadTK, tiles = (H / kHeadTC) * ntk;
+  const int t = threadIdx.x;
+  if ((int)blockIdx.x == tiles) { // db1, dw2, db2 over this chunk
+    for (int c = t; c < H; c += 256) {
+      float s1 = 0.f, s2 = 0.f;
+      for (int b = b_lo; b < b_hi; ++b) {
+        s1 += dq[(size_t)b * H + c];
+        s2 += dyall[(size_t)b * Tg + hd] * q[(size_t)b * H + c];
+      }
+      P[n1 + c] = s1;
+      P[n1 + H + c] = s2;
+    }
+    if (t == 0) {
+      float s3 = 0.f;
+      for (int b = b_lo; b < b_hi; ++b) s3 += dyall[(size_t)b * Tg + hd];
+      P[n1 + 2 * H] = s3;
+    }
+    return;
+  }
+  const int c0 = (blockIdx.x / ntk) * kHeadTC, k0 = (blockIdx.x % ntk) * kHeadTK;
+  const int ci = t / (kHeadTK / 4), kq = t % (kHeadTK / 4);
+  const int kk = k0 + 4 * kq; // first k of this thread (H is a multiple of 16)
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int r0 = b_lo; r0 < b_hi; r0 += kHeadRows) {
+    const int nr = min(kHeadRows, b_hi - r0);
+    __syncthreads();
+    // stage rows r0 .. r0 + nr - 1: dq[., c0 .. c0 + 15], g[., k0 .. k0 + 63]
+    for (int e = t; e < kHeadRows * kHeadTC; e += 256) {
+      const int r = e / kHeadTC, cc = e % kHeadTC;
+      sdq[r][cc] = r < nr ? dq[(size_t)(r0 + r) * H + c0 + cc] : 0.f;
+    }
+    for (int e = t; e < kHeadRows * (kHeadTK / 4); e += 256) {
+      const int r = e / (kHeadTK / 4), kc = e % (kHeadTK / 4), k = k0 + 4 * kc;
+      sg[r][kc] = (r < nr && k < H) ? *reinterpret_cast<const f4 *>(g + (size_t)(r0 + r) * H + k)
+                                    : f4{0.f, 0.f, 0.f, 0.f};
+    }
+    __syncthreads();
+    for (int r = 0; r < nr; ++r) acc += sdq[r][ci] * sg[r][kq];
+  }
+  if (kk < H) *reinterpret_cast<f4 *>(P + (size_t)(c0 + ci) * H + kk) = acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_head_w_sum(int H, int Z, const float *__restrict__ Pall, float *__restrict__ outall) {
+  const int n = H * H + 2 * H + 1, hd = blockIdx.y;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const float *P = Pall + (size_t)hd * Z * n + t;
+  float s = 0.f;
+  for (int z = 0; z < Z; ++z) s += P[(size_t)z * n];
+  outall[(size_t)hd * n + t] = s;
+}
+
 // ---- node-level heads (Tn of them; head s at wn + s (H^2 + 2H + 1)) ------
 // Their hidden layer Q_s = ReLU(h W1_s^T + b1_s) [N, H] comes from the NT
 // GEMM (Q_s at Qn + s capN H); these kernels do the rest.
@@ -427,15 +502,26 @@ hipError_t launch_head_backward(const Dims *dims, int capB, int H, int Tg, const
                                 const float *pred, const float *target, const float *dpred,
                                 const float *gw, float *dy, float *dq, float *dh,
                                 float *dw_head, const float *relu_of, const float *add,
-                                hipStream_t s) {
+                                float *part, hipStream_t s) {
   if (capB <= 0) return hipSuccess;
   if (Tg < 1 || Tg > kMaxGraphHeads || H > 512) return hipErrorInvalidValue;
   k_head_bwd_graph<<<capB, kHeadBwdThreads, 0, s>>>(dims, H, Tg, graph_ptr, wh, q, pred, target,
                                                  dpred, gw, dy, dq, dh, relu_of, add);
   const int n = H * H + 2 * H + 1;
-  k_head_bwd_weights<<<dim3(cdiv(n, kHeadOut), Tg), 256, 0, s>>>(dims, H, Tg, g, q, dy, dq,
-                                                                 dw_head);
+  if (part && capB >= kHeadChunkedMinB && H % 16 == 0) {
+    const int Z = std::min(kHeadChunks, cdiv(capB, kHeadRows));
+    const int tiles = (H / kHeadTC) * cdiv(H, kHeadTK);
+    k_head_w_part<<<dim3(tiles + 1, Z, Tg), 256, 0, s>>>(dims, H, Tg, Z, g, q, dy, dq, part);
+    k_head_w_sum<<<dim3(cdiv(n, 256), Tg), 256, 0, s>>>(H, Z, part, dw_head);
+  } else {
+    k_head_bwd_weights<<<dim3(cdiv(n, kHeadOut), Tg), 256, 0, s>>>(dims, H, Tg, g, q, dy, dq,
+                                                                   dw_head);
+  }
   return hipGetLastError();
+}
+
+size_t head_partial_floats(int H, int Tg) {
+  return (size_t)Tg * kHeadChunks * ((size_t)H * H + 2 * H + 1);
 }
 
 } // namespace hgnn

@@ -969,7 +969,7 @@ int head_backward(hgnn_ctx *c, Exec &ex, const float *wh, const float *target, c
   }
   hipError_t e = launch_head_backward(ex.dims, ex.B, H, c->Tg, ex.graph_ptr, wh, w.g, w.q,
                                       w.ypred, target, dpred, c->gw_dev, w.dy, w.dq, dh, dwh,
-                                      relu_of, add, s);
+                                      relu_of, add, c->part, s);
   if (e != hipSuccess) return hip_fail(c, e, "head backward");
   return HGNN_OK;
 }
@@ -1474,6 +1474,8 @@ static int create_ctx(const hgnn_config *cfg, int kind, const hgnn_heads *heads,
   }
   c->Tg = Tg;
   c->Tn = Tn;
+  // the head weight gradients' chunk partials (large batches) use part too
+  part_max = std::max(part_max, head_partial_floats(H, Tg));
   c->cfg.reserved = Tg + 256 * Tn + 65536 * kind; // part of the checkpoint's identity
   // tensors of the packed vector, for the seeded initialisation
   if (kind == HGNN_GC_CGCNN) {

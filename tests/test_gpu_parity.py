@@ -215,11 +215,13 @@ def test_fp32_forward_backward_parity(name):
 @pytest.mark.parametrize("Fe", [1, 2])
 def test_large_batch_fp32_parity(Fe):
     """A batch above 16,384 atoms, where the message weight gradient takes the
-    De rows apart (their column sums in a GEMM of their own): FP32 parity of
-    predictions, loss and every gradient tensor (decision replay), with a
-    2-layer hidden-32 model so that the FP64 oracle stays quick."""
-    b = synth.make_batch(777 + Fe, 500, 20, 50, Fe)
-    assert b.num_nodes >= 16384
+    De rows apart (their column sums in a GEMM of their own), and of at least
+    512 graphs, where the head weight gradients are summed in graph chunks:
+    FP32 parity of predictions, loss and every gradient tensor (decision
+    replay), with a 2-layer hidden-32 model so that the FP64 oracle stays
+    quick."""
+    b = synth.make_batch(777 + Fe, 520, 20, 50, Fe)
+    assert b.num_nodes >= 16384 and b.num_graphs >= 512
     L, H, delta = 2, 32, 1.3
     shape = synth.ModelShape(L, H, 9, Fe)
     params = synth.init_params(shape, 99 + Fe)
