@@ -205,20 +205,47 @@ k_scan_top(const Dims *__restrict__ dims, int nb, int *__restrict__ scan,
 // among the nodes of its degree bucket counts the block's earlier nodes of
 // that bucket (earlier waves, then earlier lanes of its wave), so the
 // permutation is stable in node id.
+//
+// fused (at most kScanFuse blocks): k_scan_top is not run; each block sums
+// the raw block records itself (a wave per column: the records of earlier
+// blocks and of all blocks), and block 0 writes rowptr[N], srcptr[N] and the
+// bucket bounds.  One dependent launch fewer on the step's critical path.
+constexpr int kScanFuse = 256;
+
 __global__ void __launch_bounds__(kScanNodes)
 k_scan_apply(const Dims *__restrict__ dims, int *__restrict__ cnt_in,
              int *__restrict__ cnt_out, const int *__restrict__ scan,
              const float *__restrict__ table, int max_degree, int nb,
              int *__restrict__ rowptr, int *__restrict__ srcptr, int *__restrict__ deg,
              float *__restrict__ sp, float *__restrict__ sm, int *__restrict__ perm,
-             const int *__restrict__ brow, int *__restrict__ err) {
+             int *__restrict__ brow, int *__restrict__ err, int fused) {
   __shared__ int s_w[2][kScanNodes / 64];
   __shared__ int s_bw[kScanNodes / 64][kMaxBuckets];
+  __shared__ int s_off[kScanRec], s_tot[kScanRec];
   const int N = dims->N;
   const int base = blockIdx.x * kScanNodes;
   if (base >= N) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int *rec = scan + (size_t)blockIdx.x * kScanRec;
+  if (fused) {
+    const int nblk = (N + kScanNodes - 1) / kScanNodes;
+    for (int c = wid; c < 2 + nb; c += kScanNodes / 64) {
+      int before = 0, total = 0;
+      for (int k = lane; k < nblk; k += 64) {
+        const int v = scan[(size_t)k * kScanRec + c];
+        total += v;
+        before += k < (int)blockIdx.x ? v : 0;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        before += __shfl_xor(before, o, 64);
+        total += __shfl_xor(total, o, 64);
+      }
+      if (lane == 0) {
+        s_off[c] = before;
+        s_tot[c] = total;
+      }
+    }
+  }
   const int i = base + tid;
   const int vi = i < N ? cnt_in[i] : 0, vo = i < N ? cnt_out[i] : 0;
   const int bq = i < N ? bucket_of(vi, max_degree) : -1;
@@ -236,8 +263,21 @@ k_scan_apply(const Dims *__restrict__ dims, int *__restrict__ cnt_in,
     if (bq == q) pos = __popcll(m & below);
   }
   __syncthreads();
+  if (fused && blockIdx.x == 0 && tid == 0) {
+    rowptr[N] = s_tot[0];
+    srcptr[N] = s_tot[1];
+    if (nb) {
+      int a = 0;
+      for (int q = 0; q < nb; ++q) {
+        brow[q] = a;
+        a += s_tot[2 + q];
+      }
+      brow[nb] = a;
+    }
+  }
   if (i >= N) return;
-  int ei_ = rec[0] + ii - vi, eo_ = rec[1] + io - vo;
+  const int r0 = fused ? s_off[0] : rec[0], r1 = fused ? s_off[1] : rec[1];
+  int ei_ = r0 + ii - vi, eo_ = r1 + io - vo;
   for (int w = 0; w < wid; ++w) {
     ei_ += s_w[0][w];
     eo_ += s_w[1][w];
@@ -250,7 +290,13 @@ k_scan_apply(const Dims *__restrict__ dims, int *__restrict__ cnt_in,
   cnt_in[i] = 0;
   cnt_out[i] = 0;
   if (nb) {
-    int p = brow[bq] + rec[2 + bq] + pos;
+    int p = pos;
+    if (fused) {
+      p += s_off[2 + bq];
+      for (int q = 0; q < bq; ++q) p += s_tot[2 + q]; // the bucket's first row
+    } else {
+      p += brow[bq] + rec[2 + bq];
+    }
     for (int w = 0; w < wid; ++w) p += s_bw[w][bq];
     perm[p] = i;
   }
@@ -440,11 +486,13 @@ hipError_t launch_csr_build(const Dims *dims, int capB, int capN, int capE,
                                                 c.cnt_in, c.cnt_out, c.err);
   {
     const int nsb = cdiv(capN > 0 ? capN : 1, kScanNodes);
+    const int fused = nsb <= kScanFuse;
     k_scan_count<<<nsb, 256, 0, s>>>(dims, c.cnt_in, c.cnt_out, max_degree, c.nb, c.scan);
-    k_scan_top<<<1, kScanTop, 0, s>>>(dims, c.nb, c.scan, c.brow, c.rowptr, c.srcptr);
+    if (!fused)
+      k_scan_top<<<1, kScanTop, 0, s>>>(dims, c.nb, c.scan, c.brow, c.rowptr, c.srcptr);
     k_scan_apply<<<nsb, 256, 0, s>>>(dims, c.cnt_in, c.cnt_out, c.scan, table, max_degree,
                                      c.nb, c.rowptr, c.srcptr, c.deg, c.sp, c.sm, c.perm,
-                                     c.brow, c.err);
+                                     c.brow, c.err, fused);
   }
   if (capE > 0)
     k_csr_fill<<<cdiv(capE, 256), 256, 0, s>>>(dims, edge_index, c.node_graph, c.rowptr,
