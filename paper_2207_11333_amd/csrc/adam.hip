@@ -211,14 +211,6 @@ __device__ void stage_transposed(const float *__restrict__ Wm, const float *__re
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_stage_t_all(const StageDesc *__restrict__ tab, int H, int Fe, int nb,
-              const float *__restrict__ table) {
-  const StageDesc &d = tab[blockIdx.y];
-  stage_transposed<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, nb, table, d.o, blockIdx.x);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256)
 k_stage_t_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F, int Fp,
                 int H, int Fe, int nb, const float *__restrict__ table, StageOut o) {
   stage_transposed<T>(Wm, Wp, F, Fp, H, Fe, nb, table, o, blockIdx.x);
@@ -231,14 +223,21 @@ k_stage_layer(const float *__restrict__ Wm, const float *__restrict__ Wp, int F,
   stage_row<T>(Wm, Wp, F, Fp, H, Fe, nb, table, o, blockIdx.x);
 }
 
-// Every layer in one launch (blockIdx.y = layer); optionally advances the
-// AdamW step counter once the preceding update has been applied.
+// Every layer's copies in one launch (blockIdx.y = layer): the first `rows`
+// workgroups write the untransposed copies a row each, the rest the
+// transposed copies a 32 x 32 tile each (the two sets are independent);
+// optionally advances the AdamW step counter once the preceding update has
+// been applied.  One launch instead of two: the step's launches cost host
+// time that the BF16 step is short enough to feel.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_stage_all(const StageDesc *__restrict__ tab, int H, int Fe, int nb,
-            const float *__restrict__ table, long long *bump) {
+            const float *__restrict__ table, long long *bump, int rows) {
   const StageDesc &d = tab[blockIdx.y];
-  stage_row<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, nb, table, d.o, blockIdx.x);
+  if ((int)blockIdx.x < rows)
+    stage_row<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, nb, table, d.o, blockIdx.x);
+  else
+    stage_transposed<T>(d.Wm, d.Wp, d.F, d.Fp, H, Fe, nb, table, d.o, blockIdx.x - rows);
   if (bump && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *bump += 1;
 }
 
@@ -277,15 +276,10 @@ static int stage_t_tiles(int Fp, int H, int nb) {
 
 hipError_t launch_stage_all(const StageDesc *tab, int L, int maxFp, int H, int Fe, int nb,
                             const float *table, int to_bf16, long long *bump, hipStream_t s) {
-  const dim3 grid(stage_rows(H, Fe, nb), L);
-  const dim3 grid_t(stage_t_tiles(maxFp, H, nb), L);
-  if (to_bf16) {
-    k_stage_all<__bf16><<<grid, 256, 0, s>>>(tab, H, Fe, nb, table, bump);
-    k_stage_t_all<__bf16><<<grid_t, 256, 0, s>>>(tab, H, Fe, nb, table);
-  } else {
-    k_stage_all<float><<<grid, 256, 0, s>>>(tab, H, Fe, nb, table, bump);
-    k_stage_t_all<float><<<grid_t, 256, 0, s>>>(tab, H, Fe, nb, table);
-  }
+  const int rows = stage_rows(H, Fe, nb);
+  const dim3 grid(rows + stage_t_tiles(maxFp, H, nb), L);
+  if (to_bf16) k_stage_all<__bf16><<<grid, 256, 0, s>>>(tab, H, Fe, nb, table, bump, rows);
+  else k_stage_all<float><<<grid, 256, 0, s>>>(tab, H, Fe, nb, table, bump, rows);
   return hipGetLastError();
 }
 
