@@ -42,10 +42,13 @@ def _case(seed, Tg, Tn, L, H, B=24):
     return synth.Batch(b.graph_ptr, b.x, b.edge_index, b.edge_attr, y), params, yn
 
 
-@pytest.mark.parametrize("Tg,Tn,L,H", [(2, 2, 2, 32), (3, 1, 3, 64), (1, 4, 2, 48), (4, 0, 2, 16)])
-def test_multitask_parity(Tg, Tn, L, H):
+# the last case has 520 graphs: its head weight gradients are summed in graph
+# chunks, one launch over all graph heads
+@pytest.mark.parametrize("Tg,Tn,L,H,B", [(2, 2, 2, 32, 24), (3, 1, 3, 64, 24), (1, 4, 2, 48, 24),
+                                         (4, 0, 2, 16, 24), (3, 1, 2, 48, 520)])
+def test_multitask_parity(Tg, Tn, L, H, B):
     from paper_2207_11333_amd import hgnn
-    b, params, yn = _case(200 + Tg * 10 + Tn, Tg, Tn, L, H)
+    b, params, yn = _case(200 + Tg * 10 + Tn, Tg, Tn, L, H, B)
     gw = [0.5, 2.0, 1.0, 0.25][:Tg]
     nw = [1.5, 0.75, 1.0, 3.0][:Tn]
     delta = 1.1
