@@ -27,12 +27,13 @@ __device__ __forceinline__ void graph_range(const int *gptr, int b, int N, int &
   hi = min(max(gptr[b + 1], lo), N);
 }
 
-// Fixed-shape tree reduction over the workgroup (deterministic).
+// Fixed-shape tree reduction over a workgroup of NT threads (deterministic).
+template <int NT = kHeadThreads>
 __device__ float block_sum(float v, float *red) {
   const int tid = threadIdx.x;
   red[tid] = v;
   __syncthreads();
-  for (int s = kHeadThreads / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
@@ -46,13 +47,20 @@ __device__ float block_sum(float v, float *red) {
 // prediction goes to pred[b Tg + t].  W1T (nullable): the staged transposes
 // [Tg][H][H] of the W1s, read along the threads' outputs (coalesced); the
 // sums run over k in the same order either way.
-__global__ void __launch_bounds__(kHeadThreads)
+// 512 threads: thread (p, c) takes feature c and the p-th of P = 512 / H
+// ranges of the graph's nodes (pooling) and of k (the W1 product); the P
+// partial sums are added in order through LDS.  One thread per feature left
+// half of a 256-thread workgroup idle at H = 128 and walked all H rows of W1
+// in one chain.
+constexpr int kHeadFwdThreads = 512;
+
+__global__ void __launch_bounds__(kHeadFwdThreads)
 k_head_forward(const Dims *__restrict__ dims, int H, int Tg, const int *__restrict__ gptr,
                const float *__restrict__ h, const float *__restrict__ wh,
                const float *__restrict__ W1T, float *__restrict__ g, float *__restrict__ q,
                float *__restrict__ pred, float *__restrict__ pred2) {
   __shared__ float gs[512];
-  __shared__ float red[kHeadThreads];
+  __shared__ float red[kHeadFwdThreads];
   const int b = blockIdx.x, t = blockIdx.y;
   const int B = dims->B;
   if (b >= B) return;
@@ -61,33 +69,59 @@ k_head_forward(const Dims *__restrict__ dims, int H, int Tg, const int *__restri
   int lo, hi;
   graph_range(gptr, b, dims->N, lo, hi);
   const float inv_n = 1.0f / (float)(hi - lo);
-  for (int c = threadIdx.x; c < H; c += kHeadThreads) {
+  const int P = kHeadFwdThreads / H; // H <= 512
+  const int tid = threadIdx.x, c = tid % H, p = tid / H;
+  const bool act = p < P;
+  // pooling: nodes lo + p R .. of this range
+  {
+    const int R = (hi - lo + P - 1) / P;
+    const int i0 = min(lo + p * R, hi), i1 = min(i0 + R, hi);
     float s = 0.f;
+    if (act) {
 #pragma unroll 8
-    for (int i = lo; i < hi; ++i) s += h[(size_t)i * H + c];
+      for (int i = i0; i < i1; ++i) s += h[(size_t)i * H + c];
+    }
+    red[tid] = s;
+  }
+  __syncthreads();
+  if (p == 0) {
+    float s = red[c];
+    for (int k = 1; k < P; ++k) s += red[k * H + c];
     const float gv = s * inv_n;
     gs[c] = gv;
     if (t == 0) g[(size_t)b * H + c] = gv;
   }
   __syncthreads();
-  float *qt = q + ((size_t)t * B + b) * H;
-  float part = 0.f;
-  const float *W1Tt = W1T ? W1T + (size_t)t * H * H : nullptr;
-  for (int c = threadIdx.x; c < H; c += kHeadThreads) {
-    float s = b1[c];
-    if (W1Tt) {
+  // the W1 product over k = p RK ..
+  {
+    const int RK = (H + P - 1) / P;
+    const int k0 = min(p * RK, H), k1 = min(k0 + RK, H);
+    float s = 0.f;
+    if (act) {
+      if (W1T) {
+        const float *W1Tt = W1T + (size_t)t * H * H;
 #pragma unroll 8
-      for (int k = 0; k < H; ++k) s += W1Tt[(size_t)k * H + c] * gs[k];
-    } else {
-      const float *row = W1 + (size_t)c * H;
+        for (int k = k0; k < k1; ++k) s += W1Tt[(size_t)k * H + c] * gs[k];
+      } else {
+        const float *row = W1 + (size_t)c * H;
 #pragma unroll 8
-      for (int k = 0; k < H; ++k) s += row[k] * gs[k];
+        for (int k = k0; k < k1; ++k) s += row[k] * gs[k];
+      }
     }
-    const float qv = s > 0.f ? s : 0.f;
-    qt[c] = qv;
-    part += w2[c] * qv;
+    __syncthreads(); // every read of red above is done
+    red[tid] = s;
   }
-  const float y = block_sum(part, red) + b2[0];
+  __syncthreads();
+  float part = 0.f;
+  if (p == 0) {
+    float s = b1[c];
+    for (int k = 0; k < P; ++k) s += red[k * H + c];
+    const float qv = s > 0.f ? s : 0.f;
+    q[((size_t)t * B + b) * H + c] = qv;
+    part = w2[c] * qv;
+  }
+  __syncthreads();
+  const float y = block_sum<kHeadFwdThreads>(part, red) + b2[0];
   if (threadIdx.x == 0) {
     pred[(size_t)b * Tg + t] = y;
     if (pred2) pred2[(size_t)b * Tg + t] = y;
@@ -459,8 +493,9 @@ hipError_t launch_head_forward(const Dims *dims, int capB, int H, int Tg, const 
                                const float *h, const float *wh, const float *W1T, float *g,
                                float *q, float *pred, float *pred2, hipStream_t s) {
   if (capB <= 0) return hipSuccess;
-  k_head_forward<<<dim3(capB, Tg), kHeadThreads, 0, s>>>(dims, H, Tg, graph_ptr, h, wh, W1T, g,
-                                                         q, pred, pred2);
+  if (Tg < 1 || Tg > kMaxGraphHeads || H < 1 || H > 512) return hipErrorInvalidValue;
+  k_head_forward<<<dim3(capB, Tg), kHeadFwdThreads, 0, s>>>(dims, H, Tg, graph_ptr, h, wh, W1T,
+                                                             g, q, pred, pred2);
   return hipGetLastError();
 }
 
